@@ -1,0 +1,202 @@
+"""Pins of the oracle's impedance matrix: regular pairs against an independent
+brute-force double integral, the singular rule against the closed-form static
+self term and against the regular rule on far pairs, reciprocity, the exact
+loop-divergence cancellation of the scalar part, and the table-mode method
+error of Section III."""
+
+import numpy as np
+import pytest
+
+from paper_1901_04162_amd import meshes
+
+
+def _two_far_triangles():
+    V = np.array([
+        [0.0, 0.0, 0.0], [0.1, 0.0, 0.01], [0.02, 0.09, -0.01],
+        [0.9, 0.3, 0.2], [1.0, 0.35, 0.25], [0.92, 0.41, 0.1],
+    ])
+    F = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    return V, F
+
+
+def _brute_pair(V, F, p, q, k, n=24, part=0):
+    """X[a][b] = mean over p and q of [(r-v_a).(r'-v_b)/4 - 1/k^2] g(R), with a
+    collapsed tensor Gauss rule of n*n points per triangle (numpy only)."""
+    x, wx = np.polynomial.legendre.leggauss(n)
+    x, wx = 0.5 * (x + 1), 0.5 * wx
+    u, v = np.meshgrid(x, x, indexing="ij")
+    w = (2 * np.outer(wx, wx) * u).ravel()
+    l1, l2 = (u * (1 - v)).ravel(), (u * v).ravel()
+    l0 = 1 - l1 - l2
+
+    def pts(t):
+        A, B, C_ = V[F[t]]
+        return l0[:, None] * A + l1[:, None] * B + l2[:, None] * C_
+
+    P, Q = pts(p), pts(q)
+    R = np.linalg.norm(P[:, None, :] - Q[None, :, :], axis=2)
+    g = np.exp(-1j * k * R) / R
+    X = np.zeros((3, 3), complex)
+    for a in range(3):
+        for b in range(3):
+            br = np.zeros_like(R)
+            if part != 2:
+                br += 0.25 * np.einsum("ic,jc->ij", P - V[F[p][a]], Q - V[F[q][b]])
+            if part != 1:
+                br -= 1.0 / k ** 2
+            X[a, b] = np.einsum("i,j,ij->", w, w, g * br)
+    return X
+
+
+@pytest.mark.parametrize("part", [0, 1, 2])
+@pytest.mark.parametrize("k", [2.0 * np.pi, 17.0])
+def test_regular_pair_converges_to_brute_force(orc, part, k):
+    V, F = _two_far_triangles()
+    ref = _brute_pair(V, F, 0, 1, k, part=part)
+    errs = []
+    for q in (3, 6, 7):
+        X = orc.pair_block(V, F, 0, 1, k, q, part=part)
+        errs.append(np.max(np.abs(X - ref)) / np.max(np.abs(ref)))
+    assert errs[2] < 5e-5 and errs[1] < 5e-4
+    assert errs[2] < errs[0]
+    # same high-order rule in the oracle: the two agree to rounding
+    X = orc.pair_block(V, F, 0, 1, k, orc.collapsed_gauss_rule(24), part=part)
+    assert np.max(np.abs(X - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_singular_rule_reduces_to_regular_on_far_pairs(orc):
+    V, F = _two_far_triangles()
+    k = 17.0
+    rule = orc.collapsed_gauss_rule(12)
+    Xr = orc.pair_block(V, F, 0, 1, k, rule)
+    Xs = orc.pair_block(V, F, 0, 1, k, rule, mode=orc.DIRECT | orc.FORCE_TOUCHING)
+    assert np.max(np.abs(Xs - Xr)) <= 1e-10 * np.max(np.abs(Xr))
+
+
+def _self_static(a, b, c):
+    """Closed form of int_T int_T 1/|r-r'| for a triangle with sides a, b, c."""
+    s = 0.5 * (a + b + c)
+    A = np.sqrt(s * (s - a) * (s - b) * (s - c))
+
+    def term(a, b, c):
+        return np.log(((a + b) ** 2 - c ** 2) / (b ** 2 - (a - c) ** 2)) / a
+
+    return 4 * A * A / 3 * (term(a, b, c) + term(b, c, a) + term(c, a, b)), A
+
+
+@pytest.mark.parametrize("tri", [
+    [[0, 0, 0], [1, 0, 0], [0.5, np.sqrt(3) / 2, 0]],
+    [[0, 0, 0], [1.3, 0.1, 0.2], [0.2, 0.7, -0.1]],
+    [[0.1, 0, 0], [0.14, 0.003, 0], [0.11, 0.05, 0.01]],
+])
+def test_self_term_static_limit(orc, tri):
+    """k -> 0: -k^2 X_Phi -> (1/A^2) int int 1/R (real part)."""
+    V = np.array(tri, float)
+    F = np.array([[0, 1, 2]], dtype=np.int32)
+    a = np.linalg.norm(V[1] - V[2])
+    b = np.linalg.norm(V[2] - V[0])
+    c = np.linalg.norm(V[0] - V[1])
+    I, A = _self_static(a, b, c)
+    k = 1e-6
+    prev = None
+    for n in (8, 16, 32, 64):
+        X = orc.pair_block(V, F, 0, 0, k, orc.collapsed_gauss_rule(n), part=orc.PART_PHI)
+        got = (-k * k * X[0, 0]).real * A * A
+        err = abs(got - I) / I
+        if prev is not None:
+            assert err < prev
+        prev = err
+    assert prev < 1e-6
+    if abs(a - b) < 1e-12 and abs(b - c) < 1e-12:
+        assert abs(I - 0.75 * a ** 3 * np.log(3.0)) < 1e-14
+
+
+def test_touching_pairs_converge_with_rule_order(orc):
+    """Edge- and vertex-adjacent pairs: the singular rule converges as the
+    outer/inner rule is refined."""
+    V, F = meshes.icosphere(1)
+    E = orc.rwg(V, F)
+    p, q = int(E[0, 2]), int(E[0, 3])  # edge-adjacent
+    vert = next(t for t in range(F.shape[0]) if t not in (p, q) and len(set(F[t]) & set(F[p])) == 1)
+    k = 3.0  # about two radians per triangle on this coarse mesh
+    for qq in (q, vert, p):
+        ref = orc.pair_block(V, F, p, qq, k, orc.collapsed_gauss_rule(40))
+        errs = [np.max(np.abs(orc.pair_block(V, F, p, qq, k, r) - ref)) / np.max(np.abs(ref))
+                for r in (3, 7) + tuple(orc.collapsed_gauss_rule(n) for n in (5, 10, 20))]
+        assert errs[1] < errs[0] < 0.1
+        assert all(b < a for a, b in zip(errs[2:], errs[3:]))
+        assert errs[-1] < 1e-4
+
+
+@pytest.fixture(scope="module")
+def ico2(orc):
+    V, F = meshes.icosphere(2)
+    E = orc.rwg(V, F)
+    k = 2.0 * np.pi
+    Z = orc.fill(V, F, k, 3, edges=E)
+    return V, F, E, k, Z
+
+
+def test_reciprocity(ico2):
+    V, F, E, k, Z = ico2
+    assert np.max(np.abs(Z - Z.T)) <= 1e-14 * np.max(np.abs(Z))
+
+
+def _loop_vectors(V, F, E):
+    """For each vertex, coefficients u[n] on its incident RWG edges such that
+    sum_n u[n] div f_n vanishes on every triangle (found by walking around
+    the vertex)."""
+    ne = E.shape[0]
+    by_tri = {}
+    for n, (lo, hi, tp, tm, ap, am) in enumerate(E):
+        for t, sgn in ((tp, 1.0), (tm, -1.0)):
+            by_tri.setdefault(int(t), []).append((n, sgn))
+    l = np.linalg.norm(V[E[:, 0]] - V[E[:, 1]], axis=1)
+    out = []
+    for v in range(V.shape[0]):
+        inc = [n for n in range(ne) if v in (E[n, 0], E[n, 1])]
+        u = np.zeros(ne)
+        u[inc[0]] = 1.0 / l[inc[0]]
+        for _ in range(len(inc) + 2):
+            for t in range(F.shape[0]):
+                if v not in F[t]:
+                    continue
+                pair = [(n, s) for n, s in by_tri[t] if n in inc]
+                (n1, s1), (n2, s2) = pair
+                # div on t: s*l/A * u ; require s1 l1 u1 + s2 l2 u2 = 0
+                if u[n1] != 0 and u[n2] == 0:
+                    u[n2] = -s1 * l[n1] * u[n1] / (s2 * l[n2])
+                elif u[n2] != 0 and u[n1] == 0:
+                    u[n1] = -s2 * l[n2] * u[n2] / (s1 * l[n1])
+        out.append(u)
+    return np.array(out), l
+
+
+def test_loop_divergence_cancels_exactly(orc, ico2):
+    V, F, E, k, _ = ico2
+    ZPhi = orc.fill(V, F, k, 3, part=orc.PART_PHI, edges=E)
+    ZA = orc.fill(V, F, k, 3, part=orc.PART_A, edges=E)
+    U, l = _loop_vectors(V, F, E)
+    res = np.abs(ZPhi @ U.T).max()
+    scale = np.abs(ZPhi).max() * np.abs(U).max()
+    assert res <= 1e-13 * scale
+    # the vector part does not vanish on loops (the check is not vacuous)
+    assert np.abs(ZA @ U.T).max() > 1e-3 * np.abs(ZA).max() * np.abs(U).max()
+
+
+@pytest.mark.parametrize("tol,bound", [(1e-4, 1e-5), (1e-6, 1e-7), (1e-8, 1e-9)])
+def test_table_method_error(orc, ico2, tol, bound):
+    V, F, E, k, Z = ico2
+    rmin, rmax = orc.r_range(V, F, 3)
+    G = orc.build_table(orc.GREEN, k, rmin, rmax, tol)
+    Zt = orc.fill(V, F, k, 3, mode=orc.TABLE, gtable=G, edges=E)
+    err = np.linalg.norm(Zt - Z) / np.linalg.norm(Z)
+    assert err < bound
+    assert err > 0.0
+
+
+def test_fill_entries_match_full(orc, ico2):
+    V, F, E, k, Z = ico2
+    rows, cols = meshes.entry_sample(E.shape[0], 500, 1)
+    z = orc.fill_entries(V, F, E, k, 3, rows, cols)
+    np.testing.assert_array_equal(z, Z[rows, cols])
