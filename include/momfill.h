@@ -1,0 +1,171 @@
+/*
+ * momfill: EFIE impedance-matrix fill on RWG basis functions for one MI355X
+ * (gfx950), with the adaptive interpolation tables of Exp(-jkr) and
+ * Exp(-jkr)/r of S. Yang and D. Su, "Fast Green Function Evaluation for
+ * Method of Moment" (Section II), beside a direct complex-exponential fill.
+ *
+ * Conventions
+ *  - Time convention exp(+j omega t); free-space impedance eta0 = 376.730313668.
+ *  - Z_mn = j k eta0/(4 pi) sum over the two triangles of m and of n of
+ *      s s' l_m l_n /(A A') int int [ (r-v).(r'-v')/4 - 1/k^2 ] g(|r-r'|),
+ *    g(R) = exp(-jkR)/R (Eq. (1)), with the symmetric triangle rule of
+ *    quad_order points on both triangles.  Triangle pairs that share a vertex
+ *    ("touching", including a triangle with itself) integrate 1/R in closed
+ *    form and the remainder g - 1/R by the rule, then are symmetrised: this
+ *    is the singularity cancellation the paper keeps for r < r_min
+ *    (Section II-C).
+ *  - RWG unknowns are the interior edges numbered in order of first
+ *    appearance when triangles are scanned in index order and, inside a
+ *    triangle, local edges 0,1,2 (local edge a is opposite vertex a).  T+ of
+ *    an edge is the triangle running v_lo -> v_hi in its cyclic vertex order.
+ *  - Z is row-major with leading dimension ldz (row = test edge), complex
+ *    values as interleaved (re, im) pairs: MF_C64 (float) or MF_C128
+ *    (double).  The arithmetic of regular triangle pairs is FP32; tables,
+ *    distance range and touching pairs are FP64.
+ *
+ * Memory and streams
+ *  - Arguments named *_dev are device pointers on the current HIP device;
+ *    the others are host pointers.  The caller owns vertices, Z, gradients
+ *    and the stream.  A mesh or table handle owns the device memory it
+ *    allocates when it is created and frees it in its destroy call.
+ *  - Every call enqueues its kernels on `stream` and returns without
+ *    synchronising, except where it says it copies a result to the host.
+ *
+ * Errors: functions return MF_OK or a negative code and never throw;
+ * mf_last_error() gives a message for the calling thread's last error.
+ */
+#ifndef MOMFILL_H
+#define MOMFILL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MF_OK = 0,
+  MF_EINVAL = -1,    /* bad argument                                     */
+  MF_EMESH = -2,     /* degenerate / non-manifold / inconsistent mesh     */
+  MF_ERANGE = -3,    /* a regular-pair distance outside the table range   */
+  MF_ENOMEM = -4,    /* device or host allocation failed                 */
+  MF_EHIP = -5,      /* HIP runtime error                                */
+  MF_ENOTCONV = -6   /* table probe check failed after 8 refinements      */
+};
+
+enum { MF_MODE_TABLE = 0, MF_MODE_DIRECT = 1 };
+/* Debug bits OR-ed into mode: keep only the vector-potential term (A) or
+ * only the scalar-potential term (PHI) of the bracket. */
+enum { MF_PART_A = 0x10, MF_PART_PHI = 0x20 };
+enum { MF_C64 = 0, MF_C128 = 1 };
+
+typedef struct mf_mesh mf_mesh;
+typedef struct mf_tables mf_tables;
+
+/* Message for the last error of the calling thread ("" if none). */
+const char *mf_last_error(void);
+
+/* ---- mesh -------------------------------------------------------------
+ * Validates the triangle list (host, n_triangles*3 vertex indices), builds
+ * the RWG edge table, the touching-pair lists and the tile plan on the host
+ * and uploads them.  Only topology is fixed here: vertex coordinates are
+ * passed to every fill call (device, FP64), so one handle serves perturbed
+ * geometries.  MF_EMESH for a repeated or out-of-range vertex index, an edge
+ * shared by more than two triangles or two triangles running an edge the
+ * same way. */
+int mf_mesh_create(int32_t n_vertices, int32_t n_triangles, const int32_t *triangles,
+                   mf_mesh **out);
+void mf_mesh_destroy(mf_mesh *mesh);
+/* Number of RWG unknowns (interior edges). */
+int mf_mesh_n_edges(const mf_mesh *mesh, int32_t *n_edges);
+/* Copies the edge table to the host: 6 ints per edge,
+ * v_lo, v_hi, T+, T-, a+, a- (a = local index of the edge in T+/T-). */
+int mf_mesh_edges(const mf_mesh *mesh, int32_t *edges);
+/* Number of ordered touching triangle pairs (p, q sharing a vertex). */
+int mf_mesh_n_touching(const mf_mesh *mesh, int64_t *n_pairs);
+
+/* ---- distance range (abstract; Section II-C) ---------------------------
+ * Exact FP64 minimum and maximum of |r_{p,i} - r_{q,j}| over all vertex-
+ * disjoint triangle pairs (p,q) and all pairs of quadrature points of the
+ * quad_order rule; these bound every distance the regular fill looks up.
+ * Copies the two values to the host (synchronises `stream`).  MF_EINVAL if
+ * quad_order is not 3, 6 or 7 or the mesh has no vertex-disjoint pair;
+ * MF_EMESH for a zero-area triangle. */
+int mf_r_range(mf_mesh *mesh, const double *vertices_dev, int quad_order, double *r_min,
+               double *r_max, hipStream_t stream);
+
+/* ---- tables (Section II-B, II-C; Eqs. (2), (4)-(6), (10)) --------------
+ * Builds on the device, in FP64, the adaptive tables of Exp(-jkr) (linear
+ * interpolation) and Exp(-jkr)/r (cubic Lagrange) over [r_min, r_max]:
+ * uniform interval t from the error bound of Eq. (10) for relative error
+ * tol (capped at a 32nd of a wavelength), refinement windows of half width
+ * 2t with interval t/2 around every zero of the real or imaginary part,
+ * forced samples at those zeros, a sample dropped when a higher-priority
+ * one is closer than t/4, the hash of Eq. (6) with bucket width equal to the
+ * smallest sample interval, and a probe check (8 points per interval and
+ * r_max) that halves t^2 and rebuilds, at most 8 times, until the maximum
+ * relative error is below tol.  Synchronises `stream` (the probe result
+ * decides the loop).  MF_EINVAL: k <= 0 or not finite, r_min <= 0,
+ * r_max <= r_min, tol outside [1e-12, 1e-1]; MF_ENOTCONV if the probe check
+ * still fails. */
+int mf_build_tables(double k, double r_min, double r_max, double tol, mf_tables **out,
+                    hipStream_t stream);
+void mf_tables_destroy(mf_tables *tables);
+/* Sizes and parameters: samples of the Exp and Green tables, hash buckets
+ * of each, their uniform intervals and the probe errors reached. */
+int mf_tables_info(const mf_tables *tables, int32_t *n_exp, int32_t *n_green,
+                   int32_t *m_exp, int32_t *m_green, double *t_exp, double *t_green,
+                   double *err_exp, double *err_green);
+/* Copies a table to the host: which = 0 Exp, 1 Green.  r: n doubles,
+ * values: 2n doubles (re, im), hash: m ints (Eq. (6) array).  Any pointer
+ * may be NULL.  Synchronises `stream`. */
+int mf_tables_get(const mf_tables *tables, int which, double *r, double *values, int32_t *hash,
+                  hipStream_t stream);
+/* Interpolated values of a table at n device points r_dev (FP64 in, FP64
+ * complex out, 2n doubles), through the same FP32 lookup and polynomial
+ * evaluation the fill uses.  Points outside [r_min, r_max] give NaN. */
+int mf_tables_eval(const mf_tables *tables, int which, int64_t n, const double *r_dev,
+                   double *out_dev, hipStream_t stream);
+
+/* ---- fill ---------------------------------------------------------------
+ * Z (device) receives all n_edges x n_edges entries.  mode: MF_MODE_TABLE
+ * (Green function from `tables`, which must cover the mesh's distance
+ * range) or MF_MODE_DIRECT (exp(-jkR)/R evaluated per point pair; tables
+ * may be NULL), optionally OR-ed with MF_PART_A or MF_PART_PHI.  A regular
+ * distance outside the table range by more than FP32 rounding is reported
+ * as MF_ERANGE by mf_sync_status. */
+int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order, int mode,
+              const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
+              hipStream_t stream);
+
+/* ---- adjoint ------------------------------------------------------------
+ * Gradient of L = Re sum_mn conj(W_mn) Z_mn, W = dLdZ_dev (same dtype and
+ * layout as Z), with respect to the vertex coordinates (dL_dvertices_dev,
+ * n_vertices*3 doubles, overwritten) and k (dL_dk_dev, one double,
+ * overwritten).  Table mode uses the tables as constants: dG/dR from the
+ * derivative of the cubic and dG/dk = -j Exp(-jkR) from the linear Exp
+ * table; direct mode differentiates exp(-jkR)/R. */
+int mf_fill_Z_backward(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
+                       int mode, const mf_tables *tables, const void *dLdZ_dev, int z_dtype,
+                       int64_t ldz, double *dL_dvertices_dev, double *dL_dk_dev,
+                       hipStream_t stream);
+
+/* Phase timing.  With mf_set_timing(1), every mf_fill_Z records HIP events
+ * on its stream around its phases; mf_mesh_timings waits for the last fill
+ * on `mesh` and writes milliseconds: ms[0] geometry preparation, ms[1]
+ * touching pairs (FP64), ms[2] regular-pair tile fill.  MF_EINVAL if no
+ * timed fill has run on the mesh. */
+void mf_set_timing(int on);
+int mf_mesh_timings(mf_mesh *mesh, float *ms3);
+
+/* Synchronises `stream` and returns a deferred device-side status of the
+ * last fill on this mesh (MF_ERANGE) or MF_OK. */
+int mf_sync_status(mf_mesh *mesh, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

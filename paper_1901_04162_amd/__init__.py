@@ -1,0 +1,201 @@
+"""MI355X EFIE impedance-matrix fill with adaptive Green-function tables.
+
+Python face of libmomfill.so: torch supplies device memory and the stream,
+every step of the fill runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as _L
+from ._lib import (MF_C64, MF_C128, MF_MODE_DIRECT, MF_MODE_TABLE, MF_PART_A,  # noqa: F401
+                   MF_PART_PHI, MomfillError, check, lib)
+
+MODES = {"table": MF_MODE_TABLE, "direct": MF_MODE_DIRECT}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """Topology of a triangle mesh (RWG edges, touching pairs, tile plan)."""
+
+    def __init__(self, F, n_vertices: int):
+        F = np.ascontiguousarray(np.asarray(F), dtype=np.int32)
+        if F.ndim != 2 or F.shape[1] != 3:
+            raise ValueError("F must be (n_triangles, 3)")
+        h = C.c_void_p()
+        check(lib().mf_mesh_create(int(n_vertices), F.shape[0],
+                                   F.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
+        self._h = h
+        self.n_vertices = int(n_vertices)
+        self.n_triangles = F.shape[0]
+        n = C.c_int32()
+        check(lib().mf_mesh_n_edges(h, C.byref(n)))
+        self.n_edges = n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def edges(self) -> np.ndarray:
+        out = np.zeros((self.n_edges, 6), dtype=np.int32)
+        check(lib().mf_mesh_edges(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def n_touching(self) -> int:
+        n = C.c_int64()
+        check(lib().mf_mesh_n_touching(self._h, C.byref(n)))
+        return n.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _L._lib is not None:
+            _L._lib.mf_mesh_destroy(self._h)
+            self._h = None
+
+
+class Tables:
+    """Device tables of Exp(-jkr) (linear) and Exp(-jkr)/r (cubic Lagrange)."""
+
+    def __init__(self, k: float, r_min: float, r_max: float, tol: float):
+        h = C.c_void_p()
+        check(lib().mf_build_tables(float(k), float(r_min), float(r_max), float(tol),
+                                    C.byref(h), _stream()))
+        self._h = h
+        self.k, self.r_min, self.r_max, self.tol = float(k), float(r_min), float(r_max), float(tol)
+        ne, ng, me, mg = (C.c_int32() for _ in range(4))
+        te, tg, ee, eg = (C.c_double() for _ in range(4))
+        check(lib().mf_tables_info(h, C.byref(ne), C.byref(ng), C.byref(me), C.byref(mg),
+                                   C.byref(te), C.byref(tg), C.byref(ee), C.byref(eg)))
+        self.n_exp, self.n_green, self.m_exp, self.m_green = ne.value, ng.value, me.value, mg.value
+        self.t_exp, self.t_green, self.err_exp, self.err_green = te.value, tg.value, ee.value, eg.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get(self, which: str):
+        """(nodes, values, hash) of the 'exp' or 'green' table as numpy arrays."""
+        w = 0 if which == "exp" else 1
+        n = self.n_exp if w == 0 else self.n_green
+        m = self.m_exp if w == 0 else self.m_green
+        r = np.zeros(n)
+        f = np.zeros(2 * n)
+        h = np.zeros(m, dtype=np.int32)
+        dp = C.POINTER(C.c_double)
+        check(lib().mf_tables_get(self._h, w, r.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                  h.ctypes.data_as(C.POINTER(C.c_int32)), _stream()))
+        return r, f[0::2] + 1j * f[1::2], h
+
+    def eval(self, which: str, r: torch.Tensor) -> torch.Tensor:
+        """FP32 lookup + interpolation at device points r (float64)."""
+        r = r.to(device="cuda", dtype=torch.float64).contiguous()
+        out = torch.empty(r.numel(), dtype=torch.complex128, device="cuda")
+        check(lib().mf_tables_eval(self._h, 0 if which == "exp" else 1, r.numel(),
+                                   C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _L._lib is not None:
+            _L._lib.mf_tables_destroy(self._h)
+            self._h = None
+
+
+def _vertices(V) -> torch.Tensor:
+    if not isinstance(V, torch.Tensor):
+        V = torch.as_tensor(np.asarray(V, dtype=np.float64))
+    return V.to(device="cuda", dtype=torch.float64).contiguous()
+
+
+def r_range(mesh: Mesh, V, quad_order: int):
+    """Exact FP64 (r_min, r_max) over regular quadrature-point pairs."""
+    Vd = _vertices(V)
+    lo, hi = C.c_double(), C.c_double()
+    check(lib().mf_r_range(mesh.handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
+                           C.byref(lo), C.byref(hi), _stream()))
+    return lo.value, hi.value
+
+
+def build_tables(k: float, r_min: float, r_max: float, tol: float) -> Tables:
+    return Tables(k, r_min, r_max, tol)
+
+
+def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables: Tables = None,
+           dtype=torch.complex64, out: torch.Tensor = None, part: int = 0) -> torch.Tensor:
+    """Impedance matrix Z (n_edges x n_edges) on the current device."""
+    Vd = _vertices(V)
+    E = mesh.n_edges
+    if out is None:
+        out = torch.empty((E, E), dtype=dtype, device="cuda")
+    if out.dtype not in (torch.complex64, torch.complex128) or out.dim() != 2 or \
+            out.shape[0] < E or out.shape[1] < E or out.stride(1) != 1:
+        raise ValueError("out must be a row-major complex64/complex128 matrix of at least E x E")
+    zt = MF_C64 if out.dtype == torch.complex64 else MF_C128
+    m = MODES[mode] | part
+    check(lib().mf_fill_Z(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order), m,
+                          tables.handle if tables is not None else None,
+                          C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
+    return out
+
+
+def set_timing(on: bool):
+    lib().mf_set_timing(1 if on else 0)
+
+
+def timings(mesh: Mesh):
+    """(geometry, touching pairs, regular fill) milliseconds of the last timed fill."""
+    ms = (C.c_float * 3)()
+    check(lib().mf_mesh_timings(mesh.handle, ms))
+    return tuple(float(x) for x in ms)
+
+
+def sync_status(mesh: Mesh):
+    check(lib().mf_sync_status(mesh.handle, _stream()))
+
+
+def fill_Z_backward(mesh: Mesh, V, k: float, quad_order: int, mode: str, tables: Tables,
+                    dLdZ: torch.Tensor):
+    """(dL/dV [nv,3] float64, dL/dk float) for L = Re sum conj(dLdZ) * Z."""
+    Vd = _vertices(V)
+    W = dLdZ.contiguous()
+    zt = MF_C64 if W.dtype == torch.complex64 else MF_C128
+    dV = torch.empty_like(Vd)
+    dk = torch.empty(1, dtype=torch.float64, device="cuda")
+    check(lib().mf_fill_Z_backward(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
+                                   int(quad_order), MODES[mode],
+                                   tables.handle if tables is not None else None,
+                                   C.c_void_p(W.data_ptr()), zt, W.stride(0),
+                                   C.c_void_p(dV.data_ptr()), C.c_void_p(dk.data_ptr()),
+                                   _stream()))
+    return dV, dk
+
+
+class _FillFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, k, mesh, quad_order, mode, tables, dtype):
+        Z = fill_Z(mesh, V, float(k), quad_order, mode, tables, dtype)
+        ctx.save_for_backward(V)
+        ctx.meta = (float(k), mesh, quad_order, mode, tables)
+        return Z
+
+    @staticmethod
+    def backward(ctx, gZ):
+        (V,) = ctx.saved_tensors
+        k, mesh, quad_order, mode, tables = ctx.meta
+        # torch hands the gradient of a real loss w.r.t. complex Z as dL/dRe + j dL/dIm,
+        # which is the W of L = Re sum conj(W) Z
+        dV, dk = fill_Z_backward(mesh, V, k, quad_order, mode, tables, gZ)
+        return dV.to(V.dtype), dk.reshape(()), None, None, None, None, None
+
+
+def fill(V: torch.Tensor, k, mesh: Mesh, quad_order: int, mode: str = "table",
+         tables: Tables = None, dtype=torch.complex64) -> torch.Tensor:
+    """Differentiable fill: gradients flow to V (vertices) and k (a tensor)."""
+    kk = k if isinstance(k, torch.Tensor) else torch.tensor(float(k), dtype=torch.float64)
+    return _FillFn.apply(V, kk, mesh, quad_order, mode, tables, dtype)

@@ -1,0 +1,464 @@
+// C-ABI entry points and host-side mesh planning of libmomfill.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mf {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error(std::string("HIP error ") + hipGetErrorString(e) + " in " + what);
+  return MF_EHIP;
+}
+
+static int fail(int code, const std::string &msg) {
+  set_error(msg);
+  return code;
+}
+
+// Symmetric triangle rules of degree 2, 4 and 5 (barycentric, weights sum
+// to one); coordinates and weights of the 6-point rule from their closed
+// forms.
+bool make_rule(int q, Rule *r) {
+  auto put = [&](int i, double a, double b, double c) {
+    r->bary[i][0] = a;
+    r->bary[i][1] = b;
+    r->bary[i][2] = c;
+  };
+  if (q == 3) {
+    const double a = 2.0 / 3.0, b = 1.0 / 6.0;
+    put(0, a, b, b);
+    put(1, b, a, b);
+    put(2, b, b, a);
+    r->w[0] = r->w[1] = r->w[2] = 1.0 / 3.0;
+  } else if (q == 6) {
+    const double s10 = std::sqrt(10.0);
+    const double rt = std::sqrt(38.0 - 44.0 * std::sqrt(2.0 / 5.0));
+    const double a1 = (8.0 - s10 + rt) / 18.0, a2 = (8.0 - s10 - rt) / 18.0;
+    const double wr = std::sqrt(213125.0 - 53320.0 * s10);
+    const double w1 = (620.0 + wr) / 3720.0, w2 = (620.0 - wr) / 3720.0;
+    const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
+    put(0, b1, a1, a1);
+    put(1, a1, b1, a1);
+    put(2, a1, a1, b1);
+    put(3, b2, a2, a2);
+    put(4, a2, b2, a2);
+    put(5, a2, a2, b2);
+    r->w[0] = r->w[1] = r->w[2] = w1;
+    r->w[3] = r->w[4] = r->w[5] = w2;
+  } else if (q == 7) {
+    const double s15 = std::sqrt(15.0);
+    const double a = (6.0 - s15) / 21.0, b = (9.0 + 2.0 * s15) / 21.0;
+    const double c = (6.0 + s15) / 21.0, d = (9.0 - 2.0 * s15) / 21.0;
+    put(0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0);
+    put(1, b, a, a);
+    put(2, a, b, a);
+    put(3, a, a, b);
+    put(4, d, c, c);
+    put(5, c, d, c);
+    put(6, c, c, d);
+    r->w[0] = 9.0 / 40.0;
+    r->w[1] = r->w[2] = r->w[3] = (155.0 - s15) / 1200.0;
+    r->w[4] = r->w[5] = r->w[6] = (155.0 + s15) / 1200.0;
+  } else {
+    return false;
+  }
+  r->nq = q;
+  return true;
+}
+
+// ---- mesh planning --------------------------------------------------------
+
+struct HalfEdge {
+  int lo, hi, t, a;
+  bool up;
+};
+
+static int build_topology(mf_mesh *m) {
+  const int nt = m->nt, nv = m->nv;
+  std::vector<HalfEdge> h(3 * (size_t)nt);
+  for (int t = 0; t < nt; ++t) {
+    const int32_t *v = &m->tri[3 * (size_t)t];
+    for (int c = 0; c < 3; ++c)
+      if (v[c] < 0 || v[c] >= nv) return fail(MF_EMESH, "vertex index out of range");
+    if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2])
+      return fail(MF_EMESH, "triangle with a repeated vertex");
+    for (int a = 0; a < 3; ++a) {
+      int from = v[(a + 1) % 3], to = v[(a + 2) % 3];
+      h[3 * (size_t)t + a] = {std::min(from, to), std::max(from, to), t, a, from < to};
+    }
+  }
+  std::vector<uint32_t> idx(h.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (uint32_t)i;
+  std::sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
+    if (h[x].lo != h[y].lo) return h[x].lo < h[y].lo;
+    if (h[x].hi != h[y].hi) return h[x].hi < h[y].hi;
+    return x < y;
+  });
+  // interior edges keyed by first appearance (3t + a of the earlier half-edge)
+  std::vector<std::pair<uint32_t, uint32_t>> interior;  // (first, group start)
+  for (size_t i = 0; i < idx.size();) {
+    size_t j = i;
+    while (j < idx.size() && h[idx[j]].lo == h[idx[i]].lo && h[idx[j]].hi == h[idx[i]].hi) ++j;
+    if (j - i > 2) return fail(MF_EMESH, "edge shared by more than two triangles");
+    if (j - i == 2) {
+      if (h[idx[i]].up == h[idx[i + 1]].up)
+        return fail(MF_EMESH, "inconsistently oriented neighbouring triangles");
+      interior.push_back({std::min(idx[i], idx[i + 1]), (uint32_t)i});
+    }
+    i = j;
+  }
+  std::sort(interior.begin(), interior.end());
+  m->ne = (int)interior.size();
+  m->edges.assign(6 * (size_t)m->ne, 0);
+  m->tedge.assign(3 * (size_t)nt, -1);
+  m->tsign.assign(3 * (size_t)nt, 0);
+  for (int e = 0; e < m->ne; ++e) {
+    const HalfEdge &x = h[idx[interior[e].second]], &y = h[idx[interior[e].second + 1]];
+    const HalfEdge &pl = x.up ? x : y, &mi = x.up ? y : x;
+    int32_t *E = &m->edges[6 * (size_t)e];
+    E[0] = x.lo;
+    E[1] = x.hi;
+    E[2] = pl.t;
+    E[3] = mi.t;
+    E[4] = pl.a;
+    E[5] = mi.a;
+    m->tedge[3 * (size_t)pl.t + pl.a] = e;
+    m->tsign[3 * (size_t)pl.t + pl.a] = 1;
+    m->tedge[3 * (size_t)mi.t + mi.a] = e;
+    m->tsign[3 * (size_t)mi.t + mi.a] = -1;
+  }
+  if (m->ne == 0) return fail(MF_EMESH, "mesh has no interior edge");
+  return MF_OK;
+}
+
+static void build_touching(mf_mesh *m) {
+  const int nt = m->nt;
+  std::vector<std::vector<int32_t>> vt(m->nv);
+  for (int t = 0; t < nt; ++t)
+    for (int c = 0; c < 3; ++c) vt[m->tri[3 * (size_t)t + c]].push_back(t);
+  m->touch_off.assign(nt + 1, 0);
+  m->touch_q.clear();
+  std::vector<int32_t> nb;
+  for (int p = 0; p < nt; ++p) {
+    nb.clear();
+    for (int c = 0; c < 3; ++c)
+      for (int32_t q : vt[m->tri[3 * (size_t)p + c]]) nb.push_back(q);
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    m->touch_q.insert(m->touch_q.end(), nb.begin(), nb.end());
+    m->touch_off[p + 1] = (int32_t)m->touch_q.size();
+  }
+  m->touch_rev.assign(m->touch_q.size(), -1);
+  for (int p = 0; p < nt; ++p)
+    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) {
+      const int q = m->touch_q[s];
+      auto b = m->touch_q.begin() + m->touch_off[q], e = m->touch_q.begin() + m->touch_off[q + 1];
+      m->touch_rev[s] = (int32_t)(std::lower_bound(b, e, p) - m->touch_q.begin());
+    }
+}
+
+// Blocks of kTileEdges consecutive edges; each lists the triangles carrying
+// them with the block-local position of each local edge (0xff: not in block).
+static void build_blocks(mf_mesh *m) {
+  const int B = kTileEdges;
+  m->nblk = (m->ne + B - 1) / B;
+  m->blk_off.assign(m->nblk + 1, 0);
+  m->blk_tri.clear();
+  m->blk_pos.clear();
+  m->max_blk_tris = 0;
+  std::vector<int32_t> tl;
+  for (int b = 0; b < m->nblk; ++b) {
+    const int e0 = b * B, e1 = std::min(m->ne, e0 + B);
+    tl.clear();
+    for (int e = e0; e < e1; ++e) {
+      tl.push_back(m->edges[6 * (size_t)e + 2]);
+      tl.push_back(m->edges[6 * (size_t)e + 3]);
+    }
+    std::sort(tl.begin(), tl.end());
+    tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
+    for (int32_t t : tl) {
+      uint32_t pk = 0;
+      for (int a = 0; a < 3; ++a) {
+        const int e = m->tedge[3 * (size_t)t + a];
+        uint32_t pos = (e >= e0 && e < e1) ? (uint32_t)(e - e0) : 0xffu;
+        pk |= pos << (8 * a);
+      }
+      m->blk_tri.push_back(t);
+      m->blk_pos.push_back((int32_t)pk);
+    }
+    m->blk_off[b + 1] = (int32_t)m->blk_tri.size();
+    m->max_blk_tris = std::max(m->max_blk_tris, (int)tl.size());
+  }
+}
+
+template <class T>
+static int upload(T **dst, const std::vector<T> &src) {
+  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  MF_HIP(hipMalloc((void **)dst, bytes));
+  if (!src.empty()) MF_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MF_OK;
+}
+
+static bool g_timing = false;
+
+static void free_mesh(mf_mesh *m) {
+  if (!m) return;
+  for (hipEvent_t &e : m->ev)
+    if (e) (void)hipEventDestroy(e);
+  void *ptrs[] = {m->d_tri,       m->d_tedge,   m->d_tsign,   m->d_touch_off, m->d_touch_q,
+                  m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos,
+                  m->d_rec,       m->d_sing1,   m->d_sing,    m->d_scratch,   m->d_status,
+                  m->d_qp64,      m->d_brad};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+// Device copies of the plan, made on the first call that needs the GPU so
+// that topology can be built and inspected without one.
+static int ensure_device(mf_mesh *m) {
+  if (m->d_rec) return MF_OK;
+  std::vector<int32_t> touch_p(m->touch_q.size());
+  for (int p = 0; p < m->nt; ++p)
+    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) touch_p[s] = p;
+  const size_t npair = m->touch_q.size();
+  int rc;
+  if ((rc = upload(&m->d_tri, m->tri)) || (rc = upload(&m->d_tedge, m->tedge)) ||
+      (rc = upload(&m->d_tsign, m->tsign)) || (rc = upload(&m->d_touch_off, m->touch_off)) ||
+      (rc = upload(&m->d_touch_q, m->touch_q)) || (rc = upload(&m->d_touch_rev, m->touch_rev)) ||
+      (rc = upload(&m->d_touch_p, touch_p)) || (rc = upload(&m->d_blk_off, m->blk_off)) ||
+      (rc = upload(&m->d_blk_tri, m->blk_tri)) || (rc = upload(&m->d_blk_pos, m->blk_pos)))
+    return rc;
+  MF_HIP(hipMalloc((void **)&m->d_sing1, sizeof(double) * 18 * std::max<size_t>(npair, 1)));
+  MF_HIP(hipMalloc((void **)&m->d_sing, sizeof(float) * 18 * std::max<size_t>(npair, 1)));
+  MF_HIP(hipMalloc((void **)&m->d_scratch, sizeof(unsigned long long) * 16));
+  MF_HIP(hipMalloc((void **)&m->d_status, sizeof(int) * 4));
+  MF_HIP(hipMalloc((void **)&m->d_qp64, sizeof(double) * 3 * kMaxQ * (size_t)m->nt));
+  MF_HIP(hipMalloc((void **)&m->d_brad, sizeof(double) * (size_t)m->nt));
+  MF_HIP(hipMemset(m->d_status, 0, sizeof(int) * 4));
+  // d_rec last: its presence marks a complete upload
+  MF_HIP(hipMalloc((void **)&m->d_rec, sizeof(float) * kRecFloats * (size_t)m->nt));
+  return MF_OK;
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+const char *mf_last_error(void) { return g_err.c_str(); }
+
+int mf_mesh_create(int32_t n_vertices, int32_t n_triangles, const int32_t *triangles,
+                   mf_mesh **out) {
+  if (!out || !triangles || n_vertices <= 0 || n_triangles <= 0)
+    return fail(MF_EINVAL, "mf_mesh_create: bad argument");
+  *out = nullptr;
+  mf_mesh *m = new (std::nothrow) mf_mesh;
+  if (!m) return fail(MF_ENOMEM, "mf_mesh_create: out of host memory");
+  m->nv = n_vertices;
+  m->nt = n_triangles;
+  m->tri.assign(triangles, triangles + 3 * (size_t)n_triangles);
+  int rc = build_topology(m);
+  if (rc) {
+    free_mesh(m);
+    return rc;
+  }
+  build_touching(m);
+  build_blocks(m);
+  if (m->max_blk_tris > kMaxBlockTris) {
+    free_mesh(m);
+    return fail(MF_EMESH, "internal: edge block needs too many triangles");
+  }
+  *out = m;
+  return MF_OK;
+}
+
+void mf_mesh_destroy(mf_mesh *mesh) { free_mesh(mesh); }
+
+int mf_mesh_n_edges(const mf_mesh *m, int32_t *n) {
+  if (!m || !n) return fail(MF_EINVAL, "mf_mesh_n_edges: bad argument");
+  *n = m->ne;
+  return MF_OK;
+}
+
+int mf_mesh_edges(const mf_mesh *m, int32_t *edges) {
+  if (!m || !edges) return fail(MF_EINVAL, "mf_mesh_edges: bad argument");
+  std::memcpy(edges, m->edges.data(), m->edges.size() * sizeof(int32_t));
+  return MF_OK;
+}
+
+int mf_mesh_n_touching(const mf_mesh *m, int64_t *n) {
+  if (!m || !n) return fail(MF_EINVAL, "mf_mesh_n_touching: bad argument");
+  *n = (int64_t)m->touch_q.size();
+  return MF_OK;
+}
+
+int mf_r_range(mf_mesh *m, const double *V, int quad_order, double *rmin, double *rmax,
+               hipStream_t s) {
+  Rule r;
+  if (!m || !V || !rmin || !rmax || !make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_r_range: bad argument (quad_order must be 3, 6 or 7)");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  return launch_r_range(m, V, r, rmin, rmax, s);
+}
+
+int mf_build_tables(double k, double rmin, double rmax, double tol, mf_tables **out,
+                    hipStream_t s) {
+  if (!out) return fail(MF_EINVAL, "mf_build_tables: out is NULL");
+  *out = nullptr;
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_build_tables: k must be > 0");
+  if (!(rmin > 0.0) || !(rmax > rmin) || !std::isfinite(rmax))
+    return fail(MF_EINVAL, "mf_build_tables: need 0 < r_min < r_max");
+  if (!(tol >= 1e-12 && tol <= 1e-1))
+    return fail(MF_EINVAL, "mf_build_tables: tol must lie in [1e-12, 1e-1]");
+  mf_tables *t = new (std::nothrow) mf_tables;
+  if (!t) return fail(MF_ENOMEM, "mf_build_tables: out of host memory");
+  t->k = k;
+  t->rmin = rmin;
+  t->rmax = rmax;
+  t->tol = tol;
+  int rc = build_tables_device(t, tol, s);
+  if (rc) {
+    mf_tables_destroy(t);
+    return rc;
+  }
+  *out = t;
+  return MF_OK;
+}
+
+void mf_tables_destroy(mf_tables *t) {
+  if (!t) return;
+  for (mf_tables::One *o : {&t->e, &t->g}) {
+    void *ptrs[] = {o->r, o->f, o->hash, o->bucket, o->node, o->coef};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+  delete t;
+}
+
+int mf_tables_info(const mf_tables *t, int32_t *n_exp, int32_t *n_green, int32_t *m_exp,
+                   int32_t *m_green, double *t_exp, double *t_green, double *err_exp,
+                   double *err_green) {
+  if (!t) return fail(MF_EINVAL, "mf_tables_info: tables is NULL");
+  if (n_exp) *n_exp = t->e.n;
+  if (n_green) *n_green = t->g.n;
+  if (m_exp) *m_exp = t->e.m;
+  if (m_green) *m_green = t->g.m;
+  if (t_exp) *t_exp = t->e.t;
+  if (t_green) *t_green = t->g.t;
+  if (err_exp) *err_exp = t->e.err;
+  if (err_green) *err_green = t->g.err;
+  return MF_OK;
+}
+
+int mf_tables_get(const mf_tables *t, int which, double *r, double *values, int32_t *hash,
+                  hipStream_t s) {
+  if (!t || (which != 0 && which != 1)) return fail(MF_EINVAL, "mf_tables_get: bad argument");
+  const mf_tables::One &o = which == 0 ? t->e : t->g;
+  if (r) MF_HIP(hipMemcpyAsync(r, o.r, sizeof(double) * o.n, hipMemcpyDeviceToHost, s));
+  if (values)
+    MF_HIP(hipMemcpyAsync(values, o.f, sizeof(double) * 2 * o.n, hipMemcpyDeviceToHost, s));
+  if (hash) MF_HIP(hipMemcpyAsync(hash, o.hash, sizeof(int32_t) * o.m, hipMemcpyDeviceToHost, s));
+  MF_HIP(hipStreamSynchronize(s));
+  return MF_OK;
+}
+
+int mf_tables_eval(const mf_tables *t, int which, int64_t n, const double *r, double *out,
+                   hipStream_t s) {
+  if (!t || (which != 0 && which != 1) || n < 0 || (n > 0 && (!r || !out)))
+    return fail(MF_EINVAL, "mf_tables_eval: bad argument");
+  if (n == 0) return MF_OK;
+  return launch_table_eval(t, which, n, r, out, s);
+}
+
+int mf_fill_Z(mf_mesh *m, const double *V, double k, int quad_order, int mode,
+              const mf_tables *tab, void *Z, int z_dtype, int64_t ldz, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !Z) return fail(MF_EINVAL, "mf_fill_Z: NULL argument");
+  if (!make_rule(quad_order, &r)) return fail(MF_EINVAL, "mf_fill_Z: quad_order must be 3, 6 or 7");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_Z: k must be > 0");
+  const int base = mode & 0xf, part = mode & (MF_PART_A | MF_PART_PHI);
+  if ((base != MF_MODE_TABLE && base != MF_MODE_DIRECT) || (mode & ~0x3f) ||
+      part == (MF_PART_A | MF_PART_PHI))
+    return fail(MF_EINVAL, "mf_fill_Z: unknown mode");
+  if (base == MF_MODE_TABLE && !tab) return fail(MF_EINVAL, "mf_fill_Z: table mode needs tables");
+  if (base == MF_MODE_TABLE && std::fabs(tab->k - k) > 1e-12 * k)
+    return fail(MF_EINVAL, "mf_fill_Z: tables were built for another k");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_fill_Z: unknown z_dtype");
+  if (ldz < m->ne) return fail(MF_EINVAL, "mf_fill_Z: ldz < number of edges");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  const bool timed = g_timing;
+  if (timed && !m->ev[0])
+    for (hipEvent_t &e : m->ev) MF_HIP(hipEventCreate(&e));
+  if (timed) MF_HIP(hipEventRecord(m->ev[0], s));
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[1], s));
+  if ((rc = launch_singular(m, V, r, k, part, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[2], s));
+  if ((rc = launch_fill(m, r, k, mode, tab, Z, z_dtype, ldz, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
+  m->timed = timed;
+  return MF_OK;
+}
+
+void mf_set_timing(int on) { g_timing = on != 0; }
+
+int mf_mesh_timings(mf_mesh *m, float *ms3) {
+  if (!m || !ms3 || !m->timed) return fail(MF_EINVAL, "mf_mesh_timings: no timed fill");
+  MF_HIP(hipEventSynchronize(m->ev[3]));
+  for (int i = 0; i < 3; ++i) MF_HIP(hipEventElapsedTime(&ms3[i], m->ev[i], m->ev[i + 1]));
+  return MF_OK;
+}
+
+int mf_fill_Z_backward(mf_mesh *m, const double *V, double k, int quad_order, int mode,
+                       const mf_tables *tab, const void *W, int z_dtype, int64_t ldz, double *dV,
+                       double *dk, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !W || !dV || !dk) return fail(MF_EINVAL, "mf_fill_Z_backward: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_fill_Z_backward: quad_order must be 3, 6 or 7");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_Z_backward: k must be > 0");
+  if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
+    return fail(MF_EINVAL, "mf_fill_Z_backward: unknown mode");
+  if (mode == MF_MODE_TABLE && !tab)
+    return fail(MF_EINVAL, "mf_fill_Z_backward: table mode needs tables");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_fill_Z_backward: unknown z_dtype");
+  if (ldz < m->ne) return fail(MF_EINVAL, "mf_fill_Z_backward: ldz < number of edges");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  return launch_backward(m, V, r, k, mode, tab, W, z_dtype, ldz, dV, dk, s);
+}
+
+int mf_sync_status(mf_mesh *m, hipStream_t s) {
+  if (!m) return fail(MF_EINVAL, "mf_sync_status: mesh is NULL");
+  if (!m->d_status) return MF_OK;
+  MF_HIP(hipStreamSynchronize(s));
+  int st[4];
+  MF_HIP(hipMemcpy(st, m->d_status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st[0] != 0) {
+    MF_HIP(hipMemset(m->d_status, 0, sizeof(int) * 4));
+    return fail(MF_ERANGE, "a regular-pair distance fell outside the table range");
+  }
+  return MF_OK;
+}
+
+}  // extern "C"

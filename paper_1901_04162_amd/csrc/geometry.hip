@@ -1,0 +1,428 @@
+// Geometry preparation, exact distance range and touching-pair blocks (FP64).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace mf {
+
+struct RuleArg {
+  int nq;
+  double b[kMaxQ][3];
+  double w[kMaxQ];
+};
+
+static RuleArg rule_arg(const Rule &r) {
+  RuleArg a{};
+  a.nq = r.nq;
+  for (int i = 0; i < r.nq; ++i) {
+    for (int c = 0; c < 3; ++c) a.b[i][c] = r.bary[i][c];
+    a.w[i] = r.w[i];
+  }
+  return a;
+}
+
+// Quadrature point i of triangle (x0,x1,x2): b0 x0 + b1 x1 + b2 x2, evaluated
+// left to right without contraction so that every distance derived from it
+// is reproducible bit for bit.
+__device__ inline void quad_point(const RuleArg &R, int i, const double *x0, const double *x1,
+                                  const double *x2, double *P) {
+#pragma clang fp contract(off)
+  for (int c = 0; c < 3; ++c) P[c] = R.b[i][0] * x0[c] + R.b[i][1] * x1[c] + R.b[i][2] * x2[c];
+}
+
+__device__ inline double exact_dist(const double *a, const double *b) {
+#pragma clang fp contract(off)
+  const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+  return sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+// ---- K0: per-triangle record for the regular-pair kernel ------------------
+
+__global__ void k_geometry(const double *__restrict__ V, const int32_t *__restrict__ tri,
+                           const int32_t *__restrict__ tedge, const int8_t *__restrict__ tsign,
+                           int nt, RuleArg R, float *__restrict__ rec, double *__restrict__ qp64,
+                           double *__restrict__ brad, int *__restrict__ status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double x[3][3];
+  int vid[3];
+  for (int a = 0; a < 3; ++a) {
+    vid[a] = tri[3 * t + a];
+    for (int c = 0; c < 3; ++c) x[a][c] = V[3 * (size_t)vid[a] + c];
+  }
+  double c[3];
+  for (int d = 0; d < 3; ++d) c[d] = (x[0][d] + x[1][d] + x[2][d]) / 3.0;
+  const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+  const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+  const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+  const double area2 = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(area2 > 0.0)) atomicOr(&status[1], 1);
+  float *o = rec + (size_t)t * kRecFloats;
+  double rb = 0.0;
+  for (int i = 0; i < kMaxQ; ++i) {
+    double P[3] = {0.0, 0.0, 0.0};
+    if (i < R.nq) quad_point(R, i, x[0], x[1], x[2], P);
+    for (int d = 0; d < 3; ++d) {
+      const double rho = i < R.nq ? P[d] - c[d] : 0.0;
+      o[kRecRho + 3 * i + d] = (float)rho;
+      o[kRecWRho + 3 * i + d] = (float)(i < R.nq ? R.w[i] * rho : 0.0);
+      if (qp64 && i < R.nq) qp64[((size_t)t * kMaxQ + i) * 3 + d] = P[d];
+    }
+    if (i < R.nq) {
+      const double dd[3] = {P[0] - c[0], P[1] - c[1], P[2] - c[2]};
+      rb = fmax(rb, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
+    }
+  }
+  if (brad) brad[t] = rb;
+  for (int a = 0; a < 3; ++a) {
+    for (int d = 0; d < 3; ++d) o[kRecAlpha + 3 * a + d] = (float)(c[d] - x[a][d]);
+    const double *u = x[(a + 1) % 3], *v = x[(a + 2) % 3];
+    const double l = sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
+                          (u[2] - v[2]) * (u[2] - v[2]));
+    o[kRecSigma + a] = tedge[3 * t + a] >= 0 ? (float)(tsign[3 * t + a] * l) : 0.0f;
+  }
+  double *cd = reinterpret_cast<double *>(o + kRecCent);
+  cd[0] = c[0];
+  cd[1] = c[1];
+  cd[2] = c[2];
+  int *vi = reinterpret_cast<int *>(o + kRecVid);
+  vi[0] = vid[0];
+  vi[1] = vid[1];
+  vi[2] = vid[2];
+  o[63] = 0.0f;
+}
+
+int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
+  RuleArg R = rule_arg(r);
+  hipLaunchKernelGGL(k_geometry, dim3((m->nt + 127) / 128), dim3(128), 0, s, V, m->d_tri,
+                     m->d_tedge, m->d_tsign, m->nt, R, m->d_rec, m->d_qp64, m->d_brad, m->d_status);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+// ---- K1: exact distance range over regular pairs --------------------------
+// Pass 1 bounds every triangle pair by its centroid distance and the radii
+// of its quadrature points and keeps, as witnesses, the first point pair's
+// distance.  Pass 2 evaluates all point pairs exactly only for the pairs
+// whose bounds could beat the witnesses.
+
+constexpr int kRangeBlock = 256;
+constexpr int kRangeChunk = 256;
+
+struct RangeTri {
+  double c[3];
+  double rb;
+  double p0[3];
+  int v[3];
+};
+
+__device__ inline void load_range_tri(const double *qp64, const double *brad, const float *rec,
+                                      int t, RangeTri &o) {
+  const double *cd = reinterpret_cast<const double *>(rec + (size_t)t * kRecFloats + kRecCent);
+  const int *vi = reinterpret_cast<const int *>(rec + (size_t)t * kRecFloats + kRecVid);
+  for (int d = 0; d < 3; ++d) {
+    o.c[d] = cd[d];
+    o.p0[d] = qp64[(size_t)t * kMaxQ * 3 + d];
+    o.v[d] = vi[d];
+  }
+  o.rb = brad[t];
+}
+
+__device__ inline bool share_vertex(const int *a, const int *b) {
+  bool s = false;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s |= a[i] == b[j];
+  return s;
+}
+
+__device__ inline double dist3(const double *a, const double *b) { return exact_dist(a, b); }
+
+__device__ inline unsigned long long wave_min_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long w = __shfl_xor(v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+template <bool kExact>
+__global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict__ qp64,
+                                                       const double *__restrict__ brad,
+                                                       const float *__restrict__ rec, int nt,
+                                                       int nq, unsigned long long *__restrict__ out) {
+  __shared__ RangeTri sq[kRangeChunk];
+  const int p = blockIdx.x * kRangeBlock + threadIdx.x;
+  const int q0 = blockIdx.y * kRangeChunk;
+  const int nqc = min(kRangeChunk, nt - q0);
+  for (int i = threadIdx.x; i < nqc; i += kRangeBlock) load_range_tri(qp64, brad, rec, q0 + i, sq[i]);
+  __syncthreads();
+  // out[0..1]: witnesses (min, max); out[2..3]: exact (min, max)
+  unsigned long long lo = ~0ull, hi = 0ull;
+  if (p < nt) {
+    RangeTri P;
+    load_range_tri(qp64, brad, rec, p, P);
+    const double wmin = __longlong_as_double((long long)out[0]);
+    const double wmax = __longlong_as_double((long long)out[1]);
+    double dlo = INFINITY, dhi = 0.0;
+    for (int j = 0; j < nqc; ++j) {
+      const RangeTri &Q = sq[j];
+      if (share_vertex(P.v, Q.v)) continue;
+      if (!kExact) {
+        const double w = dist3(P.p0, Q.p0);
+        dlo = fmin(dlo, w);
+        dhi = fmax(dhi, w);
+      } else {
+        const double d = dist3(P.c, Q.c);
+        const double rr = P.rb + Q.rb;
+        const bool low = (d - rr) * (1.0 - 1e-12) <= wmin;
+        const bool high = (d + rr) * (1.0 + 1e-12) >= wmax;
+        if (!low && !high) continue;
+        const int q = q0 + j;
+        for (int a = 0; a < nq; ++a) {
+          const double *pa = qp64 + ((size_t)p * kMaxQ + a) * 3;
+          for (int b = 0; b < nq; ++b) {
+            const double R = dist3(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
+            dlo = fmin(dlo, R);
+            dhi = fmax(dhi, R);
+          }
+        }
+      }
+    }
+    if (dlo < INFINITY) lo = (unsigned long long)__double_as_longlong(dlo);
+    hi = (unsigned long long)__double_as_longlong(dhi);
+  }
+  lo = wave_min_u64(lo);
+  hi = wave_max_u64(hi);
+  if ((threadIdx.x & 63) == 0) {
+    const int o = kExact ? 2 : 0;
+    if (lo != ~0ull) atomicMin(&out[o], lo);
+    atomicMax(&out[o + 1], hi);
+  }
+}
+
+int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
+                   hipStream_t s) {
+  (void)V;
+  unsigned long long init[4] = {~0ull, 0ull, ~0ull, 0ull};
+  MF_HIP(hipMemcpyAsync(m->d_scratch, init, sizeof(init), hipMemcpyHostToDevice, s));
+  dim3 grid((m->nt + kRangeBlock - 1) / kRangeBlock, (m->nt + kRangeChunk - 1) / kRangeChunk);
+  hipLaunchKernelGGL(k_range<false>, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
+                     m->nt, r.nq, m->d_scratch);
+  MF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_range<true>, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
+                     m->nt, r.nq, m->d_scratch);
+  MF_HIP(hipGetLastError());
+  unsigned long long res[4];
+  int st[4];
+  MF_HIP(hipMemcpyAsync(res, m->d_scratch, sizeof(res), hipMemcpyDeviceToHost, s));
+  MF_HIP(hipMemcpyAsync(st, m->d_status, sizeof(st), hipMemcpyDeviceToHost, s));
+  MF_HIP(hipStreamSynchronize(s));
+  if (st[1]) {
+    MF_HIP(hipMemset(m->d_status, 0, sizeof(int) * 4));
+    set_error("mf_r_range: zero-area triangle");
+    return MF_EMESH;
+  }
+  if (res[2] == ~0ull) {
+    set_error("mf_r_range: the mesh has no vertex-disjoint triangle pair");
+    return MF_EINVAL;
+  }
+  double lo, hi;
+  std::memcpy(&lo, &res[2], 8);
+  std::memcpy(&hi, &res[3], 8);
+  *rmin = lo;
+  *rmax = hi;
+  return MF_OK;
+}
+
+// ---- K5: touching pairs (FP64 singularity cancellation) -------------------
+// Potentials of a flat triangle with unit density at r:
+//   S = int dS'/|r-r'|,  V = int (r'-r)/|r-r'| dS'
+// from the edge formulas of Wilton et al. (IEEE TAP 32(3), 1984) and Graglia
+// (IEEE TAP 41(10), 1993): project r onto the plane, sum one logarithm per
+// edge and, off the plane, one arctangent pair per edge.
+
+__device__ void tri_potentials(const double x[3][3], const double *r, double *S, double *Vv) {
+  const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+  const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+  double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                 e1[0] * e2[1] - e1[1] * e2[0]};
+  const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  n[0] /= nn;
+  n[1] /= nn;
+  n[2] /= nn;
+  const double h = n[0] * (r[0] - x[0][0]) + n[1] * (r[1] - x[0][1]) + n[2] * (r[2] - x[0][2]);
+  const double ah = fabs(h);
+  const double pr[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
+  double s = 0.0, vin[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    const double *a = x[i], *b = x[(i + 1) % 3];
+    double t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double len = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    t[0] /= len;
+    t[1] /= len;
+    t[2] /= len;
+    const double m[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2],
+                         t[0] * n[1] - t[1] * n[0]};
+    const double ap[3] = {a[0] - pr[0], a[1] - pr[1], a[2] - pr[2]};
+    const double bp[3] = {b[0] - pr[0], b[1] - pr[1], b[2] - pr[2]};
+    const double sa = ap[0] * t[0] + ap[1] * t[1] + ap[2] * t[2];
+    const double sb = bp[0] * t[0] + bp[1] * t[1] + bp[2] * t[2];
+    const double p0 = ap[0] * m[0] + ap[1] * m[1] + ap[2] * m[2];
+    const double q2 = p0 * p0 + h * h;
+    const double Ra = sqrt((r[0] - a[0]) * (r[0] - a[0]) + (r[1] - a[1]) * (r[1] - a[1]) +
+                           (r[2] - a[2]) * (r[2] - a[2]));
+    const double Rb = sqrt((r[0] - b[0]) * (r[0] - b[0]) + (r[1] - b[1]) * (r[1] - b[1]) +
+                           (r[2] - b[2]) * (r[2] - b[2]));
+    double lg = 0.0, at = 0.0;
+    if (q2 > 0.0) {
+      // log((Rb + sb)/(Ra + sa)); R + s = q2/(R - s) when s < 0 avoids cancellation
+      const double fb = sb >= 0.0 ? Rb + sb : q2 / (Rb - sb);
+      const double fa = sa >= 0.0 ? Ra + sa : q2 / (Ra - sa);
+      lg = log(fb / fa);
+      at = atan(p0 * sb / (q2 + ah * Rb)) - atan(p0 * sa / (q2 + ah * Ra));
+    }
+    s += p0 * lg - ah * at;
+    const double cv = 0.5 * (q2 * lg + sb * Rb - sa * Ra);
+    vin[0] += cv * m[0];
+    vin[1] += cv * m[1];
+    vin[2] += cv * m[2];
+  }
+  *S = s;
+  Vv[0] = vin[0] - h * n[0] * s;
+  Vv[1] = vin[1] - h * n[1] * s;
+  Vv[2] = vin[2] - h * n[2] * s;
+}
+
+// (exp(-jkR) - 1)/R, with its Taylor series for kR < 1e-4.
+__device__ inline void ghat(double k, double R, double &re, double &im) {
+  const double x = k * R;
+  if (x < 1e-4) {
+    re = -0.5 * k * k * R;
+    im = -k + k * k * k * R * R / 6.0;
+    return;
+  }
+  double sh, ch, s1, c1;
+  sincos(0.5 * x, &sh, &ch);
+  s1 = 2.0 * sh * ch;
+  (void)c1;
+  re = -2.0 * sh * sh / R;
+  im = -s1 / R;
+}
+
+// One ordered touching pair (p,q): the inner integral over q is S_q + the
+// rule applied to g - 1/R, the outer one the rule over p; result normalised
+// by A_p A_q like the regular blocks:
+//   X[a][b] = (1/A_q) sum_i w_i [ (r_i - v_a).Psi_b(r_i)/4 - Phi(r_i)/k^2 ].
+__global__ void k_singular(const double *__restrict__ V, const int32_t *__restrict__ tri,
+                           const int32_t *__restrict__ tp, const int32_t *__restrict__ tq,
+                           int64_t npair, RuleArg R, double k, int part,
+                           const double *__restrict__ qp64, double *__restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= npair) return;
+  const int p = tp[s], q = tq[s];
+  double xp[3][3], xq[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) {
+      xp[a][c] = V[3 * (size_t)tri[3 * p + a] + c];
+      xq[a][c] = V[3 * (size_t)tri[3 * q + a] + c];
+    }
+  const double e1[3] = {xq[1][0] - xq[0][0], xq[1][1] - xq[0][1], xq[1][2] - xq[0][2]};
+  const double e2[3] = {xq[2][0] - xq[0][0], xq[2][1] - xq[0][1], xq[2][2] - xq[0][2]};
+  const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+               cz = e1[0] * e2[1] - e1[1] * e2[0];
+  const double Aq = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+  double accr[9], acci[9];
+  for (int i = 0; i < 9; ++i) accr[i] = acci[i] = 0.0;
+  const double ik2 = 1.0 / (k * k);
+  for (int i = 0; i < R.nq; ++i) {
+    const double *ri = qp64 + ((size_t)p * kMaxQ + i) * 3;
+    double S, Vv[3];
+    tri_potentials(xq, ri, &S, Vv);
+    // Phi = S + Aq sum_j w_j ghat ; Psi_b = V + (r_i - v_b) S + Aq sum_j w_j (r_j - v_b) ghat
+    double phr = S, phi = 0.0;
+    double m1r[3] = {0, 0, 0}, m1i[3] = {0, 0, 0};  // Aq sum_j w_j r_j ghat
+    double g0r = 0.0, g0i = 0.0;                    // Aq sum_j w_j ghat
+    for (int j = 0; j < R.nq; ++j) {
+      const double *rj = qp64 + ((size_t)q * kMaxQ + j) * 3;
+      const double d0 = ri[0] - rj[0], d1 = ri[1] - rj[1], d2 = ri[2] - rj[2];
+      double gr, gi;
+      ghat(k, sqrt(d0 * d0 + d1 * d1 + d2 * d2), gr, gi);
+      const double wa = Aq * R.w[j];
+      g0r += wa * gr;
+      g0i += wa * gi;
+      for (int c = 0; c < 3; ++c) {
+        m1r[c] += wa * rj[c] * gr;
+        m1i[c] += wa * rj[c] * gi;
+      }
+    }
+    phr += g0r;
+    phi += g0i;
+    for (int b = 0; b < 3; ++b) {
+      double psr[3], psi[3];
+      for (int c = 0; c < 3; ++c) {
+        psr[c] = Vv[c] + (ri[c] - xq[b][c]) * S + m1r[c] - xq[b][c] * g0r;
+        psi[c] = m1i[c] - xq[b][c] * g0i;
+      }
+      for (int a = 0; a < 3; ++a) {
+        const double ua[3] = {ri[0] - xp[a][0], ri[1] - xp[a][1], ri[2] - xp[a][2]};
+        double br = 0.0, bi = 0.0;
+        if (!(part & MF_PART_PHI)) {
+          br += 0.25 * (ua[0] * psr[0] + ua[1] * psr[1] + ua[2] * psr[2]);
+          bi += 0.25 * (ua[0] * psi[0] + ua[1] * psi[1] + ua[2] * psi[2]);
+        }
+        if (!(part & MF_PART_A)) {
+          br -= phr * ik2;
+          bi -= phi * ik2;
+        }
+        accr[3 * a + b] += R.w[i] * br;
+        acci[3 * a + b] += R.w[i] * bi;
+      }
+    }
+  }
+  double *o = out + (size_t)s * 18;
+  for (int i = 0; i < 9; ++i) {
+    o[2 * i] = accr[i] / Aq;
+    o[2 * i + 1] = acci[i] / Aq;
+  }
+}
+
+// X_sym(p,q)[a][b] = (X(p,q)[a][b] + X(q,p)[b][a]) / 2, stored as FP32.
+__global__ void k_symmetrise(const double *__restrict__ one, const int32_t *__restrict__ rev,
+                             int64_t npair, float *__restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= npair) return;
+  const double *x = one + (size_t)s * 18, *y = one + (size_t)rev[s] * 18;
+  float *o = out + (size_t)s * 18;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      o[2 * (3 * a + b)] = (float)(0.5 * (x[2 * (3 * a + b)] + y[2 * (3 * b + a)]));
+      o[2 * (3 * a + b) + 1] = (float)(0.5 * (x[2 * (3 * a + b) + 1] + y[2 * (3 * b + a) + 1]));
+    }
+}
+
+int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int part,
+                    hipStream_t s) {
+  const int64_t np = (int64_t)m->touch_q.size();
+  if (np == 0) return MF_OK;
+  RuleArg R = rule_arg(r);
+  hipLaunchKernelGGL(k_singular, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, s, V, m->d_tri,
+                     m->d_touch_p, m->d_touch_q, np, R, k, part, m->d_qp64, m->d_sing1);
+  MF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_symmetrise, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
+                     m->d_sing1, m->d_touch_rev, np, m->d_sing);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+}  // namespace mf

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host and device sources of libmomfill.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "momfill.h"
+
+namespace mf {
+
+constexpr double kEta0 = 376.730313668;  // free-space wave impedance
+constexpr int kMaxQ = 7;
+constexpr int kTileEdges = 64;            // RWG edges per row/column block of a tile
+constexpr int kMaxBlockTris = 2 * kTileEdges;
+
+// Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
+//  [0,21)  rho_i = r_i - c      (i-major, xyz)           FP32
+//  [21,42) w_i rho_i                                       FP32
+//  [42,51) alpha_a = c - v_a   (a-major, xyz)             FP32
+//  [51,54) sigma_a = s_a l_a  (0 for a boundary edge)    FP32
+//  [54,60) centroid c as three doubles                    FP64
+//  [60,63) vertex indices                                 int32
+constexpr int kRecFloats = 64;
+constexpr int kRecRho = 0, kRecWRho = 21, kRecAlpha = 42, kRecSigma = 51, kRecCent = 54,
+              kRecVid = 60;
+
+struct Rule {
+  int nq = 0;
+  double bary[kMaxQ][3] = {};
+  double w[kMaxQ] = {};
+};
+bool make_rule(int q, Rule *r);
+
+// Device view of the FP32 Green-function table used by the fill.
+struct GreenTabView {
+  const int2 *bucket;   // M: {interval index at bucket start, split (float bits)}
+  const float *node;    // N: node positions (FP32)
+  const float4 *coef;   // 2*(N-1): Horner coefficients about node i
+  int n, m;
+  float rmin, inv_delta;
+  float lo_ok, hi_ok;   // accepted distance range (FP32 rounding slack)
+};
+
+// Device view of the FP32 linear Exp table (adjoint: dG/dk).
+struct ExpTabView {
+  const int2 *bucket;
+  const float *node;
+  const float4 *coef;   // N-1: {E_i re, E_i im, slope re, slope im}
+  int n, m;
+  float rmin, inv_delta;
+};
+
+}  // namespace mf
+
+struct mf_tables {
+  double k = 0, rmin = 0, rmax = 0, tol = 0;
+  struct One {
+    int n = 0, m = 0, iters = 0;
+    double t = 0, delta = 0, err = 0;
+    double *r = nullptr;     // FP64 nodes (device)
+    double *f = nullptr;     // FP64 values, 2n (device)
+    int32_t *hash = nullptr; // Eq. (6) array (device)
+    int2 *bucket = nullptr;  // FP32 lookup (device)
+    float *node = nullptr;
+    float4 *coef = nullptr;
+  } e, g;
+};
+
+struct mf_mesh {
+  int nv = 0, nt = 0, ne = 0;
+  std::vector<int32_t> tri;        // nt*3
+  std::vector<int32_t> edges;      // ne*6
+  std::vector<int32_t> tedge;      // nt*3 global edge of local edge a, -1 if boundary
+  std::vector<int8_t> tsign;       // nt*3 +1 (T+), -1 (T-), 0
+  std::vector<int32_t> touch_off;  // nt+1 CSR of touching q per p (sorted)
+  std::vector<int32_t> touch_q;
+  std::vector<int32_t> touch_rev;  // index of (q,p) for pair (p,q)
+  std::vector<int32_t> blk_off;    // nblk+1: triangles needed by each edge block
+  std::vector<int32_t> blk_tri;
+  std::vector<int32_t> blk_pos;    // packed local-edge positions inside the block
+  int nblk = 0, max_blk_tris = 0;
+
+  // device copies
+  int32_t *d_tri = nullptr, *d_tedge = nullptr;
+  int8_t *d_tsign = nullptr;
+  int32_t *d_touch_off = nullptr, *d_touch_q = nullptr, *d_touch_rev = nullptr;
+  int32_t *d_touch_p = nullptr;    // p of each touching pair
+  int32_t *d_blk_off = nullptr, *d_blk_tri = nullptr, *d_blk_pos = nullptr;
+  float *d_rec = nullptr;          // nt * kRecFloats
+  double *d_qp64 = nullptr;        // nt * kMaxQ * 3 quadrature points (FP64)
+  double *d_brad = nullptr;        // nt radius of the quadrature points about the centroid
+  double *d_sing1 = nullptr;       // one-way touching blocks: npairs*9*2
+  float *d_sing = nullptr;         // symmetrised, FP32 complex: npairs*9*2
+  unsigned long long *d_scratch = nullptr;  // small reductions and flags
+  int *d_status = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+};
+
+namespace mf {
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define MF_HIP(call)                                             \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) return ::mf::hip_fail(e_, #call);      \
+  } while (0)
+
+
+// kernels.hip
+int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s);
+int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
+                   hipStream_t s);
+int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int part,
+                    hipStream_t s);
+int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
+                int z_dtype, int64_t ldz, hipStream_t s);
+int build_tables_device(mf_tables *t, double tol, hipStream_t s);
+int launch_table_eval(const mf_tables *t, int which, int64_t n, const double *r, double *out,
+                      hipStream_t s);
+int launch_backward(mf_mesh *m, const double *V, const Rule &r, double k, int mode,
+                    const mf_tables *tab, const void *W, int z_dtype, int64_t ldz, double *dV,
+                    double *dk, hipStream_t s);
+}  // namespace mf

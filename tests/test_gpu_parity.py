@@ -1,0 +1,267 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle on the same
+seeded inputs (distance range, tables, FP32 table evaluation, full matrices
+of small meshes, sampled entries of the full-size workloads, invariants and
+error paths)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1901_04162_amd import meshes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_04162_amd as m
+
+    m.lib()
+    return m
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+# ---- distance range and tables -------------------------------------------
+
+@pytest.mark.parametrize("name,s,q", [("ico", 2, 3), ("ico", 3, 6), ("plate", 12, 7), ("ico", 1, 7)])
+def test_r_range_matches_oracle(mf, orc, name, s, q):
+    V, F = meshes.icosphere(s) if name == "ico" else meshes.plate(n=s, h=0.1, jitter=0.005, seed=9)
+    say("r_range", name, s, q)
+    m = mf.Mesh(F, V.shape[0])
+    lo, hi = mf.r_range(m, V, q)
+    rlo, rhi = orc.r_range(V, F, q)
+    assert lo == rlo and hi == rhi
+
+
+@pytest.mark.parametrize("k,rmin,rmax,tol", [
+    (2 * np.pi, 0.31621617599108715, 1.9801182897103815, 1e-8),
+    (2 * np.pi, 0.31621617599108715, 1.9801182897103815, 1e-4),
+    (17.0, 0.0331, 1.99979, 1e-6),
+    (10.0, 0.07, 2.0, 1e-5),
+])
+def test_tables_match_oracle(mf, orc, k, rmin, rmax, tol):
+    say("tables", k, rmin, rmax, tol)
+    T = mf.build_tables(k, rmin, rmax, tol)
+    for which, kind in (("green", orc.GREEN), ("exp", orc.EXP)):
+        ref = orc.build_table(kind, k, rmin, rmax, tol)
+        r, f, h = T.get(which)
+        assert r.shape == ref.r.shape
+        np.testing.assert_array_equal(r, ref.r)  # sample placement, bit for bit
+        np.testing.assert_array_equal(h, ref.hash)  # Eq. (6) array, exactly
+        assert np.max(np.abs(f - ref.f) / np.abs(ref.f)) < 1e-15
+        t = T.t_green if which == "green" else T.t_exp
+        err = T.err_green if which == "green" else T.err_exp
+        assert t == ref.t and abs(err - ref.probe_err) <= 1e-3 * ref.probe_err + 1e-16
+
+
+@pytest.mark.parametrize("k,rmin,rmax,tol", [(2 * np.pi, 0.3162, 1.98, 1e-8), (17.0, 0.0331, 1.99979, 1e-6)])
+def test_table_fp32_evaluation(mf, orc, k, rmin, rmax, tol):
+    import torch
+
+    say("table eval", k, tol)
+    T = mf.build_tables(k, rmin, rmax, tol)
+    rng = np.random.default_rng(3)
+    r = rng.uniform(rmin, rmax, 200000)
+    g_ref = orc.build_table(orc.GREEN, k, rmin, rmax, tol)
+    e_ref = orc.build_table(orc.EXP, k, rmin, rmax, tol)
+    rf = r.astype(np.float32).astype(np.float64)  # the point the FP32 path sees
+    ok = (rf >= rmin) & (rf <= rmax)
+    for which, ref in (("green", g_ref), ("exp", e_ref)):
+        v = T.eval(which, torch.tensor(r)).cpu().numpy()
+        want = ref(rf[ok])
+        err = np.abs(v[ok] - want) / np.abs(want)
+        say(which, "max rel", err.max(), "median", np.median(err))
+        assert err.max() < 2e-6 and np.median(err) < 2e-7
+    # outside the range: NaN, never a clamped value
+    v = T.eval("green", torch.tensor([rmin * 0.5, rmax * 2.0])).cpu().numpy()
+    assert np.all(np.isnan(v))
+
+
+# ---- full matrices --------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def ico2(orc):
+    V, F = meshes.icosphere(2)
+    k, Q = 2 * np.pi, 3
+    E = orc.rwg(V, F)
+    Zd = orc.fill(V, F, k, Q, edges=E)
+    rmin, rmax = orc.r_range(V, F, Q)
+    G = orc.build_table(orc.GREEN, k, rmin, rmax, 1e-8)
+    Zt = orc.fill(V, F, k, Q, mode=orc.TABLE, gtable=G, edges=E)
+    return dict(V=V, F=F, k=k, Q=Q, E=E, Zd=Zd, Zt=Zt, rmin=rmin, rmax=rmax)
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_full_matrix_direct(mf, ico2, dtype):
+    import torch
+
+    say("full ico2 direct", dtype)
+    c = ico2
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    Z = mf.fill_Z(m, c["V"], c["k"], c["Q"], "direct", dtype=getattr(torch, dtype))
+    mf.sync_status(m)
+    Z = Z.cpu().numpy()
+    e = _rel(Z, c["Zd"])
+    say("direct rel Frobenius", e)
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_full_matrix_table(mf, ico2, dtype):
+    import torch
+
+    say("full ico2 table", dtype)
+    c = ico2
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    lo, hi = mf.r_range(m, c["V"], c["Q"])
+    T = mf.build_tables(c["k"], lo, hi, 1e-8)
+    Z = mf.fill_Z(m, c["V"], c["k"], c["Q"], "table", T, dtype=getattr(torch, dtype))
+    mf.sync_status(m)
+    Z = Z.cpu().numpy()
+    e_t, e_d = _rel(Z, c["Zt"]), _rel(Z, c["Zd"])
+    say("table rel Frobenius vs oracle-table", e_t, "vs oracle-direct", e_d)
+    assert e_t <= 1e-6 and e_d <= 1e-5
+
+
+def test_scalar_part_cancels_on_loops(mf, orc, ico2):
+    """Loop-divergence invariant through the MF_PART_PHI debug bit (FP32)."""
+    import torch
+
+    from test_oracle_fill import _loop_vectors
+
+    c = ico2
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    Zp = mf.fill_Z(m, c["V"], c["k"], c["Q"], "direct", dtype=torch.complex128,
+                   part=mf.MF_PART_PHI).cpu().numpy()
+    Za = mf.fill_Z(m, c["V"], c["k"], c["Q"], "direct", dtype=torch.complex128,
+                   part=mf.MF_PART_A).cpu().numpy()
+    Zf = mf.fill_Z(m, c["V"], c["k"], c["Q"], "direct", dtype=torch.complex128).cpu().numpy()
+    U, _ = _loop_vectors(c["V"], c["F"], c["E"])
+    res = np.abs(Zp @ U.T).max() / (np.abs(Zp).max() * np.abs(U).max())
+    say("loop residual", res)
+    assert res < 2e-6
+    assert _rel(Za + Zp, Zf) < 1e-6
+
+
+def test_reciprocity(mf, ico2):
+    import torch
+
+    c = ico2
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    Z = mf.fill_Z(m, c["V"], c["k"], c["Q"], "direct", dtype=torch.complex128).cpu().numpy()
+    assert np.max(np.abs(Z - Z.T)) / np.max(np.abs(Z)) < 1e-6
+
+
+@pytest.mark.parametrize("s", [0, 1])
+def test_small_meshes_single_ragged_tile(mf, orc, s):
+    import torch
+
+    V, F = meshes.icosphere(s)
+    V = meshes.jitter_uniform(V, F, 0.05, 20 + s)
+    say("small mesh", s)
+    m = mf.Mesh(F, V.shape[0])
+    Z = mf.fill_Z(m, V, 3.0, 6, "direct", dtype=torch.complex128).cpu().numpy()
+    Zo = orc.fill(V, F, 3.0, 6)
+    assert _rel(Z, Zo) < 1e-6
+
+
+def test_tetrahedron_only_touching_pairs(mf, orc):
+    import torch
+
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    F = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], dtype=np.int32)
+    say("tetrahedron")
+    m = mf.Mesh(F, 4)
+    assert m.n_edges == 6
+    Z = mf.fill_Z(m, V, 2.0, 7, "direct", dtype=torch.complex128).cpu().numpy()
+    assert _rel(Z, orc.fill(V, F, 2.0, 7)) < 1e-6  # FP64 blocks, FP32 accumulation
+    with pytest.raises(mf.MomfillError):
+        mf.r_range(m, V, 7)  # no vertex-disjoint pair
+
+
+def test_out_of_range_tables_reported(mf, ico2):
+    import torch
+
+    c = ico2
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    T = mf.build_tables(c["k"], c["rmin"], 0.5 * (c["rmin"] + c["rmax"]), 1e-6)
+    say("ERANGE")
+    mf.fill_Z(m, c["V"], c["k"], c["Q"], "table", T, dtype=torch.complex64)
+    with pytest.raises(mf.MomfillError) as e:
+        mf.sync_status(m)
+    assert e.value.code == mf._lib.MF_ERANGE
+    mf.sync_status(m)  # cleared
+
+
+# ---- sampled entries at larger sizes -------------------------------------
+
+def _near_sample(E, count, seed):
+    """Entries whose two edges share a triangle or a vertex (touching pairs)."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(E.shape[0], count, replace=False)
+    cols = []
+    for r in rows:
+        tris = {int(E[r, 2]), int(E[r, 3])}
+        cand = np.nonzero(np.isin(E[:, 2], list(tris)) | np.isin(E[:, 3], list(tris)))[0]
+        cols.append(int(rng.choice(cand)))
+    return rows.astype(np.int64), np.array(cols, dtype=np.int64)
+
+
+def _sampled_check(mf, orc, V, F, k, Q, tol, n_far, seed, modes=("direct", "table"),
+                   bound_direct=1e-6, bound_table=1e-5):
+    import torch
+
+    m = mf.Mesh(F, V.shape[0])
+    E = m.edges()
+    rows, cols = meshes.entry_sample(E.shape[0], n_far, seed)
+    nr, nc = _near_sample(E, 200, seed + 1)
+    rows, cols = np.concatenate([rows, nr]), np.concatenate([cols, nc])
+    ref = orc.fill_entries(V, F, E, k, Q, rows, cols)
+    lo, hi = mf.r_range(m, V, Q)
+    Z = torch.empty((E.shape[0], E.shape[0]), dtype=torch.complex64, device="cuda")
+    ri, ci = torch.tensor(rows, device="cuda"), torch.tensor(cols, device="cuda")
+    out = {}
+    for mode in modes:
+        T = mf.build_tables(k, lo, hi, tol) if mode == "table" else None
+        say("fill", mode, "E", E.shape[0], "tol", tol)
+        mf.fill_Z(m, V, k, Q, mode, T, out=Z)
+        mf.sync_status(m)
+        z = Z[ri, ci].cpu().numpy().astype(np.complex128)
+        e_all, e_near = _rel(z, ref), _rel(z[-200:], ref[-200:])
+        e_far = _rel(z[:-200], ref[:-200])
+        say(mode, "sample rel err all", e_all, "far", e_far, "near", e_near)
+        out[mode] = e_all
+        assert e_all <= (bound_direct if mode == "direct" else bound_table)
+    return out
+
+
+def test_sampled_ico4_q6(mf, orc):
+    V, F = meshes.icosphere(4)
+    V = meshes.jitter_gauss(V, 0.01, 5)
+    _sampled_check(mf, orc, V, F, 10.0, 6, 1e-6, 2000, 40)
+
+
+def test_sampled_ico5_q7_full_size(mf, orc):
+    """The 30,720-unknown workload at its launch configuration."""
+    V, F = meshes.icosphere(5)
+    _sampled_check(mf, orc, V, F, 17.0, 7, 1e-6, 3000, 2)
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6, 1e-8])
+def test_sampled_plate(mf, orc, tol):
+    V, F = meshes.plate()
+    _sampled_check(mf, orc, V, F, 2 * np.pi, 7, tol, 1500, 30, modes=("table",),
+                   bound_table=max(1e-5, 10 * tol))

@@ -1,0 +1,95 @@
+"""Host-side checks of libmomfill.so that need no GPU: it loads, exports every
+function its header declares, and its mesh planning (RWG table, touching
+pairs, error codes) agrees with the oracle."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1901_04162_amd import meshes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "momfill.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1901_04162_amd as mf
+
+    L = mf.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(mf._lib.EXPORTS)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_rwg_table_matches_oracle(orc, s):
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.icosphere(s)
+    m = mf.Mesh(F, V.shape[0])
+    np.testing.assert_array_equal(m.edges(), orc.rwg(V, F))
+
+
+def test_rwg_table_matches_oracle_plate(orc):
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.plate(n=20)
+    m = mf.Mesh(F, V.shape[0])
+    E = m.edges()
+    np.testing.assert_array_equal(E, orc.rwg(V, F))
+    assert m.n_edges == 3 * 20 * 20 - 2 * 20  # interior edges of an n x n split grid
+
+
+def test_touching_pair_count():
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.icosphere(2)
+    m = mf.Mesh(F, V.shape[0])
+    ref = sum(1 for p in range(len(F)) for q in range(len(F)) if set(F[p]) & set(F[q]))
+    assert m.n_touching() == ref
+
+
+@pytest.mark.parametrize("F", [
+    [[0, 1, 2], [1, 0, 3], [0, 1, 4]],   # edge on three triangles
+    [[0, 1, 2], [0, 1, 3]],              # inconsistent orientation
+    [[0, 0, 2], [0, 2, 3]],              # repeated vertex
+    [[0, 1, 9], [1, 0, 3]],              # index out of range
+    [[0, 1, 2]],                         # no interior edge
+])
+def test_mesh_errors(F):
+    import paper_1901_04162_amd as mf
+
+    with pytest.raises(mf.MomfillError) as e:
+        mf.Mesh(np.array(F), 5)
+    assert e.value.code == mf._lib.MF_EMESH
+
+
+def test_argument_errors_without_gpu():
+    import paper_1901_04162_amd as mf
+
+    L = mf.lib()
+    h = C.c_void_p()
+    assert L.mf_mesh_create(0, 1, None, C.byref(h)) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(-1.0, 0.1, 1.0, 1e-6, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.5, 0.1, 1e-6, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.1, 1.0, 0.5, C.byref(h), None) == mf._lib.MF_EINVAL
+    V, F = meshes.icosphere(1)
+    m = mf.Mesh(F, V.shape[0])
+    z = C.c_void_p(1)
+    assert L.mf_fill_Z(m.handle, z, 1.0, 5, 1, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
+    assert L.mf_fill_Z(m.handle, z, -1.0, 3, 1, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
+    assert L.mf_fill_Z(m.handle, z, 1.0, 3, 0, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
+    assert L.mf_fill_Z(m.handle, z, 1.0, 3, 1, None, z, 0, m.n_edges - 1, None) == mf._lib.MF_EINVAL
+    assert L.mf_fill_Z(m.handle, z, 1.0, 3, 7, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
+    assert L.mf_fill_Z(m.handle, z, 1.0, 3, 1 | 0x30, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
+    assert b"ldz" in L.mf_last_error() or L.mf_last_error()
