@@ -170,22 +170,55 @@ static void build_touching(mf_mesh *m) {
     }
 }
 
-// Blocks of kTileEdges consecutive edges; each lists the triangles carrying
-// them with the block-local position of each local edge (0xff: not in block).
+// Row/column blocks of the tiled fill: runs of consecutive edges (so every
+// tile is a contiguous rectangle of Z) carrying at most kMaxBlockTris
+// triangles and kMaxBlockEdges edges.  Boundaries come from a dynamic program
+// that minimises the number of distinct triangles summed over blocks plus a
+// per-block cost: every triangle in a block is recomputed by each tile of
+// that block row, so fewer distinct triangles means less repeated work.
 static void build_blocks(mf_mesh *m) {
-  const int B = kTileEdges;
-  m->nblk = (m->ne + B - 1) / B;
+  const int ne = m->ne;
+  const int32_t *E = m->edges.data();
+  const double kBlockCost = 32.0;
+  std::vector<double> best(ne + 1, 1e300);
+  std::vector<int32_t> from(ne + 1, 0), stamp(m->nt, -1);
+  best[0] = 0.0;
+  for (int e = 1; e <= ne; ++e) {
+    int ntri = 0;
+    for (int len = 1; len <= kMaxBlockEdges && e - len >= 0; ++len) {
+      const int s = e - len;
+      for (int c = 2; c <= 3; ++c) {
+        const int t = E[6 * (size_t)s + c];
+        if (stamp[t] != e) {
+          stamp[t] = e;
+          ++ntri;
+        }
+      }
+      if (ntri > kMaxBlockTris) break;
+      const double cost = best[s] + ntri + kBlockCost;
+      if (cost < best[e]) {
+        best[e] = cost;
+        from[e] = s;
+      }
+    }
+  }
+  std::vector<int32_t> starts;
+  for (int e = ne; e > 0; e = from[e]) starts.push_back(from[e]);
+  std::reverse(starts.begin(), starts.end());
+  m->nblk = (int)starts.size();
+  m->blk_e0 = starts;
+  m->blk_e0.push_back(ne);
   m->blk_off.assign(m->nblk + 1, 0);
   m->blk_tri.clear();
   m->blk_pos.clear();
   m->max_blk_tris = 0;
   std::vector<int32_t> tl;
   for (int b = 0; b < m->nblk; ++b) {
-    const int e0 = b * B, e1 = std::min(m->ne, e0 + B);
+    const int e0 = m->blk_e0[b], e1 = m->blk_e0[b + 1];
     tl.clear();
     for (int e = e0; e < e1; ++e) {
-      tl.push_back(m->edges[6 * (size_t)e + 2]);
-      tl.push_back(m->edges[6 * (size_t)e + 3]);
+      tl.push_back(E[6 * (size_t)e + 2]);
+      tl.push_back(E[6 * (size_t)e + 3]);
     }
     std::sort(tl.begin(), tl.end());
     tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
@@ -193,7 +226,7 @@ static void build_blocks(mf_mesh *m) {
       uint32_t pk = 0;
       for (int a = 0; a < 3; ++a) {
         const int e = m->tedge[3 * (size_t)t + a];
-        uint32_t pos = (e >= e0 && e < e1) ? (uint32_t)(e - e0) : 0xffu;
+        const uint32_t pos = (e >= e0 && e < e1) ? (uint32_t)(e - e0) : 0xffu;
         pk |= pos << (8 * a);
       }
       m->blk_tri.push_back(t);
@@ -202,6 +235,10 @@ static void build_blocks(mf_mesh *m) {
     m->blk_off[b + 1] = (int32_t)m->blk_tri.size();
     m->max_blk_tris = std::max(m->max_blk_tris, (int)tl.size());
   }
+  // Z is symmetric (Galerkin reciprocity): only block pairs I <= J are filled
+  m->tiles.clear();
+  for (int I = 0; I < m->nblk; ++I)
+    for (int J = I; J < m->nblk; ++J) m->tiles.push_back((I << 16) | J);
 }
 
 template <class T>
@@ -219,7 +256,7 @@ static void free_mesh(mf_mesh *m) {
   for (hipEvent_t &e : m->ev)
     if (e) (void)hipEventDestroy(e);
   void *ptrs[] = {m->d_tri,       m->d_tedge,   m->d_tsign,   m->d_touch_off, m->d_touch_q,
-                  m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos,
+                  m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos, m->d_tiles, m->d_blk_e0,
                   m->d_rec,       m->d_sing1,   m->d_sing,    m->d_scratch,   m->d_status,
                   m->d_qp64,      m->d_brad};
   for (void *p : ptrs)
@@ -240,7 +277,8 @@ static int ensure_device(mf_mesh *m) {
       (rc = upload(&m->d_tsign, m->tsign)) || (rc = upload(&m->d_touch_off, m->touch_off)) ||
       (rc = upload(&m->d_touch_q, m->touch_q)) || (rc = upload(&m->d_touch_rev, m->touch_rev)) ||
       (rc = upload(&m->d_touch_p, touch_p)) || (rc = upload(&m->d_blk_off, m->blk_off)) ||
-      (rc = upload(&m->d_blk_tri, m->blk_tri)) || (rc = upload(&m->d_blk_pos, m->blk_pos)))
+      (rc = upload(&m->d_blk_tri, m->blk_tri)) || (rc = upload(&m->d_blk_pos, m->blk_pos)) ||
+      (rc = upload(&m->d_tiles, m->tiles)) || (rc = upload(&m->d_blk_e0, m->blk_e0)))
     return rc;
   MF_HIP(hipMalloc((void **)&m->d_sing1, sizeof(double) * 18 * std::max<size_t>(npair, 1)));
   MF_HIP(hipMalloc((void **)&m->d_sing, sizeof(float) * 18 * std::max<size_t>(npair, 1)));
@@ -279,6 +317,10 @@ int mf_mesh_create(int32_t n_vertices, int32_t n_triangles, const int32_t *trian
   }
   build_touching(m);
   build_blocks(m);
+  if (m->nblk > 65535) {
+    free_mesh(m);
+    return fail(MF_EINVAL, "mf_mesh_create: too many RWG edges for the tile plan");
+  }
   if (m->max_blk_tris > kMaxBlockTris) {
     free_mesh(m);
     return fail(MF_EMESH, "internal: edge block needs too many triangles");

@@ -1,14 +1,18 @@
 // Regular-pair impedance fill (FP32), table and direct modes.
 //
-// The output is cut into tiles of kTileEdges x kTileEdges RWG edges.  One
-// workgroup owns a tile at a time (persistent grid, tiles strided by the
-// grid size) and accumulates its entries in LDS.  A tile needs every
-// triangle carrying one of its row edges (list I) against every triangle
-// carrying one of its column edges (list J); lane l of a wave takes test
-// triangle I[l] (its record in registers) and the wave walks source
-// triangles of J (records loaded once per wave through the scalar cache).
-// Per triangle pair the Q x Q point pairs are reduced to four moments of
-// g = exp(-jkR)/R,
+// Z is symmetric (Galerkin reciprocity of the EFIE with the same rule on
+// test and source triangles, and symmetrised touching pairs), so only the
+// block pairs I <= J of the edge blocks (runs of consecutive edges, at most
+// kMaxBlockEdges long) are computed; an off-diagonal tile is written to
+// Z[I,J] and, transposed, to Z[J,I].
+//
+// One workgroup owns a tile at a time (persistent grid) and accumulates it
+// in LDS.  A tile needs every triangle carrying one of its row edges (list
+// I) against every triangle carrying one of its column edges (list J).  Lane
+// l of a wave takes test triangle I[l] (record in VGPRs); the wave walks the
+// source triangles of J, whose records are wave-uniform and so live in
+// SGPRs.  Per triangle pair the Q x Q point pairs are reduced to four
+// moments of g = exp(-jkR)/R,
 //   S0 = sum w_i w_j g, Srho = sum w_i w_j g rho_i, Srho' = sum w_i w_j g rho'_j,
 //   Srr = sum w_i w_j g rho_i.rho'_j,
 // from which the nine local entries follow with alpha_a = c_p - v_a and
@@ -17,117 +21,106 @@
 // Touching pairs take their FP64 blocks from the singular kernel.  The
 // Green-function table sits in LDS when it fits and is read from global
 // memory otherwise.
+//
+// Distances: D = c_p - c_q is formed in FP64 and split into FP32 hi + lo;
+// the point offsets rho are FP32, so R carries no per-pair rounding of the
+// centroid distance (phase errors stay random across point pairs).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "internal.hpp"
 
 namespace mf {
 
-constexpr int kBM = kTileEdges;
-constexpr int kAccStride = 2 * kBM + 1;  // odd stride: rows land in different banks
+constexpr int kBM = kMaxBlockEdges;
+constexpr int kAccStride = 2 * kBM + 1;  // odd stride: rows fall in different banks
 constexpr int kAccFloats = kBM * kAccStride;
-constexpr int kFillThreads = 512;
+constexpr int kFillThreads = 1024;
+constexpr int kWaves = kFillThreads / 64;
 
-struct FillArgs {
-  const float *rec;
-  const int32_t *blk_off, *blk_tri, *blk_pos;
-  const int32_t *touch_off, *touch_q;
-  const float *sing;
-  int nblk, ne;
-  long long ntiles;
+struct FillScalars {
+  int ntiles, ne;
   float k, ik2;
   float pref;  // k eta0 / (4 pi)
   float w[kMaxQ];
-  // table (global memory copy)
-  const int2 *bucket;
-  const float *node;
-  const float4 *coef;
   int tn, tm;
-  float trmin, tinv, lo_ok, hi_ok;
-  void *Z;
+  float tinv, tbias, tmax;  // bucket coordinate x = r*tinv + tbias, clamp to [0, tmax]
+  float lo_ok, hi_ok;
   long long ldz;
-  int *status;
 };
 
-template <bool kLDS>
-struct Tab {
-  const int2 *bucket;
-  const float *node;
-  const float4 *coef;
-  int m;
-  float rmin, inv;
-  __device__ __forceinline__ float2 operator()(float r) const {
-    int b = (int)((r - rmin) * inv);
-    b = min(max(b, 0), m - 1);
-    const int2 w = bucket[b];
-    const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
-    const float u = r - node[i];
-    const float4 c01 = coef[2 * i], c23 = coef[2 * i + 1];
-    float re = fmaf(c23.z, u, c23.x), im = fmaf(c23.w, u, c23.y);
-    re = fmaf(re, u, c01.z);
-    im = fmaf(im, u, c01.w);
-    re = fmaf(re, u, c01.x);
-    im = fmaf(im, u, c01.y);
-    return make_float2(re, im);
-  }
+struct TabPtrs {
+  const int2 *bucket;   // {interval at bucket start, split position (float bits)}
+  const float *node;    // FP32 sample positions
+  const float4 *c01;    // per interval (c0, c1) about node i
+  const float4 *c23;    // per interval (c2, c3)
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Interval by the hash of Eq. (6) (the fix-up "one back if the sample lies
+// above r" is stored as a split position per bucket), then the cubic of
+// Eq. (5) in Horner form about the interval's first sample.
+__device__ __forceinline__ float2 green_table(const TabPtrs &T, const FillScalars &S, float r) {
+  const float x = __builtin_amdgcn_fmed3f(fmaf(r, S.tinv, S.tbias), 0.0f, S.tmax);
+  const int2 w = T.bucket[(int)x];
+  const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
+  const float u = r - T.node[i];
+  const float4 c01 = T.c01[i], c23 = T.c23[i];
+  float re = fmaf(c23.z, u, c23.x), im = fmaf(c23.w, u, c23.y);
+  re = fmaf(re, u, c01.z);
+  im = fmaf(im, u, c01.w);
+  return make_float2(fmaf(re, u, c01.x), fmaf(im, u, c01.y));
+}
+
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
-__global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
+__global__ __launch_bounds__(kFillThreads) void k_fill(
+    FillScalars S, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
+    const int32_t *__restrict__ blk_tri,
+    const int32_t *__restrict__ blk_pos, const int32_t *__restrict__ touch_off,
+    const int32_t *__restrict__ touch_q, const float *__restrict__ sing,
+    const int2 *__restrict__ g_bucket, const float *__restrict__ g_node,
+    const float4 *__restrict__ g_coef, ZT *__restrict__ Z, int *__restrict__ status) {
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
-  const int nwave = kFillThreads / 64;
 
-  Tab<kLDS> tab;
-  if (MODE == MF_MODE_TABLE) {
-    tab.m = A.tm;
-    tab.rmin = A.trmin;
-    tab.inv = A.tinv;
-    if (kLDS) {
-      float4 *c = smem4 + kAccFloats / 4 + 1;
-      int2 *b = reinterpret_cast<int2 *>(c + 2 * (A.tn - 1));
-      float *nd = reinterpret_cast<float *>(b + A.tm);
-      for (int i = threadIdx.x; i < 2 * (A.tn - 1); i += kFillThreads) c[i] = A.coef[i];
-      for (int i = threadIdx.x; i < A.tm; i += kFillThreads) b[i] = A.bucket[i];
-      for (int i = threadIdx.x; i < A.tn; i += kFillThreads) nd[i] = A.node[i];
-      tab.coef = c;
-      tab.bucket = b;
-      tab.node = nd;
-    } else {
-      tab.coef = A.coef;
-      tab.bucket = A.bucket;
-      tab.node = A.node;
-    }
+  TabPtrs tab{g_bucket, g_node, g_coef, g_coef + (S.tn - 1)};
+  if (MODE == MF_MODE_TABLE && kLDS) {
+    float4 *c = smem4 + kAccFloats / 4 + 1;
+    int2 *b = reinterpret_cast<int2 *>(c + 2 * (S.tn - 1));
+    float *nd = reinterpret_cast<float *>(b + S.tm);
+    for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kFillThreads) c[i] = g_coef[i];
+    for (int i = threadIdx.x; i < S.tm; i += kFillThreads) b[i] = g_bucket[i];
+    for (int i = threadIdx.x; i < S.tn; i += kFillThreads) nd[i] = g_node[i];
+    tab = TabPtrs{b, nd, c, c + (S.tn - 1)};
   }
   float rlo = INFINITY, rhi = 0.0f;
 
-  for (long long tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
-    const int I = (int)(tile / A.nblk), J = (int)(tile % A.nblk);
+  for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
+    const int tij = tiles[tile];
+    const int I = tij >> 16, J = tij & 0xffff;
     for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
     __syncthreads();
-    const int p0 = A.blk_off[I], np = A.blk_off[I + 1] - p0;
-    const int q0 = A.blk_off[J], nq = A.blk_off[J + 1] - q0;
+    const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
+    const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
     for (int pc = 0; pc < np; pc += 64) {
       const bool pv = pc + lane < np;
       const int pidx = pv ? pc + lane : pc;
-      const int p = A.blk_tri[p0 + pidx];
-      const int prow = pv ? A.blk_pos[p0 + pidx] : -1;
-      const float *pr = A.rec + (size_t)p * kRecFloats;
-      float prho[Q][3], pwrho[Q][3], palpha[3][3], psig[3];
+      const int p = blk_tri[p0 + pidx];
+      const int prow = pv ? blk_pos[p0 + pidx] : -1;
+      const float *pr = rec + (size_t)p * kRecFloats;
+      float prho[Q][3], palpha[3][3], psig[3];
       if (MODE == MF_MODE_TABLE) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            prho[i][c] = pr[kRecRho + 3 * i + c];
-            pwrho[i][c] = pr[kRecWRho + 3 * i + c];
-          }
+          for (int c = 0; c < 3; ++c) prho[i][c] = pr[kRecRho + 3 * i + c];
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -140,10 +133,10 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
       const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
       const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
 
-      for (int qi = wave; qi < nq; qi += nwave) {
-        const int q = uniform(A.blk_tri[q0 + qi]);
-        const int qcol = uniform(A.blk_pos[q0 + qi]);
-        const float *qr = A.rec + (size_t)q * kRecFloats;
+      for (int qi = wave; qi < nq; qi += kWaves) {
+        const int q = uniform(blk_tri[q0 + qi]);
+        const int qcol = uniform(blk_pos[q0 + qi]);
+        const float *qr = rec + (size_t)q * kRecFloats;
         const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
         const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
         const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
@@ -155,108 +148,98 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
           const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
           const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                       lz = (float)(Dz - (double)hz);
-          float qrho[Q][3], qwrho[Q][3];
-#pragma unroll
-          for (int j = 0; j < Q; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              qrho[j][c] = qr[kRecRho + 3 * j + c];
-              qwrho[j][c] = qr[kRecWRho + 3 * j + c];
-            }
           float s0r = 0.f, s0i = 0.f, srr = 0.f, sri = 0.f;
           float spr[3] = {0.f, 0.f, 0.f}, spi[3] = {0.f, 0.f, 0.f};  // Srho
           float sqr[3] = {0.f, 0.f, 0.f}, sqi[3] = {0.f, 0.f, 0.f};  // Srho'
-          // direct mode keeps the outer loop rolled (the inlined sincos is long)
-          // and reads the test point from the record each time
-#pragma unroll(MODE == MF_MODE_TABLE ? Q : 1)
+#pragma unroll MODE == MF_MODE_TABLE ? Q : 1
           for (int i = 0; i < Q; ++i) {
-            float pri[3], pwi[3];
+            float pri[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < 3; ++c)
               pri[c] = MODE == MF_MODE_TABLE ? prho[i][c] : pr[kRecRho + 3 * i + c];
-              pwi[c] = MODE == MF_MODE_TABLE ? pwrho[i][c] : pr[kRecWRho + 3 * i + c];
-            }
             const float ax = pri[0] + lx, ay = pri[1] + ly, az = pri[2] + lz;
             float t0r = 0.f, t0i = 0.f;
             float t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
-              const float dx = hx + (ax - qrho[j][0]);
-              const float dy = hy + (ay - qrho[j][1]);
-              const float dz = hz + (az - qrho[j][2]);
+              const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
+              const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
+              const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
               const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
               float gr, gi;
               if (MODE == MF_MODE_TABLE) {
                 const float r = __builtin_amdgcn_sqrtf(r2);
                 rlo = fminf(rlo, r);
                 rhi = fmaxf(rhi, r);
-                const float2 g = tab(r);
+                const float2 g = green_table(tab, S, r);
                 gr = g.x;
                 gi = g.y;
               } else {
                 const float ri = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * ri;
                 float sn, cs;
-                sincosf(A.k * r, &sn, &cs);
+                sincosf(S.k * r, &sn, &cs);
                 gr = cs * ri;
                 gi = -sn * ri;
               }
-              t0r = fmaf(A.w[j], gr, t0r);
-              t0i = fmaf(A.w[j], gi, t0i);
+              t0r = fmaf(S.w[j], gr, t0r);
+              t0i = fmaf(S.w[j], gi, t0i);
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                t1r[c] = fmaf(qwrho[j][c], gr, t1r[c]);
-                t1i[c] = fmaf(qwrho[j][c], gi, t1i[c]);
+                const float wq = qr[kRecWRho + 3 * j + c];
+                t1r[c] = fmaf(wq, gr, t1r[c]);
+                t1i[c] = fmaf(wq, gi, t1i[c]);
               }
             }
-            s0r = fmaf(A.w[i], t0r, s0r);
-            s0i = fmaf(A.w[i], t0i, s0i);
+            // w_i T0, w_i T1, then the rho_i-weighted moments
+            t0r *= S.w[i];
+            t0i *= S.w[i];
+            s0r += t0r;
+            s0i += t0i;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              spr[c] = fmaf(pwi[c], t0r, spr[c]);
-              spi[c] = fmaf(pwi[c], t0i, spi[c]);
-              sqr[c] = fmaf(A.w[i], t1r[c], sqr[c]);
-              sqi[c] = fmaf(A.w[i], t1i[c], sqi[c]);
-              srr = fmaf(pwi[c], t1r[c], srr);
-              sri = fmaf(pwi[c], t1i[c], sri);
+              t1r[c] *= S.w[i];
+              t1i[c] *= S.w[i];
+              spr[c] = fmaf(pri[c], t0r, spr[c]);
+              spi[c] = fmaf(pri[c], t0i, spi[c]);
+              sqr[c] += t1r[c];
+              sqi[c] += t1i[c];
+              srr = fmaf(pri[c], t1r[c], srr);
+              sri = fmaf(pri[c], t1i[c], sri);
             }
           }
-          float beta[3][3];
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) beta[b][c] = qr[kRecAlpha + 3 * b + c];
 #pragma unroll
           for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               float vr = 0.f, vi = 0.f;
               if (!(PART & MF_PART_PHI)) {
-                const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
-                                 palpha[a][2] * beta[b][2];
-                vr = srr + ab * s0r;
-                vi = sri + ab * s0i;
+                const float *beta = qr + kRecAlpha + 3 * b;
+                const float ab = palpha[a][0] * beta[0] + palpha[a][1] * beta[1] +
+                                 palpha[a][2] * beta[2];
+                vr = fmaf(ab, s0r, srr);
+                vi = fmaf(ab, s0i, sri);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                  vr = fmaf(palpha[a][c], sqr[c], fmaf(beta[b][c], spr[c], vr));
-                  vi = fmaf(palpha[a][c], sqi[c], fmaf(beta[b][c], spi[c], vi));
+                  vr = fmaf(palpha[a][c], sqr[c], fmaf(beta[c], spr[c], vr));
+                  vi = fmaf(palpha[a][c], sqi[c], fmaf(beta[c], spi[c], vi));
                 }
                 vr *= 0.25f;
                 vi *= 0.25f;
               }
               if (!(PART & MF_PART_A)) {
-                vr = fmaf(-A.ik2, s0r, vr);
-                vi = fmaf(-A.ik2, s0i, vi);
+                vr = fmaf(-S.ik2, s0r, vr);
+                vi = fmaf(-S.ik2, s0i, vi);
               }
               Xr[a][b] = vr;
               Xi[a][b] = vi;
             }
         } else {
-          int s = A.touch_off[p];
-          const int s1 = A.touch_off[p + 1];
-          while (s < s1 && A.touch_q[s] != q) ++s;
-          const bool found = s < s1;  // always, touching pairs are listed both ways
-          const float *x = A.sing + (size_t)(found ? s : 0) * 18;
+          int s = touch_off[p];
+          const int s1 = touch_off[p + 1];
+          while (s < s1 && touch_q[s] != q) ++s;
+          const bool found = s < s1;  // always: touching pairs are listed both ways
+          const float *x = sing + (size_t)(found ? s : 0) * 18;
 #pragma unroll
           for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -266,9 +249,6 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
             }
         }
         if (pv) {
-          float qsig[3];
-#pragma unroll
-          for (int b = 0; b < 3; ++b) qsig[b] = qr[kRecSigma + b];
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const int row = (prow >> (8 * a)) & 0xff;
@@ -277,7 +257,7 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
             for (int b = 0; b < 3; ++b) {
               const int col = (qcol >> (8 * b)) & 0xff;
               if (col == 0xff) continue;
-              const float sg = psig[a] * qsig[b];
+              const float sg = psig[a] * qr[kRecSigma + b];
               float *dst = acc + row * kAccStride + 2 * col;
               atomicAdd(dst, sg * Xr[a][b]);
               atomicAdd(dst + 1, sg * Xi[a][b]);
@@ -287,114 +267,138 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(FillArgs A) {
       }
     }
     __syncthreads();
-    // Z = j k eta/(4 pi) * acc
-    const int i0 = I * kBM, j0 = J * kBM;
-    for (int e = threadIdx.x; e < kBM * kBM; e += kFillThreads) {
-      const int r = e / kBM, c = e % kBM;
-      if (i0 + r < A.ne && j0 + c < A.ne) {
+    // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
+    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+    for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+      const int r = e / nj, c = e % nj;
+      {
         const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
         ZT v;
-        v.x = -A.pref * ai;
-        v.y = A.pref * ar;
-        reinterpret_cast<ZT *>(A.Z)[(size_t)(i0 + r) * A.ldz + (j0 + c)] = v;
+        v.x = -S.pref * ai;
+        v.y = S.pref * ar;
+        Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+      }
+    }
+    if (I != J) {
+      for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+        const int c = e / ni, r = e % ni;
+        {
+          const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+          ZT v;
+          v.x = -S.pref * ai;
+          v.y = S.pref * ar;
+          Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+        }
       }
     }
     __syncthreads();
   }
-  if (MODE == MF_MODE_TABLE && (rlo < A.lo_ok || rhi > A.hi_ok)) atomicOr(A.status, 1);
+  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(status, 1);
 }
 
+struct LaunchCtx {
+  FillScalars S;
+  const mf_mesh *m;
+  const int2 *bucket;
+  const float *node;
+  const float4 *coef;
+  void *Z;
+  size_t lds;
+};
+
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
-static int launch_t(const FillArgs &A, size_t lds, hipStream_t s) {
+static int launch_t(const LaunchCtx &L, hipStream_t s) {
   auto kern = k_fill<Q, MODE, kLDS, PART, ZT>;
-  if (lds > 65536) MF_HIP(hipFuncSetAttribute((const void *)kern,
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (L.lds > 65536)
+    MF_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)L.lds));
   int dev = 0, ncu = 0, per = 0;
   MF_HIP(hipGetDevice(&dev));
   MF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kFillThreads, lds));
+  MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kFillThreads, L.lds));
   if (per < 1) {
     set_error("mf_fill_Z: fill kernel does not fit on a compute unit");
     return MF_EINVAL;
   }
   long long grid = (long long)ncu * per;
-  if (grid > A.ntiles) grid = A.ntiles;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kFillThreads), lds, s, A);
+  if (grid > L.S.ntiles) grid = L.S.ntiles;
+  if (getenv("MOMFILL_VERBOSE"))
+    fprintf(stderr, "[momfill] k_fill Q=%d mode=%d lds_table=%d grid=%lld x %d lds=%zu B\n", Q,
+            MODE, (int)kLDS, grid, kFillThreads, L.lds);
+  const mf_mesh *m = L.m;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kFillThreads), L.lds, s, L.S, m->d_rec,
+                     m->d_tiles, m->d_blk_e0, m->d_blk_off, m->d_blk_tri, m->d_blk_pos,
+                     m->d_touch_off,
+                     m->d_touch_q, m->d_sing, L.bucket, L.node, L.coef,
+                     reinterpret_cast<ZT *>(L.Z), m->d_status);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
 template <int Q, int MODE, bool kLDS, typename ZT>
-static int launch_part(const FillArgs &A, int part, size_t lds, hipStream_t s) {
-  if (part == MF_PART_A) return launch_t<Q, MODE, kLDS, MF_PART_A, ZT>(A, lds, s);
-  if (part == MF_PART_PHI) return launch_t<Q, MODE, kLDS, MF_PART_PHI, ZT>(A, lds, s);
-  return launch_t<Q, MODE, kLDS, 0, ZT>(A, lds, s);
+static int launch_part(const LaunchCtx &L, int part, hipStream_t s) {
+  if (part == MF_PART_A) return launch_t<Q, MODE, kLDS, MF_PART_A, ZT>(L, s);
+  if (part == MF_PART_PHI) return launch_t<Q, MODE, kLDS, MF_PART_PHI, ZT>(L, s);
+  return launch_t<Q, MODE, kLDS, 0, ZT>(L, s);
 }
 
 template <int Q, typename ZT>
-static int launch_q(const FillArgs &A, int mode, int part, bool lds_tab, size_t lds,
-                    hipStream_t s) {
-  if (mode == MF_MODE_DIRECT) return launch_part<Q, MF_MODE_DIRECT, false, ZT>(A, part, lds, s);
-  if (lds_tab) return launch_part<Q, MF_MODE_TABLE, true, ZT>(A, part, lds, s);
-  return launch_part<Q, MF_MODE_TABLE, false, ZT>(A, part, lds, s);
+static int launch_q(const LaunchCtx &L, int mode, int part, bool lds_tab, hipStream_t s) {
+  if (mode == MF_MODE_DIRECT) return launch_part<Q, MF_MODE_DIRECT, false, ZT>(L, part, s);
+  if (lds_tab) return launch_part<Q, MF_MODE_TABLE, true, ZT>(L, part, s);
+  return launch_part<Q, MF_MODE_TABLE, false, ZT>(L, part, s);
 }
 
 template <typename ZT>
-static int launch_z(const FillArgs &A, int nq, int mode, int part, bool lds_tab, size_t lds,
-                    hipStream_t s) {
+static int launch_z(const LaunchCtx &L, int nq, int mode, int part, bool lds_tab, hipStream_t s) {
   switch (nq) {
-    case 3: return launch_q<3, ZT>(A, mode, part, lds_tab, lds, s);
-    case 6: return launch_q<6, ZT>(A, mode, part, lds_tab, lds, s);
-    default: return launch_q<7, ZT>(A, mode, part, lds_tab, lds, s);
+    case 3: return launch_q<3, ZT>(L, mode, part, lds_tab, s);
+    case 6: return launch_q<6, ZT>(L, mode, part, lds_tab, s);
+    default: return launch_q<7, ZT>(L, mode, part, lds_tab, s);
   }
 }
 
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s) {
-  FillArgs A{};
-  A.rec = m->d_rec;
-  A.blk_off = m->d_blk_off;
-  A.blk_tri = m->d_blk_tri;
-  A.blk_pos = m->d_blk_pos;
-  A.touch_off = m->d_touch_off;
-  A.touch_q = m->d_touch_q;
-  A.sing = m->d_sing;
-  A.nblk = m->nblk;
-  A.ne = m->ne;
-  A.ntiles = (long long)m->nblk * m->nblk;
-  A.k = (float)k;
-  A.ik2 = (float)(1.0 / (k * k));
-  A.pref = (float)(k * kEta0 / (4.0 * M_PI));
-  for (int i = 0; i < kMaxQ; ++i) A.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
-  A.Z = Z;
-  A.ldz = ldz;
-  A.status = m->d_status;
+  LaunchCtx L{};
+  L.m = m;
+  L.Z = Z;
+  FillScalars &S = L.S;
+  S.ntiles = (int)m->tiles.size();
+  S.ne = m->ne;
+  S.k = (float)k;
+  S.ik2 = (float)(1.0 / (k * k));
+  S.pref = (float)(k * kEta0 / (4.0 * M_PI));
+  for (int i = 0; i < kMaxQ; ++i) S.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+  S.ldz = ldz;
   const int base = mode & 0xf, part = mode & (MF_PART_A | MF_PART_PHI);
-  size_t lds = sizeof(float) * kAccFloats + 16;
+  L.lds = sizeof(float) * kAccFloats + 16;
   bool lds_tab = false;
   if (base == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g;
-    A.bucket = g.bucket;
-    A.node = g.node;
-    A.coef = g.coef;
-    A.tn = g.n;
-    A.tm = g.m;
-    A.trmin = (float)tab->rmin;
-    A.tinv = (float)(1.0 / g.delta);
-    A.lo_ok = (float)(tab->rmin * (1.0 - 1e-6));
-    A.hi_ok = (float)(tab->rmax * (1.0 + 1e-6));
+    L.bucket = g.bucket;
+    L.node = g.node;
+    L.coef = g.coef;
+    S.tn = g.n;
+    S.tm = g.m;
+    S.tinv = (float)(1.0 / g.delta);
+    S.tbias = (float)(-tab->rmin / g.delta);
+    S.tmax = (float)(g.m - 1);
+    S.lo_ok = (float)(tab->rmin * (1.0 - 1e-6));
+    S.hi_ok = (float)(tab->rmax * (1.0 + 1e-6));
     const size_t tbytes = sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int2) * (size_t)g.m +
                           sizeof(float) * (size_t)g.n;
     int dev = 0, maxlds = 0;
     MF_HIP(hipGetDevice(&dev));
     MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (lds + tbytes <= (size_t)maxlds) {
+    if (L.lds + tbytes <= (size_t)maxlds) {
       lds_tab = true;
-      lds += tbytes;
+      L.lds += tbytes;
     }
   }
-  if (z_dtype == MF_C64) return launch_z<float2>(A, r.nq, base, part, lds_tab, lds, s);
-  return launch_z<double2>(A, r.nq, base, part, lds_tab, lds, s);
+  if (z_dtype == MF_C64) return launch_z<float2>(L, r.nq, base, part, lds_tab, s);
+  return launch_z<double2>(L, r.nq, base, part, lds_tab, s);
 }
 
 int launch_backward(mf_mesh *, const double *, const Rule &, double, int, const mf_tables *,

@@ -105,10 +105,13 @@ int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
 }
 
 // ---- K1: exact distance range over regular pairs --------------------------
-// Pass 1 bounds every triangle pair by its centroid distance and the radii
-// of its quadrature points and keeps, as witnesses, the first point pair's
-// distance.  Pass 2 evaluates all point pairs exactly only for the pairs
-// whose bounds could beat the witnesses.
+// Every unordered vertex-disjoint pair (p,q) is bounded by its centroid
+// distance d and the radii rb of the quadrature points about the centroids:
+// all point distances lie in [d - rb_p - rb_q, d + rb_p + rb_q].  The exact
+// FP64 point-pair distances are evaluated only for pairs whose bounds can
+// still lower the running minimum or raise the running maximum; the running
+// values start from witnesses (exact distances of a sample of pairs), so the
+// result is the exact extreme whatever the order of evaluation.
 
 constexpr int kRangeBlock = 256;
 constexpr int kRangeChunk = 256;
@@ -116,17 +119,14 @@ constexpr int kRangeChunk = 256;
 struct RangeTri {
   double c[3];
   double rb;
-  double p0[3];
   int v[3];
 };
 
-__device__ inline void load_range_tri(const double *qp64, const double *brad, const float *rec,
-                                      int t, RangeTri &o) {
+__device__ inline void load_range_tri(const double *brad, const float *rec, int t, RangeTri &o) {
   const double *cd = reinterpret_cast<const double *>(rec + (size_t)t * kRecFloats + kRecCent);
   const int *vi = reinterpret_cast<const int *>(rec + (size_t)t * kRecFloats + kRecVid);
   for (int d = 0; d < 3; ++d) {
     o.c[d] = cd[d];
-    o.p0[d] = qp64[(size_t)t * kMaxQ * 3 + d];
     o.v[d] = vi[d];
   }
   o.rb = brad[t];
@@ -156,74 +156,90 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
   return v;
 }
 
-template <bool kExact>
+__device__ inline void pair_extremes(const double *qp64, int nq, int p, int q, double &lo,
+                                     double &hi) {
+  for (int a = 0; a < nq; ++a) {
+    const double *pa = qp64 + ((size_t)p * kMaxQ + a) * 3;
+    for (int b = 0; b < nq; ++b) {
+      const double R = dist3(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
+      lo = fmin(lo, R);
+      hi = fmax(hi, R);
+    }
+  }
+}
+
+__device__ inline void flush_extremes(double lo, double hi, unsigned long long *out) {
+  unsigned long long l = lo < INFINITY ? (unsigned long long)__double_as_longlong(lo) : ~0ull;
+  unsigned long long h = (unsigned long long)__double_as_longlong(hi);
+  l = wave_min_u64(l);
+  h = wave_max_u64(h);
+  if ((threadIdx.x & 63) == 0) {
+    if (l != ~0ull) atomicMin(&out[0], l);
+    atomicMax(&out[1], h);
+  }
+}
+
+// Witnesses: each triangle against a few index neighbours (close in space for
+// meshes numbered with locality) and a few pseudo-random partners.
+__global__ void k_range_seed(const double *__restrict__ qp64, const float *__restrict__ rec, int nt,
+                             int nq, unsigned long long *__restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  double lo = INFINITY, hi = 0.0;
+  if (p < nt) {
+    const int *pv = reinterpret_cast<const int *>(rec + (size_t)p * kRecFloats + kRecVid);
+    for (int j = 0; j < 48; ++j) {
+      const int q = j < 32 ? (p + 2 + j) % nt
+                           : (int)(((long long)p * 7919 + (long long)j * 104729) % nt);
+      const int *qv = reinterpret_cast<const int *>(rec + (size_t)q * kRecFloats + kRecVid);
+      if (q == p || share_vertex(pv, qv)) continue;
+      pair_extremes(qp64, nq, p, q, lo, hi);
+    }
+  }
+  flush_extremes(lo, hi, out);
+}
+
 __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict__ qp64,
                                                        const double *__restrict__ brad,
                                                        const float *__restrict__ rec, int nt,
-                                                       int nq, unsigned long long *__restrict__ out) {
+                                                       int nq, unsigned long long *out) {
+  const int p0 = blockIdx.x * kRangeBlock, q0 = blockIdx.y * kRangeChunk;
+  if (q0 + kRangeChunk <= p0) return;  // unordered pairs: q > p only
   __shared__ RangeTri sq[kRangeChunk];
-  const int p = blockIdx.x * kRangeBlock + threadIdx.x;
-  const int q0 = blockIdx.y * kRangeChunk;
+  const int p = p0 + threadIdx.x;
   const int nqc = min(kRangeChunk, nt - q0);
-  for (int i = threadIdx.x; i < nqc; i += kRangeBlock) load_range_tri(qp64, brad, rec, q0 + i, sq[i]);
+  for (int i = threadIdx.x; i < nqc; i += kRangeBlock) load_range_tri(brad, rec, q0 + i, sq[i]);
   __syncthreads();
-  // out[0..1]: witnesses (min, max); out[2..3]: exact (min, max)
-  unsigned long long lo = ~0ull, hi = 0ull;
+  double lo = INFINITY, hi = 0.0;
   if (p < nt) {
     RangeTri P;
-    load_range_tri(qp64, brad, rec, p, P);
-    const double wmin = __longlong_as_double((long long)out[0]);
-    const double wmax = __longlong_as_double((long long)out[1]);
-    double dlo = INFINITY, dhi = 0.0;
-    for (int j = 0; j < nqc; ++j) {
+    load_range_tri(brad, rec, p, P);
+    lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
+    hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
+    for (int j = max(0, p + 1 - q0); j < nqc; ++j) {
       const RangeTri &Q = sq[j];
       if (share_vertex(P.v, Q.v)) continue;
-      if (!kExact) {
-        const double w = dist3(P.p0, Q.p0);
-        dlo = fmin(dlo, w);
-        dhi = fmax(dhi, w);
-      } else {
-        const double d = dist3(P.c, Q.c);
-        const double rr = P.rb + Q.rb;
-        const bool low = (d - rr) * (1.0 - 1e-12) <= wmin;
-        const bool high = (d + rr) * (1.0 + 1e-12) >= wmax;
-        if (!low && !high) continue;
-        const int q = q0 + j;
-        for (int a = 0; a < nq; ++a) {
-          const double *pa = qp64 + ((size_t)p * kMaxQ + a) * 3;
-          for (int b = 0; b < nq; ++b) {
-            const double R = dist3(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
-            dlo = fmin(dlo, R);
-            dhi = fmax(dhi, R);
-          }
-        }
-      }
+      const double d = dist3(P.c, Q.c);
+      const double rr = P.rb + Q.rb;
+      if ((d - rr) * (1.0 - 1e-12) <= lo || (d + rr) * (1.0 + 1e-12) >= hi)
+        pair_extremes(qp64, nq, p, q0 + j, lo, hi);
     }
-    if (dlo < INFINITY) lo = (unsigned long long)__double_as_longlong(dlo);
-    hi = (unsigned long long)__double_as_longlong(dhi);
   }
-  lo = wave_min_u64(lo);
-  hi = wave_max_u64(hi);
-  if ((threadIdx.x & 63) == 0) {
-    const int o = kExact ? 2 : 0;
-    if (lo != ~0ull) atomicMin(&out[o], lo);
-    atomicMax(&out[o + 1], hi);
-  }
+  flush_extremes(lo, hi, out);
 }
 
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s) {
   (void)V;
-  unsigned long long init[4] = {~0ull, 0ull, ~0ull, 0ull};
+  unsigned long long init[2] = {~0ull, 0ull};
   MF_HIP(hipMemcpyAsync(m->d_scratch, init, sizeof(init), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_range_seed, dim3((m->nt + 255) / 256), dim3(256), 0, s, m->d_qp64,
+                     m->d_rec, m->nt, r.nq, m->d_scratch);
+  MF_HIP(hipGetLastError());
   dim3 grid((m->nt + kRangeBlock - 1) / kRangeBlock, (m->nt + kRangeChunk - 1) / kRangeChunk);
-  hipLaunchKernelGGL(k_range<false>, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
+  hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
                      m->nt, r.nq, m->d_scratch);
   MF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_range<true>, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
-                     m->nt, r.nq, m->d_scratch);
-  MF_HIP(hipGetLastError());
-  unsigned long long res[4];
+  unsigned long long res[2];
   int st[4];
   MF_HIP(hipMemcpyAsync(res, m->d_scratch, sizeof(res), hipMemcpyDeviceToHost, s));
   MF_HIP(hipMemcpyAsync(st, m->d_status, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -233,13 +249,13 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
     set_error("mf_r_range: zero-area triangle");
     return MF_EMESH;
   }
-  if (res[2] == ~0ull) {
+  if (res[0] == ~0ull) {
     set_error("mf_r_range: the mesh has no vertex-disjoint triangle pair");
     return MF_EINVAL;
   }
   double lo, hi;
-  std::memcpy(&lo, &res[2], 8);
-  std::memcpy(&hi, &res[3], 8);
+  std::memcpy(&lo, &res[0], 8);
+  std::memcpy(&hi, &res[1], 8);
   *rmin = lo;
   *rmax = hi;
   return MF_OK;

@@ -13,8 +13,8 @@ namespace mf {
 
 constexpr double kEta0 = 376.730313668;  // free-space wave impedance
 constexpr int kMaxQ = 7;
-constexpr int kTileEdges = 64;            // RWG edges per row/column block of a tile
-constexpr int kMaxBlockTris = 2 * kTileEdges;
+constexpr int kMaxBlockEdges = 88;  // RWG edges per row/column block of a tile
+constexpr int kMaxBlockTris = 64;   // triangles carrying a block's edges (one per lane)
 
 // Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
 //  [0,21)  rho_i = r_i - c      (i-major, xyz)           FP32
@@ -78,9 +78,11 @@ struct mf_mesh {
   std::vector<int32_t> touch_off;  // nt+1 CSR of touching q per p (sorted)
   std::vector<int32_t> touch_q;
   std::vector<int32_t> touch_rev;  // index of (q,p) for pair (p,q)
+  std::vector<int32_t> blk_e0;     // nblk+1: first edge of each block
   std::vector<int32_t> blk_off;    // nblk+1: triangles needed by each edge block
   std::vector<int32_t> blk_tri;
   std::vector<int32_t> blk_pos;    // packed local-edge positions inside the block
+  std::vector<int32_t> tiles;      // (I << 16) | J for every block pair I <= J
   int nblk = 0, max_blk_tris = 0;
 
   // device copies
@@ -89,6 +91,7 @@ struct mf_mesh {
   int32_t *d_touch_off = nullptr, *d_touch_q = nullptr, *d_touch_rev = nullptr;
   int32_t *d_touch_p = nullptr;    // p of each touching pair
   int32_t *d_blk_off = nullptr, *d_blk_tri = nullptr, *d_blk_pos = nullptr;
+  int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr;
   float *d_rec = nullptr;          // nt * kRecFloats
   double *d_qp64 = nullptr;        // nt * kMaxQ * 3 quadrature points (FP64)
   double *d_brad = nullptr;        // nt radius of the quadrature points about the centroid

@@ -264,7 +264,8 @@ __global__ void k_pack_buckets(const int32_t *h, const double *r, int n, int m, 
 }
 
 // Cubic Lagrange polynomial of interval i (stencil s..s+3) re-expanded in
-// powers of u = r - float(r_i): sum_k c_k u^k, coefficients in FP64.
+// powers of u = r - float(r_i): sum_k c_k u^k, coefficients in FP64, stored
+// as two arrays of n-1 records, (c0, c1) then (c2, c3).
 __global__ void k_pack_green(const double *r, const double *f, int n, float *node, float4 *coef) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) node[i] = (float)r[i];
@@ -296,8 +297,8 @@ __global__ void k_pack_green(const double *r, const double *f, int n, float *nod
     cr[0] -= e3 * pr;
     ci[0] -= e3 * pi;
   }
-  coef[2 * i] = make_float4((float)cr[0], (float)ci[0], (float)cr[1], (float)ci[1]);
-  coef[2 * i + 1] = make_float4((float)cr[2], (float)ci[2], (float)cr[3], (float)ci[3]);
+  coef[i] = make_float4((float)cr[0], (float)ci[0], (float)cr[1], (float)ci[1]);
+  coef[(n - 1) + i] = make_float4((float)cr[2], (float)ci[2], (float)cr[3], (float)ci[3]);
 }
 
 // Linear interpolant of interval i written about float(r_i).
@@ -473,14 +474,14 @@ int build_tables_device(mf_tables *T, double tol, hipStream_t s) {
 
 __device__ inline float2 green_lookup(const int2 *__restrict__ bucket,
                                       const float *__restrict__ node,
-                                      const float4 *__restrict__ coef, int m, float rmin,
+                                      const float4 *__restrict__ coef, int n, int m, float rmin,
                                       float inv_delta, float r) {
   int b = (int)((r - rmin) * inv_delta);
   b = min(max(b, 0), m - 1);
   const int2 w = bucket[b];
   const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
   const float u = r - node[i];
-  const float4 c01 = coef[2 * i], c23 = coef[2 * i + 1];
+  const float4 c01 = coef[i], c23 = coef[(n - 1) + i];
   float re = fmaf(c23.z, u, c23.x), im = fmaf(c23.w, u, c23.y);
   re = fmaf(re, u, c01.z);
   im = fmaf(im, u, c01.w);
@@ -501,8 +502,8 @@ __device__ inline float2 exp_lookup(const int2 *__restrict__ bucket, const float
   return make_float2(fmaf(c.z, u, c.x), fmaf(c.w, u, c.y));
 }
 
-__global__ void k_table_eval(const int2 *bucket, const float *node, const float4 *coef, int m,
-                             float rmin, float inv_delta, double lo, double hi, int kind,
+__global__ void k_table_eval(const int2 *bucket, const float *node, const float4 *coef, int tn,
+                             int m, float rmin, float inv_delta, double lo, double hi, int kind,
                              int64_t n, const double *r, double *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -511,7 +512,7 @@ __global__ void k_table_eval(const int2 *bucket, const float *node, const float4
     out[2 * i] = out[2 * i + 1] = __longlong_as_double(0x7ff8000000000000ll);
     return;
   }
-  const float2 v = kind == kGreen ? green_lookup(bucket, node, coef, m, rmin, inv_delta, (float)x)
+  const float2 v = kind == kGreen ? green_lookup(bucket, node, coef, tn, m, rmin, inv_delta, (float)x)
                                   : exp_lookup(bucket, node, coef, m, rmin, inv_delta, (float)x);
   out[2 * i] = v.x;
   out[2 * i + 1] = v.y;
@@ -521,7 +522,7 @@ int launch_table_eval(const mf_tables *T, int which, int64_t n, const double *r,
                       hipStream_t s) {
   const mf_tables::One &o = which == 0 ? T->e : T->g;
   hipLaunchKernelGGL(k_table_eval, dim3(blocks(n, 256)), dim3(256), 0, s, o.bucket, o.node,
-                     o.coef, o.m, (float)T->rmin, (float)(1.0 / o.delta), T->rmin, T->rmax,
+                     o.coef, o.n, o.m, (float)T->rmin, (float)(1.0 / o.delta), T->rmin, T->rmax,
                      which == 0 ? kExp : kGreen, n, r, out);
   MF_HIP(hipGetLastError());
   return MF_OK;
