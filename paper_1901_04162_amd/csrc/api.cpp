@@ -285,7 +285,7 @@ static int ensure_device(mf_mesh *m) {
   MF_HIP(hipMalloc((void **)&m->d_scratch, sizeof(unsigned long long) * 16));
   MF_HIP(hipMalloc((void **)&m->d_status, sizeof(int) * 4));
   MF_HIP(hipMalloc((void **)&m->d_qp64, sizeof(double) * 3 * kMaxQ * (size_t)m->nt));
-  MF_HIP(hipMalloc((void **)&m->d_brad, sizeof(double) * (size_t)m->nt));
+  MF_HIP(hipMalloc((void **)&m->d_brad, sizeof(double) * 4 * (size_t)m->nt));
   MF_HIP(hipMemset(m->d_status, 0, sizeof(int) * 4));
   // d_rec last: its presence marks a complete upload
   MF_HIP(hipMalloc((void **)&m->d_rec, sizeof(float) * kRecFloats * (size_t)m->nt));

@@ -38,8 +38,12 @@ namespace mf {
 constexpr int kBM = kMaxBlockEdges;
 constexpr int kAccStride = 2 * kBM + 1;  // odd stride: rows fall in different banks
 constexpr int kAccFloats = kBM * kAccStride;
-constexpr int kFillThreads = 1024;
-constexpr int kWaves = kFillThreads / 64;
+// Table mode runs 768 threads (3 waves per SIMD, room for the batched
+// lookups of one test point in registers); direct mode 1024.
+template <int MODE>
+constexpr int fill_threads() {
+  return MODE == MF_MODE_TABLE ? 768 : 1024;
+}
 
 struct FillScalars {
   int ntiles, ne;
@@ -61,23 +65,139 @@ struct TabPtrs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Interval by the hash of Eq. (6) (the fix-up "one back if the sample lies
-// above r" is stored as a split position per bucket), then the cubic of
-// Eq. (5) in Horner form about the interval's first sample.
-__device__ __forceinline__ float2 green_table(const TabPtrs &T, const FillScalars &S, float r) {
-  const float x = __builtin_amdgcn_fmed3f(fmaf(r, S.tinv, S.tbias), 0.0f, S.tmax);
-  const int2 w = T.bucket[(int)x];
-  const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
-  const float u = r - T.node[i];
-  const float4 c01 = T.c01[i], c23 = T.c23[i];
-  float re = fmaf(c23.z, u, c23.x), im = fmaf(c23.w, u, c23.y);
-  re = fmaf(re, u, c01.z);
-  im = fmaf(im, u, c01.w);
-  return make_float2(fmaf(re, u, c01.x), fmaf(im, u, c01.y));
+// The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
+struct Moments {
+  float s0r, s0i, srr, sri;
+  float spr[3], spi[3];  // Srho
+  float sqr[3], sqi[3];  // Srho'
+};
+
+// Adds w_i T0 and w_i T1 of test point i (rho_i = pri) into the moments.
+__device__ __forceinline__ void add_point(Moments &M, float wi, const float *pri, float t0r,
+                                          float t0i, const float *t1r, const float *t1i) {
+  t0r *= wi;
+  t0i *= wi;
+  M.s0r += t0r;
+  M.s0i += t0i;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float ar = t1r[c] * wi, ai = t1i[c] * wi;
+    M.spr[c] = fmaf(pri[c], t0r, M.spr[c]);
+    M.spi[c] = fmaf(pri[c], t0i, M.spi[c]);
+    M.sqr[c] += ar;
+    M.sqi[c] += ai;
+    M.srr = fmaf(pri[c], ar, M.srr);
+    M.sri = fmaf(pri[c], ai, M.sri);
+  }
+}
+
+__device__ __forceinline__ void zero(Moments &M) {
+  M.s0r = M.s0i = M.srr = M.sri = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.spr[c] = M.spi[c] = M.sqr[c] = M.sqi[c] = 0.0f;
+}
+
+// Table mode.  The Q lookups of one test point go in three batches
+// (distances and bucket reads, then interval and coefficient reads, then the
+// cubic and the sums) so that the dependent LDS reads of the Q source
+// points overlap each other.  Interval search is the hash of Eq. (6): a
+// bucket holds the interval containing its start and, when a sample lies
+// inside it, that sample's position, above which the next interval applies
+// (the paper's compare-with-the-sample fix-up, resolved per bucket).  The
+// cubic of Eq. (5) is evaluated in Horner form about the interval's first
+// sample.
+template <int Q>
+__device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
+                                              const FillScalars &S, const float (&prho)[Q][3],
+                                              float hx, float hy, float hz, float lx, float ly,
+                                              float lz, const float *qr, float &rlo,
+                                              float &rhi) {
+  zero(M);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float ax = prho[i][0] + lx, ay = prho[i][1] + ly, az = prho[i][2] + lz;
+    float r[Q];
+    int2 w[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
+      const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
+      const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
+      r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      rlo = fminf(rlo, r[j]);
+      rhi = fmaxf(rhi, r[j]);
+      const float x = __builtin_amdgcn_fmed3f(fmaf(r[j], S.tinv, S.tbias), 0.0f, S.tmax);
+      w[j] = tab.bucket[(int)x];
+    }
+    float u[Q];
+    float4 A[Q], B[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int ii = w[j].x + (r[j] >= __int_as_float(w[j].y) ? 1 : 0);
+      u[j] = r[j] - tab.node[ii];
+      A[j] = tab.c01[ii];
+      B[j] = tab.c23[ii];
+    }
+    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      float re = fmaf(B[j].z, u[j], B[j].x), im = fmaf(B[j].w, u[j], B[j].y);
+      re = fmaf(re, u[j], A[j].z);
+      im = fmaf(im, u[j], A[j].w);
+      const float gr = fmaf(re, u[j], A[j].x), gi = fmaf(im, u[j], A[j].y);
+      t0r = fmaf(S.w[j], gr, t0r);
+      t0i = fmaf(S.w[j], gi, t0i);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float wq = qr[kRecWRho + 3 * j + c];
+        t1r[c] = fmaf(wq, gr, t1r[c]);
+        t1i[c] = fmaf(wq, gi, t1i[c]);
+      }
+    }
+    add_point(M, S.w[i], prho[i], t0r, t0i, t1r, t1i);
+  }
+}
+
+// Direct mode: exp(-jkR)/R from rsqrt and sincos; the test-point loop stays
+// rolled (the inlined sincos is long) and reads rho_i from the record.
+template <int Q>
+__device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S, const float *pr,
+                                               float hx, float hy, float hz, float lx, float ly,
+                                               float lz, const float *qr) {
+  zero(M);
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    float pri[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
+    const float ax = pri[0] + lx, ay = pri[1] + ly, az = pri[2] + lz;
+    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
+      const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
+      const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      float sn, cs;
+      sincosf(S.k * (r2 * ri), &sn, &cs);
+      const float gr = cs * ri, gi = -sn * ri;
+      t0r = fmaf(S.w[j], gr, t0r);
+      t0i = fmaf(S.w[j], gi, t0i);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float wq = qr[kRecWRho + 3 * j + c];
+        t1r[c] = fmaf(wq, gr, t1r[c]);
+        t1i[c] = fmaf(wq, gi, t1i[c]);
+      }
+    }
+    add_point(M, S.w[i], pri, t0r, t0i, t1r, t1i);
+  }
 }
 
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
-__global__ __launch_bounds__(kFillThreads) void k_fill(
+__global__ __launch_bounds__(fill_threads<MODE>())
+__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
     FillScalars S, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
     const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
     const int32_t *__restrict__ blk_tri,
@@ -85,6 +205,8 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(
     const int32_t *__restrict__ touch_q, const float *__restrict__ sing,
     const int2 *__restrict__ g_bucket, const float *__restrict__ g_node,
     const float4 *__restrict__ g_coef, ZT *__restrict__ Z, int *__restrict__ status) {
+  constexpr int kFillThreads = fill_threads<MODE>();
+  constexpr int kWaves = kFillThreads / 64;
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
   const int lane = threadIdx.x & 63;
@@ -148,66 +270,13 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(
           const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
           const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                       lz = (float)(Dz - (double)hz);
-          float s0r = 0.f, s0i = 0.f, srr = 0.f, sri = 0.f;
-          float spr[3] = {0.f, 0.f, 0.f}, spi[3] = {0.f, 0.f, 0.f};  // Srho
-          float sqr[3] = {0.f, 0.f, 0.f}, sqi[3] = {0.f, 0.f, 0.f};  // Srho'
-#pragma unroll MODE == MF_MODE_TABLE ? Q : 1
-          for (int i = 0; i < Q; ++i) {
-            float pri[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-              pri[c] = MODE == MF_MODE_TABLE ? prho[i][c] : pr[kRecRho + 3 * i + c];
-            const float ax = pri[0] + lx, ay = pri[1] + ly, az = pri[2] + lz;
-            float t0r = 0.f, t0i = 0.f;
-            float t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int j = 0; j < Q; ++j) {
-              const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
-              const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
-              const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
-              const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-              float gr, gi;
-              if (MODE == MF_MODE_TABLE) {
-                const float r = __builtin_amdgcn_sqrtf(r2);
-                rlo = fminf(rlo, r);
-                rhi = fmaxf(rhi, r);
-                const float2 g = green_table(tab, S, r);
-                gr = g.x;
-                gi = g.y;
-              } else {
-                const float ri = __builtin_amdgcn_rsqf(r2);
-                const float r = r2 * ri;
-                float sn, cs;
-                sincosf(S.k * r, &sn, &cs);
-                gr = cs * ri;
-                gi = -sn * ri;
-              }
-              t0r = fmaf(S.w[j], gr, t0r);
-              t0i = fmaf(S.w[j], gi, t0i);
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const float wq = qr[kRecWRho + 3 * j + c];
-                t1r[c] = fmaf(wq, gr, t1r[c]);
-                t1i[c] = fmaf(wq, gi, t1i[c]);
-              }
-            }
-            // w_i T0, w_i T1, then the rho_i-weighted moments
-            t0r *= S.w[i];
-            t0i *= S.w[i];
-            s0r += t0r;
-            s0i += t0i;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              t1r[c] *= S.w[i];
-              t1i[c] *= S.w[i];
-              spr[c] = fmaf(pri[c], t0r, spr[c]);
-              spi[c] = fmaf(pri[c], t0i, spi[c]);
-              sqr[c] += t1r[c];
-              sqi[c] += t1i[c];
-              srr = fmaf(pri[c], t1r[c], srr);
-              sri = fmaf(pri[c], t1i[c], sri);
-            }
-          }
+          Moments M;
+          if (MODE == MF_MODE_TABLE)
+            moments_table<Q>(M, tab, S, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          else
+            moments_direct<Q>(M, S, pr, hx, hy, hz, lx, ly, lz, qr);
+          const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
+          const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
           for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -309,6 +378,7 @@ struct LaunchCtx {
 
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
 static int launch_t(const LaunchCtx &L, hipStream_t s) {
+  constexpr int kFillThreads = fill_threads<MODE>();
   auto kern = k_fill<Q, MODE, kLDS, PART, ZT>;
   if (L.lds > 65536)
     MF_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

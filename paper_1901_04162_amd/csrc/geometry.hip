@@ -77,7 +77,10 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
       rb = fmax(rb, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
     }
   }
-  if (brad) brad[t] = rb;
+  if (brad) {
+    brad[4 * t] = rb;
+    for (int d = 0; d < 3; ++d) brad[4 * t + 1 + d] = area2 > 0.0 ? n[d] / area2 : 0.0;
+  }
   for (int a = 0; a < 3; ++a) {
     for (int d = 0; d < 3; ++d) o[kRecAlpha + 3 * a + d] = (float)(c[d] - x[a][d]);
     const double *u = x[(a + 1) % 3], *v = x[(a + 2) % 3];
@@ -105,13 +108,19 @@ int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
 }
 
 // ---- K1: exact distance range over regular pairs --------------------------
-// Every unordered vertex-disjoint pair (p,q) is bounded by its centroid
-// distance d and the radii rb of the quadrature points about the centroids:
-// all point distances lie in [d - rb_p - rb_q, d + rb_p + rb_q].  The exact
-// FP64 point-pair distances are evaluated only for pairs whose bounds can
-// still lower the running minimum or raise the running maximum; the running
-// values start from witnesses (exact distances of a sample of pairs), so the
-// result is the exact extreme whatever the order of evaluation.
+// Every unordered vertex-disjoint pair (p,q) is bounded from its centroid
+// offset D (d = |D|), the radii rb of the quadrature points about the
+// centroids and the reach h of those points along D (points lie in the
+// triangle's plane, so h <= rb sin(angle(D, normal))): with delta the
+// offset between two points, |delta| <= rb_p + rb_q = rr and
+// |D.delta|/d <= h_p + h_q = hh, so every squared point distance lies in
+// [d^2 - 2 d hh, d^2 + 2 d hh + rr^2].  The exact FP64 point-pair distances
+// are evaluated only for pairs whose bounds can still lower the running
+// minimum or raise the running maximum; the running values start from
+// witnesses (exact distances of a sample of pairs), so the result is the
+// exact extreme whatever the order of evaluation.  Squared distances are
+// compared and the square root taken once: sqrt is correctly rounded and
+// monotone, so this gives the same extreme as comparing distances.
 
 constexpr int kRangeBlock = 256;
 constexpr int kRangeChunk = 256;
@@ -119,6 +128,7 @@ constexpr int kRangeChunk = 256;
 struct RangeTri {
   double c[3];
   double rb;
+  double n[3];
   int v[3];
 };
 
@@ -128,8 +138,15 @@ __device__ inline void load_range_tri(const double *brad, const float *rec, int 
   for (int d = 0; d < 3; ++d) {
     o.c[d] = cd[d];
     o.v[d] = vi[d];
+    o.n[d] = brad[4 * t + 1 + d];
   }
-  o.rb = brad[t];
+  o.rb = brad[4 * t];
+}
+
+__device__ inline double sq_dist(const double *a, const double *b) {
+#pragma clang fp contract(off)
+  const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+  return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
 __device__ inline bool share_vertex(const int *a, const int *b) {
@@ -156,18 +173,20 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
   return v;
 }
 
+// lo, hi: running extremes of the squared distance
 __device__ inline void pair_extremes(const double *qp64, int nq, int p, int q, double &lo,
                                      double &hi) {
   for (int a = 0; a < nq; ++a) {
     const double *pa = qp64 + ((size_t)p * kMaxQ + a) * 3;
     for (int b = 0; b < nq; ++b) {
-      const double R = dist3(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
-      lo = fmin(lo, R);
-      hi = fmax(hi, R);
+      const double R2 = sq_dist(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
+      lo = fmin(lo, R2);
+      hi = fmax(hi, R2);
     }
   }
 }
 
+// out[0], out[1]: bits of the extreme squared distances found so far
 __device__ inline void flush_extremes(double lo, double hi, unsigned long long *out) {
   unsigned long long l = lo < INFINITY ? (unsigned long long)__double_as_longlong(lo) : ~0ull;
   unsigned long long h = (unsigned long long)__double_as_longlong(hi);
@@ -187,8 +206,8 @@ __global__ void k_range_seed(const double *__restrict__ qp64, const float *__res
   double lo = INFINITY, hi = 0.0;
   if (p < nt) {
     const int *pv = reinterpret_cast<const int *>(rec + (size_t)p * kRecFloats + kRecVid);
-    for (int j = 0; j < 48; ++j) {
-      const int q = j < 32 ? (p + 2 + j) % nt
+    for (int j = 0; j < 24; ++j) {
+      const int q = j < 16 ? (p + 2 + j) % nt
                            : (int)(((long long)p * 7919 + (long long)j * 104729) % nt);
       const int *qv = reinterpret_cast<const int *>(rec + (size_t)q * kRecFloats + kRecVid);
       if (q == p || share_vertex(pv, qv)) continue;
@@ -218,10 +237,15 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
     for (int j = max(0, p + 1 - q0); j < nqc; ++j) {
       const RangeTri &Q = sq[j];
       if (share_vertex(P.v, Q.v)) continue;
-      const double d = dist3(P.c, Q.c);
+      const double D[3] = {Q.c[0] - P.c[0], Q.c[1] - P.c[1], Q.c[2] - P.c[2]};
+      const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d = sqrt(d2);
+      const double cp = (D[0] * P.n[0] + D[1] * P.n[1] + D[2] * P.n[2]) / d;
+      const double cq = (D[0] * Q.n[0] + D[1] * Q.n[1] + D[2] * Q.n[2]) / d;
+      const double hh = P.rb * sqrt(fmax(0.0, 1.0 - cp * cp)) + Q.rb * sqrt(fmax(0.0, 1.0 - cq * cq));
       const double rr = P.rb + Q.rb;
-      if ((d - rr) * (1.0 - 1e-12) <= lo || (d + rr) * (1.0 + 1e-12) >= hi)
-        pair_extremes(qp64, nq, p, q0 + j, lo, hi);
+      const double lo_b = (d2 - 2.0 * d * hh) * (1.0 - 1e-9);
+      const double hi_b = (d2 + 2.0 * d * hh + rr * rr) * (1.0 + 1e-9);
+      if (lo_b <= lo || hi_b >= hi) pair_extremes(qp64, nq, p, q0 + j, lo, hi);
     }
   }
   flush_extremes(lo, hi, out);
@@ -253,11 +277,11 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
     set_error("mf_r_range: the mesh has no vertex-disjoint triangle pair");
     return MF_EINVAL;
   }
-  double lo, hi;
-  std::memcpy(&lo, &res[0], 8);
-  std::memcpy(&hi, &res[1], 8);
-  *rmin = lo;
-  *rmax = hi;
+  double lo2, hi2;
+  std::memcpy(&lo2, &res[0], 8);
+  std::memcpy(&hi2, &res[1], 8);
+  *rmin = std::sqrt(lo2);
+  *rmax = std::sqrt(hi2);
   return MF_OK;
 }
 

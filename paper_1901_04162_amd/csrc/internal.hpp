@@ -94,7 +94,7 @@ struct mf_mesh {
   int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr;
   float *d_rec = nullptr;          // nt * kRecFloats
   double *d_qp64 = nullptr;        // nt * kMaxQ * 3 quadrature points (FP64)
-  double *d_brad = nullptr;        // nt radius of the quadrature points about the centroid
+  double *d_brad = nullptr;        // nt*4: radius of the quadrature points about the centroid, unit normal
   double *d_sing1 = nullptr;       // one-way touching blocks: npairs*9*2
   float *d_sing = nullptr;         // symmetrised, FP32 complex: npairs*9*2
   unsigned long long *d_scratch = nullptr;  // small reductions and flags
