@@ -69,11 +69,10 @@ def lib():
                                       dp, dp, C.c_int, C.c_int, vp, C.c_int64, lp, lp, dp]
         L.or_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
                                     C.c_int, dp, dp, C.c_int, C.c_int, vp, dp]
-        if hasattr(L, "or_grad"):
-            L.or_grad.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int, dp,
-                                  dp, dp, C.c_int, ip, dp, C.c_int, dp]
-            L.or_loss.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int, dp,
-                                  dp, dp, dp]
+        L.or_loss.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int, dp,
+                              dp, dp, dp]
+        L.or_loss_local.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
+                                    dp, dp, dp, C.c_int, dp]
         _lib = L
     return _lib
 
@@ -260,3 +259,47 @@ def collapsed_gauss_rule(n: int):
     w = 2.0 * wu * wv * u
     b = np.stack([l0.ravel(), l1.ravel(), l2.ravel()], axis=1)
     return b, w.ravel()
+
+
+def loss(V, F, edges, k, Q, W, vertex=None):
+    """L = Re sum conj(W) Z (direct mode); with `vertex`, only the entries that
+    move with that vertex (so differences in it equal differences of L)."""
+    V, F, edges = _d(V), _i(F), _i(edges)
+    b, w = _rule(Q)
+    Wd = np.ascontiguousarray(np.asarray(W, dtype=np.complex128)).view(np.float64)
+    out = C.c_double()
+    args = [V.shape[0], _pd(V), F.shape[0], _pi(F), edges.shape[0], _pi(edges), float(k), len(w),
+            _pd(b), _pd(w), _pd(Wd)]
+    if vertex is None:
+        _check(lib().or_loss(*args, C.byref(out)), "loss")
+    else:
+        _check(lib().or_loss_local(*args, int(vertex), C.byref(out)), "loss")
+    return out.value
+
+
+def grad_fd(V, F, edges, k, Q, W, coords=None, with_k=True, h=1e-4):
+    """Gradient of L by central differences with one Richardson step
+    (steps h and h/2, error O(h^4)): dL/dV at the given flat coordinate
+    indices (all if None) and dL/dk.  This is the derivative by its
+    definition, evaluated on the FP64 oracle."""
+    V = np.array(V, dtype=np.float64)
+    n = V.size
+    idx = np.arange(n) if coords is None else np.asarray(coords)
+    g = np.zeros(len(idx))
+    for s, c in enumerate(idx):
+        v = int(c) // 3
+        d = []
+        for hh in (h, h / 2):
+            Vp = V.copy()
+            Vp.flat[c] += hh
+            Vm = V.copy()
+            Vm.flat[c] -= hh
+            d.append((loss(Vp, F, edges, k, Q, W, v) - loss(Vm, F, edges, k, Q, W, v)) / (2 * hh))
+        g[s] = (4 * d[1] - d[0]) / 3
+    gk = None
+    if with_k:
+        hk = h * k
+        d = [(loss(V, F, edges, k + hh, Q, W) - loss(V, F, edges, k - hh, Q, W)) / (2 * hh)
+             for hh in (hk, hk / 2)]
+        gk = (4 * d[1] - d[0]) / 3
+    return g, gk

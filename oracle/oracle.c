@@ -905,3 +905,71 @@ int or_fill_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
   mesh_free(&M);
   return err;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Loss L = Re sum_mn conj(W_mn) Z_mn (direct mode), for finite differences   */
+/* of the adjoint: the full sum, or only the entries whose row or column     */
+/* edge lies on a triangle containing vertex v (the only entries that move   */
+/* when v moves).                                                            */
+/* ------------------------------------------------------------------------ */
+
+static int loss_impl(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                     const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                     const double *W, int vsel, double *L) {
+  if (!(k > 0.0) || ne <= 0) return -1;
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  if (rc) {
+    mesh_free(&M);
+    return rc;
+  }
+  fillctx C = {&M, k, OR_MODE_DIRECT, OR_PART_ALL, NULL, 0};
+  /* mark the edges that lie on a triangle containing vsel */
+  char *mark = (char *)calloc((size_t)ne, 1);
+  if (!mark) {
+    mesh_free(&M);
+    return -4;
+  }
+  for (int m = 0; m < ne; ++m) {
+    if (vsel < 0) {
+      mark[m] = 1;
+      continue;
+    }
+    for (int s = 0; s < 2; ++s) {
+      const int t = edges[6 * m + 2 + s];
+      for (int c = 0; c < 3; ++c)
+        if (tri[3 * t + c] == vsel) mark[m] = 1;
+    }
+  }
+  double acc = 0.0;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : acc)
+  for (int m = 0; m < ne; ++m)
+    for (int n = 0; n < ne; ++n) {
+      if (vsel >= 0 && !mark[m] && !mark[n]) continue;
+      cplx Z;
+      int r2 = entry_value(&C, edges + 6 * (size_t)m, edges + 6 * (size_t)n, &Z);
+      if (r2) {
+#pragma omp atomic write
+        err = r2;
+      }
+      const double wr = W[2 * ((size_t)m * ne + n)], wi = W[2 * ((size_t)m * ne + n) + 1];
+      acc += wr * creal(Z) + wi * cimag(Z); /* Re(conj(W) Z) */
+    }
+  free(mark);
+  mesh_free(&M);
+  *L = acc;
+  return err;
+}
+
+int or_loss(int nv, const double *V, int nt, const int32_t *tri, int ne, const int32_t *edges,
+            double k, int nq, const double *bary, const double *w, const double *W, double *L) {
+  return loss_impl(nv, V, nt, tri, ne, edges, k, nq, bary, w, W, -1, L);
+}
+
+int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                  const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                  const double *W, int v, double *L) {
+  if (v < 0 || v >= nv) return -1;
+  return loss_impl(nv, V, nt, tri, ne, edges, k, nq, bary, w, W, v, L);
+}

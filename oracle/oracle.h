@@ -100,6 +100,16 @@ int or_pair_block(int nv, const double *V, int nt, const int32_t *tri, int p,
                   int q, double k, int nq, const double *bary, const double *w,
                   int mode, int part, const ortable *gtable, double *out18);
 
+/* L = Re sum_mn conj(W_mn) Z_mn in direct mode, W row-major complex
+ * (2*ne*ne doubles).  or_loss_local sums only the entries whose row or
+ * column edge lies on a triangle containing vertex v: moving v changes no
+ * other entry, so differences of it in v equal differences of L. */
+int or_loss(int nv, const double *V, int nt, const int32_t *tri, int ne, const int32_t *edges,
+            double k, int nq, const double *bary, const double *w, const double *W, double *L);
+int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                  const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                  const double *W, int v, double *L);
+
 #ifdef __cplusplus
 }
 #endif

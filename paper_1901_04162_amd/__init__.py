@@ -182,6 +182,7 @@ class _FillFn(torch.autograd.Function):
         Z = fill_Z(mesh, V, float(k), quad_order, mode, tables, dtype)
         ctx.save_for_backward(V)
         ctx.meta = (float(k), mesh, quad_order, mode, tables)
+        ctx.k_like = (k.device, k.dtype) if isinstance(k, torch.Tensor) else (None, None)
         return Z
 
     @staticmethod
@@ -191,7 +192,9 @@ class _FillFn(torch.autograd.Function):
         # torch hands the gradient of a real loss w.r.t. complex Z as dL/dRe + j dL/dIm,
         # which is the W of L = Re sum conj(W) Z
         dV, dk = fill_Z_backward(mesh, V, k, quad_order, mode, tables, gZ)
-        return dV.to(V.dtype), dk.reshape(()), None, None, None, None, None
+        kdev, kdt = ctx.k_like
+        dk = dk.reshape(()) if kdev is None else dk.reshape(()).to(device=kdev, dtype=kdt)
+        return dV.to(V.dtype), dk, None, None, None, None, None
 
 
 def fill(V: torch.Tensor, k, mesh: Mesh, quad_order: int, mode: str = "table",

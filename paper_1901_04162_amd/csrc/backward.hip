@@ -1,0 +1,573 @@
+// Adjoint of the fill: gradient of L = Re sum_mn conj(W_mn) Z_mn with respect
+// to the vertex coordinates and k.
+//
+// Regular triangle pairs (FP32, analytic).  Writing
+//   Omega_ab = conj(W[e(p,a), e(q,b)]) s_a l_a s_b l_b      (zero off the tile)
+// the pair's share of L is Re[c sum_ij w_i w_j g(R_ij) B_ij], c = j k eta/(4 pi),
+//   B_ij = sum_ab Omega_ab [ (r_i - v_a).(r_j - v_b)/4 - 1/k^2 ]
+//        = (O rho_i.rho'_j + rho_i.P + Qv.rho'_j + Gamma)/4 - O/k^2
+// with O = sum Omega, P = sum Omega_ab beta_b, Qv = sum Omega_ab alpha_a,
+// Gamma = sum Omega_ab alpha_a.beta_b.  Differentiating:
+//   d/dr_i : w_i w_j [ g'(R) B (r_i - r_j)/R + g (O rho'_j + P)/4 ]   (and the
+//            mirror for r_j), chained to the vertices through the barycentric
+//            weights of the rule;
+//   d/dv_a : -(c/4) [ Omega_a. Srho' + P_a S0 ]   (v_a = free vertex a of p);
+//   d/dl_a : Re[c sum_b Omega_ab X_ab] / l_a, chained through l_a = |edge a|;
+//   d/dk   : Re[(c/k) sum w w g B + c sum w w (dg/dk) B + c (2 O/k^3) S0].
+// Table mode treats the tables as fixed: dg/dR is the derivative of the
+// interval's cubic and dg/dk = -j exp(-jkR) comes from the linear Exp table
+// (Eq. (4)); direct mode differentiates exp(-jkR)/R.
+//
+// The tile plan is the forward one (block pairs I <= J): an off-diagonal tile
+// stands for Z[I,J] and its mirror Z[J,I], so its weight is W[I,J] + W[J,I]^T.
+//
+// Touching pairs (FP64): their blocks are smooth in the vertices of the pair
+// (the pair keeps its shared vertices), so each ordered pair's share of L is
+// differentiated by central differences with one Richardson step, moving
+// each of the pair's distinct vertices in both triangles at once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.hpp"
+#include "singular.hpp"
+
+namespace mf {
+
+constexpr int kBwdThreads = 256;
+constexpr int kBwdBM = kMaxBlockEdges;
+
+struct BwdScalars {
+  int ntiles;
+  float k, ik2, pref;  // pref = k eta0 / (4 pi)
+  float w[kMaxQ];
+  float bary[kMaxQ][3];
+  // Green table (cubic) and Exp table (linear), global memory
+  const int2 *gb;
+  const float *gn;
+  const float4 *g01, *g23;
+  const int2 *eb;
+  const float *en;
+  const float4 *ec;
+  int gm, em;
+  float ginv, gbias, gmax, einv, ebias, emax;
+  long long ldz;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Omega_ab = conj(W[row(a), col(b)]) sigma_a sigma_b, zero where the local
+// edge is a boundary edge or lies outside the tile's blocks.
+__device__ __forceinline__ void omega(const float2 *Wt, int prow, int qcol, int a, int b, float sg,
+                                      float &re, float &im) {
+  const int row = (prow >> (8 * a)) & 0xff, col = (qcol >> (8 * b)) & 0xff;
+  float2 w = make_float2(0.f, 0.f);
+  if (row != 0xff && col != 0xff) w = Wt[row * kBwdBM + col];
+  re = w.x * sg;
+  im = -w.y * sg;
+}
+
+template <int Q, int MODE, typename ZT>
+__global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
+    BwdScalars S, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
+    const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
+    const ZT *__restrict__ W, double *__restrict__ dV, double *__restrict__ dk) {
+  __shared__ float2 Wt[kBwdBM * kBwdBM];
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  constexpr int kWaves = kBwdThreads / 64;
+  float gk = 0.0f;
+
+  for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
+    const int tij = tiles[tile];
+    const int I = tij >> 16, J = tij & 0xffff;
+    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ni * nj; e += kBwdThreads) {
+      const int r = e / nj, c = e % nj;
+      const ZT v = W[(size_t)(i0 + r) * S.ldz + (j0 + c)];
+      Wt[r * kBwdBM + c] = make_float2((float)v.x, (float)v.y);
+    }
+    __syncthreads();
+    if (I != J) {
+      for (int e = threadIdx.x; e < ni * nj; e += kBwdThreads) {
+        const int c = e / ni, r = e % ni;
+        const ZT v = W[(size_t)(j0 + c) * S.ldz + (i0 + r)];
+        float2 &t = Wt[r * kBwdBM + c];
+        t.x += (float)v.x;
+        t.y += (float)v.y;
+      }
+      __syncthreads();
+    }
+    const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
+    const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
+    for (int pc = 0; pc < np; pc += 64) {
+      const bool pv = pc + lane < np;
+      const int pidx = pv ? pc + lane : pc;
+      const int p = blk_tri[p0 + pidx];
+      const int prow = pv ? blk_pos[p0 + pidx] : -1;
+      const float *pr = rec + (size_t)p * kRecFloats;
+      float pal[3][3], psig[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pal[a][c] = pr[kRecAlpha + 3 * a + c];
+        psig[a] = pr[kRecSigma + a];
+      }
+      const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
+      const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
+      const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
+      float Gv[3][3], Gl[3];  // gradient on p's vertices; d/dl_a
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Gv[a][0] = Gv[a][1] = Gv[a][2] = Gl[a] = 0.f;
+
+      for (int qi = wave; qi < nq; qi += kWaves) {
+        const int q = uni(blk_tri[q0 + qi]);
+        const int qcol = uni(blk_pos[q0 + qi]);
+        const float *qr = rec + (size_t)q * kRecFloats;
+        const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
+        const bool touch = pv0 == qvi[0] || pv0 == qvi[1] || pv0 == qvi[2] || pv1 == qvi[0] ||
+                           pv1 == qvi[1] || pv1 == qvi[2] || pv2 == qvi[0] || pv2 == qvi[1] ||
+                           pv2 == qvi[2];
+        float gq[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // q vertex gradient
+        if (!touch && pv) {
+          float beta[3][3], qsig[3];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) beta[b][c] = qr[kRecAlpha + 3 * b + c];
+            qsig[b] = qr[kRecSigma + b];
+          }
+          // O = sum Omega, P = sum Omega_ab beta_b, Qv = sum Omega_ab alpha_a,
+          // Gamma = sum Omega_ab alpha_a.beta_b
+          float O_r = 0.f, O_i = 0.f, Gm_r = 0.f, Gm_i = 0.f;
+          float P_r[3] = {0.f, 0.f, 0.f}, P_i[3] = {0.f, 0.f, 0.f};
+          float Qv_r[3] = {0.f, 0.f, 0.f}, Qv_i[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              float wr, wi;
+              omega(Wt, prow, qcol, a, b, psig[a] * qsig[b], wr, wi);
+              O_r += wr;
+              O_i += wi;
+              const float ab = pal[a][0] * beta[b][0] + pal[a][1] * beta[b][1] +
+                               pal[a][2] * beta[b][2];
+              Gm_r = fmaf(wr, ab, Gm_r);
+              Gm_i = fmaf(wi, ab, Gm_i);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                P_r[c] = fmaf(wr, beta[b][c], P_r[c]);
+                P_i[c] = fmaf(wi, beta[b][c], P_i[c]);
+                Qv_r[c] = fmaf(wr, pal[a][c], Qv_r[c]);
+                Qv_i[c] = fmaf(wi, pal[a][c], Qv_i[c]);
+              }
+            }
+          const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
+          const double Dx = pcd[0] - qcd[0], Dy = pcd[1] - qcd[1], Dz = pcd[2] - qcd[2];
+          const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
+          const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                      lz = (float)(Dz - (double)hz);
+          // moments of w w g: S0, Srho.rho', Srho, Srho'
+          float s0r = 0.f, s0i = 0.f, srr = 0.f, sri = 0.f;
+          float spr[3] = {0.f, 0.f, 0.f}, spi[3] = {0.f, 0.f, 0.f};
+          float sqr_[3] = {0.f, 0.f, 0.f}, sqi_[3] = {0.f, 0.f, 0.f};
+          float kg_i = 0.f, ke_r = 0.f;  // Im sum w w g B, Re sum w w exp(-jkR) B
+          // Only imaginary parts survive Re[c z] with c = j pref.
+          float Fq[Q][3];
+#pragma unroll
+          for (int j = 0; j < Q; ++j) Fq[j][0] = Fq[j][1] = Fq[j][2] = 0.f;
+#pragma unroll 1
+          for (int i = 0; i < Q; ++i) {
+            const float prho[3] = {pr[kRecRho + 3 * i], pr[kRecRho + 3 * i + 1],
+                                   pr[kRecRho + 3 * i + 2]};
+            const float ax = prho[0] + lx, ay = prho[1] + ly, az = prho[2] + lz;
+            float Fp[3] = {0.f, 0.f, 0.f};
+            // B_ij pieces that do not depend on j
+            const float bpr = 0.25f * (P_r[0] * prho[0] + P_r[1] * prho[1] +
+                                       P_r[2] * prho[2] + Gm_r) - S.ik2 * O_r;
+            const float bpi = 0.25f * (P_i[0] * prho[0] + P_i[1] * prho[1] +
+                                       P_i[2] * prho[2] + Gm_i) - S.ik2 * O_i;
+            float tq_r[3], tq_i[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              tq_r[c] = 0.25f * fmaf(O_r, prho[c], Qv_r[c]);
+              tq_i[c] = 0.25f * fmaf(O_i, prho[c], Qv_i[c]);
+            }
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+              const float rq0 = qr[kRecRho + 3 * j], rq1 = qr[kRecRho + 3 * j + 1],
+                          rq2 = qr[kRecRho + 3 * j + 2];
+              const float d0 = hx + (ax - rq0), d1 = hy + (ay - rq1), d2 = hz + (az - rq2);
+              const float R2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+              const float ri = __builtin_amdgcn_rsqf(R2);
+              const float R = R2 * ri;
+              float gr, gi, dgr, dgi, er;  // g, dg/dR, Re exp(-jkR)
+              float ei;
+              if (MODE == MF_MODE_TABLE) {
+                const float x = __builtin_amdgcn_fmed3f(fmaf(R, S.ginv, S.gbias), 0.0f, S.gmax);
+                const int2 wb = S.gb[(int)x];
+                const int ii = wb.x + (R >= __int_as_float(wb.y) ? 1 : 0);
+                const float u = R - S.gn[ii];
+                const float4 A = S.g01[ii], B = S.g23[ii];
+                // g = c0 + c1 u + c2 u^2 + c3 u^3, g' = c1 + 2 c2 u + 3 c3 u^2
+                const float der = fmaf(3.0f * B.z, u, 2.0f * B.x);
+                const float dei = fmaf(3.0f * B.w, u, 2.0f * B.y);
+                dgr = fmaf(der, u, A.z);
+                dgi = fmaf(dei, u, A.w);
+                float re = fmaf(fmaf(B.z, u, B.x), u, A.z), im = fmaf(fmaf(B.w, u, B.y), u, A.w);
+                gr = fmaf(re, u, A.x);
+                gi = fmaf(im, u, A.y);
+                const float xe = __builtin_amdgcn_fmed3f(fmaf(R, S.einv, S.ebias), 0.0f, S.emax);
+                const int2 we = S.eb[(int)xe];
+                const int ie = we.x + (R >= __int_as_float(we.y) ? 1 : 0);
+                const float ue = R - S.en[ie];
+                const float4 Ec = S.ec[ie];
+                er = fmaf(Ec.z, ue, Ec.x);
+                ei = fmaf(Ec.w, ue, Ec.y);
+              } else {
+                float sn, cs;
+                sincosf(S.k * R, &sn, &cs);
+                er = cs;
+                ei = -sn;
+                gr = er * ri;
+                gi = ei * ri;
+                // dg/dR = -(jk + 1/R) g
+                dgr = fmaf(S.k, gi, -ri * gr);
+                dgi = fmaf(-S.k, gr, -ri * gi);
+              }
+              const float rr = prho[0] * rq0 + prho[1] * rq1 + prho[2] * rq2;
+              const float qdot_r = Qv_r[0] * rq0 + Qv_r[1] * rq1 + Qv_r[2] * rq2;
+              const float qdot_i = Qv_i[0] * rq0 + Qv_i[1] * rq1 + Qv_i[2] * rq2;
+              const float Br = fmaf(0.25f, fmaf(O_r, rr, qdot_r), bpr);
+              const float Bi = fmaf(0.25f, fmaf(O_i, rr, qdot_i), bpi);
+              const float ww = S.w[i] * S.w[j];
+              const float wri = ww * ri;
+              const float hi = wri * (dgr * Bi + dgi * Br);  // Im(w w g' B / R)
+              const float wgr = ww * gr, wgi = ww * gi;
+              const float rq[3] = {rq0, rq1, rq2}, d[3] = {d0, d1, d2};
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const float tpr = 0.25f * fmaf(O_r, rq[c], P_r[c]);
+                const float tpi = 0.25f * fmaf(O_i, rq[c], P_i[c]);
+                Fp[c] += fmaf(hi, d[c], fmaf(wgr, tpi, wgi * tpr));
+                Fq[j][c] += fmaf(-hi, d[c], fmaf(wgr, tq_i[c], wgi * tq_r[c]));
+                spr[c] = fmaf(wgr, prho[c], spr[c]);
+                spi[c] = fmaf(wgi, prho[c], spi[c]);
+                sqr_[c] = fmaf(wgr, rq[c], sqr_[c]);
+                sqi_[c] = fmaf(wgi, rq[c], sqi_[c]);
+              }
+              kg_i += wgr * Bi + wgi * Br;
+              ke_r += ww * (er * Br - ei * Bi);
+              s0r += wgr;
+              s0i += wgi;
+              srr = fmaf(wgr, rr, srr);
+              sri = fmaf(wgi, rr, sri);
+            }
+            // Re[c z] = -pref Im z, chained to the vertices through r_i's weights
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) Gv[v][c] = fmaf(-S.pref * S.bary[i][v], Fp[c], Gv[v][c]);
+          }
+          // source points to q's vertices
+#pragma unroll
+          for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int v = 0; v < 3; ++v)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) gq[3 * v + c] -= S.bary[j][v] * S.pref * Fq[j][c];
+          // d/dk
+          gk += -(S.pref / S.k) * kg_i + S.pref * ke_r -
+                S.pref * 2.0f * S.ik2 / S.k * (O_r * s0i + O_i * s0r);
+          // free-vertex and edge-length terms, Omega re-read from the tile
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              float wr, wi;
+              omega(Wt, prow, qcol, a, b, psig[a] * qsig[b], wr, wi);
+              const float ab = pal[a][0] * beta[b][0] + pal[a][1] * beta[b][1] +
+                               pal[a][2] * beta[b][2];
+              // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + alpha_a.beta_b S0)/4 - S0/k^2
+              float xr = fmaf(ab, s0r, srr), xi = fmaf(ab, s0i, sri);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                xr += pal[a][c] * sqr_[c] + beta[b][c] * spr[c];
+                xi += pal[a][c] * sqi_[c] + beta[b][c] * spi[c];
+                // d/dv_a: -(1/4) Omega_ab (Srho' + beta_b S0); d/dv_b: -(1/4) Omega_ab (Srho + alpha_a S0)
+                const float ya = (wr * fmaf(beta[b][c], s0i, sqi_[c]) +
+                                  wi * fmaf(beta[b][c], s0r, sqr_[c]));
+                const float yb = (wr * fmaf(pal[a][c], s0i, spi[c]) +
+                                  wi * fmaf(pal[a][c], s0r, spr[c]));
+                Gv[a][c] = fmaf(0.25f * S.pref, ya, Gv[a][c]);
+                gq[3 * b + c] = fmaf(0.25f * S.pref, yb, gq[3 * b + c]);
+              }
+              xr = fmaf(0.25f, xr, -S.ik2 * s0r);
+              xi = fmaf(0.25f, xi, -S.ik2 * s0i);
+              const float im = wr * xi + wi * xr;  // Im(Omega X)
+              const float la = fabsf(psig[a]), lb = fabsf(qsig[b]);
+              if (la > 0.f) Gl[a] -= S.pref * im / la;
+              if (lb > 0.f) {
+                // l_b = |x_{b+1} - x_{b+2}| and x_{b+1} - x_{b+2} = beta_{b+2} - beta_{b+1}
+                const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+                const float g = -S.pref * im / (lb * lb);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  const float e = beta[b2][c] - beta[b1][c];
+                  gq[3 * b1 + c] = fmaf(g, e, gq[3 * b1 + c]);
+                  gq[3 * b2 + c] = fmaf(-g, e, gq[3 * b2 + c]);
+                }
+              }
+            }
+        }
+        // sum over lanes, one atomic per coordinate of q
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float v = wave_sum(gq[c]);
+          if (lane == 0 && v != 0.0f) atomicAdd(&dV[3 * (size_t)qvi[c / 3] + c % 3], (double)v);
+        }
+      }
+      if (pv) {
+        float gpv[9];
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            gpv[3 * v + c] = Gv[v][c];
+          }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float la = fabsf(psig[a]);
+          if (la > 0.f) {
+            const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const float e = pal[a2][c] - pal[a1][c];
+              gpv[3 * a1 + c] += Gl[a] * e / la;
+              gpv[3 * a2 + c] -= Gl[a] * e / la;
+            }
+          }
+        }
+        const int vids[3] = {pv0, pv1, pv2};
+#pragma unroll
+        for (int c = 0; c < 9; ++c)
+          if (gpv[c] != 0.0f) atomicAdd(&dV[3 * (size_t)vids[c / 3] + c % 3], (double)gpv[c]);
+      }
+    }
+  }
+  const float s = wave_sum(gk);
+  if (lane == 0) atomicAdd(dk, (double)s);
+}
+
+// ---- touching pairs -------------------------------------------------------
+
+template <typename ZT>
+__device__ double touching_share(const double xp[3][3], const double xq[3][3], const RuleArg &R,
+                                 double k, const int *ep, const int *eq, const signed char *sp,
+                                 const signed char *sq, const ZT *W, long long ldz) {
+  double x1r[9], x1i[9], x2r[9], x2i[9];
+  oneway_block(xp, xq, R, k, 0, x1r, x1i);
+  oneway_block(xq, xp, R, k, 0, x2r, x2i);
+  double sr = 0.0, si = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (ep[a] < 0) continue;
+    const double *u = xp[(a + 1) % 3], *v = xp[(a + 2) % 3];
+    const double la = sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
+                           (u[2] - v[2]) * (u[2] - v[2]));
+    for (int b = 0; b < 3; ++b) {
+      if (eq[b] < 0) continue;
+      const double *s = xq[(b + 1) % 3], *t = xq[(b + 2) % 3];
+      const double lb = sqrt((s[0] - t[0]) * (s[0] - t[0]) + (s[1] - t[1]) * (s[1] - t[1]) +
+                             (s[2] - t[2]) * (s[2] - t[2]));
+      const ZT w = W[(size_t)ep[a] * ldz + eq[b]];
+      const double xr = 0.5 * (x1r[3 * a + b] + x2r[3 * b + a]);
+      const double xi = 0.5 * (x1i[3 * a + b] + x2i[3 * b + a]);
+      const double f = (double)sp[a] * (double)sq[b] * la * lb;
+      // conj(w) * X
+      sr += f * ((double)w.x * xr + (double)w.y * xi);
+      si += f * ((double)w.x * xi - (double)w.y * xr);
+    }
+  }
+  // Re[j k eta/(4 pi) (sr + j si)]
+  return -k * kEta0 / (4.0 * M_PI) * si;
+}
+
+template <typename ZT>
+__global__ void k_bwd_touching(const double *__restrict__ V, const int32_t *__restrict__ tri,
+                               const int32_t *__restrict__ tp, const int32_t *__restrict__ tq,
+                               const int32_t *__restrict__ tedge,
+                               const signed char *__restrict__ tsign, int64_t npair, RuleArg R,
+                               double k, const ZT *__restrict__ W, long long ldz,
+                               double *__restrict__ dV, double *__restrict__ dk) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= npair) return;
+  const int p = tp[s], q = tq[s];
+  int vp[3], vq[3], ep[3], eq[3];
+  signed char sp[3], sq[3];
+  double xp[3][3], xq[3][3];
+  double scale = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    vp[a] = tri[3 * p + a];
+    vq[a] = tri[3 * q + a];
+    ep[a] = tedge[3 * p + a];
+    eq[a] = tedge[3 * q + a];
+    sp[a] = tsign[3 * p + a];
+    sq[a] = tsign[3 * q + a];
+    for (int c = 0; c < 3; ++c) {
+      xp[a][c] = V[3 * (size_t)vp[a] + c];
+      xq[a][c] = V[3 * (size_t)vq[a] + c];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double *u = xp[(a + 1) % 3], *v = xp[(a + 2) % 3];
+    scale = fmax(scale, sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
+                             (u[2] - v[2]) * (u[2] - v[2])));
+  }
+  // distinct vertices of the pair
+  int vid[6], nvid = 0;
+  for (int a = 0; a < 3; ++a) vid[nvid++] = vp[a];
+  for (int a = 0; a < 3; ++a) {
+    bool seen = false;
+    for (int b = 0; b < 3; ++b) seen |= vq[a] == vp[b];
+    if (!seen) vid[nvid++] = vq[a];
+  }
+  const double h0 = 1e-4 * scale;
+  for (int t = 0; t < nvid; ++t)
+    for (int c = 0; c < 3; ++c) {
+      double d[2];
+      for (int r = 0; r < 2; ++r) {
+        const double h = r == 0 ? h0 : 0.5 * h0;
+        double f[2];
+        for (int sgn = 0; sgn < 2; ++sgn) {
+          double yp[3][3], yq[3][3];
+          for (int a = 0; a < 3; ++a)
+            for (int e = 0; e < 3; ++e) {
+              yp[a][e] = xp[a][e];
+              yq[a][e] = xq[a][e];
+            }
+          const double dh = sgn == 0 ? h : -h;
+          for (int a = 0; a < 3; ++a) {
+            if (vp[a] == vid[t]) yp[a][c] += dh;
+            if (vq[a] == vid[t]) yq[a][c] += dh;
+          }
+          f[sgn] = touching_share(yp, yq, R, k, ep, eq, sp, sq, W, ldz);
+        }
+        d[r] = (f[0] - f[1]) / (2.0 * h);
+      }
+      atomicAdd(&dV[3 * (size_t)vid[t] + c], (4.0 * d[1] - d[0]) / 3.0);
+    }
+  double d[2];
+  for (int r = 0; r < 2; ++r) {
+    const double h = (r == 0 ? 1e-4 : 0.5e-4) * k;
+    d[r] = (touching_share(xp, xq, R, k + h, ep, eq, sp, sq, W, ldz) -
+            touching_share(xp, xq, R, k - h, ep, eq, sp, sq, W, ldz)) /
+           (2.0 * h);
+  }
+  atomicAdd(dk, (4.0 * d[1] - d[0]) / 3.0);
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+template <int Q, int MODE, typename ZT>
+static int launch_bwd_t(mf_mesh *m, const BwdScalars &S, const ZT *W, double *dV, double *dk,
+                        hipStream_t s) {
+  auto kern = k_bwd_regular<Q, MODE, ZT>;
+  int dev = 0, ncu = 0, per = 0;
+  MF_HIP(hipGetDevice(&dev));
+  MF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBwdThreads, 0));
+  if (per < 1) per = 1;
+  long long grid = (long long)ncu * per;
+  if (grid > S.ntiles) grid = S.ntiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBwdThreads), 0, s, S, m->d_rec, m->d_tiles,
+                     m->d_blk_e0, m->d_blk_off, m->d_blk_tri, m->d_blk_pos, W, dV, dk);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename ZT>
+static int launch_bwd_z(mf_mesh *m, const Rule &r, int mode, const BwdScalars &S, const void *W,
+                        double *dV, double *dk, hipStream_t s) {
+  const ZT *w = reinterpret_cast<const ZT *>(W);
+  int rc;
+  if (mode == MF_MODE_TABLE) {
+    rc = r.nq == 3 ? launch_bwd_t<3, MF_MODE_TABLE, ZT>(m, S, w, dV, dk, s)
+         : r.nq == 6 ? launch_bwd_t<6, MF_MODE_TABLE, ZT>(m, S, w, dV, dk, s)
+                     : launch_bwd_t<7, MF_MODE_TABLE, ZT>(m, S, w, dV, dk, s);
+  } else {
+    rc = r.nq == 3 ? launch_bwd_t<3, MF_MODE_DIRECT, ZT>(m, S, w, dV, dk, s)
+         : r.nq == 6 ? launch_bwd_t<6, MF_MODE_DIRECT, ZT>(m, S, w, dV, dk, s)
+                     : launch_bwd_t<7, MF_MODE_DIRECT, ZT>(m, S, w, dV, dk, s);
+  }
+  if (rc) return rc;
+  return MF_OK;
+}
+
+template <typename ZT>
+static int launch_bwd_touch(mf_mesh *m, const double *V, const Rule &r, double k, const void *W,
+                            int64_t ldz, double *dV, double *dk, hipStream_t s) {
+  const int64_t np = (int64_t)m->touch_q.size();
+  if (np == 0) return MF_OK;
+  RuleArg R = rule_arg(r);
+  hipLaunchKernelGGL(k_bwd_touching<ZT>, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, V,
+                     m->d_tri, m->d_touch_p, m->d_touch_q, m->d_tedge,
+                     reinterpret_cast<const signed char *>(m->d_tsign), np, R, k,
+                     reinterpret_cast<const ZT *>(W), (long long)ldz, dV, dk);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+int launch_backward(mf_mesh *m, const double *V, const Rule &r, double k, int mode,
+                    const mf_tables *tab, const void *W, int z_dtype, int64_t ldz, double *dV,
+                    double *dk, hipStream_t s) {
+  const int64_t nvc = 3 * (int64_t)m->nv;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((nvc + 255) / 256)), dim3(256), 0, s, dV, nvc);
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, dk, (int64_t)1);
+  MF_HIP(hipGetLastError());
+  BwdScalars S{};
+  S.ntiles = (int)m->tiles.size();
+  S.k = (float)k;
+  S.ik2 = (float)(1.0 / (k * k));
+  S.pref = (float)(k * kEta0 / (4.0 * M_PI));
+  for (int i = 0; i < kMaxQ; ++i) {
+    S.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+    for (int c = 0; c < 3; ++c) S.bary[i][c] = i < r.nq ? (float)r.bary[i][c] : 0.0f;
+  }
+  S.ldz = ldz;
+  if (mode == MF_MODE_TABLE) {
+    const mf_tables::One &g = tab->g, &e = tab->e;
+    S.gb = g.bucket;
+    S.gn = g.node;
+    S.g01 = g.coef;
+    S.g23 = g.coef + (g.n - 1);
+    S.gm = g.m;
+    S.ginv = (float)(1.0 / g.delta);
+    S.gbias = (float)(-tab->rmin / g.delta);
+    S.gmax = (float)(g.m - 1);
+    S.eb = e.bucket;
+    S.en = e.node;
+    S.ec = e.coef;
+    S.em = e.m;
+    S.einv = (float)(1.0 / e.delta);
+    S.ebias = (float)(-tab->rmin / e.delta);
+    S.emax = (float)(e.m - 1);
+  }
+  int rc = z_dtype == MF_C64 ? launch_bwd_z<float2>(m, r, mode, S, W, dV, dk, s)
+                             : launch_bwd_z<double2>(m, r, mode, S, W, dV, dk, s);
+  if (rc) return rc;
+  return z_dtype == MF_C64 ? launch_bwd_touch<float2>(m, V, r, k, W, ldz, dV, dk, s)
+                           : launch_bwd_touch<double2>(m, V, r, k, W, ldz, dV, dk, s);
+}
+
+}  // namespace mf

@@ -471,10 +471,4 @@ int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *
   return launch_z<double2>(L, r.nq, base, part, lds_tab, s);
 }
 
-int launch_backward(mf_mesh *, const double *, const Rule &, double, int, const mf_tables *,
-                    const void *, int, int64_t, double *, double *, hipStream_t) {
-  set_error("mf_fill_Z_backward: not available in this build");
-  return MF_EINVAL;
-}
-
 }  // namespace mf

@@ -113,7 +113,9 @@ int hip_fail(hipError_t e, const char *what);
   } while (0)
 
 
-// kernels.hip
+struct RuleArg;
+RuleArg rule_arg(const Rule &r);
+
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s);
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s);
