@@ -21,7 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Z entries/s + Green evals/s, table vs direct-exp, at rel err ≤1e-5 vs FP64"
-FLOPS_PER_EVAL = 40           # algorithmic FP32 flops per Green evaluation
+# Algorithmic FP32 flops per regular quadrature-point pair in table mode (an FMA
+# counts 2): distance 8, R from rsqrt 1, bucket 2, offset 1, complex cubic
+# 12, four complex moment sums 16.
+FLOPS_PER_EVAL = 40
 PEAK_FP32 = 157.3             # TFLOP/s, MI355X FP32 vector peak
 FILL_KERNEL_SRC = os.path.join(ROOT, "paper_1901_04162_amd", "csrc", "fill.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fill_table_ico5_traffic.txt")
@@ -51,32 +54,72 @@ def _traffic():
 
 
 def cpu_baseline(V, F, edges, k, Q, seconds):
-    """The oracle, untuned, on a sample of entries of the same matrix."""
+    """The oracle, untuned, on a sample of entries of the same matrix: a short
+    calibration run, then a sample sized to take about `seconds`."""
     import numpy as np
 
     import oracle
-    from paper_1901_04162_amd import meshes
 
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = 2000
-    rows, cols = meshes.entry_sample(edges.shape[0], n, 101)
-    t0 = time.perf_counter()
-    oracle.fill_entries(V, F, edges, k, Q, rows, cols)
-    dt = time.perf_counter() - t0
-    n2 = int(min(5_000_000, max(n, n * seconds / max(dt, 1e-6))))
-    rows, cols = meshes.entry_sample(edges.shape[0], n2, 102)
-    t0 = time.perf_counter()
-    oracle.fill_entries(V, F, edges, k, Q, rows, cols)
-    dt = time.perf_counter() - t0
+    E = edges.shape[0]
+    rng = np.random.default_rng(101)
+
+    def run(n):
+        rows = rng.integers(0, E, n, dtype=np.int64)
+        cols = rng.integers(0, E, n, dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.fill_entries(V, F, edges, k, Q, rows, cols)
+        return time.perf_counter() - t0
+
+    n = 100_000
+    dt = run(n)
+    n2 = int(min(200_000_000, max(n, n * seconds / max(dt, 1e-6))))
+    dt = run(n2)
     return {
         "value": n2 / dt,
         "unit": "Z entries/s",
-        "cores": cores,
+        "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"{n2} entries drawn uniformly from the same {edges.shape[0]}^2 matrix, "
-                  f"FP64 direct exp, one entry at a time ({dt:.1f} s)",
+        "sample": f"{n2} entries drawn uniformly with replacement from the same {E}x{E} matrix "
+                  f"(seed 101), FP64 direct exp, one entry at a time (4 triangle pairs x "
+                  f"{Q * Q} point pairs each), {dt:.1f} s",
         "green_evals_per_s": n2 * 4 * Q * Q / dt,
     }
+
+
+def adjoint_timing(mf, steps):
+    """dL/dV and dL/dk of L = Re sum conj(W) Z on the 7,680-unknown jittered
+    sphere (k = 10, 6-point rule, W complex64 N(0,1))."""
+    import torch
+
+    from paper_1901_04162_amd import meshes
+
+    wl = meshes.workload("ico4_grad")
+    V, F, k, Q = wl["V"], wl["F"], wl["k"], wl["Q"]
+    m = mf.Mesh(F, V.shape[0])
+    E = m.n_edges
+    g = torch.Generator(device="cuda").manual_seed(6)
+    W = torch.complex(torch.randn(E, E, device="cuda", generator=g),
+                      torch.randn(E, E, device="cuda", generator=g))
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    lo, hi = mf.r_range(m, Vd, Q)
+    T = mf.build_tables(k, lo, hi, 1e-5)
+    out = {"workload": f"icosphere 4 subdivisions, N(0, 0.01^2) vertex jitter ({F.shape[0]} "
+                       f"triangles, {E} unknowns), k={k}, {Q}-point rule, W complex64"}
+    for mode in ("table", "direct"):
+        for _ in range(2):
+            mf.fill_Z_backward(m, Vd, k, Q, mode, T, W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mf.fill_Z_backward(m, Vd, k, Q, mode, T, W)
+        torch.cuda.synchronize()
+        out[f"{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mf.fill_Z(m, Vd, k, Q, "table", T)
+    torch.cuda.synchronize()
+    out["forward_table_ms"] = (time.perf_counter() - t0) / steps * 1e3
+    return out
 
 
 def main():
@@ -91,10 +134,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB buffer three times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the fill shards by row blocks across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(the fill would shard by row blocks of test edges, one block per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -104,13 +150,22 @@ def main():
     from paper_1901_04162_amd import meshes
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 4, "copies": 3}), flush=True)
+        return
     V, F = meshes.icosphere(args.subdiv)
     k, Q = args.k, args.q
     mesh = mf.Mesh(F, V.shape[0])
     E = mesh.n_edges
     T_ = F.shape[0]
     n_touch = mesh.n_touching()
-    evals = (T_ * T_ - n_touch) * Q * Q  # regular quadrature-point pairs
+    evals = (T_ * T_ - n_touch) * Q * Q  # regular quadrature-point pairs, ordered (metric)
+    evals_alg = evals // 2  # Z = Z^T: each unordered regular pair is needed once
     Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
     Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
     log(f"workload: icosphere s={args.subdiv} T={T_} E={E} k={k} Q={Q} tol={args.tol}; "
@@ -190,7 +245,7 @@ def main():
         out["table_over_direct"] = s_direct / s_table
         out["table_over_direct_fill_only"] = float(ph_direct[:, 2].mean() / ph_table[:, 2].mean())
     fill_s = float(ph_table[:, 2].mean()) * 1e-3
-    achieved = FLOPS_PER_EVAL * evals / fill_s / 1e12
+    achieved = FLOPS_PER_EVAL * evals_alg / fill_s / 1e12
     traffic = _traffic()
     out["roofline"] = {
         "bound": "alu",
@@ -200,8 +255,12 @@ def main():
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32,
         "traffic": traffic,
-        "flops_per_launch": FLOPS_PER_EVAL * evals,
+        "flops_per_launch": FLOPS_PER_EVAL * evals_alg,
+        "launch_ms": fill_s * 1e3,
     }
+    if not args.no_adjoint:
+        log("adjoint ...")
+        out["adjoint"] = adjoint_timing(mf, args.steps)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(V, F, mesh.edges(), k, Q, args.cpu_seconds)

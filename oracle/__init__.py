@@ -73,8 +73,14 @@ def lib():
                               dp, dp, dp]
         L.or_loss_local.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
                                     dp, dp, dp, C.c_int, dp]
+        L.or_max_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops run on."""
+    return int(lib().or_max_threads())
 
 
 class OracleError(RuntimeError):

@@ -27,6 +27,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -972,4 +975,13 @@ int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
                   const double *W, int v, double *L) {
   if (v < 0 || v >= nv) return -1;
   return loss_impl(nv, V, nt, tri, ne, edges, k, nq, bary, w, W, v, L);
+}
+
+/* Threads the OpenMP loops of this library use (1 without OpenMP). */
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

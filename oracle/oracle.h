@@ -110,6 +110,9 @@ int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
                   const int32_t *edges, double k, int nq, const double *bary, const double *w,
                   const double *W, int v, double *L);
 
+/* Number of threads the OpenMP loops use. */
+int or_max_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

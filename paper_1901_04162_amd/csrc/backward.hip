@@ -23,8 +23,8 @@
 //
 // Touching pairs (FP64): their blocks are smooth in the vertices of the pair
 // (the pair keeps its shared vertices), so each ordered pair's share of L is
-// differentiated by central differences with one Richardson step, moving
-// each of the pair's distinct vertices in both triangles at once.
+// differentiated by central differences, moving each of the pair's distinct
+// vertices in both triangles at once.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -369,51 +369,68 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
 
 // ---- touching pairs -------------------------------------------------------
 
+// Share of L carried by the ordered touching pair (p,q):
+//   Re[c sum_ab conj(W_ab) s_a s_b l_a l_b (X(p,q)[a][b] + X(q,p)[b][a]) / 2],
+// contracted term by term so no 3x3 block is held.
 template <typename ZT>
 __device__ double touching_share(const double xp[3][3], const double xq[3][3], const RuleArg &R,
                                  double k, const int *ep, const int *eq, const signed char *sp,
                                  const signed char *sq, const ZT *W, long long ldz) {
-  double x1r[9], x1i[9], x2r[9], x2i[9];
-  oneway_block(xp, xq, R, k, 0, x1r, x1i);
-  oneway_block(xq, xp, R, k, 0, x2r, x2i);
-  double sr = 0.0, si = 0.0;
+  double Or[9], Oi[9];  // conj(W_ab) s_a s_b l_a l_b
   for (int a = 0; a < 3; ++a) {
-    if (ep[a] < 0) continue;
     const double *u = xp[(a + 1) % 3], *v = xp[(a + 2) % 3];
     const double la = sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
                            (u[2] - v[2]) * (u[2] - v[2]));
     for (int b = 0; b < 3; ++b) {
-      if (eq[b] < 0) continue;
       const double *s = xq[(b + 1) % 3], *t = xq[(b + 2) % 3];
       const double lb = sqrt((s[0] - t[0]) * (s[0] - t[0]) + (s[1] - t[1]) * (s[1] - t[1]) +
                              (s[2] - t[2]) * (s[2] - t[2]));
-      const ZT w = W[(size_t)ep[a] * ldz + eq[b]];
-      const double xr = 0.5 * (x1r[3 * a + b] + x2r[3 * b + a]);
-      const double xi = 0.5 * (x1i[3 * a + b] + x2i[3 * b + a]);
+      double wr = 0.0, wi = 0.0;
+      if (ep[a] >= 0 && eq[b] >= 0) {
+        const ZT w = W[(size_t)ep[a] * ldz + eq[b]];
+        wr = (double)w.x;
+        wi = (double)w.y;
+      }
       const double f = (double)sp[a] * (double)sq[b] * la * lb;
-      // conj(w) * X
-      sr += f * ((double)w.x * xr + (double)w.y * xi);
-      si += f * ((double)w.x * xi - (double)w.y * xr);
+      Or[3 * a + b] = f * wr;
+      Oi[3 * a + b] = -f * wi;
     }
   }
+  double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+  const double A1 = oneway_terms(xp, xq, R, k, 0, [&](int a, int b, double re, double im) {
+    s1r += Or[3 * a + b] * re - Oi[3 * a + b] * im;
+    s1i += Or[3 * a + b] * im + Oi[3 * a + b] * re;
+  });
+  const double A2 = oneway_terms(xq, xp, R, k, 0, [&](int b, int a, double re, double im) {
+    s2r += Or[3 * a + b] * re - Oi[3 * a + b] * im;
+    s2i += Or[3 * a + b] * im + Oi[3 * a + b] * re;
+  });
+  const double si = 0.5 * (s1i / A1 + s2i / A2);
   // Re[j k eta/(4 pi) (sr + j si)]
   return -k * kEta0 / (4.0 * M_PI) * si;
 }
 
+// One thread per (ordered touching pair, coordinate): coordinates 0..17 are
+// x/y/z of the pair's distinct vertices (p's three, then q's others), 18 is
+// k.  Plain central differences with a step of 1e-5 of the pair's longest
+// edge (or of k): the truncation error is about 1e-10 relative and the
+// rounding error about 1e-11.
+constexpr int kTouchCoords = 19;
+
 template <typename ZT>
-__global__ void k_bwd_touching(const double *__restrict__ V, const int32_t *__restrict__ tri,
-                               const int32_t *__restrict__ tp, const int32_t *__restrict__ tq,
-                               const int32_t *__restrict__ tedge,
-                               const signed char *__restrict__ tsign, int64_t npair, RuleArg R,
-                               double k, const ZT *__restrict__ W, long long ldz,
-                               double *__restrict__ dV, double *__restrict__ dk) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_bwd_touching(
+    const double *__restrict__ V, const int32_t *__restrict__ tri, const int32_t *__restrict__ tp,
+    const int32_t *__restrict__ tq, const int32_t *__restrict__ tedge,
+    const signed char *__restrict__ tsign, int64_t npair, RuleArg R, double k,
+    const ZT *__restrict__ W, long long ldz, double *__restrict__ dV, double *__restrict__ dk) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= npair) return;
-  const int p = tp[s], q = tq[s];
+  if (s >= npair * kTouchCoords) return;
+  const int64_t pair = s / kTouchCoords;
+  const int coord = (int)(s % kTouchCoords);
+  const int p = tp[pair], q = tq[pair];
   int vp[3], vq[3], ep[3], eq[3];
   signed char sp[3], sq[3];
   double xp[3][3], xq[3][3];
-  double scale = 0.0;
   for (int a = 0; a < 3; ++a) {
     vp[a] = tri[3 * p + a];
     vq[a] = tri[3 * q + a];
@@ -426,52 +443,47 @@ __global__ void k_bwd_touching(const double *__restrict__ V, const int32_t *__re
       xq[a][c] = V[3 * (size_t)vq[a] + c];
     }
   }
-  for (int a = 0; a < 3; ++a) {
-    const double *u = xp[(a + 1) % 3], *v = xp[(a + 2) % 3];
-    scale = fmax(scale, sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
-                             (u[2] - v[2]) * (u[2] - v[2])));
+  if (coord == kTouchCoords - 1) {
+    const double h = 1e-5 * k;
+    const double d = (touching_share(xp, xq, R, k + h, ep, eq, sp, sq, W, ldz) -
+                      touching_share(xp, xq, R, k - h, ep, eq, sp, sq, W, ldz)) /
+                     (2.0 * h);
+    atomicAdd(dk, d);
+    return;
   }
-  // distinct vertices of the pair
-  int vid[6], nvid = 0;
-  for (int a = 0; a < 3; ++a) vid[nvid++] = vp[a];
+  // the t-th distinct vertex of the pair: p's three, then q's vertices not in p
+  const int t = coord / 3, c = coord % 3;
+  int v = -1, nvid = 3;
+  for (int a = 0; a < 3; ++a)
+    if (t == a) v = vp[a];
   for (int a = 0; a < 3; ++a) {
-    bool seen = false;
-    for (int b = 0; b < 3; ++b) seen |= vq[a] == vp[b];
-    if (!seen) vid[nvid++] = vq[a];
-  }
-  const double h0 = 1e-4 * scale;
-  for (int t = 0; t < nvid; ++t)
-    for (int c = 0; c < 3; ++c) {
-      double d[2];
-      for (int r = 0; r < 2; ++r) {
-        const double h = r == 0 ? h0 : 0.5 * h0;
-        double f[2];
-        for (int sgn = 0; sgn < 2; ++sgn) {
-          double yp[3][3], yq[3][3];
-          for (int a = 0; a < 3; ++a)
-            for (int e = 0; e < 3; ++e) {
-              yp[a][e] = xp[a][e];
-              yq[a][e] = xq[a][e];
-            }
-          const double dh = sgn == 0 ? h : -h;
-          for (int a = 0; a < 3; ++a) {
-            if (vp[a] == vid[t]) yp[a][c] += dh;
-            if (vq[a] == vid[t]) yq[a][c] += dh;
-          }
-          f[sgn] = touching_share(yp, yq, R, k, ep, eq, sp, sq, W, ldz);
-        }
-        d[r] = (f[0] - f[1]) / (2.0 * h);
-      }
-      atomicAdd(&dV[3 * (size_t)vid[t] + c], (4.0 * d[1] - d[0]) / 3.0);
+    const bool seen = vq[a] == vp[0] || vq[a] == vp[1] || vq[a] == vp[2];
+    if (!seen) {
+      if (t == nvid) v = vq[a];
+      ++nvid;
     }
-  double d[2];
-  for (int r = 0; r < 2; ++r) {
-    const double h = (r == 0 ? 1e-4 : 0.5e-4) * k;
-    d[r] = (touching_share(xp, xq, R, k + h, ep, eq, sp, sq, W, ldz) -
-            touching_share(xp, xq, R, k - h, ep, eq, sp, sq, W, ldz)) /
-           (2.0 * h);
   }
-  atomicAdd(dk, (4.0 * d[1] - d[0]) / 3.0);
+  if (v < 0) return;
+  double scale = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double *e0 = xp[(a + 1) % 3], *e1 = xp[(a + 2) % 3];
+    scale = fmax(scale, sqrt((e0[0] - e1[0]) * (e0[0] - e1[0]) + (e0[1] - e1[1]) * (e0[1] - e1[1]) +
+                             (e0[2] - e1[2]) * (e0[2] - e1[2])));
+  }
+  const double h = 1e-5 * scale;
+  double f[2];
+#pragma unroll 1
+  for (int sgn = 0; sgn < 2; ++sgn) {
+    // move vertex v by +h, then by -h (from the +h position)
+    const double dh = sgn == 0 ? h : -2.0 * h;
+    for (int a = 0; a < 3; ++a)
+      for (int e = 0; e < 3; ++e) {
+        if (vp[a] == v && e == c) xp[a][e] += dh;
+        if (vq[a] == v && e == c) xq[a][e] += dh;
+      }
+    f[sgn] = touching_share(xp, xq, R, k, ep, eq, sp, sq, W, ldz);
+  }
+  atomicAdd(&dV[3 * (size_t)v + c], (f[0] - f[1]) / (2.0 * h));
 }
 
 __global__ void k_zero(double *p, int64_t n) {
@@ -520,7 +532,8 @@ static int launch_bwd_touch(mf_mesh *m, const double *V, const Rule &r, double k
   const int64_t np = (int64_t)m->touch_q.size();
   if (np == 0) return MF_OK;
   RuleArg R = rule_arg(r);
-  hipLaunchKernelGGL(k_bwd_touching<ZT>, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, V,
+  const int64_t nthreads = np * kTouchCoords;
+  hipLaunchKernelGGL(k_bwd_touching<ZT>, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, s, V,
                      m->d_tri, m->d_touch_p, m->d_touch_q, m->d_tedge,
                      reinterpret_cast<const signed char *>(m->d_tsign), np, R, k,
                      reinterpret_cast<const ZT *>(W), (long long)ldz, dV, dk);

@@ -95,19 +95,17 @@ __device__ inline void ghat(double k, double R, double &re, double &im) {
 //   Phi = S_q + A_q sum_j w_j ghat(R_ij),
 //   Psi_b = V_q + (r_i - v_b) S_q + A_q sum_j w_j (r_j - v_b) ghat(R_ij).
 // Quadrature points are b0 x0 + b1 x1 + b2 x2 as in the rest of the path.
-__device__ inline void oneway_block(const double xp[3][3], const double xq[3][3], const RuleArg &R,
-                                    double k, int part, double *accr, double *acci) {
+// oneway_terms hands every term w_i [...] of the sum to sink(a, b, re, im)
+// and returns A_q; the caller applies the 1/A_q.
+template <class Sink>
+__device__ inline double oneway_terms(const double xp[3][3], const double xq[3][3],
+                                      const RuleArg &R, double k, int part, Sink &&sink) {
   const double e1[3] = {xq[1][0] - xq[0][0], xq[1][1] - xq[0][1], xq[1][2] - xq[0][2]};
   const double e2[3] = {xq[2][0] - xq[0][0], xq[2][1] - xq[0][1], xq[2][2] - xq[0][2]};
   const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
                cz = e1[0] * e2[1] - e1[1] * e2[0];
   const double Aq = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
-  for (int i = 0; i < 9; ++i) accr[i] = acci[i] = 0.0;
   const double ik2 = 1.0 / (k * k);
-  double rq[kMaxQ][3];
-  for (int j = 0; j < R.nq; ++j)
-    for (int c = 0; c < 3; ++c)
-      rq[j][c] = R.b[j][0] * xq[0][c] + R.b[j][1] * xq[1][c] + R.b[j][2] * xq[2][c];
   for (int i = 0; i < R.nq; ++i) {
     double ri[3];
     for (int c = 0; c < 3; ++c)
@@ -117,15 +115,18 @@ __device__ inline void oneway_block(const double xp[3][3], const double xq[3][3]
     double m1r[3] = {0, 0, 0}, m1i[3] = {0, 0, 0};  // Aq sum_j w_j r_j ghat
     double g0r = 0.0, g0i = 0.0;                    // Aq sum_j w_j ghat
     for (int j = 0; j < R.nq; ++j) {
-      const double d0 = ri[0] - rq[j][0], d1 = ri[1] - rq[j][1], d2 = ri[2] - rq[j][2];
+      double rq[3];
+      for (int c = 0; c < 3; ++c)
+        rq[c] = R.b[j][0] * xq[0][c] + R.b[j][1] * xq[1][c] + R.b[j][2] * xq[2][c];
+      const double d0 = ri[0] - rq[0], d1 = ri[1] - rq[1], d2 = ri[2] - rq[2];
       double gr, gi;
       ghat(k, sqrt(d0 * d0 + d1 * d1 + d2 * d2), gr, gi);
       const double wa = Aq * R.w[j];
       g0r += wa * gr;
       g0i += wa * gi;
       for (int c = 0; c < 3; ++c) {
-        m1r[c] += wa * rq[j][c] * gr;
-        m1i[c] += wa * rq[j][c] * gi;
+        m1r[c] += wa * rq[c] * gr;
+        m1i[c] += wa * rq[c] * gi;
       }
     }
     const double phr = S + g0r, phi = g0i;
@@ -146,11 +147,21 @@ __device__ inline void oneway_block(const double xp[3][3], const double xq[3][3]
           br -= phr * ik2;
           bi -= phi * ik2;
         }
-        accr[3 * a + b] += R.w[i] * br;
-        acci[3 * a + b] += R.w[i] * bi;
+        sink(a, b, R.w[i] * br, R.w[i] * bi);
       }
     }
   }
+  return Aq;
+}
+
+// The one-way block X[a][b] of the pair (row-major, 9 complex).
+__device__ inline void oneway_block(const double xp[3][3], const double xq[3][3], const RuleArg &R,
+                                    double k, int part, double *accr, double *acci) {
+  for (int i = 0; i < 9; ++i) accr[i] = acci[i] = 0.0;
+  const double Aq = oneway_terms(xp, xq, R, k, part, [&](int a, int b, double re, double im) {
+    accr[3 * a + b] += re;
+    acci[3 * a + b] += im;
+  });
   for (int i = 0; i < 9; ++i) {
     accr[i] /= Aq;
     acci[i] /= Aq;
