@@ -53,6 +53,13 @@ class Mesh:
         check(lib().mf_mesh_n_touching(self._h, C.byref(n)))
         return n.value
 
+    def plan(self):
+        """(blocks, tiles, largest triangles per block) of the regular fill."""
+        nb, mt = C.c_int32(), C.c_int32()
+        nt = C.c_int64()
+        check(lib().mf_mesh_plan(self._h, C.byref(nb), C.byref(nt), C.byref(mt)))
+        return nb.value, nt.value, mt.value
+
     def __del__(self):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_mesh_destroy(self._h)

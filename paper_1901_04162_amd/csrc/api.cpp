@@ -349,6 +349,16 @@ int mf_mesh_n_touching(const mf_mesh *m, int64_t *n) {
   return MF_OK;
 }
 
+int mf_mesh_plan(const mf_mesh *m, int32_t *n_blocks, int64_t *n_tiles,
+                 int32_t *max_block_triangles) {
+  if (!m || !n_blocks || !n_tiles || !max_block_triangles)
+    return fail(MF_EINVAL, "mf_mesh_plan: bad argument");
+  *n_blocks = m->nblk;
+  *n_tiles = (int64_t)m->tiles.size();
+  *max_block_triangles = m->max_blk_tris;
+  return MF_OK;
+}
+
 int mf_r_range(mf_mesh *m, const double *V, int quad_order, double *rmin, double *rmax,
                hipStream_t s) {
   Rule r;
@@ -387,7 +397,7 @@ int mf_build_tables(double k, double rmin, double rmax, double tol, mf_tables **
 void mf_tables_destroy(mf_tables *t) {
   if (!t) return;
   for (mf_tables::One *o : {&t->e, &t->g}) {
-    void *ptrs[] = {o->r, o->f, o->hash, o->bucket, o->node, o->coef};
+    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
   }

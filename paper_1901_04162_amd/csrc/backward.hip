@@ -30,6 +30,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "lookup.hpp"
 #include "singular.hpp"
 
 namespace mf {
@@ -43,13 +44,10 @@ struct BwdScalars {
   float w[kMaxQ];
   float bary[kMaxQ][3];
   // Green table (cubic) and Exp table (linear), global memory
-  const int2 *gb;
-  const float *gn;
+  const int4 *gl;
   const float4 *g01, *g23;
-  const int2 *eb;
-  const float *en;
+  const int4 *el;
   const float4 *ec;
-  int gm, em;
   float ginv, gbias, gmax, einv, ebias, emax;
   long long ldz;
 };
@@ -212,23 +210,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
               float gr, gi, dgr, dgi, er;  // g, dg/dR, Re exp(-jkR)
               float ei;
               if (MODE == MF_MODE_TABLE) {
-                const float x = __builtin_amdgcn_fmed3f(fmaf(R, S.ginv, S.gbias), 0.0f, S.gmax);
-                const int2 wb = S.gb[(int)x];
-                const int ii = wb.x + (R >= __int_as_float(wb.y) ? 1 : 0);
-                const float u = R - S.gn[ii];
+                float u;
+                const int ii = look_interval(S.gl[look_bucket(R, S.ginv, S.gbias, S.gmax)], R, u);
                 const float4 A = S.g01[ii], B = S.g23[ii];
                 // g = c0 + c1 u + c2 u^2 + c3 u^3, g' = c1 + 2 c2 u + 3 c3 u^2
                 const float der = fmaf(3.0f * B.z, u, 2.0f * B.x);
                 const float dei = fmaf(3.0f * B.w, u, 2.0f * B.y);
                 dgr = fmaf(der, u, A.z);
                 dgi = fmaf(dei, u, A.w);
-                float re = fmaf(fmaf(B.z, u, B.x), u, A.z), im = fmaf(fmaf(B.w, u, B.y), u, A.w);
-                gr = fmaf(re, u, A.x);
-                gi = fmaf(im, u, A.y);
-                const float xe = __builtin_amdgcn_fmed3f(fmaf(R, S.einv, S.ebias), 0.0f, S.emax);
-                const int2 we = S.eb[(int)xe];
-                const int ie = we.x + (R >= __int_as_float(we.y) ? 1 : 0);
-                const float ue = R - S.en[ie];
+                const float2 g = cubic(A, B, u);
+                gr = g.x;
+                gi = g.y;
+                float ue;
+                const int ie = look_interval(S.el[look_bucket(R, S.einv, S.ebias, S.emax)], R, ue);
                 const float4 Ec = S.ec[ie];
                 er = fmaf(Ec.z, ue, Ec.x);
                 ei = fmaf(Ec.w, ue, Ec.y);
@@ -560,21 +554,17 @@ int launch_backward(mf_mesh *m, const double *V, const Rule &r, double k, int mo
   S.ldz = ldz;
   if (mode == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g, &e = tab->e;
-    S.gb = g.bucket;
-    S.gn = g.node;
+    S.gl = g.look;
     S.g01 = g.coef;
     S.g23 = g.coef + (g.n - 1);
-    S.gm = g.m;
-    S.ginv = (float)(1.0 / g.delta);
-    S.gbias = (float)(-tab->rmin / g.delta);
-    S.gmax = (float)(g.m - 1);
-    S.eb = e.bucket;
-    S.en = e.node;
+    S.ginv = g.binv;
+    S.gbias = g.bbias;
+    S.gmax = g.btop;
+    S.el = e.look;
     S.ec = e.coef;
-    S.em = e.m;
-    S.einv = (float)(1.0 / e.delta);
-    S.ebias = (float)(-tab->rmin / e.delta);
-    S.emax = (float)(e.m - 1);
+    S.einv = e.binv;
+    S.ebias = e.bbias;
+    S.emax = e.btop;
   }
   int rc = z_dtype == MF_C64 ? launch_bwd_z<float2>(m, r, mode, S, W, dV, dk, s)
                              : launch_bwd_z<double2>(m, r, mode, S, W, dV, dk, s);

@@ -32,6 +32,7 @@
 #include <cstdlib>
 
 #include "internal.hpp"
+#include "lookup.hpp"
 
 namespace mf {
 
@@ -51,15 +52,14 @@ struct FillScalars {
   float pref;  // k eta0 / (4 pi)
   float w[kMaxQ];
   int tn, tm;
-  float tinv, tbias, tmax;  // bucket coordinate x = r*tinv + tbias, clamp to [0, tmax]
+  float tinv, tbias, tmax;  // bucket coordinate x = r*tinv + tbias, clamped to [0, tmax]
   float lo_ok, hi_ok;
   long long ldz;
 };
 
 struct TabPtrs {
-  const int2 *bucket;   // {interval at bucket start, split position (float bits)}
-  const float *node;    // FP32 sample positions
-  const float4 *c01;    // per interval (c0, c1) about node i
+  const int4 *look;     // bucket records {i0, x(i0), s1, s2}
+  const float4 *c01;    // per interval (c0, c1) about its first sample
   const float4 *c23;    // per interval (c2, c3)
 };
 
@@ -98,14 +98,12 @@ __device__ __forceinline__ void zero(Moments &M) {
 }
 
 // Table mode.  The Q lookups of one test point go in three batches
-// (distances and bucket reads, then interval and coefficient reads, then the
-// cubic and the sums) so that the dependent LDS reads of the Q source
-// points overlap each other.  Interval search is the hash of Eq. (6): a
-// bucket holds the interval containing its start and, when a sample lies
-// inside it, that sample's position, above which the next interval applies
-// (the paper's compare-with-the-sample fix-up, resolved per bucket).  The
-// cubic of Eq. (5) is evaluated in Horner form about the interval's first
-// sample.
+// (distances and bucket-record reads, then coefficient reads, then the cubic
+// and the sums) so that the dependent LDS reads of the Q source points
+// overlap each other.  The interval search is the bucket lookup of Eq. (6)
+// in the record form of lookup.hpp (one 16-byte read gives the interval and
+// its first sample), and the cubic of Eq. (5) is evaluated in Horner form
+// about that sample.
 template <int Q>
 __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
                                               const FillScalars &S, const float (&prho)[Q][3],
@@ -117,7 +115,7 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
   for (int i = 0; i < Q; ++i) {
     const float ax = prho[i][0] + lx, ay = prho[i][1] + ly, az = prho[i][2] + lz;
     float r[Q];
-    int2 w[Q];
+    int4 w[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
@@ -126,25 +124,21 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
       r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
       rlo = fminf(rlo, r[j]);
       rhi = fmaxf(rhi, r[j]);
-      const float x = __builtin_amdgcn_fmed3f(fmaf(r[j], S.tinv, S.tbias), 0.0f, S.tmax);
-      w[j] = tab.bucket[(int)x];
+      w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
     }
     float u[Q];
     float4 A[Q], B[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const int ii = w[j].x + (r[j] >= __int_as_float(w[j].y) ? 1 : 0);
-      u[j] = r[j] - tab.node[ii];
+      const int ii = look_interval(w[j], r[j], u[j]);
       A[j] = tab.c01[ii];
       B[j] = tab.c23[ii];
     }
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      float re = fmaf(B[j].z, u[j], B[j].x), im = fmaf(B[j].w, u[j], B[j].y);
-      re = fmaf(re, u[j], A[j].z);
-      im = fmaf(im, u[j], A[j].w);
-      const float gr = fmaf(re, u[j], A[j].x), gi = fmaf(im, u[j], A[j].y);
+      const float2 g = cubic(A[j], B[j], u[j]);
+      const float gr = g.x, gi = g.y;
       t0r = fmaf(S.w[j], gr, t0r);
       t0i = fmaf(S.w[j], gi, t0i);
 #pragma unroll
@@ -203,8 +197,8 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
     const int32_t *__restrict__ blk_tri,
     const int32_t *__restrict__ blk_pos, const int32_t *__restrict__ touch_off,
     const int32_t *__restrict__ touch_q, const float *__restrict__ sing,
-    const int2 *__restrict__ g_bucket, const float *__restrict__ g_node,
-    const float4 *__restrict__ g_coef, ZT *__restrict__ Z, int *__restrict__ status) {
+    const int4 *__restrict__ g_look, const float4 *__restrict__ g_coef, ZT *__restrict__ Z,
+    int *__restrict__ status) {
   constexpr int kFillThreads = fill_threads<MODE>();
   constexpr int kWaves = kFillThreads / 64;
   extern __shared__ float4 smem4[];
@@ -212,15 +206,13 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
 
-  TabPtrs tab{g_bucket, g_node, g_coef, g_coef + (S.tn - 1)};
+  TabPtrs tab{g_look, g_coef, g_coef + (S.tn - 1)};
   if (MODE == MF_MODE_TABLE && kLDS) {
     float4 *c = smem4 + kAccFloats / 4 + 1;
-    int2 *b = reinterpret_cast<int2 *>(c + 2 * (S.tn - 1));
-    float *nd = reinterpret_cast<float *>(b + S.tm);
+    int4 *b = reinterpret_cast<int4 *>(c + 2 * (S.tn - 1));
     for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kFillThreads) c[i] = g_coef[i];
-    for (int i = threadIdx.x; i < S.tm; i += kFillThreads) b[i] = g_bucket[i];
-    for (int i = threadIdx.x; i < S.tn; i += kFillThreads) nd[i] = g_node[i];
-    tab = TabPtrs{b, nd, c, c + (S.tn - 1)};
+    for (int i = threadIdx.x; i < S.tm; i += kFillThreads) b[i] = g_look[i];
+    tab = TabPtrs{b, c, c + (S.tn - 1)};
   }
   float rlo = INFINITY, rhi = 0.0f;
 
@@ -369,8 +361,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
 struct LaunchCtx {
   FillScalars S;
   const mf_mesh *m;
-  const int2 *bucket;
-  const float *node;
+  const int4 *look;
   const float4 *coef;
   void *Z;
   size_t lds;
@@ -400,7 +391,7 @@ static int launch_t(const LaunchCtx &L, hipStream_t s) {
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kFillThreads), L.lds, s, L.S, m->d_rec,
                      m->d_tiles, m->d_blk_e0, m->d_blk_off, m->d_blk_tri, m->d_blk_pos,
                      m->d_touch_off,
-                     m->d_touch_q, m->d_sing, L.bucket, L.node, L.coef,
+                     m->d_touch_q, m->d_sing, L.look, L.coef,
                      reinterpret_cast<ZT *>(L.Z), m->d_status);
   MF_HIP(hipGetLastError());
   return MF_OK;
@@ -447,18 +438,16 @@ int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *
   bool lds_tab = false;
   if (base == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g;
-    L.bucket = g.bucket;
-    L.node = g.node;
+    L.look = g.look;
     L.coef = g.coef;
     S.tn = g.n;
-    S.tm = g.m;
-    S.tinv = (float)(1.0 / g.delta);
-    S.tbias = (float)(-tab->rmin / g.delta);
-    S.tmax = (float)(g.m - 1);
+    S.tm = g.mb;
+    S.tinv = g.binv;
+    S.tbias = g.bbias;
+    S.tmax = g.btop;
     S.lo_ok = (float)(tab->rmin * (1.0 - 1e-6));
     S.hi_ok = (float)(tab->rmax * (1.0 + 1e-6));
-    const size_t tbytes = sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int2) * (size_t)g.m +
-                          sizeof(float) * (size_t)g.n;
+    const size_t tbytes = sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int4) * (size_t)g.mb;
     int dev = 0, maxlds = 0;
     MF_HIP(hipGetDevice(&dev));
     MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

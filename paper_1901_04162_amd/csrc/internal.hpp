@@ -34,25 +34,6 @@ struct Rule {
 };
 bool make_rule(int q, Rule *r);
 
-// Device view of the FP32 Green-function table used by the fill.
-struct GreenTabView {
-  const int2 *bucket;   // M: {interval index at bucket start, split (float bits)}
-  const float *node;    // N: node positions (FP32)
-  const float4 *coef;   // 2*(N-1): Horner coefficients about node i
-  int n, m;
-  float rmin, inv_delta;
-  float lo_ok, hi_ok;   // accepted distance range (FP32 rounding slack)
-};
-
-// Device view of the FP32 linear Exp table (adjoint: dG/dk).
-struct ExpTabView {
-  const int2 *bucket;
-  const float *node;
-  const float4 *coef;   // N-1: {E_i re, E_i im, slope re, slope im}
-  int n, m;
-  float rmin, inv_delta;
-};
-
 }  // namespace mf
 
 struct mf_tables {
@@ -63,8 +44,13 @@ struct mf_tables {
     double *r = nullptr;     // FP64 nodes (device)
     double *f = nullptr;     // FP64 values, 2n (device)
     int32_t *hash = nullptr; // Eq. (6) array (device)
-    int2 *bucket = nullptr;  // FP32 lookup (device)
-    float *node = nullptr;
+    // FP32 lookup (device): mb bucket records of 16 bytes (lookup.hpp) with
+    // bucket coordinate x = r*binv + bbias clamped to [0, btop], and the
+    // interval coefficients: Green 2(n-1) records, (c0,c1) then (c2,c3)
+    // about each interval's first sample; Exp n-1 records {E_i, slope}.
+    int4 *look = nullptr;
+    int mb = 0;
+    float binv = 0.0f, bbias = 0.0f, btop = 0.0f;
     float4 *coef = nullptr;
   } e, g;
 };

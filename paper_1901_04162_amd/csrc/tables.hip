@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "lookup.hpp"
 
 namespace mf {
 
@@ -242,33 +243,50 @@ __global__ void k_probe(const double *r, const double *f, int n, int kind, doubl
 }
 
 // ---- FP32 packing --------------------------------------------------------
-// Lookup word per bucket: the interval that contains the bucket's start and,
-// if a sample lies inside the bucket, that sample's position (FP32) above
-// which the next interval applies.  This is the hash of Eq. (6) with its
-// "one interval back if the sample lies above r" fix-up resolved ahead of
-// time.
-__global__ void k_pack_buckets(const int32_t *h, const double *r, int n, int m, double rmin,
-                               double delta, int2 *bucket) {
-#pragma clang fp contract(off)
+// Bucket of every sample, by the FP32 formula of the lookup itself.
+__global__ void k_node_bucket(const double *r, int n, float inv, float bias, float top, int *nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) nb[i] = look_bucket((float)r[i], inv, bias, top);
+}
+
+// Bucket records of the FP32 lookup (layout in lookup.hpp).  The bucket's
+// samples are found by binary search over the samples' buckets; the first
+// sample (r_min) and the last (r_max) are never splits, so the interval
+// index stays in [0, n - 2].  More than two samples in a bucket sets *bad.
+__global__ void k_pack_look(const double *r, const int *nb, int n, int mb, int4 *look, int *bad) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= m) return;
-  const int i = h[b];
-  int ib = i;
-  float split = __int_as_float(0x7f800000);  // +inf
-  if (i > 0 && (int)floor((r[i] - rmin) / delta) == b) {
-    ib = i - 1;
-    if (i <= n - 2) split = (float)r[i];
+  if (b >= mb) return;
+  int lo = 0, hi = n;  // first sample whose bucket is >= b
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (nb[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
-  if (ib > n - 2) ib = n - 2;
-  bucket[b] = make_int2(ib, __float_as_int(split));
+  int i0 = lo - 1, c = lo;
+  if (i0 < 0) {
+    i0 = 0;
+    c = 1;
+  }
+  if (i0 > n - 2) i0 = n - 2;
+  const float inf = __int_as_float(0x7f800000);
+  float s1 = inf, s2 = inf;
+  if (c < n - 1 && nb[c] == b) {
+    s1 = (float)r[c];
+    if (c + 1 < n - 1 && nb[c + 1] == b) {
+      s2 = (float)r[c + 1];
+      if (c + 2 < n - 1 && nb[c + 2] == b) atomicOr(bad, 1);
+    }
+  }
+  look[b] = make_int4(i0, __float_as_int((float)r[i0]), __float_as_int(s1), __float_as_int(s2));
 }
 
 // Cubic Lagrange polynomial of interval i (stencil s..s+3) re-expanded in
 // powers of u = r - float(r_i): sum_k c_k u^k, coefficients in FP64, stored
 // as two arrays of n-1 records, (c0, c1) then (c2, c3).
-__global__ void k_pack_green(const double *r, const double *f, int n, float *node, float4 *coef) {
+__global__ void k_pack_green(const double *r, const double *f, int n, float4 *coef) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) node[i] = (float)r[i];
   if (i >= n - 1) return;
   int s = i - 1;
   if (s > n - 4) s = n - 4;
@@ -302,9 +320,8 @@ __global__ void k_pack_green(const double *r, const double *f, int n, float *nod
 }
 
 // Linear interpolant of interval i written about float(r_i).
-__global__ void k_pack_exp(const double *r, const double *f, int n, float *node, float4 *coef) {
+__global__ void k_pack_exp(const double *r, const double *f, int n, float4 *coef) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) node[i] = (float)r[i];
   if (i >= n - 1) return;
   const double h = r[i + 1] - r[i];
   const double sr = (f[2 * i + 2] - f[2 * i]) / h, si = (f[2 * i + 3] - f[2 * i + 1]) / h;
@@ -336,13 +353,12 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  void *ptrs[] = {o.r, o.f, o.hash, o.bucket, o.node, o.coef};
+  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   o.r = o.f = nullptr;
   o.hash = nullptr;
-  o.bucket = nullptr;
-  o.node = nullptr;
+  o.look = nullptr;
   o.coef = nullptr;
 }
 
@@ -429,19 +445,51 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
   return rc;
 }
 
+// Bucket width of the FP32 lookup: just under twice the smallest sample
+// interval, so that FP32 rounding of the bucket coordinate can never put
+// three samples in one bucket.
+constexpr double kBucketWidth = 1.99;
+
 static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
-  MF_HIP(hipMalloc((void **)&o.bucket, sizeof(int2) * o.m));
-  MF_HIP(hipMalloc((void **)&o.node, sizeof(float) * o.n));
+  const double bw = kBucketWidth * o.delta;
+  o.mb = (int)std::floor((T->rmax - T->rmin) / bw) + 1;
+  o.binv = (float)(1.0 / bw);
+  o.bbias = (float)(-T->rmin / bw);
+  o.btop = (float)(o.mb - 1);
+  MF_HIP(hipMalloc((void **)&o.look, sizeof(int4) * o.mb));
   MF_HIP(hipMalloc((void **)&o.coef, sizeof(float4) * (kind == kGreen ? 2 : 1) * (o.n - 1)));
-  hipLaunchKernelGGL(k_pack_buckets, dim3(blocks(o.m, 256)), dim3(256), 0, s, o.hash, o.r, o.n,
-                     o.m, T->rmin, o.delta, o.bucket);
+  int *nb = nullptr, *bad = nullptr;
+  auto cleanup = [&]() {
+    if (nb) (void)hipFree(nb);
+    if (bad) (void)hipFree(bad);
+  };
+  hipError_t e = hipMalloc((void **)&nb, sizeof(int) * (o.n + 1));
+  if (e == hipSuccess) e = hipMalloc((void **)&bad, sizeof(int));
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "table packing buffers");
+  }
+  hipLaunchKernelGGL(k_node_bucket, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n, o.binv,
+                     o.bbias, o.btop, nb);
+  hipLaunchKernelGGL(k_pack_look, dim3(blocks(o.mb, 256)), dim3(256), 0, s, o.r, nb, o.n, o.mb,
+                     o.look, bad);
   if (kind == kGreen)
     hipLaunchKernelGGL(k_pack_green, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
-                       o.node, o.coef);
+                       o.coef);
   else
     hipLaunchKernelGGL(k_pack_exp, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
-                       o.node, o.coef);
-  MF_HIP(hipGetLastError());
+                       o.coef);
+  int hbad = 0;
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(e, "table packing");
+  if (hbad) {
+    set_error("mf_build_tables: a lookup bucket holds more than two samples");
+    return MF_EINVAL;
+  }
   return MF_OK;
 }
 
@@ -472,39 +520,9 @@ int build_tables_device(mf_tables *T, double tol, hipStream_t s) {
 
 // ---- FP32 evaluation (the lookup and polynomial the fill uses) ------------
 
-__device__ inline float2 green_lookup(const int2 *__restrict__ bucket,
-                                      const float *__restrict__ node,
-                                      const float4 *__restrict__ coef, int n, int m, float rmin,
-                                      float inv_delta, float r) {
-  int b = (int)((r - rmin) * inv_delta);
-  b = min(max(b, 0), m - 1);
-  const int2 w = bucket[b];
-  const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
-  const float u = r - node[i];
-  const float4 c01 = coef[i], c23 = coef[(n - 1) + i];
-  float re = fmaf(c23.z, u, c23.x), im = fmaf(c23.w, u, c23.y);
-  re = fmaf(re, u, c01.z);
-  im = fmaf(im, u, c01.w);
-  re = fmaf(re, u, c01.x);
-  im = fmaf(im, u, c01.y);
-  return make_float2(re, im);
-}
-
-__device__ inline float2 exp_lookup(const int2 *__restrict__ bucket, const float *__restrict__ node,
-                                    const float4 *__restrict__ coef, int m, float rmin,
-                                    float inv_delta, float r) {
-  int b = (int)((r - rmin) * inv_delta);
-  b = min(max(b, 0), m - 1);
-  const int2 w = bucket[b];
-  const int i = w.x + (r >= __int_as_float(w.y) ? 1 : 0);
-  const float u = r - node[i];
-  const float4 c = coef[i];
-  return make_float2(fmaf(c.z, u, c.x), fmaf(c.w, u, c.y));
-}
-
-__global__ void k_table_eval(const int2 *bucket, const float *node, const float4 *coef, int tn,
-                             int m, float rmin, float inv_delta, double lo, double hi, int kind,
-                             int64_t n, const double *r, double *out) {
+__global__ void k_table_eval(const int4 *look, const float4 *coef, int tn, float binv,
+                             float bbias, float btop, double lo, double hi, int kind, int64_t n,
+                             const double *r, double *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double x = r[i];
@@ -512,8 +530,16 @@ __global__ void k_table_eval(const int2 *bucket, const float *node, const float4
     out[2 * i] = out[2 * i + 1] = __longlong_as_double(0x7ff8000000000000ll);
     return;
   }
-  const float2 v = kind == kGreen ? green_lookup(bucket, node, coef, tn, m, rmin, inv_delta, (float)x)
-                                  : exp_lookup(bucket, node, coef, m, rmin, inv_delta, (float)x);
+  const float rf = (float)x;
+  float u;
+  const int ii = look_interval(look[look_bucket(rf, binv, bbias, btop)], rf, u);
+  float2 v;
+  if (kind == kGreen) {
+    v = cubic(coef[ii], coef[(tn - 1) + ii], u);
+  } else {
+    const float4 c = coef[ii];
+    v = make_float2(fmaf(c.z, u, c.x), fmaf(c.w, u, c.y));
+  }
   out[2 * i] = v.x;
   out[2 * i + 1] = v.y;
 }
@@ -521,9 +547,9 @@ __global__ void k_table_eval(const int2 *bucket, const float *node, const float4
 int launch_table_eval(const mf_tables *T, int which, int64_t n, const double *r, double *out,
                       hipStream_t s) {
   const mf_tables::One &o = which == 0 ? T->e : T->g;
-  hipLaunchKernelGGL(k_table_eval, dim3(blocks(n, 256)), dim3(256), 0, s, o.bucket, o.node,
-                     o.coef, o.n, o.m, (float)T->rmin, (float)(1.0 / o.delta), T->rmin, T->rmax,
-                     which == 0 ? kExp : kGreen, n, r, out);
+  hipLaunchKernelGGL(k_table_eval, dim3(blocks(n, 256)), dim3(256), 0, s, o.look, o.coef, o.n,
+                     o.binv, o.bbias, o.btop, T->rmin, T->rmax, which == 0 ? kExp : kGreen, n,
+                     r, out);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

@@ -84,7 +84,8 @@ def test_table_fp32_evaluation(mf, orc, k, rmin, rmax, tol):
         want = ref(rf[ok])
         err = np.abs(v[ok] - want) / np.abs(want)
         say(which, "max rel", err.max(), "median", np.median(err))
-        assert err.max() < 2e-6 and np.median(err) < 2e-7
+        # FP32 coefficients (2^-24 each) and four FP32 Horner steps: a few 2^-24
+        assert err.max() < 5e-7 and np.median(err) < 1e-7
     # outside the range: NaN, never a clamped value
     v = T.eval("green", torch.tensor([rmin * 0.5, rmax * 2.0])).cpu().numpy()
     assert np.all(np.isnan(v))

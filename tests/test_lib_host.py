@@ -93,3 +93,15 @@ def test_argument_errors_without_gpu():
     assert L.mf_fill_Z(m.handle, z, 1.0, 3, 7, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
     assert L.mf_fill_Z(m.handle, z, 1.0, 3, 1 | 0x30, None, z, 0, m.n_edges, None) == mf._lib.MF_EINVAL
     assert b"ldz" in L.mf_last_error() or L.mf_last_error()
+
+
+@pytest.mark.parametrize("s", [2, 4])
+def test_tile_plan_shape(s):
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.icosphere(s)
+    m = mf.Mesh(F, V.shape[0])
+    nb, nt, mt = m.plan()
+    assert nt == nb * (nb + 1) // 2
+    assert 1 <= mt <= 64
+    assert nb * 88 >= m.n_edges
