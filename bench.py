@@ -122,6 +122,69 @@ def adjoint_timing(mf, steps):
     return out
 
 
+def sweep_timing(mf, steps, group=8, tol=1e-5):
+    """Frequency sweep: three jittered icospheres (1,920 / 7,680 / 30,720
+    unknowns) x 32 wavenumbers in [4, 20], 6-point rule, per-(mesh, k)
+    tables.  The 96 items run as 4 batched launches of 3 meshes x 8
+    wavenumbers, captured together in one CUDA graph; the groups share one
+    set of complex64 outputs (64 GB), as a consumer would reuse them."""
+    import torch
+
+    from paper_1901_04162_amd import meshes
+
+    wl = meshes.workload("sweep")
+    Q, ks = wl["Q"], wl["k"]
+    mesh_data = []
+    for V, F in wl["meshes"]:
+        m = mf.Mesh(F, V.shape[0])
+        Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+        lo, hi = mf.r_range(m, Vd, Q)
+        Zs = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device="cuda")
+              for _ in range(group)]
+        mesh_data.append((m, Vd, lo, hi, Zs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tables = {(i, j): mf.build_tables(float(k), md[2], md[3], tol)
+              for i, md in enumerate(mesh_data) for j, k in enumerate(ks)}
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t0
+    batches = []
+    for g0 in range(0, len(ks), group):
+        items = [(md[0], md[1], float(ks[j]), tables[(i, j)], md[4][j - g0])
+                 for i, md in enumerate(mesh_data) for j in range(g0, min(g0 + group, len(ks)))]
+        batches.append(mf.Batch(items, Q, "table"))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for b in batches:
+            b.fill()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for b in batches:
+            b.fill()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for md in mesh_data:
+        mf.sync_status(md[0])
+    entries = sum(md[0].n_edges ** 2 for md in mesh_data) * len(ks)
+    return {
+        "workload": "3 jittered icospheres (1280/5120/20480 triangles) x 32 k in [4, 20] rad/m, "
+                    "6-point rule, table tol 1e-5, complex64; 4 launches of 24 items in one graph",
+        "items": len(mesh_data) * len(ks),
+        "ms_per_sweep": dt * 1e3,
+        "z_entries_per_s": entries / dt,
+        "table_build_ms_per_sweep": t_tables * 1e3,
+        "z_entries_per_s_with_tables": entries / (dt + t_tables),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -258,9 +322,16 @@ def main():
         "flops_per_launch": FLOPS_PER_EVAL * evals_alg,
         "launch_ms": fill_s * 1e3,
     }
+    del Z
+    torch.cuda.empty_cache()
     if not args.no_adjoint:
         log("adjoint ...")
         out["adjoint"] = adjoint_timing(mf, args.steps)
+        torch.cuda.empty_cache()
+    if not args.no_sweep:
+        log("sweep ...")
+        out["sweep"] = sweep_timing(mf, max(1, min(args.steps, 3)))
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(V, F, mesh.edges(), k, Q, args.cpu_seconds)

@@ -148,6 +148,27 @@ int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_orde
               const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
               hipStream_t stream);
 
+/* ---- batched fill (frequency sweeps, several meshes) --------------------
+ * One persistent fill launch over n items, item i being (meshes[i],
+ * vertices_dev[i], k[i], tables[i], Z_dev[i] with leading dimension
+ * ldz[i]): the workgroups walk one tile list spanning every item, so items
+ * of uneven size share the GPU without a tail per item.  All items share
+ * quad_order, mode and z_dtype; items that share a mesh handle must share
+ * its vertex pointer (one geometry pass per mesh).  mf_batch_create checks
+ * the items as mf_fill_Z does, allocates the per-item touching-pair blocks
+ * and copies the item list to the device (synchronous); the meshes, tables,
+ * vertices and outputs must outlive the batch.  MF_EINVAL for n < 1, a
+ * NULL array or any item mf_fill_Z would reject. */
+typedef struct mf_batch mf_batch;
+int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *vertices_dev,
+                    const double *k, const mf_tables *const *tables, int quad_order, int mode,
+                    void *const *Z_dev, int z_dtype, const int64_t *ldz, mf_batch **out);
+/* Enqueues the batch on `stream`: geometry once per distinct mesh, the
+ * touching-pair blocks of every item, then the single fill launch.  It
+ * allocates nothing and copies nothing, so a HIP graph can capture it. */
+int mf_batch_fill(mf_batch *batch, hipStream_t stream);
+void mf_batch_destroy(mf_batch *batch);
+
 /* ---- adjoint ------------------------------------------------------------
  * Gradient of L = Re sum_mn conj(W_mn) Z_mn, W = dLdZ_dev (same dtype and
  * layout as Z), with respect to the vertex coordinates (dL_dvertices_dev,

@@ -151,6 +151,58 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     return out
 
 
+class Batch:
+    """One persistent fill launch over several (mesh, k) items.
+
+    items: sequence of (mesh, V, k, tables, Z), Z a row-major complex tensor
+    of at least E x E on the current device.  All items share quad_order,
+    mode and the dtype of Z; items sharing a mesh must share V (the same
+    device tensor).  The tensors must stay alive while the batch exists.
+    fill() only enqueues kernels (no allocation, no copy), so it can be
+    captured in a CUDA graph.
+    """
+
+    def __init__(self, items, quad_order: int, mode: str = "table"):
+        items = list(items)
+        n = len(items)
+        if n < 1:
+            raise ValueError("empty batch")
+        self._keep = []
+        zt = None
+        meshes, vps, ks, tps, zps, lds = [], [], [], [], [], []
+        for mesh, V, k, tables, Z in items:
+            Vd = _vertices(V)  # the library checks that a shared mesh has one V
+            if Z.dtype not in (torch.complex64, torch.complex128) or Z.dim() != 2 or \
+                    Z.stride(1) != 1 or Z.shape[0] < mesh.n_edges or Z.shape[1] < mesh.n_edges:
+                raise ValueError("each Z must be a row-major complex matrix of at least E x E")
+            t = MF_C64 if Z.dtype == torch.complex64 else MF_C128
+            if zt is not None and t != zt:
+                raise ValueError("all outputs of a batch share one dtype")
+            zt = t
+            meshes.append(mesh.handle.value)
+            vps.append(Vd.data_ptr())
+            ks.append(float(k))
+            tps.append(tables.handle.value if tables is not None else None)
+            zps.append(Z.data_ptr())
+            lds.append(Z.stride(0))
+            self._keep += [mesh, Vd, tables, Z]
+        arr = C.c_void_p * n
+        self._h = C.c_void_p()
+        check(lib().mf_batch_create(n, arr(*meshes), arr(*vps), (C.c_double * n)(*ks),
+                                    arr(*tps) if mode == "table" else None, int(quad_order),
+                                    MODES[mode], arr(*zps), zt, (C.c_int64 * n)(*lds),
+                                    C.byref(self._h)))
+        self.n = n
+
+    def fill(self):
+        check(lib().mf_batch_fill(self._h, _stream()))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _L._lib is not None:
+            _L._lib.mf_batch_destroy(self._h)
+            self._h = None
+
+
 def set_timing(on: bool):
     lib().mf_set_timing(1 if on else 0)
 

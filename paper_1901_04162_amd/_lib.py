@@ -23,7 +23,8 @@ EXPORTS = [
     "mf_last_error", "mf_mesh_create", "mf_mesh_destroy", "mf_mesh_n_edges", "mf_mesh_edges",
     "mf_mesh_n_touching", "mf_mesh_plan", "mf_r_range", "mf_build_tables", "mf_tables_destroy",
     "mf_tables_info", "mf_tables_get", "mf_tables_eval", "mf_fill_Z", "mf_fill_Z_backward",
-    "mf_sync_status", "mf_set_timing", "mf_mesh_timings",
+    "mf_sync_status", "mf_set_timing", "mf_mesh_timings", "mf_batch_create", "mf_batch_fill",
+    "mf_batch_destroy",
 ]
 
 
@@ -53,6 +54,13 @@ def lib():
         L.mf_mesh_n_edges.argtypes = [vp, ip]
         L.mf_mesh_edges.argtypes = [vp, ip]
         L.mf_mesh_n_touching.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.mf_batch_create.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(C.c_double), C.POINTER(vp), C.c_int, C.c_int,
+                                      C.POINTER(vp), C.c_int, C.POINTER(C.c_int64),
+                                      C.POINTER(vp)]
+        L.mf_batch_fill.argtypes = [vp, vp]
+        L.mf_batch_destroy.argtypes = [vp]
+        L.mf_batch_destroy.restype = None
         L.mf_mesh_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]
         L.mf_r_range.argtypes = [vp, vp, C.c_int, dp, dp, vp]

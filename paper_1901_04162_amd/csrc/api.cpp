@@ -294,6 +294,16 @@ static int ensure_device(mf_mesh *m) {
 
 }  // namespace mf
 
+struct mf_batch {
+  mf::Rule r;
+  int part = 0;
+  std::vector<mf_mesh *> mesh;
+  std::vector<const double *> V;
+  std::vector<double> k;
+  std::vector<float *> sing;  // per-item touching-pair blocks (owned)
+  mf::FillLaunch *launch = nullptr;
+};
+
 using namespace mf;
 
 extern "C" {
@@ -468,6 +478,85 @@ int mf_fill_Z(mf_mesh *m, const double *V, double k, int quad_order, int mode,
   if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
   m->timed = timed;
   return MF_OK;
+}
+
+int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, const double *k,
+                    const mf_tables *const *tab, int quad_order, int mode, void *const *Z,
+                    int z_dtype, const int64_t *ldz, mf_batch **out) {
+  Rule r;
+  if (n < 1 || !meshes || !V || !k || !Z || !ldz || !out)
+    return fail(MF_EINVAL, "mf_batch_create: bad argument");
+  *out = nullptr;
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_batch_create: quad_order must be 3, 6 or 7");
+  const int base = mode & 0xf, part = mode & (MF_PART_A | MF_PART_PHI);
+  if ((base != MF_MODE_TABLE && base != MF_MODE_DIRECT) || (mode & ~0x3f) ||
+      part == (MF_PART_A | MF_PART_PHI))
+    return fail(MF_EINVAL, "mf_batch_create: unknown mode");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_batch_create: unknown z_dtype");
+  if (base == MF_MODE_TABLE && !tab)
+    return fail(MF_EINVAL, "mf_batch_create: table mode needs tables");
+  for (int i = 0; i < n; ++i) {
+    const std::string at = "mf_batch_create: item " + std::to_string(i) + ": ";
+    if (!meshes[i] || !V[i] || !Z[i]) return fail(MF_EINVAL, at + "NULL argument");
+    if (!(k[i] > 0.0) || !std::isfinite(k[i])) return fail(MF_EINVAL, at + "k must be > 0");
+    if (base == MF_MODE_TABLE && (!tab[i] || std::fabs(tab[i]->k - k[i]) > 1e-12 * k[i]))
+      return fail(MF_EINVAL, at + "tables missing or built for another k");
+    if (ldz[i] < meshes[i]->ne) return fail(MF_EINVAL, at + "ldz < number of edges");
+    for (int j = 0; j < i; ++j)
+      if (meshes[j] == meshes[i] && V[j] != V[i])
+        return fail(MF_EINVAL, at + "a mesh shared by two items needs one vertex pointer");
+  }
+  mf_batch *b = new (std::nothrow) mf_batch;
+  if (!b) return fail(MF_ENOMEM, "mf_batch_create: out of host memory");
+  b->r = r;
+  b->part = part;
+  b->mesh.assign(meshes, meshes + n);
+  b->V.assign(V, V + n);
+  b->k.assign(k, k + n);
+  int rc = MF_OK;
+  for (int i = 0; i < n && !rc; ++i) rc = ensure_device(meshes[i]);
+  b->sing.assign(n, nullptr);
+  for (int i = 0; i < n && !rc; ++i) {
+    const size_t np = std::max<size_t>(meshes[i]->touch_q.size(), 1);
+    hipError_t e = hipMalloc((void **)&b->sing[i], sizeof(float) * 18 * np);
+    if (e != hipSuccess) rc = hip_fail(e, "mf_batch_create: touching-pair blocks");
+  }
+  if (!rc) {
+    std::vector<const float *> sing(b->sing.begin(), b->sing.end());
+    rc = fill_launch_create(n, meshes, k, tab, r, mode, Z, z_dtype, ldz, sing.data(),
+                            &b->launch);
+  }
+  if (rc) {
+    mf_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return MF_OK;
+}
+
+int mf_batch_fill(mf_batch *b, hipStream_t s) {
+  if (!b) return fail(MF_EINVAL, "mf_batch_fill: batch is NULL");
+  const int n = (int)b->mesh.size();
+  int rc;
+  for (int i = 0; i < n; ++i) {
+    bool seen = false;
+    for (int j = 0; j < i; ++j) seen |= b->mesh[j] == b->mesh[i];
+    if (!seen && (rc = launch_geometry(b->mesh[i], b->V[i], b->r, s))) return rc;
+  }
+  for (int i = 0; i < n; ++i)
+    if ((rc = launch_singular(b->mesh[i], b->V[i], b->r, b->k[i], b->part, s, b->sing[i])))
+      return rc;
+  return fill_launch_run(b->launch, s);
+}
+
+void mf_batch_destroy(mf_batch *b) {
+  if (!b) return;
+  fill_launch_destroy(b->launch);
+  for (float *p : b->sing)
+    if (p) (void)hipFree(p);
+  delete b;
 }
 
 void mf_set_timing(int on) { g_timing = on != 0; }

@@ -30,6 +30,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <new>
+#include <vector>
 
 #include "internal.hpp"
 #include "lookup.hpp"
@@ -46,15 +48,31 @@ constexpr int fill_threads() {
   return MODE == MF_MODE_TABLE ? 768 : 1024;
 }
 
-struct FillScalars {
-  int ntiles, ne;
+// One fill item: a mesh, a wavenumber, its table and its output.  A launch
+// walks the global tile list of one or more items (tiles tile_begin ..
+// tile_end - 1 belong to this item).
+struct FillItem {
+  int tile_begin, tile_end;
+  int ne;
   float k, ik2;
   float pref;  // k eta0 / (4 pi)
-  float w[kMaxQ];
   int tn, tm;
   float tinv, tbias, tmax;  // bucket coordinate x = r*tinv + tbias, clamped to [0, tmax]
   float lo_ok, hi_ok;
   long long ldz;
+  const float *rec;
+  const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q;
+  const float *sing;
+  const int4 *look;
+  const float4 *coef;
+  void *Z;
+  int *status;
+};
+typedef FillItem FillScalars;
+
+// Quadrature weights, common to every item of a launch.
+struct FillRule {
+  float w[kMaxQ];
 };
 
 struct TabPtrs {
@@ -106,7 +124,8 @@ __device__ __forceinline__ void zero(Moments &M) {
 // about that sample.
 template <int Q>
 __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
-                                              const FillScalars &S, const float (&prho)[Q][3],
+                                              const FillScalars &S, const FillRule &W,
+                                              const float (&prho)[Q][3],
                                               float hx, float hy, float hz, float lx, float ly,
                                               float lz, const float *qr, float &rlo,
                                               float &rhi) {
@@ -139,8 +158,8 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
     for (int j = 0; j < Q; ++j) {
       const float2 g = cubic(A[j], B[j], u[j]);
       const float gr = g.x, gi = g.y;
-      t0r = fmaf(S.w[j], gr, t0r);
-      t0i = fmaf(S.w[j], gi, t0i);
+      t0r = fmaf(W.w[j], gr, t0r);
+      t0i = fmaf(W.w[j], gi, t0i);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float wq = qr[kRecWRho + 3 * j + c];
@@ -148,14 +167,15 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
         t1i[c] = fmaf(wq, gi, t1i[c]);
       }
     }
-    add_point(M, S.w[i], prho[i], t0r, t0i, t1r, t1i);
+    add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);
   }
 }
 
 // Direct mode: exp(-jkR)/R from rsqrt and sincos; the test-point loop stays
 // rolled (the inlined sincos is long) and reads rho_i from the record.
 template <int Q>
-__device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S, const float *pr,
+__device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S, const FillRule &W,
+                                               const float *pr,
                                                float hx, float hy, float hz, float lx, float ly,
                                                float lz, const float *qr) {
   zero(M);
@@ -176,8 +196,8 @@ __device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S,
       float sn, cs;
       sincosf(S.k * (r2 * ri), &sn, &cs);
       const float gr = cs * ri, gi = -sn * ri;
-      t0r = fmaf(S.w[j], gr, t0r);
-      t0i = fmaf(S.w[j], gi, t0i);
+      t0r = fmaf(W.w[j], gr, t0r);
+      t0i = fmaf(W.w[j], gi, t0i);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float wq = qr[kRecWRho + 3 * j + c];
@@ -185,261 +205,339 @@ __device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S,
         t1i[c] = fmaf(wq, gi, t1i[c]);
       }
     }
-    add_point(M, S.w[i], pri, t0r, t0i, t1r, t1i);
+    add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
   }
 }
 
-template <int Q, int MODE, bool kLDS, int PART, typename ZT>
-__global__ __launch_bounds__(fill_threads<MODE>())
-__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
-    FillScalars S, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+// The item's Green table: copied into LDS after the accumulator when it
+// fits, read from global memory otherwise.
+template <bool kLDS, int kThreads>
+__device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coef) {
+  if (!kLDS) return TabPtrs{S.look, S.coef, S.coef + (S.tn - 1)};
+  int4 *b = reinterpret_cast<int4 *>(lds_coef + 2 * (S.tn - 1));
+  for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kThreads) lds_coef[i] = S.coef[i];
+  for (int i = threadIdx.x; i < S.tm; i += kThreads) b[i] = S.look[i];
+  return TabPtrs{b, lds_coef, lds_coef + (S.tn - 1)};
+}
+
+// One tile of one item: accumulate it in LDS, then write it and its mirror.
+template <int Q, int MODE, int PART, typename ZT, int kFillThreads>
+// The item's arrays come in as separate __restrict__ parameters: once the
+// function is inlined they carry no-alias scopes, which lets the
+// wave-uniform source records go through scalar loads into SGPRs.
+__device__ __forceinline__ void fill_tile(
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
+    float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
     const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
-    const int32_t *__restrict__ blk_tri,
-    const int32_t *__restrict__ blk_pos, const int32_t *__restrict__ touch_off,
-    const int32_t *__restrict__ touch_q, const float *__restrict__ sing,
-    const int4 *__restrict__ g_look, const float4 *__restrict__ g_coef, ZT *__restrict__ Z,
-    int *__restrict__ status) {
-  constexpr int kFillThreads = fill_threads<MODE>();
+    const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
+    const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
+    const float *__restrict__ sing, ZT *__restrict__ Z) {
   constexpr int kWaves = kFillThreads / 64;
-  extern __shared__ float4 smem4[];
-  float *acc = reinterpret_cast<float *>(smem4);
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
+  const int tij = tiles[local];
+  const int I = tij >> 16, J = tij & 0xffff;
+  for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
+  __syncthreads();
+  const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
+  const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
+  for (int pc = 0; pc < np; pc += 64) {
+    const bool pv = pc + lane < np;
+    const int pidx = pv ? pc + lane : pc;
+    const int p = blk_tri[p0 + pidx];
+    const int prow = pv ? blk_pos[p0 + pidx] : -1;
+    const float *pr = rec + (size_t)p * kRecFloats;
+    float prho[Q][3], palpha[3][3], psig[3];
+    if (MODE == MF_MODE_TABLE) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) prho[i][c] = pr[kRecRho + 3 * i + c];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+      psig[a] = pr[kRecSigma + a];
+    }
+    const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
+    const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
+    const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
+    const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
 
-  TabPtrs tab{g_look, g_coef, g_coef + (S.tn - 1)};
-  if (MODE == MF_MODE_TABLE && kLDS) {
-    float4 *c = smem4 + kAccFloats / 4 + 1;
-    int4 *b = reinterpret_cast<int4 *>(c + 2 * (S.tn - 1));
-    for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kFillThreads) c[i] = g_coef[i];
-    for (int i = threadIdx.x; i < S.tm; i += kFillThreads) b[i] = g_look[i];
-    tab = TabPtrs{b, c, c + (S.tn - 1)};
-  }
-  float rlo = INFINITY, rhi = 0.0f;
-
-  for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
-    const int tij = tiles[tile];
-    const int I = tij >> 16, J = tij & 0xffff;
-    for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
-    __syncthreads();
-    const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
-    const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
-    for (int pc = 0; pc < np; pc += 64) {
-      const bool pv = pc + lane < np;
-      const int pidx = pv ? pc + lane : pc;
-      const int p = blk_tri[p0 + pidx];
-      const int prow = pv ? blk_pos[p0 + pidx] : -1;
-      const float *pr = rec + (size_t)p * kRecFloats;
-      float prho[Q][3], palpha[3][3], psig[3];
-      if (MODE == MF_MODE_TABLE) {
+    for (int qi = wave; qi < nq; qi += kWaves) {
+      const int q = uniform(blk_tri[q0 + qi]);
+      const int qcol = uniform(blk_pos[q0 + qi]);
+      const float *qr = rec + (size_t)q * kRecFloats;
+      const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
+      const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
+      const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
+                         pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
+      float Xr[3][3], Xi[3][3];
+      if (!touch) {
+        const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
+        const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
+        const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
+        const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                    lz = (float)(Dz - (double)hz);
+        Moments M;
+        if (MODE == MF_MODE_TABLE)
+          moments_table<Q>(M, tab, S, W, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+        else
+          moments_direct<Q>(M, S, W, pr, hx, hy, hz, lx, ly, lz, qr);
+        const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
+        const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) prho[i][c] = pr[kRecRho + 3 * i + c];
-      }
+          for (int b = 0; b < 3; ++b) {
+            float vr = 0.f, vi = 0.f;
+            if (!(PART & MF_PART_PHI)) {
+              const float *beta = qr + kRecAlpha + 3 * b;
+              const float ab = palpha[a][0] * beta[0] + palpha[a][1] * beta[1] +
+                               palpha[a][2] * beta[2];
+              vr = fmaf(ab, s0r, srr);
+              vi = fmaf(ab, s0i, sri);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
-        psig[a] = pr[kRecSigma + a];
-      }
-      const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
-      const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
-      const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
-      const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
-
-      for (int qi = wave; qi < nq; qi += kWaves) {
-        const int q = uniform(blk_tri[q0 + qi]);
-        const int qcol = uniform(blk_pos[q0 + qi]);
-        const float *qr = rec + (size_t)q * kRecFloats;
-        const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
-        const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
-        const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
-                           pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
-        float Xr[3][3], Xi[3][3];
-        if (!touch) {
-          const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
-          const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
-          const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
-          const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
-                      lz = (float)(Dz - (double)hz);
-          Moments M;
-          if (MODE == MF_MODE_TABLE)
-            moments_table<Q>(M, tab, S, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
-          else
-            moments_direct<Q>(M, S, pr, hx, hy, hz, lx, ly, lz, qr);
-          const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
-          const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              float vr = 0.f, vi = 0.f;
-              if (!(PART & MF_PART_PHI)) {
-                const float *beta = qr + kRecAlpha + 3 * b;
-                const float ab = palpha[a][0] * beta[0] + palpha[a][1] * beta[1] +
-                                 palpha[a][2] * beta[2];
-                vr = fmaf(ab, s0r, srr);
-                vi = fmaf(ab, s0i, sri);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                  vr = fmaf(palpha[a][c], sqr[c], fmaf(beta[c], spr[c], vr));
-                  vi = fmaf(palpha[a][c], sqi[c], fmaf(beta[c], spi[c], vi));
-                }
-                vr *= 0.25f;
-                vi *= 0.25f;
+              for (int c = 0; c < 3; ++c) {
+                vr = fmaf(palpha[a][c], sqr[c], fmaf(beta[c], spr[c], vr));
+                vi = fmaf(palpha[a][c], sqi[c], fmaf(beta[c], spi[c], vi));
               }
-              if (!(PART & MF_PART_A)) {
-                vr = fmaf(-S.ik2, s0r, vr);
-                vi = fmaf(-S.ik2, s0i, vi);
-              }
-              Xr[a][b] = vr;
-              Xi[a][b] = vi;
+              vr *= 0.25f;
+              vi *= 0.25f;
             }
-        } else {
-          int s = touch_off[p];
-          const int s1 = touch_off[p + 1];
-          while (s < s1 && touch_q[s] != q) ++s;
-          const bool found = s < s1;  // always: touching pairs are listed both ways
-          const float *x = sing + (size_t)(found ? s : 0) * 18;
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
-              Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
+            if (!(PART & MF_PART_A)) {
+              vr = fmaf(-S.ik2, s0r, vr);
+              vi = fmaf(-S.ik2, s0i, vi);
             }
-        }
-        if (pv) {
+            Xr[a][b] = vr;
+            Xi[a][b] = vi;
+          }
+      } else {
+        int s = touch_off[p];
+        const int s1 = touch_off[p + 1];
+        while (s < s1 && touch_q[s] != q) ++s;
+        const bool found = s < s1;  // always: touching pairs are listed both ways
+        const float *x = sing + (size_t)(found ? s : 0) * 18;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int row = (prow >> (8 * a)) & 0xff;
-            if (row == 0xff) continue;
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const int col = (qcol >> (8 * b)) & 0xff;
-              if (col == 0xff) continue;
-              const float sg = psig[a] * qr[kRecSigma + b];
-              float *dst = acc + row * kAccStride + 2 * col;
-              atomicAdd(dst, sg * Xr[a][b]);
-              atomicAdd(dst + 1, sg * Xi[a][b]);
-            }
+          for (int b = 0; b < 3; ++b) {
+            Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
+            Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
+          }
+      }
+      if (pv) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int row = (prow >> (8 * a)) & 0xff;
+          if (row == 0xff) continue;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const int col = (qcol >> (8 * b)) & 0xff;
+            if (col == 0xff) continue;
+            const float sg = psig[a] * qr[kRecSigma + b];
+            float *dst = acc + row * kAccStride + 2 * col;
+            atomicAdd(dst, sg * Xr[a][b]);
+            atomicAdd(dst + 1, sg * Xi[a][b]);
           }
         }
       }
     }
-    __syncthreads();
-    // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
-    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
-    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+  }
+  __syncthreads();
+  // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
+  const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+  const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+  for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+    const int r = e / nj, c = e % nj;
+    {
+      const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+      ZT v;
+      v.x = -S.pref * ai;
+      v.y = S.pref * ar;
+      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+    }
+  }
+  if (I != J) {
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
-      const int r = e / nj, c = e % nj;
+      const int c = e / ni, r = e % ni;
       {
         const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
         ZT v;
         v.x = -S.pref * ai;
         v.y = S.pref * ar;
-        Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+        Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
       }
     }
-    if (I != J) {
-      for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
-        const int c = e / ni, r = e % ni;
-        {
-          const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
-          ZT v;
-          v.x = -S.pref * ai;
-          v.y = S.pref * ar;
-          Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
-        }
-      }
-    }
-    __syncthreads();
   }
-  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(status, 1);
+  __syncthreads();
 }
 
-struct LaunchCtx {
-  FillScalars S;
-  const mf_mesh *m;
-  const int4 *look;
-  const float4 *coef;
-  void *Z;
-  size_t lds;
+template <int Q, int MODE, bool kLDS, int PART, typename ZT>
+__global__ __launch_bounds__(fill_threads<MODE>())
+__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
+    FillItem S, FillRule W) {
+  constexpr int kFillThreads = fill_threads<MODE>();
+  extern __shared__ float4 smem4[];
+  float *acc = reinterpret_cast<float *>(smem4);
+  const TabPtrs tab =
+      load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + kAccFloats / 4 + 1);
+  float rlo = INFINITY, rhi = 0.0f;
+  const int ntiles = S.tile_end - S.tile_begin;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+    fill_tile<Q, MODE, PART, ZT, kFillThreads>(
+        S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
+        S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
+  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+}
+
+// Several items in one persistent launch: the workgroups stride through the
+// concatenated tile list, so every workgroup visits the items in order and
+// loads each item's table once.
+template <int Q, int MODE, bool kLDS, typename ZT>
+__global__ __launch_bounds__(fill_threads<MODE>())
+__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill_batch(
+    const FillItem *__restrict__ items, int n_items, FillRule W) {
+  constexpr int kFillThreads = fill_threads<MODE>();
+  extern __shared__ float4 smem4[];
+  float *acc = reinterpret_cast<float *>(smem4);
+  const int G = gridDim.x;
+  for (int it = 0; it < n_items; ++it) {
+    const FillItem &S = items[it];
+    // first tile of this item that falls to this workgroup
+    int t = S.tile_begin + (((int)blockIdx.x - S.tile_begin) % G + G) % G;
+    if (t >= S.tile_end) continue;
+    const TabPtrs tab =
+        load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + kAccFloats / 4 + 1);
+    float rlo = INFINITY, rhi = 0.0f;
+    for (; t < S.tile_end; t += G)
+      fill_tile<Q, MODE, 0, ZT, kFillThreads>(
+          S, W, tab, acc, t - S.tile_begin, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off,
+          S.blk_tri, S.blk_pos, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
+    if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+  }
+}
+
+// A prepared launch over one or more items: the first item travels as a
+// kernel argument, the full list (when there are several) in device memory.
+struct FillLaunch {
+  FillItem first;
+  FillRule rule;
+  FillItem *d_items = nullptr;  // owned; null for a single item
+  int total_tiles = 0, n = 0;
+  size_t lds = 0;
+  int nq = 0, base = 0, part = 0, z_dtype = 0;
+  bool lds_tab = false;
+  long long grid = 0;
 };
 
-template <int Q, int MODE, bool kLDS, int PART, typename ZT>
-static int launch_t(const LaunchCtx &L, hipStream_t s) {
-  constexpr int kFillThreads = fill_threads<MODE>();
-  auto kern = k_fill<Q, MODE, kLDS, PART, ZT>;
+template <typename K>
+static int plan_grid(FillLaunch &L, K kern, int threads) {
   if (L.lds > 65536)
     MF_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)L.lds));
   int dev = 0, ncu = 0, per = 0;
   MF_HIP(hipGetDevice(&dev));
   MF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kFillThreads, L.lds));
+  MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, L.lds));
   if (per < 1) {
     set_error("mf_fill_Z: fill kernel does not fit on a compute unit");
     return MF_EINVAL;
   }
-  long long grid = (long long)ncu * per;
-  if (grid > L.S.ntiles) grid = L.S.ntiles;
+  L.grid = (long long)ncu * per;
+  if (L.grid > L.total_tiles) L.grid = L.total_tiles;
   if (getenv("MOMFILL_VERBOSE"))
-    fprintf(stderr, "[momfill] k_fill Q=%d mode=%d lds_table=%d grid=%lld x %d lds=%zu B\n", Q,
-            MODE, (int)kLDS, grid, kFillThreads, L.lds);
-  const mf_mesh *m = L.m;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kFillThreads), L.lds, s, L.S, m->d_rec,
-                     m->d_tiles, m->d_blk_e0, m->d_blk_off, m->d_blk_tri, m->d_blk_pos,
-                     m->d_touch_off,
-                     m->d_touch_q, m->d_sing, L.look, L.coef,
-                     reinterpret_cast<ZT *>(L.Z), m->d_status);
+    fprintf(stderr, "[momfill] k_fill Q=%d mode=%d lds_table=%d items=%d grid=%lld x %d lds=%zu B\n",
+            L.nq, L.base, (int)L.lds_tab, L.n, L.grid, threads, L.lds);
+  return MF_OK;
+}
+
+template <int Q, int MODE, bool kLDS, int PART, typename ZT>
+static int launch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
+  constexpr int kFillThreads = fill_threads<MODE>();
+  if (L.n == 1) {
+    auto kern = k_fill<Q, MODE, kLDS, PART, ZT>;
+    if (L.grid == 0) {
+      const int rc = plan_grid(L, kern, kFillThreads);
+      if (rc) return rc;
+    }
+    if (plan_only || L.total_tiles == 0) return MF_OK;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.first,
+                       L.rule);
+  } else {
+    auto kern = k_fill_batch<Q, MODE, kLDS, ZT>;
+    if (L.grid == 0) {
+      const int rc = plan_grid(L, kern, kFillThreads);
+      if (rc) return rc;
+    }
+    if (plan_only || L.total_tiles == 0) return MF_OK;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.d_items,
+                       L.n, L.rule);
+  }
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
 template <int Q, int MODE, bool kLDS, typename ZT>
-static int launch_part(const LaunchCtx &L, int part, hipStream_t s) {
-  if (part == MF_PART_A) return launch_t<Q, MODE, kLDS, MF_PART_A, ZT>(L, s);
-  if (part == MF_PART_PHI) return launch_t<Q, MODE, kLDS, MF_PART_PHI, ZT>(L, s);
-  return launch_t<Q, MODE, kLDS, 0, ZT>(L, s);
+static int launch_part(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.part == MF_PART_A) return launch_t<Q, MODE, kLDS, MF_PART_A, ZT>(L, plan_only, s);
+  if (L.part == MF_PART_PHI) return launch_t<Q, MODE, kLDS, MF_PART_PHI, ZT>(L, plan_only, s);
+  return launch_t<Q, MODE, kLDS, 0, ZT>(L, plan_only, s);
 }
 
 template <int Q, typename ZT>
-static int launch_q(const LaunchCtx &L, int mode, int part, bool lds_tab, hipStream_t s) {
-  if (mode == MF_MODE_DIRECT) return launch_part<Q, MF_MODE_DIRECT, false, ZT>(L, part, s);
-  if (lds_tab) return launch_part<Q, MF_MODE_TABLE, true, ZT>(L, part, s);
-  return launch_part<Q, MF_MODE_TABLE, false, ZT>(L, part, s);
+static int launch_q(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.base == MF_MODE_DIRECT) return launch_part<Q, MF_MODE_DIRECT, false, ZT>(L, plan_only, s);
+  if (L.lds_tab) return launch_part<Q, MF_MODE_TABLE, true, ZT>(L, plan_only, s);
+  return launch_part<Q, MF_MODE_TABLE, false, ZT>(L, plan_only, s);
 }
 
 template <typename ZT>
-static int launch_z(const LaunchCtx &L, int nq, int mode, int part, bool lds_tab, hipStream_t s) {
-  switch (nq) {
-    case 3: return launch_q<3, ZT>(L, mode, part, lds_tab, s);
-    case 6: return launch_q<6, ZT>(L, mode, part, lds_tab, s);
-    default: return launch_q<7, ZT>(L, mode, part, lds_tab, s);
+static int launch_z(FillLaunch &L, bool plan_only, hipStream_t s) {
+  switch (L.nq) {
+    case 3: return launch_q<3, ZT>(L, plan_only, s);
+    case 6: return launch_q<6, ZT>(L, plan_only, s);
+    default: return launch_q<7, ZT>(L, plan_only, s);
   }
 }
 
-int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
-                int z_dtype, int64_t ldz, hipStream_t s) {
-  LaunchCtx L{};
-  L.m = m;
-  L.Z = Z;
-  FillScalars &S = L.S;
-  S.ntiles = (int)m->tiles.size();
+static int dispatch(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.z_dtype == MF_C64) return launch_z<float2>(L, plan_only, s);
+  return launch_z<double2>(L, plan_only, s);
+}
+
+static size_t table_lds_bytes(const mf_tables *tab) {
+  const mf_tables::One &g = tab->g;
+  return sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int4) * (size_t)g.mb;
+}
+
+static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
+                          const mf_tables *tab, void *Z, int64_t ldz, const float *sing,
+                          int tile_begin) {
+  FillItem S{};
+  S.tile_begin = tile_begin;
+  S.tile_end = tile_begin + (int)m->tiles.size();
   S.ne = m->ne;
   S.k = (float)k;
   S.ik2 = (float)(1.0 / (k * k));
   S.pref = (float)(k * kEta0 / (4.0 * M_PI));
-  for (int i = 0; i < kMaxQ; ++i) S.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
   S.ldz = ldz;
-  const int base = mode & 0xf, part = mode & (MF_PART_A | MF_PART_PHI);
-  L.lds = sizeof(float) * kAccFloats + 16;
-  bool lds_tab = false;
+  S.rec = m->d_rec;
+  S.tiles = m->d_tiles;
+  S.blk_e0 = m->d_blk_e0;
+  S.blk_off = m->d_blk_off;
+  S.blk_tri = m->d_blk_tri;
+  S.blk_pos = m->d_blk_pos;
+  S.touch_off = m->d_touch_off;
+  S.touch_q = m->d_touch_q;
+  S.sing = sing;
+  S.Z = Z;
+  S.status = m->d_status;
   if (base == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g;
-    L.look = g.look;
-    L.coef = g.coef;
+    S.look = g.look;
+    S.coef = g.coef;
     S.tn = g.n;
     S.tm = g.mb;
     S.tinv = g.binv;
@@ -447,17 +545,83 @@ int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *
     S.tmax = g.btop;
     S.lo_ok = (float)(tab->rmin * (1.0 - 1e-6));
     S.hi_ok = (float)(tab->rmax * (1.0 + 1e-6));
-    const size_t tbytes = sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int4) * (size_t)g.mb;
+  }
+  return S;
+}
+
+// Builds the launch of n items (all with the same rule, mode and Z type).
+// With more than one item the item list is copied to the device here
+// (synchronously); running the launch afterwards only enqueues the kernel.
+int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
+                       const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
+                       const float *const *sing, FillLaunch **out) {
+  FillLaunch *L = new (std::nothrow) FillLaunch;
+  if (!L) {
+    set_error("out of host memory");
+    return MF_ENOMEM;
+  }
+  L->n = n;
+  L->nq = r.nq;
+  L->base = mode & 0xf;
+  L->part = mode & (MF_PART_A | MF_PART_PHI);
+  L->z_dtype = z_dtype;
+  for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+  L->lds = sizeof(float) * kAccFloats + 16;
+  std::vector<FillItem> items(n);
+  size_t tmax = 0;
+  int tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    items[i] = make_item(m[i], r, k[i], L->base, tab ? tab[i] : nullptr, Z[i], ldz[i], sing[i],
+                         tiles);
+    tiles = items[i].tile_end;
+    if (L->base == MF_MODE_TABLE) tmax = std::max(tmax, table_lds_bytes(tab[i]));
+  }
+  L->total_tiles = tiles;
+  L->first = items[0];
+  int rc = MF_OK;
+  if (L->base == MF_MODE_TABLE) {
     int dev = 0, maxlds = 0;
-    MF_HIP(hipGetDevice(&dev));
-    MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (L.lds + tbytes <= (size_t)maxlds) {
-      lds_tab = true;
-      L.lds += tbytes;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+      e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) rc = hip_fail(e, "device attributes");
+    if (!rc && L->lds + tmax <= (size_t)maxlds) {
+      L->lds_tab = true;
+      L->lds += tmax;
     }
   }
-  if (z_dtype == MF_C64) return launch_z<float2>(L, r.nq, base, part, lds_tab, s);
-  return launch_z<double2>(L, r.nq, base, part, lds_tab, s);
+  if (!rc && n > 1) {
+    hipError_t e = hipMalloc((void **)&L->d_items, sizeof(FillItem) * n);
+    if (e == hipSuccess)
+      e = hipMemcpy(L->d_items, items.data(), sizeof(FillItem) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = hip_fail(e, "fill item list");
+  }
+  if (!rc) rc = dispatch(*L, true, nullptr);
+  if (rc) {
+    fill_launch_destroy(L);
+    return rc;
+  }
+  *out = L;
+  return MF_OK;
+}
+
+int fill_launch_run(FillLaunch *L, hipStream_t s) { return dispatch(*L, false, s); }
+
+void fill_launch_destroy(FillLaunch *L) {
+  if (!L) return;
+  if (L->d_items) (void)hipFree(L->d_items);
+  delete L;
+}
+
+int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
+                int z_dtype, int64_t ldz, hipStream_t s) {
+  FillLaunch *L = nullptr;
+  const float *sing = m->d_sing;
+  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &Z, z_dtype, &ldz, &sing, &L);
+  if (rc) return rc;
+  rc = fill_launch_run(L, s);
+  fill_launch_destroy(L);
+  return rc;
 }
 
 }  // namespace mf

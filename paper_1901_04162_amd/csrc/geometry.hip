@@ -318,7 +318,7 @@ __global__ void k_symmetrise(const double *__restrict__ one, const int32_t *__re
 }
 
 int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int part,
-                    hipStream_t s) {
+                    hipStream_t s, float *out) {
   const int64_t np = (int64_t)m->touch_q.size();
   if (np == 0) return MF_OK;
   RuleArg R = rule_arg(r);
@@ -326,7 +326,7 @@ int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int pa
                      m->d_touch_p, m->d_touch_q, np, R, k, part, m->d_sing1);
   MF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_symmetrise, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
-                     m->d_sing1, m->d_touch_rev, np, m->d_sing);
+                     m->d_sing1, m->d_touch_rev, np, out ? out : m->d_sing);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

@@ -105,10 +105,18 @@ RuleArg rule_arg(const Rule &r);
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s);
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s);
+// Touching-pair blocks into out (m->d_sing when out is null).
 int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int part,
-                    hipStream_t s);
+                    hipStream_t s, float *out = nullptr);
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s);
+// Several items (meshes x wavenumbers) in one persistent fill launch.
+struct FillLaunch;
+int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
+                       const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
+                       const float *const *sing, FillLaunch **out);
+int fill_launch_run(FillLaunch *L, hipStream_t s);
+void fill_launch_destroy(FillLaunch *L);
 int build_tables_device(mf_tables *t, double tol, hipStream_t s);
 int launch_table_eval(const mf_tables *t, int which, int64_t n, const double *r, double *out,
                       hipStream_t s);

@@ -155,4 +155,11 @@ def workload(name: str):
         V, F = icosphere(4)
         V = jitter_gauss(V, 0.01, 5)
         return dict(V=V, F=F, k=10.0, Q=6)
+    if name == "sweep":
+        # three jittered icospheres (no re-projection) for a frequency sweep
+        out = []
+        for s, seed in ((3, 41), (4, 42), (5, 43)):
+            V, F = icosphere(s)
+            out.append((jitter_uniform(V, F, 0.05, seed), F))
+        return dict(meshes=out, k=np.linspace(4.0, 20.0, 32), Q=6)
     raise KeyError(name)

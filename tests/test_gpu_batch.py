@@ -1,0 +1,185 @@
+"""GPU parity of the batched fill: several (mesh, k) items in one persistent
+launch must give, item by item, the matrix of the single fill (same
+arithmetic; only the order of the LDS accumulation may differ) and agree with
+the oracle on sampled entries; the launch replays correctly from a CUDA
+graph."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1901_04162_amd import meshes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_04162_amd as m
+
+    m.lib()
+    return m
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _items(mf, mode, Q, tol=1e-6):
+    """ico1 at two wavenumbers (one mesh handle shared), ico2, a small plate."""
+    import torch
+
+    specs = []
+    V1, F1 = meshes.icosphere(1)
+    V2, F2 = meshes.icosphere(2)
+    Vp, Fp = meshes.plate(n=12, h=0.1, jitter=0.005, seed=9)
+    m1, m2, mp = mf.Mesh(F1, V1.shape[0]), mf.Mesh(F2, V2.shape[0]), mf.Mesh(Fp, Vp.shape[0])
+    V1d = torch.tensor(V1, dtype=torch.float64, device="cuda")
+    for mesh, Vd, V, F, k in ((m1, V1d, V1, F1, 3.0), (m1, V1d, V1, F1, 7.5),
+                              (m2, torch.tensor(V2, dtype=torch.float64, device="cuda"), V2, F2,
+                               2 * np.pi),
+                              (mp, torch.tensor(Vp, dtype=torch.float64, device="cuda"), Vp, Fp,
+                               2 * np.pi)):
+        T = None
+        if mode == "table":
+            lo, hi = mf.r_range(mesh, Vd, Q)
+            T = mf.build_tables(k, lo, hi, tol)
+        E = mesh.n_edges
+        Z = torch.full((E, E), float("nan"), dtype=torch.complex64, device="cuda")
+        specs.append(dict(mesh=mesh, Vd=Vd, V=V, F=F, k=k, T=T, Z=Z))
+    return specs
+
+
+@pytest.mark.parametrize("mode", ["table", "direct"])
+def test_batch_matches_single_fills(mf, mode):
+    import torch
+
+    Q = 6
+    say("batch vs single", mode)
+    specs = _items(mf, mode, Q)
+    b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, mode)
+    b.fill()
+    torch.cuda.synchronize()
+    for s in specs:
+        mf.sync_status(s["mesh"])
+        ref = mf.fill_Z(s["mesh"], s["Vd"], s["k"], Q, mode, s["T"]).cpu().numpy()
+        z = s["Z"].cpu().numpy()
+        assert np.all(np.isfinite(z))
+        err = _rel(z, ref)
+        say(f"  E={s['mesh'].n_edges} k={s['k']:.3f} rel {err:.2e}")
+        assert err <= 1e-6
+
+
+def test_batch_matches_oracle(mf, orc):
+    import torch
+
+    Q = 6
+    say("batch vs oracle")
+    specs = _items(mf, "table", Q, tol=1e-6)
+    b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
+    b.fill()
+    torch.cuda.synchronize()
+    for i, s in enumerate(specs):
+        E = s["mesh"].edges()
+        rows, cols = meshes.entry_sample(E.shape[0], 3000, 50 + i)
+        ref = orc.fill_entries(s["V"], s["F"], E, s["k"], Q, rows, cols)
+        z = s["Z"].cpu().numpy()[rows, cols]
+        err = _rel(z, ref)
+        say(f"  item {i} sampled rel {err:.2e}")
+        assert err <= 1e-5
+
+
+def test_batch_graph_replay(mf):
+    """Captured once, replayed three times with eager work in between; every
+    replay must reproduce the eager batch."""
+    import torch
+
+    Q = 6
+    say("batch graph replay")
+    specs = _items(mf, "table", Q)
+    b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
+    b.fill()
+    torch.cuda.synchronize()
+    eager = [s["Z"].clone() for s in specs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.fill()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.fill()
+    for rep in range(3):
+        for s in specs:
+            s["Z"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for s, e in zip(specs, eager):
+            err = float((s["Z"] - e).abs().max() / e.abs().max())
+            assert err <= 1e-6, (rep, err)
+    say("  3 replays match")
+
+
+def test_batch_rejects_bad_items(mf):
+    import torch
+
+    V, F = meshes.icosphere(1)
+    m = mf.Mesh(F, V.shape[0])
+    E = m.n_edges
+    Va = torch.tensor(V, device="cuda")
+    Vb = torch.tensor(V, device="cuda")
+    Z = [torch.empty((E, E), dtype=torch.complex64, device="cuda") for _ in range(2)]
+    with pytest.raises(mf.MomfillError):
+        mf.Batch([(m, Va, 3.0, None, Z[0]), (m, Vb, 4.0, None, Z[1])], 6, "direct")
+    with pytest.raises(mf.MomfillError):
+        mf.Batch([(m, Va, -1.0, None, Z[0])], 6, "direct")
+    lo, hi = mf.r_range(m, Va, 6)
+    T = mf.build_tables(3.0, lo, hi, 1e-6)
+    with pytest.raises(mf.MomfillError):  # tables built for another k
+        mf.Batch([(m, Va, 4.0, T, Z[0])], 6, "table")
+
+
+def test_sweep_meshes_sampled(mf, orc):
+    """The three jittered icospheres of the sweep (1,920 / 7,680 / 30,720
+    unknowns) at two wavenumbers in one launch, against the oracle on
+    sampled entries."""
+    import torch
+
+    wl = meshes.workload("sweep")
+    Q = 6
+    ks = [4.0, 20.0]
+    say("sweep meshes", [F.shape[0] for _, F in wl["meshes"]], ks)
+    items, keep = [], []
+    for V, F in wl["meshes"]:
+        m = mf.Mesh(F, V.shape[0])
+        Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+        lo, hi = mf.r_range(m, Vd, Q)
+        for k in ks:
+            T = mf.build_tables(k, lo, hi, 1e-5)
+            Z = torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device="cuda")
+            items.append((m, Vd, k, T, Z))
+            keep.append((V, F))
+    b = mf.Batch(items, Q, "table")
+    b.fill()
+    torch.cuda.synchronize()
+    for (m, Vd, k, T, Z), (V, F) in zip(items, keep):
+        mf.sync_status(m)
+        E = m.edges()
+        rows, cols = meshes.entry_sample(E.shape[0], 2000, 400 + len(E) % 97)
+        ref = orc.fill_entries(V, F, E, k, Q, rows, cols)
+        z = Z[torch.tensor(rows, device="cuda"), torch.tensor(cols, device="cuda")].cpu().numpy()
+        err = _rel(z, ref)
+        say(f"  E={E.shape[0]} k={k} sampled rel {err:.2e}")
+        assert err <= 1e-5
