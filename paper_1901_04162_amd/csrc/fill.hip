@@ -23,8 +23,9 @@
 // memory otherwise.
 //
 // Distances: D = c_p - c_q is formed in FP64 and split into FP32 hi + lo;
-// the point offsets rho are FP32, so R carries no per-pair rounding of the
-// centroid distance (phase errors stay random across point pairs).
+// each test point's offset hi + (lo + rho_i) is rounded once in FP32, then
+// the source offsets are subtracted: R carries a few FP32 roundings at its
+// own size and no cancellation error of the centroids.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -132,14 +133,17 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
   zero(M);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float ax = prho[i][0] + lx, ay = prho[i][1] + ly, az = prho[i][2] + lz;
+    // test point relative to the source centroid: the FP64 centroid offset
+    // enters as hi + (lo + rho), one FP32 rounding at the size of R
+    const float ax = hx + (prho[i][0] + lx), ay = hy + (prho[i][1] + ly),
+                az = hz + (prho[i][2] + lz);
     float r[Q];
     int4 w[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
-      const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
-      const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
+      const float dx = ax - qr[kRecRho + 3 * j + 0];
+      const float dy = ay - qr[kRecRho + 3 * j + 1];
+      const float dz = az - qr[kRecRho + 3 * j + 2];
       r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
       rlo = fminf(rlo, r[j]);
       rhi = fmaxf(rhi, r[j]);
@@ -184,13 +188,13 @@ __device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S,
     float pri[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
-    const float ax = pri[0] + lx, ay = pri[1] + ly, az = pri[2] + lz;
+    const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const float dx = hx + (ax - qr[kRecRho + 3 * j + 0]);
-      const float dy = hy + (ay - qr[kRecRho + 3 * j + 1]);
-      const float dz = hz + (az - qr[kRecRho + 3 * j + 2]);
+      const float dx = ax - qr[kRecRho + 3 * j + 0];
+      const float dy = ay - qr[kRecRho + 3 * j + 1];
+      const float dz = az - qr[kRecRho + 3 * j + 2];
       const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
       const float ri = __builtin_amdgcn_rsqf(r2);
       float sn, cs;
