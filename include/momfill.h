@@ -169,6 +169,31 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *vert
 int mf_batch_fill(mf_batch *batch, hipStream_t stream);
 void mf_batch_destroy(mf_batch *batch);
 
+/* ---- near-field fill (Section II-A) --------------------------------------
+ * With a fast method (MLFMA, pFFT, AIM) only the near-field interactions
+ * are filled directly.  Here two RWG unknowns are near when the midpoints
+ * of their edges are at most r_near apart (every unknown is near itself).
+ * mf_near_create builds, on the host, the CSR pattern of those pairs from
+ * the host vertex array (n_vertices*3 doubles) and the list of edge-block
+ * tiles that hold a near pair; the first mf_fill_near uploads the tile
+ * lists.  The pattern keeps the mesh handle, which must outlive it.
+ * MF_EINVAL for r_near <= 0 or more than 2^31 pairs. */
+typedef struct mf_near mf_near;
+int mf_near_create(mf_mesh *mesh, const double *vertices_host, double r_near, mf_near **out);
+/* Number of near pairs and of tiles the near fill runs over. */
+int mf_near_info(const mf_near *pattern, int64_t *nnz, int64_t *n_tiles);
+/* Host copy of the pattern: row_ptr (n_edges + 1 int64), col (nnz int32,
+ * ascending within a row). */
+int mf_near_pattern(const mf_near *pattern, int64_t *row_ptr, int32_t *col);
+/* values_dev[i] (nnz complex values, MF_C64 or MF_C128) receives Z at the
+ * i-th CSR position: the same entries mf_fill_Z computes, from the same
+ * kernels run over the near tiles only.  Arguments as for mf_fill_Z; the
+ * pattern must belong to `mesh`. */
+int mf_fill_near(mf_mesh *mesh, mf_near *pattern, const double *vertices_dev, double k,
+                 int quad_order, int mode, const mf_tables *tables, void *values_dev,
+                 int z_dtype, hipStream_t stream);
+void mf_near_destroy(mf_near *pattern);
+
 /* ---- adjoint ------------------------------------------------------------
  * Gradient of L = Re sum_mn conj(W_mn) Z_mn, W = dLdZ_dev (same dtype and
  * layout as Z), with respect to the vertex coordinates (dL_dvertices_dev,

@@ -151,6 +151,49 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     return out
 
 
+class NearField:
+    """CSR pattern of the near-field unknown pairs (edge midpoints at most
+    r_near apart) and the fill of their entries."""
+
+    def __init__(self, mesh: Mesh, V, r_near: float):
+        Vh = np.ascontiguousarray(np.asarray(V, dtype=np.float64))
+        self._h = C.c_void_p()
+        check(lib().mf_near_create(mesh.handle, Vh.ctypes.data_as(C.POINTER(C.c_double)),
+                                   float(r_near), C.byref(self._h)))
+        self.mesh = mesh
+        nnz, nt = C.c_int64(), C.c_int64()
+        check(lib().mf_near_info(self._h, C.byref(nnz), C.byref(nt)))
+        self.nnz, self.n_tiles = nnz.value, nt.value
+
+    def pattern(self):
+        """(row_ptr int64 [E+1], col int32 [nnz]) on the host."""
+        rp = np.zeros(self.mesh.n_edges + 1, dtype=np.int64)
+        col = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        check(lib().mf_near_pattern(self._h, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    col.ctypes.data_as(C.POINTER(C.c_int32))))
+        return rp, col[:self.nnz]
+
+    def fill(self, V, k: float, quad_order: int, mode: str = "table", tables: Tables = None,
+             dtype=torch.complex64, out: torch.Tensor = None) -> torch.Tensor:
+        Vd = _vertices(V)
+        if out is None:
+            out = torch.empty(self.nnz, dtype=dtype, device="cuda")
+        if out.dtype not in (torch.complex64, torch.complex128) or out.numel() < self.nnz or \
+                not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex vector of nnz values")
+        zt = MF_C64 if out.dtype == torch.complex64 else MF_C128
+        check(lib().mf_fill_near(self.mesh.handle, self._h, C.c_void_p(Vd.data_ptr()), float(k),
+                                 int(quad_order), MODES[mode],
+                                 tables.handle if tables is not None else None,
+                                 C.c_void_p(out.data_ptr()), zt, _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _L._lib is not None:
+            _L._lib.mf_near_destroy(self._h)
+            self._h = None
+
+
 class Batch:
     """One persistent fill launch over several (mesh, k) items.
 

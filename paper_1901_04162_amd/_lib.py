@@ -24,7 +24,8 @@ EXPORTS = [
     "mf_mesh_n_touching", "mf_mesh_plan", "mf_r_range", "mf_build_tables", "mf_tables_destroy",
     "mf_tables_info", "mf_tables_get", "mf_tables_eval", "mf_fill_Z", "mf_fill_Z_backward",
     "mf_sync_status", "mf_set_timing", "mf_mesh_timings", "mf_batch_create", "mf_batch_fill",
-    "mf_batch_destroy",
+    "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
+    "mf_near_destroy",
 ]
 
 
@@ -61,6 +62,12 @@ def lib():
         L.mf_batch_fill.argtypes = [vp, vp]
         L.mf_batch_destroy.argtypes = [vp]
         L.mf_batch_destroy.restype = None
+        L.mf_near_create.argtypes = [vp, dp, C.c_double, C.POINTER(vp)]
+        L.mf_near_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.mf_near_pattern.argtypes = [vp, C.POINTER(C.c_int64), ip]
+        L.mf_fill_near.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, C.c_int, vp]
+        L.mf_near_destroy.argtypes = [vp]
+        L.mf_near_destroy.restype = None
         L.mf_mesh_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]
         L.mf_r_range.argtypes = [vp, vp, C.c_int, dp, dp, vp]

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -294,6 +295,17 @@ static int ensure_device(mf_mesh *m) {
 
 }  // namespace mf
 
+struct mf_near {
+  mf_mesh *mesh = nullptr;
+  double r_near = 0.0;
+  std::vector<int64_t> row_ptr;  // E + 1
+  std::vector<int32_t> col;      // nnz, sorted per row
+  std::vector<int32_t> tiles;    // (I << 16) | J, I <= J, tiles holding a near pair
+  std::vector<int32_t> toff;     // tiles + 1
+  std::vector<int32_t> ent;      // 4 ints per entry
+  int32_t *d_tiles = nullptr, *d_toff = nullptr, *d_ent = nullptr;
+};
+
 struct mf_batch {
   mf::Rule r;
   int part = 0;
@@ -557,6 +569,132 @@ void mf_batch_destroy(mf_batch *b) {
   for (float *p : b->sing)
     if (p) (void)hipFree(p);
   delete b;
+}
+
+int mf_near_create(mf_mesh *m, const double *V, double r_near, mf_near **out) {
+  if (!m || !V || !out || !(r_near > 0.0) || !std::isfinite(r_near))
+    return fail(MF_EINVAL, "mf_near_create: bad argument");
+  *out = nullptr;
+  const int ne = m->ne;
+  // edge midpoints, bucketed in a grid of cells of side r_near
+  std::vector<double> mid(3 * (size_t)ne);
+  double lo[3] = {1e300, 1e300, 1e300};
+  for (int e = 0; e < ne; ++e)
+    for (int c = 0; c < 3; ++c) {
+      const int32_t *E = &m->edges[6 * (size_t)e];
+      mid[3 * e + c] = 0.5 * (V[3 * (size_t)E[0] + c] + V[3 * (size_t)E[1] + c]);
+      lo[c] = std::min(lo[c], mid[3 * e + c]);
+    }
+  std::map<std::array<int64_t, 3>, std::vector<int32_t>> cells;
+  auto cell_of = [&](int e) {
+    std::array<int64_t, 3> key;
+    for (int c = 0; c < 3; ++c) key[c] = (int64_t)std::floor((mid[3 * e + c] - lo[c]) / r_near);
+    return key;
+  };
+  for (int e = 0; e < ne; ++e) cells[cell_of(e)].push_back(e);
+  mf_near *nf = new (std::nothrow) mf_near;
+  if (!nf) return fail(MF_ENOMEM, "mf_near_create: out of host memory");
+  nf->mesh = m;
+  nf->r_near = r_near;
+  nf->row_ptr.assign(ne + 1, 0);
+  const double r2 = r_near * r_near;
+  std::vector<int32_t> row;
+  for (int e = 0; e < ne; ++e) {
+    row.clear();
+    const std::array<int64_t, 3> k0 = cell_of(e);
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          auto it = cells.find({k0[0] + dx, k0[1] + dy, k0[2] + dz});
+          if (it == cells.end()) continue;
+          for (int32_t f : it->second) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+              const double d = mid[3 * e + c] - mid[3 * (size_t)f + c];
+              d2 += d * d;
+            }
+            if (d2 <= r2) row.push_back(f);
+          }
+        }
+    std::sort(row.begin(), row.end());
+    nf->col.insert(nf->col.end(), row.begin(), row.end());
+    nf->row_ptr[e + 1] = (int64_t)nf->col.size();
+  }
+  if (nf->col.size() > (size_t)INT32_MAX) {
+    mf_near_destroy(nf);
+    return fail(MF_EINVAL, "mf_near_create: more than 2^31 near pairs");
+  }
+  // block of every edge, then the tiles (I <= J) that hold a near pair
+  std::vector<int32_t> blk(ne);
+  for (int b = 0; b < m->nblk; ++b)
+    for (int e = m->blk_e0[b]; e < m->blk_e0[b + 1]; ++e) blk[e] = b;
+  std::map<int32_t, std::vector<std::array<int32_t, 4>>> per_tile;
+  auto pos = [&](int r, int c) -> int32_t {
+    const auto b = nf->col.begin() + nf->row_ptr[r], e = nf->col.begin() + nf->row_ptr[r + 1];
+    return (int32_t)(std::lower_bound(b, e, c) - nf->col.begin());
+  };
+  for (int e = 0; e < ne; ++e)
+    for (int64_t s = nf->row_ptr[e]; s < nf->row_ptr[e + 1]; ++s) {
+      const int f = nf->col[s];
+      const int I = blk[e], J = blk[f];
+      if (I > J) continue;  // taken as the mirror of (f, e)
+      const int r = e - m->blk_e0[I], c = f - m->blk_e0[J];
+      // on a diagonal tile both orders are computed, so no mirror write
+      per_tile[(I << 16) | J].push_back({(r << 8) | c, (int32_t)s, I == J ? -1 : pos(f, e), 0});
+    }
+  nf->toff.push_back(0);
+  for (auto &kv : per_tile) {
+    nf->tiles.push_back(kv.first);
+    for (auto &en : kv.second) nf->ent.insert(nf->ent.end(), en.begin(), en.end());
+    nf->toff.push_back((int32_t)(nf->ent.size() / 4));
+  }
+  *out = nf;  // device copies follow at the first fill
+  return MF_OK;
+}
+
+int mf_near_info(const mf_near *nf, int64_t *nnz, int64_t *n_tiles) {
+  if (!nf || !nnz || !n_tiles) return fail(MF_EINVAL, "mf_near_info: bad argument");
+  *nnz = (int64_t)nf->col.size();
+  *n_tiles = (int64_t)nf->tiles.size();
+  return MF_OK;
+}
+
+int mf_near_pattern(const mf_near *nf, int64_t *row_ptr, int32_t *col) {
+  if (!nf || !row_ptr || !col) return fail(MF_EINVAL, "mf_near_pattern: bad argument");
+  std::memcpy(row_ptr, nf->row_ptr.data(), sizeof(int64_t) * nf->row_ptr.size());
+  std::memcpy(col, nf->col.data(), sizeof(int32_t) * nf->col.size());
+  return MF_OK;
+}
+
+int mf_fill_near(mf_mesh *m, mf_near *nf, const double *V, double k, int quad_order,
+                 int mode, const mf_tables *tab, void *values, int z_dtype, hipStream_t s) {
+  Rule r;
+  if (!m || !nf || !V || !values || nf->mesh != m)
+    return fail(MF_EINVAL, "mf_fill_near: bad argument (the pattern belongs to another mesh?)");
+  if (!make_rule(quad_order, &r)) return fail(MF_EINVAL, "mf_fill_near: quad_order must be 3, 6 or 7");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_near: k must be > 0");
+  if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
+    return fail(MF_EINVAL, "mf_fill_near: unknown mode");
+  if (mode == MF_MODE_TABLE && (!tab || std::fabs(tab->k - k) > 1e-12 * k))
+    return fail(MF_EINVAL, "mf_fill_near: tables missing or built for another k");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_fill_near: unknown z_dtype");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if (!nf->d_ent && ((rc = upload(&nf->d_tiles, nf->tiles)) ||
+                     (rc = upload(&nf->d_toff, nf->toff)) || (rc = upload(&nf->d_ent, nf->ent))))
+    return rc;
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  if ((rc = launch_singular(m, V, r, k, 0, s))) return rc;
+  if (nf->tiles.empty()) return MF_OK;
+  return launch_fill_near(m, r, k, mode, tab, nf->d_tiles, (int)nf->tiles.size(), nf->d_toff,
+                          reinterpret_cast<const int4 *>(nf->d_ent), values, z_dtype, s);
+}
+
+void mf_near_destroy(mf_near *nf) {
+  if (!nf) return;
+  for (int32_t *p : {nf->d_tiles, nf->d_toff, nf->d_ent})
+    if (p) (void)hipFree(p);
+  delete nf;
 }
 
 void mf_set_timing(int on) { g_timing = on != 0; }

@@ -68,6 +68,10 @@ struct FillItem {
   const float4 *coef;
   void *Z;
   int *status;
+  // near-field fill: entries of tile t are sp_ent[sp_off[t] .. sp_off[t+1]),
+  // each {r << 8 | c, position of (row, col), position of the mirror or -1}
+  const int32_t *sp_off;
+  const int4 *sp_ent;
 };
 typedef FillItem FillScalars;
 
@@ -225,10 +229,10 @@ __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coe
 }
 
 // One tile of one item: accumulate it in LDS, then write it and its mirror.
-template <int Q, int MODE, int PART, typename ZT, int kFillThreads>
 // The item's arrays come in as separate __restrict__ parameters: once the
 // function is inlined they carry no-alias scopes, which lets the
 // wave-uniform source records go through scalar loads into SGPRs.
+template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false>
 __device__ __forceinline__ void fill_tile(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
@@ -350,35 +354,49 @@ __device__ __forceinline__ void fill_tile(
     }
   }
   __syncthreads();
-  // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
-  const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
-  const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
-  for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
-    const int r = e / nj, c = e % nj;
-    {
+  if (kSparse) {
+    // near-field entries only, into the CSR values (Z) at their positions
+    for (int e = S.sp_off[local] + threadIdx.x; e < S.sp_off[local + 1]; e += kFillThreads) {
+      const int4 en = S.sp_ent[e];
+      const int r = en.x >> 8, c = en.x & 0xff;
       const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
-      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+      Z[en.y] = v;
+      if (en.z >= 0) Z[en.z] = v;
     }
-  }
-  if (I != J) {
+  } else {
+    // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
+    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
-      const int c = e / ni, r = e % ni;
+      const int r = e / nj, c = e % nj;
       {
         const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
         ZT v;
         v.x = -S.pref * ai;
         v.y = S.pref * ar;
-        Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+        Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+      }
+    }
+    if (I != J) {
+      for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+        const int c = e / ni, r = e % ni;
+        {
+          const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+          ZT v;
+          v.x = -S.pref * ai;
+          v.y = S.pref * ar;
+          Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+        }
       }
     }
   }
   __syncthreads();
 }
 
-template <int Q, int MODE, bool kLDS, int PART, typename ZT>
+template <int Q, int MODE, bool kLDS, int PART, typename ZT, bool kSparse>
 __global__ __launch_bounds__(fill_threads<MODE>())
 __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
     FillItem S, FillRule W) {
@@ -390,7 +408,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
   float rlo = INFINITY, rhi = 0.0f;
   const int ntiles = S.tile_end - S.tile_begin;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile<Q, MODE, PART, ZT, kFillThreads>(
+    fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse>(
         S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
         S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
@@ -432,7 +450,7 @@ struct FillLaunch {
   int total_tiles = 0, n = 0;
   size_t lds = 0;
   int nq = 0, base = 0, part = 0, z_dtype = 0;
-  bool lds_tab = false;
+  bool lds_tab = false, sparse = false;
   long long grid = 0;
 };
 
@@ -460,8 +478,17 @@ static int plan_grid(FillLaunch &L, K kern, int threads) {
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
 static int launch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
   constexpr int kFillThreads = fill_threads<MODE>();
-  if (L.n == 1) {
-    auto kern = k_fill<Q, MODE, kLDS, PART, ZT>;
+  if (L.n == 1 && L.sparse) {
+    auto kern = k_fill<Q, MODE, kLDS, PART, ZT, true>;
+    if (L.grid == 0) {
+      const int rc = plan_grid(L, kern, kFillThreads);
+      if (rc) return rc;
+    }
+    if (plan_only || L.total_tiles == 0) return MF_OK;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.first,
+                       L.rule);
+  } else if (L.n == 1) {
+    auto kern = k_fill<Q, MODE, kLDS, PART, ZT, false>;
     if (L.grid == 0) {
       const int rc = plan_grid(L, kern, kFillThreads);
       if (rc) return rc;
@@ -615,6 +642,27 @@ void fill_launch_destroy(FillLaunch *L) {
   if (!L) return;
   if (L->d_items) (void)hipFree(L->d_items);
   delete L;
+}
+
+int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab,
+                     const int32_t *tiles, int ntiles, const int32_t *sp_off, const int4 *sp_ent,
+                     void *values, int z_dtype, hipStream_t s) {
+  FillLaunch *L = nullptr;
+  const float *sing = m->d_sing;
+  int64_t ld = m->ne;
+  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &values, z_dtype, &ld, &sing, &L);
+  if (rc) return rc;
+  L->sparse = true;
+  L->first.tiles = tiles;
+  L->first.tile_begin = 0;
+  L->first.tile_end = ntiles;
+  L->first.sp_off = sp_off;
+  L->first.sp_ent = sp_ent;
+  L->total_tiles = ntiles;
+  L->grid = 0;  // plan again for the sparse kernel and this tile count
+  rc = fill_launch_run(L, s);
+  fill_launch_destroy(L);
+  return rc;
 }
 
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,

@@ -110,6 +110,10 @@ int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int pa
                     hipStream_t s, float *out = nullptr);
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s);
+// Near-field fill: only the listed tiles, scattered into CSR values.
+int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab,
+                     const int32_t *tiles, int ntiles, const int32_t *sp_off, const int4 *sp_ent,
+                     void *values, int z_dtype, hipStream_t s);
 // Several items (meshes x wavenumbers) in one persistent fill launch.
 struct FillLaunch;
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,

@@ -105,3 +105,24 @@ def test_tile_plan_shape(s):
     assert nt == nb * (nb + 1) // 2
     assert 1 <= mt <= 64
     assert nb * 88 >= m.n_edges
+
+
+@pytest.mark.parametrize("s,r", [(2, 0.25), (3, 0.12)])
+def test_near_pattern_brute_force(s, r):
+    """The near-field CSR pattern equals a brute-force distance test on the
+    edge midpoints (host planning only)."""
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.icosphere(s)
+    m = mf.Mesh(F, V.shape[0])
+    nf = mf.NearField(m, V, r)
+    rp, col = nf.pattern()
+    E = m.edges()
+    mid = 0.5 * (V[E[:, 0]] + V[E[:, 1]])
+    d2 = ((mid[:, None, :] - mid[None, :, :]) ** 2).sum(-1)
+    near = d2 <= r * r
+    assert nf.nnz == int(near.sum())
+    for e in range(E.shape[0]):
+        np.testing.assert_array_equal(col[rp[e]:rp[e + 1]], np.nonzero(near[e])[0])
+    nb, nt, _ = m.plan()
+    assert 1 <= nf.n_tiles <= nt
