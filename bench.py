@@ -185,6 +185,30 @@ def sweep_timing(mf, steps, group=8, tol=1e-5):
     }
 
 
+def near_timing(mf, mesh, V, Vd, k, Q, tables, steps):
+    """Near-field fill (unknowns whose edge midpoints are within a quarter
+    wavelength) of the same sphere, table and direct mode."""
+    import torch
+
+    r = 0.25 * 2 * 3.141592653589793 / k
+    nf = mf.NearField(mesh, V, r)
+    vals = torch.empty(nf.nnz, dtype=torch.complex64, device="cuda")
+    out = {"r_near": r, "nnz": nf.nnz, "tiles": nf.n_tiles,
+           "pairs_per_row": nf.nnz / mesh.n_edges}
+    for mode in ("table", "direct"):
+        for _ in range(2):
+            nf.fill(Vd, k, Q, mode, tables, out=vals)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            nf.fill(Vd, k, Q, mode, tables, out=vals)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"{mode}_ms"] = dt * 1e3
+        out[f"{mode}_near_entries_per_s"] = nf.nnz / dt
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +223,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-near", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -324,6 +349,9 @@ def main():
     }
     del Z
     torch.cuda.empty_cache()
+    if not args.no_near:
+        log("near field ...")
+        out["near_field"] = near_timing(mf, mesh, V, Vd, k, Q, T, args.steps)
     if not args.no_adjoint:
         log("adjoint ...")
         out["adjoint"] = adjoint_timing(mf, args.steps)
