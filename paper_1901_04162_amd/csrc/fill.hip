@@ -120,10 +120,10 @@ __device__ __forceinline__ void zero(Moments &M) {
   for (int c = 0; c < 3; ++c) M.spr[c] = M.spi[c] = M.sqr[c] = M.sqi[c] = 0.0f;
 }
 
-// Table mode.  The Q lookups of one test point go in three batches
-// (distances and bucket-record reads, then coefficient reads, then the cubic
-// and the sums) so that the dependent LDS reads of the Q source points
-// overlap each other.  The interval search is the bucket lookup of Eq. (6)
+// Table mode.  The lookups of one test point go in two groups of source
+// points, each in three steps (distances and bucket-record reads, then
+// coefficient reads, then the cubic and the sums), so that the dependent LDS
+// reads of a group overlap each other.  The interval search is the bucket lookup of Eq. (6)
 // in the record form of lookup.hpp (one 16-byte read gives the interval and
 // its first sample), and the cubic of Eq. (5) is evaluated in Horner form
 // about that sample.
@@ -141,38 +141,43 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
     // enters as hi + (lo + rho), one FP32 rounding at the size of R
     const float ax = hx + (prho[i][0] + lx), ay = hy + (prho[i][1] + ly),
                 az = hz + (prho[i][2] + lz);
-    float r[Q];
-    int4 w[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const float dx = ax - qr[kRecRho + 3 * j + 0];
-      const float dy = ay - qr[kRecRho + 3 * j + 1];
-      const float dz = az - qr[kRecRho + 3 * j + 2];
-      r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-      rlo = fminf(rlo, r[j]);
-      rhi = fmaxf(rhi, r[j]);
-      w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
-    }
-    float u[Q];
-    float4 A[Q], B[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const int ii = look_interval(w[j], r[j], u[j]);
-      A[j] = tab.c01[ii];
-      B[j] = tab.c23[ii];
-    }
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+    // two batches of source points keep fewer lookups live at once
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const float2 g = cubic(A[j], B[j], u[j]);
-      const float gr = g.x, gi = g.y;
-      t0r = fmaf(W.w[j], gr, t0r);
-      t0i = fmaf(W.w[j], gi, t0i);
+    for (int half = 0; half < 2; ++half) {
+      const int j0 = half == 0 ? 0 : (Q + 1) / 2, j1 = half == 0 ? (Q + 1) / 2 : Q;
+      float r[Q];
+      int4 w[Q];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float wq = qr[kRecWRho + 3 * j + c];
-        t1r[c] = fmaf(wq, gr, t1r[c]);
-        t1i[c] = fmaf(wq, gi, t1i[c]);
+      for (int j = j0; j < j1; ++j) {
+        const float dx = ax - qr[kRecRho + 3 * j + 0];
+        const float dy = ay - qr[kRecRho + 3 * j + 1];
+        const float dz = az - qr[kRecRho + 3 * j + 2];
+        r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        rlo = fminf(rlo, r[j]);
+        rhi = fmaxf(rhi, r[j]);
+        w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
+      }
+      float u[Q];
+      float4 A[Q], B[Q];
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        const int ii = look_interval(w[j], r[j], u[j]);
+        A[j] = tab.c01[ii];
+        B[j] = tab.c23[ii];
+      }
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        const float2 g = cubic(A[j], B[j], u[j]);
+        const float gr = g.x, gi = g.y;
+        t0r = fmaf(W.w[j], gr, t0r);
+        t0i = fmaf(W.w[j], gi, t0i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float wq = qr[kRecWRho + 3 * j + c];
+          t1r[c] = fmaf(wq, gr, t1r[c]);
+          t1i[c] = fmaf(wq, gi, t1i[c]);
+        }
       }
     }
     add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);

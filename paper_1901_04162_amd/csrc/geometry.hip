@@ -118,7 +118,7 @@ int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
 // monotone, so this gives the same extreme as comparing distances.
 
 constexpr int kRangeBlock = 256;
-constexpr int kRangeChunk = 256;
+constexpr int kRangeChunk = 256;  // equal to kRangeBlock: one sphere list serves both
 
 struct RangeTri {
   double c[3];
@@ -212,12 +212,65 @@ __global__ void k_range_seed(const double *__restrict__ qp64, const float *__res
   flush_extremes(lo, hi, out);
 }
 
+// Bounding sphere of every run of kRangeBlock triangles (centre, radius
+// covering all their quadrature points), for skipping whole block pairs.
+__global__ __launch_bounds__(kRangeBlock) void k_range_spheres(const double *__restrict__ brad,
+                                                               const float *__restrict__ rec,
+                                                               int nt, double *__restrict__ sph) {
+  __shared__ double red[kRangeBlock][3];
+  __shared__ double cen[3];
+  const int t = blockIdx.x * kRangeBlock + threadIdx.x;
+  const int n = min(kRangeBlock, nt - (int)blockIdx.x * kRangeBlock);
+  RangeTri T{};
+  if (t < nt) load_range_tri(brad, rec, t, T);
+  for (int d = 0; d < 3; ++d) red[threadIdx.x][d] = t < nt ? T.c[d] : 0.0;
+  __syncthreads();
+  for (int h = kRangeBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int d = 0; d < 3; ++d) red[threadIdx.x][d] += red[threadIdx.x + h][d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) cen[d] = red[0][d] / n;
+  __syncthreads();
+  double r = 0.0;
+  if (t < nt) r = sqrt(sq_dist(T.c, cen)) + T.rb;
+  __syncthreads();
+  red[threadIdx.x][0] = r;
+  __syncthreads();
+  for (int h = kRangeBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x][0] = fmax(red[threadIdx.x][0], red[threadIdx.x + h][0]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *o = sph + 4 * blockIdx.x;
+    o[0] = cen[0];
+    o[1] = cen[1];
+    o[2] = cen[2];
+    o[3] = red[0][0] * (1.0 + 1e-12) + 1e-300;
+  }
+}
+
 __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict__ qp64,
                                                        const double *__restrict__ brad,
                                                        const float *__restrict__ rec, int nt,
-                                                       int nq, unsigned long long *out) {
+                                                       int nq, const double *__restrict__ sph,
+                                                       unsigned long long *out) {
   const int p0 = blockIdx.x * kRangeBlock, q0 = blockIdx.y * kRangeChunk;
   if (q0 + kRangeChunk <= p0) return;  // unordered pairs: q > p only
+  // Skip the block pair when no point pair in it can lower the running
+  // minimum or raise the running maximum (one thread decides for all).
+  __shared__ int skip;
+  if (threadIdx.x == 0) {
+    const double *a = sph + 4 * blockIdx.x, *b = sph + 4 * blockIdx.y;
+    const double dc = sqrt(sq_dist(a, b)), rr = a[3] + b[3];
+    const double dmin = fmax(0.0, dc - rr), dmax = dc + rr;
+    const double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
+    const double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
+    skip = dmin * dmin * (1.0 - 1e-9) > lo && dmax * dmax * (1.0 + 1e-9) < hi;
+  }
+  __syncthreads();
+  if (skip) return;
   __shared__ RangeTri sq[kRangeChunk];
   const int p = p0 + threadIdx.x;
   const int nqc = min(kRangeChunk, nt - q0);
@@ -254,9 +307,16 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
   hipLaunchKernelGGL(k_range_seed, dim3((m->nt + 255) / 256), dim3(256), 0, s, m->d_qp64,
                      m->d_rec, m->nt, r.nq, m->d_scratch);
   MF_HIP(hipGetLastError());
-  dim3 grid((m->nt + kRangeBlock - 1) / kRangeBlock, (m->nt + kRangeChunk - 1) / kRangeChunk);
+  const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
+  double *sph = nullptr;
+  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * nb, s));
+  hipLaunchKernelGGL(k_range_spheres, dim3(nb), dim3(kRangeBlock), 0, s, m->d_brad, m->d_rec,
+                     m->nt, sph);
+  dim3 grid(nb, (m->nt + kRangeChunk - 1) / kRangeChunk);
   hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
-                     m->nt, r.nq, m->d_scratch);
+                     m->nt, r.nq, sph, m->d_scratch);
+  MF_HIP(hipGetLastError());
+  MF_HIP(hipFreeAsync(sph, s));
   MF_HIP(hipGetLastError());
   unsigned long long res[2];
   int st[4];
