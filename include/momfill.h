@@ -194,6 +194,25 @@ int mf_fill_near(mf_mesh *mesh, mf_near *pattern, const double *vertices_dev, do
                  int z_dtype, hipStream_t stream);
 void mf_near_destroy(mf_near *pattern);
 
+/* ---- plane-wave scattering (Section IV-B) --------------------------------
+ * Excitation of the EFIE system for E_inc(r) = E0 exp(-j k khat.r):
+ *   out_dev[m] = int f_m . E_inc dS,
+ * with the quad_order rule on each triangle, in FP64 (stored as z_dtype).
+ * khat: host, 3 doubles (unit vector); E0: host, 3 complex as (re, im)
+ * pairs.  k = 0 gives the static excitation. */
+int mf_rhs_planewave(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
+                     const double *khat, const double *E0, void *out_dev, int z_dtype,
+                     hipStream_t stream);
+/* Far field of the currents I_dev (n_edges values of z_dtype) in the
+ * n_dirs unit directions dirs_dev (device, n_dirs*3 doubles), in FP64:
+ *   F_dev[d] = sum_n I_n int f_n exp(+j k rhat_d.r') dS'   (3 complex, (re, im) pairs)
+ * and, when sigma_dev is not NULL, the bistatic cross-section
+ *   sigma_dev[d] = (k eta0)^2/(4 pi) |F - rhat (rhat.F)|^2 / e0_norm^2
+ * (the scattered field being E = -j k eta0 exp(-jkr)/(4 pi r) (F - rhat (rhat.F))). */
+int mf_far_field(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
+                 const void *I_dev, int z_dtype, int32_t n_dirs, const double *dirs_dev,
+                 double e0_norm, double *F_dev, double *sigma_dev, hipStream_t stream);
+
 /* ---- adjoint ------------------------------------------------------------
  * Gradient of L = Re sum_mn conj(W_mn) Z_mn, W = dLdZ_dev (same dtype and
  * layout as Z), with respect to the vertex coordinates (dL_dvertices_dev,

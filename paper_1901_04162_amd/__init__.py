@@ -151,6 +151,38 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     return out
 
 
+def rhs_planewave(mesh: Mesh, V, k: float, quad_order: int, khat, E0,
+                  dtype=torch.complex64) -> torch.Tensor:
+    """V_m = int f_m . E0 exp(-j k khat.r) dS on the current device."""
+    Vd = _vertices(V)
+    kh = np.ascontiguousarray(np.asarray(khat, dtype=np.float64))
+    e0 = np.asarray(E0, dtype=np.complex128)
+    e0 = np.ascontiguousarray(np.stack([e0.real, e0.imag], 1).ravel())
+    out = torch.empty(mesh.n_edges, dtype=dtype, device="cuda")
+    dp = C.POINTER(C.c_double)
+    check(lib().mf_rhs_planewave(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
+                                 int(quad_order), kh.ctypes.data_as(dp), e0.ctypes.data_as(dp),
+                                 C.c_void_p(out.data_ptr()),
+                                 MF_C64 if dtype == torch.complex64 else MF_C128, _stream()))
+    return out
+
+
+def far_field(mesh: Mesh, V, k: float, quad_order: int, I: torch.Tensor, dirs, e0_norm=1.0):
+    """(F [n,3] complex128, sigma [n] float64) for currents I in unit directions dirs."""
+    Vd = _vertices(V)
+    d = torch.as_tensor(np.asarray(dirs, dtype=np.float64)).to("cuda").contiguous()
+    I = I.contiguous()
+    n = d.shape[0]
+    F = torch.empty((n, 3), dtype=torch.complex128, device="cuda")
+    sig = torch.empty(n, dtype=torch.float64, device="cuda")
+    check(lib().mf_far_field(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+                             C.c_void_p(I.data_ptr()),
+                             MF_C64 if I.dtype == torch.complex64 else MF_C128, n,
+                             C.c_void_p(d.data_ptr()), float(e0_norm),
+                             C.c_void_p(F.data_ptr()), C.c_void_p(sig.data_ptr()), _stream()))
+    return F, sig
+
+
 class NearField:
     """CSR pattern of the near-field unknown pairs (edge midpoints at most
     r_near apart) and the fill of their entries."""

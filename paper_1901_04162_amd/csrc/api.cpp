@@ -259,7 +259,7 @@ static void free_mesh(mf_mesh *m) {
   void *ptrs[] = {m->d_tri,       m->d_tedge,   m->d_tsign,   m->d_touch_off, m->d_touch_q,
                   m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos, m->d_tiles, m->d_blk_e0,
                   m->d_rec,       m->d_sing1,   m->d_sing,    m->d_scratch,   m->d_status,
-                  m->d_qp64,      m->d_brad};
+                  m->d_qp64,      m->d_brad,    m->d_edges};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -275,6 +275,7 @@ static int ensure_device(mf_mesh *m) {
   const size_t npair = m->touch_q.size();
   int rc;
   if ((rc = upload(&m->d_tri, m->tri)) || (rc = upload(&m->d_tedge, m->tedge)) ||
+      (rc = upload(&m->d_edges, m->edges)) ||
       (rc = upload(&m->d_tsign, m->tsign)) || (rc = upload(&m->d_touch_off, m->touch_off)) ||
       (rc = upload(&m->d_touch_q, m->touch_q)) || (rc = upload(&m->d_touch_rev, m->touch_rev)) ||
       (rc = upload(&m->d_touch_p, touch_p)) || (rc = upload(&m->d_blk_off, m->blk_off)) ||
@@ -695,6 +696,38 @@ void mf_near_destroy(mf_near *nf) {
   for (int32_t *p : {nf->d_tiles, nf->d_toff, nf->d_ent})
     if (p) (void)hipFree(p);
   delete nf;
+}
+
+int mf_rhs_planewave(mf_mesh *m, const double *V, double k, int quad_order, const double *khat,
+                     const double *E0, void *out, int z_dtype, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !khat || !E0 || !out) return fail(MF_EINVAL, "mf_rhs_planewave: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_rhs_planewave: quad_order must be 3, 6 or 7");
+  if (!(k >= 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_rhs_planewave: k must be >= 0");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_rhs_planewave: unknown z_dtype");
+  const double kn = std::sqrt(khat[0] * khat[0] + khat[1] * khat[1] + khat[2] * khat[2]);
+  if (!(std::fabs(kn - 1.0) < 1e-9)) return fail(MF_EINVAL, "mf_rhs_planewave: khat must be a unit vector");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  return launch_rhs(m, V, r, k, khat, E0, out, z_dtype, s);
+}
+
+int mf_far_field(mf_mesh *m, const double *V, double k, int quad_order, const void *I,
+                 int z_dtype, int32_t n_dirs, const double *dirs, double e0_norm, double *F,
+                 double *sigma, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !I || !dirs || !F || n_dirs < 0)
+    return fail(MF_EINVAL, "mf_far_field: bad argument");
+  if (!make_rule(quad_order, &r)) return fail(MF_EINVAL, "mf_far_field: quad_order must be 3, 6 or 7");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_far_field: k must be > 0");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_far_field: unknown z_dtype");
+  if (sigma && !(e0_norm > 0.0)) return fail(MF_EINVAL, "mf_far_field: e0_norm must be > 0");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if (n_dirs == 0) return MF_OK;
+  return launch_far_field(m, V, r, k, I, z_dtype, n_dirs, dirs, e0_norm * e0_norm, F, sigma, s);
 }
 
 void mf_set_timing(int on) { g_timing = on != 0; }

@@ -73,6 +73,7 @@ struct mf_mesh {
 
   // device copies
   int32_t *d_tri = nullptr, *d_tedge = nullptr;
+  int32_t *d_edges = nullptr;      // ne*6, as edges
   int8_t *d_tsign = nullptr;
   int32_t *d_touch_off = nullptr, *d_touch_q = nullptr, *d_touch_rev = nullptr;
   int32_t *d_touch_p = nullptr;    // p of each touching pair
@@ -110,6 +111,12 @@ int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int pa
                     hipStream_t s, float *out = nullptr);
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s);
+// Plane-wave excitation (E0: 3 complex as re/im pairs) and far field.
+int launch_rhs(mf_mesh *m, const double *V, const Rule &r, double k, const double *khat,
+               const double *E0, void *out, int z_dtype, hipStream_t s);
+int launch_far_field(mf_mesh *m, const double *V, const Rule &r, double k, const void *I,
+                     int z_dtype, int n_dirs, const double *dirs, double e0n2, double *F,
+                     double *sigma, hipStream_t s);
 // Near-field fill: only the listed tiles, scattered into CSR values.
 int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab,
                      const int32_t *tiles, int ntiles, const int32_t *sp_off, const int4 *sp_ent,
