@@ -209,6 +209,51 @@ def near_timing(mf, mesh, V, Vd, k, Q, tables, steps):
     return out
 
 
+def scatter_timing(mf, steps):
+    """The paper's scattering case: a PEC sphere of radius half a wavelength
+    (ka = pi; icosphere with 4 subdivisions, 7,680 unknowns, 6-point rule)
+    under an x-polarised plane wave along z: table fill (tol 1e-6),
+    excitation, dense solve (library LU, complex128), far field in 361
+    E-plane directions; the RCS of the table fill against that of the direct
+    fill (the comparison with the Mie series is a test, not a benchmark)."""
+    import numpy as np
+    import torch
+
+    from paper_1901_04162_amd import meshes
+
+    V, F = meshes.icosphere(4)
+    m = mf.Mesh(F, V.shape[0])
+    k, Q = float(np.pi), 6
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    lo, hi = mf.r_range(m, Vd, Q)
+    T = mf.build_tables(k, lo, hi, 1e-6)
+    th = np.linspace(0.0, np.pi, 361)
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    out = {}
+
+    def run(mode):
+        Z = mf.fill_Z(m, Vd, k, Q, mode, T if mode == "table" else None, dtype=torch.complex64)
+        rhs = mf.rhs_planewave(m, Vd, k, Q, [0, 0, 1.0], [1.0, 0, 0], dtype=torch.complex128)
+        I = torch.linalg.solve(Z.to(torch.complex128), rhs.unsqueeze(1)).squeeze(1)
+        return mf.far_field(m, Vd, k, Q, I, dirs)[1]
+
+    for mode in ("table", "direct"):
+        run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sig = run(mode)
+        torch.cuda.synchronize()
+        out[f"{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+        out[f"{mode}_rcs"] = sig.cpu().numpy()
+    st, sd = out.pop("table_rcs"), out.pop("direct_rcs")
+    out["rcs_rel_l2_table_vs_direct"] = float(np.linalg.norm(st - sd) / np.linalg.norm(sd))
+    out["workload"] = ("PEC sphere, radius half a wavelength (ka = pi), 5120 triangles, 7680 "
+                       "unknowns, x-polarised plane wave along z; fill + excitation + solve + "
+                       "far field")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +269,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-near", action="store_true")
+    ap.add_argument("--no-scatter", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB buffer three times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -355,6 +401,10 @@ def main():
     if not args.no_adjoint:
         log("adjoint ...")
         out["adjoint"] = adjoint_timing(mf, args.steps)
+        torch.cuda.empty_cache()
+    if not args.no_scatter:
+        log("scattering ...")
+        out["scatter"] = scatter_timing(mf, max(1, min(args.steps, 3)))
         torch.cuda.empty_cache()
     if not args.no_sweep:
         log("sweep ...")
