@@ -74,6 +74,12 @@ def lib():
         L.or_loss_local.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
                                     dp, dp, dp, C.c_int, dp]
         L.or_max_threads.argtypes = []
+        L.or_grad_potential.argtypes = [dp, dp, dp, dp, dp]
+        L.or_grad_potential.restype = None
+        L.or_mfie_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
+                                         C.c_int, dp, dp, C.c_int, dp]
+        L.or_mfie_entries.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
+                                      dp, dp, C.c_int64, lp, lp, dp]
         _lib = L
     return _lib
 
@@ -309,3 +315,44 @@ def grad_fd(V, F, edges, k, Q, W, coords=None, with_k=True, h=1e-4):
              for hh in (hk, hk / 2)]
         gk = (4 * d[1] - d[0]) / 3
     return g, gk
+
+
+def grad_potential(x0, x1, x2, r):
+    """Gradient of S(r) = int dS'/|r - r'| over the triangle (x0, x1, x2)."""
+    a = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (x0, x1, x2, r)]
+    g = np.zeros(3)
+    lib().or_grad_potential(*[_pd(v) for v in a], _pd(g))
+    return g
+
+
+def mfie_pair_block(V, F, p, q, k, Q, force_touching=False):
+    """3x3 block of the MFIE K operator for triangles p (test) and q."""
+    V, F = _d(V), _i(F)
+    b, w = _rule(Q)
+    out = np.zeros(18)
+    _check(lib().or_mfie_pair_block(V.shape[0], _pd(V), F.shape[0], _pi(F), int(p), int(q),
+                                    float(k), len(w), _pd(b), _pd(w), int(force_touching),
+                                    _pd(out)), "mfie pair block")
+    return (out[0::2] + 1j * out[1::2]).reshape(3, 3)
+
+
+def mfie_entries(V, F, edges, k, Q, rows, cols):
+    """MFIE matrix entries <f_m, f_n>/2 - K_mn (FP64, direct exponential)."""
+    V, F, edges = _d(V), _i(F), _i(edges)
+    b, w = _rule(Q)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros(2 * rows.size)
+    _check(lib().or_mfie_entries(V.shape[0], _pd(V), F.shape[0], _pi(F), edges.shape[0],
+                                 _pi(edges), float(k), len(w), _pd(b), _pd(w), rows.size,
+                                 _pl(rows), _pl(cols), _pd(out)), "mfie entries")
+    return out[0::2] + 1j * out[1::2]
+
+
+def mfie_fill(V, F, k, Q, edges=None):
+    """Full MFIE matrix, one entry at a time."""
+    if edges is None:
+        edges = rwg(V, F)
+    E = edges.shape[0]
+    rr, cc = np.meshgrid(np.arange(E), np.arange(E), indexing="ij")
+    return mfie_entries(V, F, edges, k, Q, rr.ravel(), cc.ravel()).reshape(E, E)

@@ -985,3 +985,220 @@ int or_max_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* MFIE K operator (the magnetic-field formulation the paper fills beside    */
+/* the EFIE, Section IV-B), FP64, direct exponential.                        */
+/*                                                                          */
+/*   K_mn = <f_m, n x PV int grad G x f_n dS'>                              */
+/*        = -(1/4pi) int int f_m . n x (d x f_n) (1 + jkR) exp(-jkR)/R^3    */
+/* with d = r - r', n the outward normal at r.  With a = r - v_a,           */
+/* b = r' - v_b and t = a x n the integrand is b.(t x d) K(R).  The MFIE    */
+/* matrix is Z_mn = <f_m, f_n>/2 - K_mn.                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient of S(r) = int dS'/|r - r'| over the triangle:
+ *   grad S = -sum_i uh_i f_i - sign(d) Omega n,
+ * uh_i the outward in-plane edge normals, f_i the edge logarithms of S and
+ * Omega the solid angle (sum of the arctangent pairs of S). */
+void or_grad_potential(const double *x0, const double *x1, const double *x2, const double *r,
+                       double *g) {
+  const double *x[3] = {x0, x1, x2};
+  double e1[3], e2[3], n[3];
+  sub3(x1, x0, e1);
+  sub3(x2, x0, e2);
+  cross3(e1, e2, n);
+  const double nn = norm3(n);
+  n[0] /= nn;
+  n[1] /= nn;
+  n[2] /= nn;
+  double rx0[3];
+  sub3(r, x0, rx0);
+  const double d = dot3(n, rx0), ad = fabs(d);
+  const double rho[3] = {r[0] - d * n[0], r[1] - d * n[1], r[2] - d * n[2]};
+  double gi[3] = {0.0, 0.0, 0.0}, omega = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const double *xm = x[i], *xp = x[(i + 1) % 3];
+    double L[3], lh[3], uh[3], pm[3], pp[3];
+    sub3(xp, xm, L);
+    const double len = norm3(L);
+    lh[0] = L[0] / len;
+    lh[1] = L[1] / len;
+    lh[2] = L[2] / len;
+    cross3(lh, n, uh);
+    sub3(xp, rho, pp);
+    sub3(xm, rho, pm);
+    const double lp = dot3(pp, lh), lm = dot3(pm, lh);
+    const double p0 = dot3(pm, uh);
+    const double r0sq = p0 * p0 + d * d;
+    const double Rp = dist3(r, xp), Rm = dist3(r, xm);
+    if (r0sq > 0.0) {
+      const double psp = lp >= 0.0 ? Rp + lp : r0sq / (Rp - lp);
+      const double psm = lm >= 0.0 ? Rm + lm : r0sq / (Rm - lm);
+      const double f = log(psp / psm);
+      for (int c = 0; c < 3; ++c) gi[c] -= uh[c] * f;
+      omega += atan(p0 * lp / (r0sq + ad * Rp)) - atan(p0 * lm / (r0sq + ad * Rm));
+    }
+  }
+  const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+  for (int c = 0; c < 3; ++c) g[c] = gi[c] - sg * omega * n[c];
+}
+
+/* (1 + jkR) exp(-jkR)/R^3 */
+static cplx kkernel(double k, double R) {
+  return (1.0 + I * k * R) * cexp(-I * k * R) / (R * R * R);
+}
+
+/* K(R) - 1/R^3 - k^2/(2R), bounded; Taylor series for kR < 1e-2 */
+static cplx kkernel_rem(double k, double R) {
+  const double x = k * R;
+  if (x < 1e-2) {
+    const double k3 = k * k * k;
+    return -I * k3 / 3.0 - k3 * x / 8.0 + I * k3 * x * x / 30.0 + k3 * x * x * x / 144.0;
+  }
+  return kkernel(k, R) - 1.0 / (R * R * R) - 0.5 * k * k / R;
+}
+
+static void unit_normal(const mesh *M, int t, double *n) {
+  double e1[3], e2[3];
+  sub3(vtx(M, t, 1), vtx(M, t, 0), e1);
+  sub3(vtx(M, t, 2), vtx(M, t, 0), e2);
+  cross3(e1, e2, n);
+  const double nn = norm3(n);
+  n[0] /= nn;
+  n[1] /= nn;
+  n[2] /= nn;
+}
+
+/* X = (1/4) sum_i sum_j w_i w_j b_j.(t_i x d_ij) K(R_ij), t_i = (r_i - v_a) x n_p */
+static void mfie_regular(const mesh *M, double k, int p, int q, int a, int b, cplx *X) {
+  const double *va = vtx(M, p, a), *vb = vtx(M, q, b);
+  double n[3];
+  unit_normal(M, p, n);
+  cplx acc = 0.0;
+  for (int i = 0; i < M->nq; ++i) {
+    const double *ri = qpt(M, p, i);
+    double ua[3], t[3];
+    sub3(ri, va, ua);
+    cross3(ua, n, t);
+    for (int j = 0; j < M->nq; ++j) {
+      const double *rj = qpt(M, q, j);
+      double ub[3], d[3], td[3];
+      sub3(rj, vb, ub);
+      sub3(ri, rj, d);
+      cross3(t, d, td);
+      acc += M->w[i] * M->w[j] * dot3(ub, td) * kkernel(k, norm3(d));
+    }
+  }
+  *X = 0.25 * acc;
+}
+
+/* Touching pair p != q: the inner integral of b.(t x d)[1/R^3 + k^2/(2R)]
+ * in closed form, t.[(-grad S - (k^2/2) V) x (r - v_b)] (d x (r' - v_b) =
+ * d x (r - v_b), int d/R^3 = -grad S, int d/R = -V), the bounded remainder
+ * by the rule. */
+static void mfie_touching(const mesh *M, double k, int p, int q, int a, int b, cplx *X) {
+  const double *va = vtx(M, p, a), *vb = vtx(M, q, b);
+  const double Aq = M->area[q];
+  double n[3];
+  unit_normal(M, p, n);
+  cplx acc = 0.0;
+  for (int i = 0; i < M->nq; ++i) {
+    const double *ri = qpt(M, p, i);
+    double ua[3], t[3], gS[3], S, Vq[3], rb[3], w3[3], cr[3];
+    sub3(ri, va, ua);
+    cross3(ua, n, t);
+    or_grad_potential(vtx(M, q, 0), vtx(M, q, 1), vtx(M, q, 2), ri, gS);
+    or_tri_potentials(vtx(M, q, 0), vtx(M, q, 1), vtx(M, q, 2), ri, &S, Vq);
+    sub3(ri, vb, rb);
+    for (int c = 0; c < 3; ++c) w3[c] = -gS[c] - 0.5 * k * k * Vq[c];
+    cross3(w3, rb, cr);
+    cplx inner = dot3(t, cr) / Aq;
+    for (int j = 0; j < M->nq; ++j) {
+      const double *rj = qpt(M, q, j);
+      double ub[3], d[3], td[3];
+      sub3(rj, vb, ub);
+      sub3(ri, rj, d);
+      cross3(t, d, td);
+      inner += M->w[j] * dot3(ub, td) * kkernel_rem(k, norm3(d));
+    }
+    acc += M->w[i] * inner;
+  }
+  *X = 0.25 * acc;
+}
+
+static void mfie_pair(const mesh *M, double k, int p, int q, int a, int b, int force, cplx *X) {
+  if (p == q) {
+    *X = 0.0; /* flat triangle: the integrand vanishes (principal value) */
+    return;
+  }
+  if (force || touching(M, p, q))
+    mfie_touching(M, k, p, q, a, b, X);
+  else
+    mfie_regular(M, k, p, q, a, b, X);
+}
+
+int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int p, int q, double k,
+                       int nq, const double *bary, const double *w, int force_touching,
+                       double *out18) {
+  if (p < 0 || q < 0 || p >= nt || q >= nt || !(k > 0.0)) return -1;
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  if (rc == 0)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        cplx X;
+        mfie_pair(&M, k, p, q, a, b, force_touching, &X);
+        out18[2 * (3 * a + b)] = creal(X);
+        out18[2 * (3 * a + b) + 1] = cimag(X);
+      }
+  mesh_free(&M);
+  return rc;
+}
+
+/* Z_mn = l_m l_n sum over the four triangle pairs s s' [ [p = q] (1/(8 A_p))
+ * sum_i w_i (r_i - v_a).(r_i - v_b) + X(p,q;a,b)/(4 pi) ]. */
+int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                    const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                    int64_t ns, const int64_t *rows, const int64_t *cols, double *out) {
+  if (!(k > 0.0) || !isfinite(k) || ne <= 0) return -1;
+  for (int64_t s = 0; s < ns; ++s)
+    if (rows[s] < 0 || rows[s] >= ne || cols[s] < 0 || cols[s] >= ne) return -1;
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  if (rc) {
+    mesh_free(&M);
+    return rc;
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t s = 0; s < ns; ++s) {
+    const int32_t *em = edges + 6 * rows[s], *en = edges + 6 * cols[s];
+    const double lm = dist3(V + 3 * (size_t)em[0], V + 3 * (size_t)em[1]);
+    const double ln = dist3(V + 3 * (size_t)en[0], V + 3 * (size_t)en[1]);
+    cplx acc = 0.0;
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        const int p = em[2 + u], a = em[4 + u], q = en[2 + v], b = en[4 + v];
+        const double sg = (u == 0 ? 1.0 : -1.0) * (v == 0 ? 1.0 : -1.0);
+        cplx X;
+        mfie_pair(&M, k, p, q, a, b, 0, &X);
+        cplx val = X / (4.0 * M_PI);
+        if (p == q) {
+          double gram = 0.0;
+          for (int i = 0; i < M.nq; ++i) {
+            double ua[3], ub[3];
+            sub3(qpt(&M, p, i), vtx(&M, p, a), ua);
+            sub3(qpt(&M, p, i), vtx(&M, p, b), ub);
+            gram += M.w[i] * dot3(ua, ub);
+          }
+          val += gram / (8.0 * M.area[p]);
+        }
+        acc += sg * val;
+      }
+    const cplx Z = lm * ln * acc;
+    out[2 * s] = creal(Z);
+    out[2 * s + 1] = cimag(Z);
+  }
+  mesh_free(&M);
+  return 0;
+}

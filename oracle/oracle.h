@@ -113,6 +113,21 @@ int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
 /* Number of threads the OpenMP loops use. */
 int or_max_threads(void);
 
+/* MFIE (magnetic-field) operator, FP64 direct exponential.
+ * Gradient of the triangle potential S at r (g: 3 doubles). */
+void or_grad_potential(const double *x0, const double *x1, const double *x2, const double *r,
+                       double *g);
+/* Pair block X[a][b] of the K operator (see oracle.c), 9 complex; a
+ * non-zero force_touching applies the singularity-subtracted rule to any
+ * pair (test hook). */
+int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int p, int q, double k,
+                       int nq, const double *bary, const double *w, int force_touching,
+                       double *out18);
+/* MFIE matrix entries Z = <f_m, f_n>/2 - K_mn at (rows[s], cols[s]). */
+int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                    const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                    int64_t ns, const int64_t *rows, const int64_t *cols, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,26 @@ def rhs_planewave(V, F, edges, k, bary, w, khat, E0):
     return out
 
 
+def rhs_planewave_mfie(V, F, edges, k, bary, w, khat, E0):
+    """V_m = int f_m . (n x H_inc) dS, H_inc = khat x E0 exp(-j k khat.r)/eta0,
+    n the outward unit normal of each (counter-clockwise) triangle."""
+    V = np.asarray(V, dtype=np.float64)
+    khat = np.asarray(khat, dtype=np.float64)
+    H0 = np.cross(khat, np.asarray(E0, dtype=np.complex128)) / ETA0
+    out = np.zeros(edges.shape[0], dtype=np.complex128)
+    for e, (hp, hm, l) in enumerate(_halves(V, F, edges)):
+        acc = 0.0j
+        for t, v, s in (hp, hm):
+            X = V[F[t]]
+            n = np.cross(X[1] - X[0], X[2] - X[0])
+            n /= np.linalg.norm(n)
+            P = bary @ X
+            ph = np.exp(-1j * k * (P @ khat))
+            acc += s * l / 2.0 * np.sum(w * ph * ((P - V[v]) @ np.cross(n, H0)))
+        out[e] = acc
+    return out
+
+
 def far_field(V, F, edges, I, k, bary, w, dirs):
     """F(rhat) = sum_n I_n int f_n exp(+j k rhat.r') dS' for each unit rhat."""
     V = np.asarray(V, dtype=np.float64)
