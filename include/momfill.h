@@ -148,6 +148,23 @@ int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_orde
               const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
               hipStream_t stream);
 
+/* ---- MFIE fill (Section IV-B: the K operator beside the EFIE) -----------
+ * Z_dev receives the MFIE matrix of the closed PEC surface, tested with the
+ * RWG functions themselves (n the unit normal (x1 - x0) x (x2 - x0) of each
+ * triangle, outward for counter-clockwise triangles seen from outside):
+ *   Z_mn = <f_m, f_n>/2 + (1/4 pi) int int f_m . n x (f_n x grad' G) ...
+ *        = <f_m, f_n>/2 - <f_m, n x PV int grad G x f_n dS'>,
+ * G = exp(-jkR)/(4 pi R), so that Z I = <f_m, n x H_inc> (mf_rhs_planewave_mfie).
+ * Regular pairs use the kernel (1 + jkR) exp(-jkR)/R^3 = (1/R + jk) g/R
+ * with g from the Green table (MF_MODE_TABLE) or computed (MF_MODE_DIRECT);
+ * touching pairs take their singular part in closed form in FP64.  The
+ * matrix is not symmetric: every entry is computed.  mode is MF_MODE_TABLE
+ * or MF_MODE_DIRECT (no MF_PART_ flags); the other arguments, the checks
+ * and the MF_ERANGE report are those of mf_fill_Z. */
+int mf_fill_mfie(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order, int mode,
+                 const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
+                 hipStream_t stream);
+
 /* ---- batched fill (frequency sweeps, several meshes) --------------------
  * One persistent fill launch over n items, item i being (meshes[i],
  * vertices_dev[i], k[i], tables[i], Z_dev[i] with leading dimension
@@ -203,6 +220,12 @@ void mf_near_destroy(mf_near *pattern);
 int mf_rhs_planewave(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
                      const double *khat, const double *E0, void *out_dev, int z_dtype,
                      hipStream_t stream);
+/* MFIE excitation (FP64): out_dev[m] = int f_m . (n x H_inc) dS with
+ * H_inc = (khat x E0) exp(-j k khat.r) / eta0 and n the unit normal
+ * (x1 - x0) x (x2 - x0) of each triangle; arguments as mf_rhs_planewave. */
+int mf_rhs_planewave_mfie(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
+                          const double *khat, const double *E0, void *out_dev, int z_dtype,
+                          hipStream_t stream);
 /* Far field of the currents I_dev (n_edges values of z_dtype) in the
  * n_dirs unit directions dirs_dev (device, n_dirs*3 doubles), in FP64:
  *   F_dev[d] = sum_n I_n int f_n exp(+j k rhat_d.r') dS'   (3 complex, (re, im) pairs)

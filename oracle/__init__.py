@@ -79,7 +79,7 @@ def lib():
         L.or_mfie_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
                                          C.c_int, dp, dp, C.c_int, dp]
         L.or_mfie_entries.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
-                                      dp, dp, C.c_int64, lp, lp, dp]
+                                      dp, dp, C.c_int, vp, C.c_int64, lp, lp, dp]
         _lib = L
     return _lib
 
@@ -336,23 +336,25 @@ def mfie_pair_block(V, F, p, q, k, Q, force_touching=False):
     return (out[0::2] + 1j * out[1::2]).reshape(3, 3)
 
 
-def mfie_entries(V, F, edges, k, Q, rows, cols):
-    """MFIE matrix entries <f_m, f_n>/2 - K_mn (FP64, direct exponential)."""
+def mfie_entries(V, F, edges, k, Q, rows, cols, mode=DIRECT, gtable=None):
+    """MFIE matrix entries <f_m, f_n>/2 - K_mn (FP64); regular pairs take the
+    kernel from the direct exponential or (mode=TABLE) from the Green table."""
     V, F, edges = _d(V), _i(F), _i(edges)
     b, w = _rule(Q)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     cols = np.ascontiguousarray(cols, dtype=np.int64)
     out = np.zeros(2 * rows.size)
     _check(lib().or_mfie_entries(V.shape[0], _pd(V), F.shape[0], _pi(F), edges.shape[0],
-                                 _pi(edges), float(k), len(w), _pd(b), _pd(w), rows.size,
+                                 _pi(edges), float(k), len(w), _pd(b), _pd(w), int(mode),
+                                 gtable.handle if gtable is not None else None, rows.size,
                                  _pl(rows), _pl(cols), _pd(out)), "mfie entries")
     return out[0::2] + 1j * out[1::2]
 
 
-def mfie_fill(V, F, k, Q, edges=None):
+def mfie_fill(V, F, k, Q, edges=None, mode=DIRECT, gtable=None):
     """Full MFIE matrix, one entry at a time."""
     if edges is None:
         edges = rwg(V, F)
     E = edges.shape[0]
     rr, cc = np.meshgrid(np.arange(E), np.arange(E), indexing="ij")
-    return mfie_entries(V, F, edges, k, Q, rr.ravel(), cc.ravel()).reshape(E, E)
+    return mfie_entries(V, F, edges, k, Q, rr.ravel(), cc.ravel(), mode, gtable).reshape(E, E)

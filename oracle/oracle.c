@@ -1070,8 +1070,10 @@ static void unit_normal(const mesh *M, int t, double *n) {
   n[2] /= nn;
 }
 
-/* X = (1/4) sum_i sum_j w_i w_j b_j.(t_i x d_ij) K(R_ij), t_i = (r_i - v_a) x n_p */
-static void mfie_regular(const mesh *M, double k, int p, int q, int a, int b, cplx *X) {
+/* X = (1/4) sum_i sum_j w_i w_j b_j.(t_i x d_ij) K(R_ij), t_i = (r_i - v_a) x n_p.
+ * With a Green table G (table mode) the kernel is K = (1/R + jk) G(R)/R. */
+static int mfie_regular(const mesh *M, double k, const ortable *G, int p, int q, int a, int b,
+                        cplx *X) {
   const double *va = vtx(M, p, a), *vb = vtx(M, q, b);
   double n[3];
   unit_normal(M, p, n);
@@ -1087,10 +1089,21 @@ static void mfie_regular(const mesh *M, double k, int p, int q, int a, int b, cp
       sub3(rj, vb, ub);
       sub3(ri, rj, d);
       cross3(t, d, td);
-      acc += M->w[i] * M->w[j] * dot3(ub, td) * kkernel(k, norm3(d));
+      const double R = norm3(d);
+      cplx K;
+      if (G) {
+        cplx g;
+        int rc = table_value(G, R, &g);
+        if (rc) return rc;
+        K = (1.0 / R + I * k) * g / R;
+      } else {
+        K = kkernel(k, R);
+      }
+      acc += M->w[i] * M->w[j] * dot3(ub, td) * K;
     }
   }
   *X = 0.25 * acc;
+  return 0;
 }
 
 /* Touching pair p != q: the inner integral of b.(t x d)[1/R^3 + k^2/(2R)]
@@ -1127,15 +1140,17 @@ static void mfie_touching(const mesh *M, double k, int p, int q, int a, int b, c
   *X = 0.25 * acc;
 }
 
-static void mfie_pair(const mesh *M, double k, int p, int q, int a, int b, int force, cplx *X) {
+static int mfie_pair(const mesh *M, double k, const ortable *G, int p, int q, int a, int b,
+                     int force, cplx *X) {
   if (p == q) {
     *X = 0.0; /* flat triangle: the integrand vanishes (principal value) */
-    return;
+    return 0;
   }
-  if (force || touching(M, p, q))
+  if (force || touching(M, p, q)) {
     mfie_touching(M, k, p, q, a, b, X);
-  else
-    mfie_regular(M, k, p, q, a, b, X);
+    return 0;
+  }
+  return mfie_regular(M, k, G, p, q, a, b, X);
 }
 
 int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int p, int q, double k,
@@ -1148,7 +1163,7 @@ int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int 
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
         cplx X;
-        mfie_pair(&M, k, p, q, a, b, force_touching, &X);
+        mfie_pair(&M, k, NULL, p, q, a, b, force_touching, &X);
         out18[2 * (3 * a + b)] = creal(X);
         out18[2 * (3 * a + b) + 1] = cimag(X);
       }
@@ -1160,8 +1175,12 @@ int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int 
  * sum_i w_i (r_i - v_a).(r_i - v_b) + X(p,q;a,b)/(4 pi) ]. */
 int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
                     const int32_t *edges, double k, int nq, const double *bary, const double *w,
-                    int64_t ns, const int64_t *rows, const int64_t *cols, double *out) {
+                    int mode, const ortable *gtable, int64_t ns, const int64_t *rows,
+                    const int64_t *cols, double *out) {
   if (!(k > 0.0) || !isfinite(k) || ne <= 0) return -1;
+  if (mode != OR_MODE_DIRECT && mode != OR_MODE_TABLE) return -1;
+  if (mode == OR_MODE_TABLE && (!gtable || gtable->kind != OR_TABLE_GREEN)) return -1;
+  const ortable *G = mode == OR_MODE_TABLE ? gtable : NULL;
   for (int64_t s = 0; s < ns; ++s)
     if (rows[s] < 0 || rows[s] >= ne || cols[s] < 0 || cols[s] >= ne) return -1;
   mesh M;
@@ -1170,6 +1189,7 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
     mesh_free(&M);
     return rc;
   }
+  int err = 0;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t s = 0; s < ns; ++s) {
     const int32_t *em = edges + 6 * rows[s], *en = edges + 6 * cols[s];
@@ -1180,8 +1200,12 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
       for (int v = 0; v < 2; ++v) {
         const int p = em[2 + u], a = em[4 + u], q = en[2 + v], b = en[4 + v];
         const double sg = (u == 0 ? 1.0 : -1.0) * (v == 0 ? 1.0 : -1.0);
-        cplx X;
-        mfie_pair(&M, k, p, q, a, b, 0, &X);
+        cplx X = 0.0;
+        int r2 = mfie_pair(&M, k, G, p, q, a, b, 0, &X);
+        if (r2) {
+#pragma omp atomic write
+          err = r2;
+        }
         cplx val = X / (4.0 * M_PI);
         if (p == q) {
           double gram = 0.0;
@@ -1200,5 +1224,5 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
     out[2 * s + 1] = cimag(Z);
   }
   mesh_free(&M);
-  return 0;
+  return err;
 }

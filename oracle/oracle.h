@@ -126,7 +126,8 @@ int or_mfie_pair_block(int nv, const double *V, int nt, const int32_t *tri, int 
 /* MFIE matrix entries Z = <f_m, f_n>/2 - K_mn at (rows[s], cols[s]). */
 int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
                     const int32_t *edges, double k, int nq, const double *bary, const double *w,
-                    int64_t ns, const int64_t *rows, const int64_t *cols, double *out);
+                    int mode, const ortable *gtable, int64_t ns, const int64_t *rows,
+                    const int64_t *cols, double *out);
 
 #ifdef __cplusplus
 }

@@ -133,17 +133,21 @@ def build_tables(k: float, r_min: float, r_max: float, tol: float) -> Tables:
     return Tables(k, r_min, r_max, tol)
 
 
-def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables: Tables = None,
-           dtype=torch.complex64, out: torch.Tensor = None, part: int = 0) -> torch.Tensor:
-    """Impedance matrix Z (n_edges x n_edges) on the current device."""
-    Vd = _vertices(V)
+def _z_out(mesh: Mesh, dtype, out):
     E = mesh.n_edges
     if out is None:
         out = torch.empty((E, E), dtype=dtype, device="cuda")
     if out.dtype not in (torch.complex64, torch.complex128) or out.dim() != 2 or \
             out.shape[0] < E or out.shape[1] < E or out.stride(1) != 1:
         raise ValueError("out must be a row-major complex64/complex128 matrix of at least E x E")
-    zt = MF_C64 if out.dtype == torch.complex64 else MF_C128
+    return out, (MF_C64 if out.dtype == torch.complex64 else MF_C128)
+
+
+def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables: Tables = None,
+           dtype=torch.complex64, out: torch.Tensor = None, part: int = 0) -> torch.Tensor:
+    """Impedance matrix Z (n_edges x n_edges) on the current device."""
+    Vd = _vertices(V)
+    out, zt = _z_out(mesh, dtype, out)
     m = MODES[mode] | part
     check(lib().mf_fill_Z(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order), m,
                           tables.handle if tables is not None else None,
@@ -151,20 +155,41 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     return out
 
 
-def rhs_planewave(mesh: Mesh, V, k: float, quad_order: int, khat, E0,
-                  dtype=torch.complex64) -> torch.Tensor:
-    """V_m = int f_m . E0 exp(-j k khat.r) dS on the current device."""
+def fill_mfie(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table",
+              tables: Tables = None, dtype=torch.complex64,
+              out: torch.Tensor = None) -> torch.Tensor:
+    """MFIE matrix <f_m, f_n>/2 - K_mn (n_edges x n_edges) on the current device."""
+    Vd = _vertices(V)
+    out, zt = _z_out(mesh, dtype, out)
+    check(lib().mf_fill_mfie(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+                             MODES[mode], tables.handle if tables is not None else None,
+                             C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
+    return out
+
+
+def _rhs(fn, mesh: Mesh, V, k, quad_order, khat, E0, dtype):
     Vd = _vertices(V)
     kh = np.ascontiguousarray(np.asarray(khat, dtype=np.float64))
     e0 = np.asarray(E0, dtype=np.complex128)
     e0 = np.ascontiguousarray(np.stack([e0.real, e0.imag], 1).ravel())
     out = torch.empty(mesh.n_edges, dtype=dtype, device="cuda")
     dp = C.POINTER(C.c_double)
-    check(lib().mf_rhs_planewave(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
-                                 int(quad_order), kh.ctypes.data_as(dp), e0.ctypes.data_as(dp),
-                                 C.c_void_p(out.data_ptr()),
-                                 MF_C64 if dtype == torch.complex64 else MF_C128, _stream()))
+    check(fn(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+             kh.ctypes.data_as(dp), e0.ctypes.data_as(dp), C.c_void_p(out.data_ptr()),
+             MF_C64 if dtype == torch.complex64 else MF_C128, _stream()))
     return out
+
+
+def rhs_planewave(mesh: Mesh, V, k: float, quad_order: int, khat, E0,
+                  dtype=torch.complex64) -> torch.Tensor:
+    """V_m = int f_m . E0 exp(-j k khat.r) dS on the current device."""
+    return _rhs(lib().mf_rhs_planewave, mesh, V, k, quad_order, khat, E0, dtype)
+
+
+def rhs_planewave_mfie(mesh: Mesh, V, k: float, quad_order: int, khat, E0,
+                       dtype=torch.complex64) -> torch.Tensor:
+    """V_m = int f_m . (n x H_inc) dS, H_inc = khat x E0 exp(-j k khat.r)/eta0."""
+    return _rhs(lib().mf_rhs_planewave_mfie, mesh, V, k, quad_order, khat, E0, dtype)
 
 
 def far_field(mesh: Mesh, V, k: float, quad_order: int, I: torch.Tensor, dirs, e0_norm=1.0):

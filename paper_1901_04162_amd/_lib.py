@@ -25,7 +25,8 @@ EXPORTS = [
     "mf_tables_info", "mf_tables_get", "mf_tables_eval", "mf_fill_Z", "mf_fill_Z_backward",
     "mf_sync_status", "mf_set_timing", "mf_mesh_timings", "mf_batch_create", "mf_batch_fill",
     "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
-    "mf_near_destroy", "mf_rhs_planewave", "mf_far_field",
+    "mf_near_destroy", "mf_rhs_planewave", "mf_far_field", "mf_fill_mfie",
+    "mf_rhs_planewave_mfie",
 ]
 
 
@@ -69,6 +70,10 @@ def lib():
         L.mf_near_destroy.argtypes = [vp]
         L.mf_near_destroy.restype = None
         L.mf_rhs_planewave.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int, vp]
+        L.mf_rhs_planewave_mfie.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int,
+                                            vp]
+        L.mf_fill_mfie.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, C.c_int,
+                                   C.c_int64, vp]
         L.mf_far_field.argtypes = [vp, vp, C.c_double, C.c_int, vp, C.c_int, C.c_int32, vp,
                                    C.c_double, vp, vp, vp]
         L.mf_mesh_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmomfill.so")
-SOURCES = ["api.cpp", "geometry.hip", "tables.hip", "fill.hip", "backward.hip", "scatter.hip"]
+SOURCES = ["api.cpp", "geometry.hip", "tables.hip", "fill.hip", "backward.hip", "scatter.hip",
+           "mfie.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

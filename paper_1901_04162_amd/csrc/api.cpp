@@ -493,6 +493,37 @@ int mf_fill_Z(mf_mesh *m, const double *V, double k, int quad_order, int mode,
   return MF_OK;
 }
 
+int mf_fill_mfie(mf_mesh *m, const double *V, double k, int quad_order, int mode,
+                 const mf_tables *tab, void *Z, int z_dtype, int64_t ldz, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !Z) return fail(MF_EINVAL, "mf_fill_mfie: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_fill_mfie: quad_order must be 3, 6 or 7");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_mfie: k must be > 0");
+  if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
+    return fail(MF_EINVAL, "mf_fill_mfie: unknown mode");
+  if (mode == MF_MODE_TABLE && !tab) return fail(MF_EINVAL, "mf_fill_mfie: table mode needs tables");
+  if (mode == MF_MODE_TABLE && std::fabs(tab->k - k) > 1e-12 * k)
+    return fail(MF_EINVAL, "mf_fill_mfie: tables were built for another k");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_fill_mfie: unknown z_dtype");
+  if (ldz < m->ne) return fail(MF_EINVAL, "mf_fill_mfie: ldz < number of edges");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  const bool timed = g_timing;
+  if (timed && !m->ev[0])
+    for (hipEvent_t &e : m->ev) MF_HIP(hipEventCreate(&e));
+  if (timed) MF_HIP(hipEventRecord(m->ev[0], s));
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[1], s));
+  if ((rc = launch_singular_mfie(m, V, r, k, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[2], s));
+  if ((rc = launch_fill(m, r, k, mode | kModeMfie, tab, Z, z_dtype, ldz, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
+  m->timed = timed;
+  return MF_OK;
+}
+
 int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, const double *k,
                     const mf_tables *const *tab, int quad_order, int mode, void *const *Z,
                     int z_dtype, const int64_t *ldz, mf_batch **out) {
@@ -712,6 +743,26 @@ int mf_rhs_planewave(mf_mesh *m, const double *V, double k, int quad_order, cons
   int rc = ensure_device(m);
   if (rc) return rc;
   return launch_rhs(m, V, r, k, khat, E0, out, z_dtype, s);
+}
+
+int mf_rhs_planewave_mfie(mf_mesh *m, const double *V, double k, int quad_order,
+                          const double *khat, const double *E0, void *out, int z_dtype,
+                          hipStream_t s) {
+  Rule r;
+  if (!m || !V || !khat || !E0 || !out)
+    return fail(MF_EINVAL, "mf_rhs_planewave_mfie: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_rhs_planewave_mfie: quad_order must be 3, 6 or 7");
+  if (!(k >= 0.0) || !std::isfinite(k))
+    return fail(MF_EINVAL, "mf_rhs_planewave_mfie: k must be >= 0");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_rhs_planewave_mfie: unknown z_dtype");
+  const double kn = std::sqrt(khat[0] * khat[0] + khat[1] * khat[1] + khat[2] * khat[2]);
+  if (!(std::fabs(kn - 1.0) < 1e-9))
+    return fail(MF_EINVAL, "mf_rhs_planewave_mfie: khat must be a unit vector");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  return launch_rhs(m, V, r, k, khat, E0, out, z_dtype, s, true);
 }
 
 int mf_far_field(mf_mesh *m, const double *V, double k, int quad_order, const void *I,

@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -120,17 +121,92 @@ __device__ __forceinline__ void zero(Moments &M) {
   for (int c = 0; c < 3; ++c) M.spr[c] = M.spi[c] = M.sqr[c] = M.sqi[c] = 0.0f;
 }
 
-// Table mode.  The lookups of one test point go in two groups of source
+// MFIE (K operator).  The kernel is K = (1 + jkR) exp(-jkR)/R^3 =
+// (1/R + jk) g/R, taken from the same Green table, and the integrand of the
+// local entry (a, b) is (r' - v_b).(t_a,i x d) K with t_a,i = (r_i - v_a) x n
+// and d = r - r'.  Writing r_i - v_a = alpha_a + rho_i, r' - v_b = beta_b +
+// rho'_j, a_i = c_p - c_q + rho_i (so d = a_i - rho'_j), tau_a = alpha_a x n,
+// sigma_i = rho_i x n, and per test point T0 = sum_j w_j K, T1 = sum_j w_j K
+// rho'_j (the EFIE's inner sums with K in place of g), the entry needs four
+// moments over the test points:
+//   Md = sum w_i (a_i T0 - T1),       Mx = sum w_i a_i x T1,
+//   Ms = sum w_i sigma_i x (a_i T0 - T1),  M0 = sum w_i sigma_i.(a_i x T1),
+//   X_ab = (beta_b.(tau_a x Md + Ms) + tau_a.Mx + M0)/4.
+struct MomentsM {
+  float dr[3], di[3], xr[3], xi[3], sr[3], si[3], m0r, m0i;
+};
+
+__device__ __forceinline__ void zero(MomentsM &M) {
+  M.m0r = M.m0i = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.dr[c] = M.di[c] = M.xr[c] = M.xi[c] = M.sr[c] = M.si[c] = 0.0f;
+}
+
+__device__ __forceinline__ void cross3(const float *u, const float *v, float *o) {
+  o[0] = fmaf(u[1], v[2], -u[2] * v[1]);
+  o[1] = fmaf(u[2], v[0], -u[0] * v[2]);
+  o[2] = fmaf(u[0], v[1], -u[1] * v[0]);
+}
+
+__device__ __forceinline__ float dot3(const float *u, const float *v) {
+  return fmaf(u[0], v[0], fmaf(u[1], v[1], u[2] * v[2]));
+}
+
+__device__ __forceinline__ void add_point(MomentsM &M, float wi, const float *pri, const float *a,
+                                          const float *nrm, float t0r, float t0i,
+                                          const float *t1r, const float *t1i) {
+  float vr[3], vi[3], cr[3], ci[3], sg[3], u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    vr[c] = wi * fmaf(a[c], t0r, -t1r[c]);
+    vi[c] = wi * fmaf(a[c], t0i, -t1i[c]);
+    M.dr[c] += vr[c];
+    M.di[c] += vi[c];
+  }
+  float wt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wt[c] = wi * t1r[c];
+  cross3(a, wt, cr);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wt[c] = wi * t1i[c];
+  cross3(a, wt, ci);
+  cross3(pri, nrm, sg);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    M.xr[c] += cr[c];
+    M.xi[c] += ci[c];
+  }
+  M.m0r += dot3(sg, cr);
+  M.m0i += dot3(sg, ci);
+  cross3(sg, vr, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.sr[c] += u[c];
+  cross3(sg, vi, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.si[c] += u[c];
+}
+
+// g -> K = (1/R + jk) g / R (MFIE kernel from the Green-function value).
+__device__ __forceinline__ void green_to_k(float k, float ri, float &gr, float &gi) {
+  const float ur = fmaf(gr, ri, -k * gi), ui = fmaf(gi, ri, k * gr);
+  gr = ur * ri;
+  gi = ui * ri;
+}
+
+template <int OP>
+using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>::type;
+
+// Table mode.  The lookups of one test point go in groups of source
 // points, each in three steps (distances and bucket-record reads, then
 // coefficient reads, then the cubic and the sums), so that the dependent LDS
 // reads of a group overlap each other.  The interval search is the bucket lookup of Eq. (6)
 // in the record form of lookup.hpp (one 16-byte read gives the interval and
 // its first sample), and the cubic of Eq. (5) is evaluated in Horner form
 // about that sample.
-template <int Q>
-__device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
+template <int Q, int OP>
+__device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
                                               const FillScalars &S, const FillRule &W,
-                                              const float (&prho)[Q][3],
+                                              const float (&prho)[Q][3], const float *nrm,
                                               float hx, float hy, float hz, float lx, float ly,
                                               float lz, const float *qr, float &rlo,
                                               float &rhi) {
@@ -142,10 +218,12 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
     const float ax = hx + (prho[i][0] + lx), ay = hy + (prho[i][1] + ly),
                 az = hz + (prho[i][2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
-    // two batches of source points keep fewer lookups live at once
+    // batches of source points keep fewer lookups live at once (three for
+    // the MFIE, whose moments hold more registers)
+    constexpr int kG = OP == MF_OP_MFIE ? 3 : 2;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int j0 = half == 0 ? 0 : (Q + 1) / 2, j1 = half == 0 ? (Q + 1) / 2 : Q;
+    for (int grp = 0; grp < kG; ++grp) {
+      const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
       float r[Q];
       int4 w[Q];
 #pragma unroll
@@ -169,7 +247,8 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
 #pragma unroll
       for (int j = j0; j < j1; ++j) {
         const float2 g = cubic(A[j], B[j], u[j]);
-        const float gr = g.x, gi = g.y;
+        float gr = g.x, gi = g.y;
+        if constexpr (OP == MF_OP_MFIE) green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
         t0r = fmaf(W.w[j], gr, t0r);
         t0i = fmaf(W.w[j], gi, t0i);
 #pragma unroll
@@ -180,16 +259,21 @@ __device__ __forceinline__ void moments_table(Moments &M, const TabPtrs &tab,
         }
       }
     }
-    add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);
+    if constexpr (OP == MF_OP_MFIE) {
+      const float a[3] = {ax, ay, az};
+      add_point(M, W.w[i], prho[i], a, nrm, t0r, t0i, t1r, t1i);
+    } else {
+      add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);
+    }
   }
 }
 
 // Direct mode: exp(-jkR)/R from rsqrt and sincos; the test-point loop stays
 // rolled (the inlined sincos is long) and reads rho_i from the record.
-template <int Q>
-__device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S, const FillRule &W,
-                                               const float *pr,
-                                               float hx, float hy, float hz, float lx, float ly,
+template <int Q, int OP>
+__device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScalars &S,
+                                               const FillRule &W, const float *pr,
+                                               const float *nrm, float hx, float hy, float hz, float lx, float ly,
                                                float lz, const float *qr) {
   zero(M);
 #pragma unroll 1
@@ -208,7 +292,8 @@ __device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S,
       const float ri = __builtin_amdgcn_rsqf(r2);
       float sn, cs;
       sincosf(S.k * (r2 * ri), &sn, &cs);
-      const float gr = cs * ri, gi = -sn * ri;
+      float gr = cs * ri, gi = -sn * ri;
+      if constexpr (OP == MF_OP_MFIE) green_to_k(S.k, ri, gr, gi);
       t0r = fmaf(W.w[j], gr, t0r);
       t0i = fmaf(W.w[j], gi, t0i);
 #pragma unroll
@@ -218,7 +303,12 @@ __device__ __forceinline__ void moments_direct(Moments &M, const FillScalars &S,
         t1i[c] = fmaf(wq, gi, t1i[c]);
       }
     }
-    add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
+    if constexpr (OP == MF_OP_MFIE) {
+      const float a[3] = {ax, ay, az};
+      add_point(M, W.w[i], pri, a, nrm, t0r, t0i, t1r, t1i);
+    } else {
+      add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
+    }
   }
 }
 
@@ -237,7 +327,12 @@ __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coe
 // The item's arrays come in as separate __restrict__ parameters: once the
 // function is inlined they carry no-alias scopes, which lets the
 // wave-uniform source records go through scalar loads into SGPRs.
-template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false>
+//
+// The MFIE operator is not symmetric: a tile (I, J) with I != J is then
+// accumulated twice, rows I against columns J and rows J against columns I,
+// each written once.
+template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false,
+          int OP = MF_OP_EFIE>
 __device__ __forceinline__ void fill_tile(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
@@ -245,11 +340,15 @@ __device__ __forceinline__ void fill_tile(
     const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
     const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
     const float *__restrict__ sing, ZT *__restrict__ Z) {
+  constexpr bool kM = OP == MF_OP_MFIE;
   constexpr int kWaves = kFillThreads / 64;
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
   const int tij = tiles[local];
-  const int I = tij >> 16, J = tij & 0xffff;
+  const int I0 = tij >> 16, J0 = tij & 0xffff;
+  const int ndir = kM && I0 != J0 ? 2 : 1;
+  for (int dir = 0; dir < ndir; ++dir) {
+  const int I = dir ? J0 : I0, J = dir ? I0 : J0;
   for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   __syncthreads();
   const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
@@ -273,6 +372,28 @@ __device__ __forceinline__ void fill_tile(
       for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
       psig[a] = pr[kRecSigma + a];
     }
+    // MFIE: unit normal of p (alpha_0 - alpha_a = v_a - v_0) and tau_a =
+    // alpha_a x n, held in place of alpha
+    float nrm[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (kM) {
+      float e1[3], e2[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e1[c] = palpha[0][c] - palpha[1][c];
+        e2[c] = palpha[0][c] - palpha[2][c];
+      }
+      cross3(e1, e2, nrm);
+      const float inv = __builtin_amdgcn_rsqf(dot3(nrm, nrm));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nrm[c] *= inv;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float t[3];
+        cross3(palpha[a], nrm, t);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) palpha[a][c] = t[c];
+      }
+    }
     const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
     const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
     const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
@@ -293,11 +414,32 @@ __device__ __forceinline__ void fill_tile(
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
-        Moments M;
+        MomentsOf<OP> M;
         if (MODE == MF_MODE_TABLE)
-          moments_table<Q>(M, tab, S, W, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          moments_table<Q, OP>(M, tab, S, W, prho, nrm, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
         else
-          moments_direct<Q>(M, S, W, pr, hx, hy, hz, lx, ly, lz, qr);
+          moments_direct<Q, OP>(M, S, W, pr, nrm, hx, hy, hz, lx, ly, lz, qr);
+        if constexpr (kM) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float Yr[3], Yi[3];
+            cross3(palpha[a], M.dr, Yr);
+            cross3(palpha[a], M.di, Yi);
+            const float yr = dot3(palpha[a], M.xr) + M.m0r;
+            const float yi = dot3(palpha[a], M.xi) + M.m0i;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              Yr[c] += M.sr[c];
+              Yi[c] += M.si[c];
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const float *beta = qr + kRecAlpha + 3 * b;
+              Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
+              Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
+            }
+          }
+        } else {
         const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
         const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
@@ -326,6 +468,7 @@ __device__ __forceinline__ void fill_tile(
             Xr[a][b] = vr;
             Xi[a][b] = vi;
           }
+        }
       } else {
         int s = touch_off[p];
         const int s1 = touch_off[p + 1];
@@ -371,6 +514,17 @@ __device__ __forceinline__ void fill_tile(
       Z[en.y] = v;
       if (en.z >= 0) Z[en.z] = v;
     }
+  } else if (kM) {
+    // Z = acc/(4 pi), rows of block I, columns of block J
+    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+    for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+      const int r = e / nj, c = e % nj;
+      ZT v;
+      v.x = S.pref * acc[r * kAccStride + 2 * c];
+      v.y = S.pref * acc[r * kAccStride + 2 * c + 1];
+      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+    }
   } else {
     // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
     const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
@@ -399,9 +553,10 @@ __device__ __forceinline__ void fill_tile(
     }
   }
   __syncthreads();
+  }
 }
 
-template <int Q, int MODE, bool kLDS, int PART, typename ZT, bool kSparse>
+template <int Q, int MODE, bool kLDS, int PART, typename ZT, bool kSparse, int OP = MF_OP_EFIE>
 __global__ __launch_bounds__(fill_threads<MODE>())
 __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
     FillItem S, FillRule W) {
@@ -413,7 +568,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
   float rlo = INFINITY, rhi = 0.0f;
   const int ntiles = S.tile_end - S.tile_begin;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse>(
+    fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse, OP>(
         S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
         S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
@@ -454,7 +609,7 @@ struct FillLaunch {
   FillItem *d_items = nullptr;  // owned; null for a single item
   int total_tiles = 0, n = 0;
   size_t lds = 0;
-  int nq = 0, base = 0, part = 0, z_dtype = 0;
+  int nq = 0, base = 0, part = 0, z_dtype = 0, op = MF_OP_EFIE;
   bool lds_tab = false, sparse = false;
   long long grid = 0;
 };
@@ -483,7 +638,21 @@ static int plan_grid(FillLaunch &L, K kern, int threads) {
 template <int Q, int MODE, bool kLDS, int PART, typename ZT>
 static int launch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
   constexpr int kFillThreads = fill_threads<MODE>();
-  if (L.n == 1 && L.sparse) {
+  if (L.op == MF_OP_MFIE) {
+    if constexpr (PART == 0) {
+      auto kern = k_fill<Q, MODE, kLDS, 0, ZT, false, MF_OP_MFIE>;
+      if (L.grid == 0) {
+        const int rc = plan_grid(L, kern, kFillThreads);
+        if (rc) return rc;
+      }
+      if (plan_only || L.total_tiles == 0) return MF_OK;
+      hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.first,
+                         L.rule);
+    } else {
+      set_error("the MFIE fill has no partial modes");
+      return MF_EINVAL;
+    }
+  } else if (L.n == 1 && L.sparse) {
     auto kern = k_fill<Q, MODE, kLDS, PART, ZT, true>;
     if (L.grid == 0) {
       const int rc = plan_grid(L, kern, kFillThreads);
@@ -600,6 +769,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->nq = r.nq;
   L->base = mode & 0xf;
   L->part = mode & (MF_PART_A | MF_PART_PHI);
+  L->op = (mode & kModeMfie) ? MF_OP_MFIE : MF_OP_EFIE;
   L->z_dtype = z_dtype;
   for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
   L->lds = sizeof(float) * kAccFloats + 16;
@@ -609,6 +779,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   for (int i = 0; i < n; ++i) {
     items[i] = make_item(m[i], r, k[i], L->base, tab ? tab[i] : nullptr, Z[i], ldz[i], sing[i],
                          tiles);
+    if (L->op == MF_OP_MFIE) items[i].pref = (float)(1.0 / (4.0 * M_PI));
     tiles = items[i].tile_end;
     if (L->base == MF_MODE_TABLE) tmax = std::max(tmax, table_lds_bytes(tab[i]));
   }
@@ -625,6 +796,10 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
       L->lds_tab = true;
       L->lds += tmax;
     }
+  }
+  if (!rc && n > 1 && L->op == MF_OP_MFIE) {
+    set_error("the MFIE fill takes one item");
+    rc = MF_EINVAL;
   }
   if (!rc && n > 1) {
     hipError_t e = hipMalloc((void **)&L->d_items, sizeof(FillItem) * n);

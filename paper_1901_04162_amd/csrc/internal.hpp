@@ -13,6 +13,10 @@ namespace mf {
 
 constexpr double kEta0 = 376.730313668;  // free-space wave impedance
 constexpr int kMaxQ = 7;
+// Operator of a fill: the EFIE (L operator) or the MFIE (K operator plus the
+// identity term).  kModeMfie marks an MFIE fill in the internal mode word.
+enum { MF_OP_EFIE = 0, MF_OP_MFIE = 1 };
+constexpr int kModeMfie = 0x100;
 constexpr int kMaxBlockEdges = 88;  // RWG edges per row/column block of a tile
 constexpr int kMaxBlockTris = 64;   // triangles carrying a block's edges (one per lane)
 
@@ -111,9 +115,12 @@ int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int pa
                     hipStream_t s, float *out = nullptr);
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s);
+// MFIE: touching-pair blocks (FP64, one-way, with the identity term on the
+// self pairs) into m->d_sing; then the fill with mode | kModeMfie.
+int launch_singular_mfie(mf_mesh *m, const double *V, const Rule &r, double k, hipStream_t s);
 // Plane-wave excitation (E0: 3 complex as re/im pairs) and far field.
 int launch_rhs(mf_mesh *m, const double *V, const Rule &r, double k, const double *khat,
-               const double *E0, void *out, int z_dtype, hipStream_t s);
+               const double *E0, void *out, int z_dtype, hipStream_t s, bool mfie = false);
 int launch_far_field(mf_mesh *m, const double *V, const Rule &r, double k, const void *I,
                      int z_dtype, int n_dirs, const double *dirs, double e0n2, double *F,
                      double *sigma, hipStream_t s);

@@ -4,6 +4,8 @@
 //
 //   V_m = int f_m . E0 exp(-j k khat.r) dS
 //       = sum over the two triangles of m of s l/2 sum_i w_i (r_i - v).E0 exp(-j k khat.r_i)
+//   MFIE: E0 replaced on each triangle by n x H0, H0 = khat x E0 / eta0
+//       (the tested n x H_inc; n the unit normal (x1 - x0) x (x2 - x0))
 //   F(rhat) = sum_n I_n int f_n exp(+j k rhat.r') dS'
 //   sigma(rhat) = (k eta0)^2/(4 pi) |F - rhat (rhat.F)|^2 / |E0|^2
 #include <hip/hip_runtime.h>
@@ -18,7 +20,7 @@ struct Vec3d {
 };
 
 // One thread per RWG edge.
-template <typename ZT>
+template <typename ZT, bool kMfie>
 __global__ void k_rhs(const double *__restrict__ V, const int32_t *__restrict__ tri,
                       const int32_t *__restrict__ edges, int ne, RuleArg R, double k, Vec3d kh,
                       Vec3d e0r, Vec3d e0i, ZT *__restrict__ out) {
@@ -38,14 +40,40 @@ __global__ void k_rhs(const double *__restrict__ V, const int32_t *__restrict__ 
     double x[3][3];
     for (int v = 0; v < 3; ++v)
       for (int c = 0; c < 3; ++c) x[v][c] = V[3 * (size_t)tri[3 * t + v] + c];
+    // the field the edge function is tested with on this triangle
+    double fr[3], fi[3];
+    if (kMfie) {
+      const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+      const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+      double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                     e1[0] * e2[1] - e1[1] * e2[0]};
+      const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      for (int c = 0; c < 3; ++c) n[c] /= nn;
+      double hr[3], hi[3];  // khat x E0 / eta0
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        hr[c] = (kh.v[c1] * e0r.v[c2] - kh.v[c2] * e0r.v[c1]) / kEta0;
+        hi[c] = (kh.v[c1] * e0i.v[c2] - kh.v[c2] * e0i.v[c1]) / kEta0;
+      }
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        fr[c] = n[c1] * hr[c2] - n[c2] * hr[c1];
+        fi[c] = n[c1] * hi[c2] - n[c2] * hi[c1];
+      }
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        fr[c] = e0r.v[c];
+        fi[c] = e0i.v[c];
+      }
+    }
     for (int i = 0; i < R.nq; ++i) {
       double r[3];
       for (int c = 0; c < 3; ++c)
         r[c] = R.b[i][0] * x[0][c] + R.b[i][1] * x[1][c] + R.b[i][2] * x[2][c];
-      double dr = 0.0, di = 0.0;  // (r - v) . E0
+      double dr = 0.0, di = 0.0;  // (r - v) . field
       for (int c = 0; c < 3; ++c) {
-        dr += (r[c] - x[a][c]) * e0r.v[c];
-        di += (r[c] - x[a][c]) * e0i.v[c];
+        dr += (r[c] - x[a][c]) * fr[c];
+        di += (r[c] - x[a][c]) * fi[c];
       }
       double sn, cs;
       sincos(k * (kh.v[0] * r[0] + kh.v[1] * r[1] + kh.v[2] * r[2]), &sn, &cs);
@@ -130,18 +158,28 @@ __global__ __launch_bounds__(kFarThreads) void k_far_field(
   }
 }
 
+template <bool kMfie>
+static void launch_rhs_t(mf_mesh *m, const double *V, const RuleArg &R, double k, const Vec3d &kh,
+                         const Vec3d &er, const Vec3d &ei, void *out, int z_dtype,
+                         hipStream_t s) {
+  const dim3 grid((m->ne + 127) / 128);
+  if (z_dtype == MF_C64)
+    hipLaunchKernelGGL((k_rhs<float2, kMfie>), grid, dim3(128), 0, s, V, m->d_tri, m->d_edges,
+                       m->ne, R, k, kh, er, ei, reinterpret_cast<float2 *>(out));
+  else
+    hipLaunchKernelGGL((k_rhs<double2, kMfie>), grid, dim3(128), 0, s, V, m->d_tri, m->d_edges,
+                       m->ne, R, k, kh, er, ei, reinterpret_cast<double2 *>(out));
+}
+
 int launch_rhs(mf_mesh *m, const double *V, const Rule &r, double k, const double *khat,
-               const double *E0, void *out, int z_dtype, hipStream_t s) {
+               const double *E0, void *out, int z_dtype, hipStream_t s, bool mfie) {
   RuleArg R = rule_arg(r);
   const Vec3d kh{{khat[0], khat[1], khat[2]}};
   const Vec3d er{{E0[0], E0[2], E0[4]}}, ei{{E0[1], E0[3], E0[5]}};
-  const dim3 grid((m->ne + 127) / 128);
-  if (z_dtype == MF_C64)
-    hipLaunchKernelGGL(k_rhs<float2>, grid, dim3(128), 0, s, V, m->d_tri, m->d_edges, m->ne, R,
-                       k, kh, er, ei, reinterpret_cast<float2 *>(out));
+  if (mfie)
+    launch_rhs_t<true>(m, V, R, k, kh, er, ei, out, z_dtype, s);
   else
-    hipLaunchKernelGGL(k_rhs<double2>, grid, dim3(128), 0, s, V, m->d_tri, m->d_edges, m->ne, R,
-                       k, kh, er, ei, reinterpret_cast<double2 *>(out));
+    launch_rhs_t<false>(m, V, R, k, kh, er, ei, out, z_dtype, s);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

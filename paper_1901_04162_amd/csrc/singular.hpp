@@ -71,6 +71,68 @@ __device__ inline void tri_potentials(const double x[3][3], const double *r, dou
   Vv[2] = vin[2] - h * n[2] * s;
 }
 
+// S, V and grad S = int (r'-r)/|r-r'|^3 dS' of a flat triangle at r.  The
+// gradient has one in-plane term per edge (its outward normal m times the
+// edge logarithm, negated) and a normal term from the solid angle the
+// triangle subtends at r (the arctangent pairs of S): grad S = -sum m_i L_i
+// - sign(h) Omega n, which also follows from differentiating the edge
+// formulas of S.
+__device__ inline void tri_field(const double x[3][3], const double *r, double *S, double *Vv,
+                                 double *G) {
+  const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+  const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+  double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                 e1[0] * e2[1] - e1[1] * e2[0]};
+  const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  n[0] /= nn;
+  n[1] /= nn;
+  n[2] /= nn;
+  const double h = n[0] * (r[0] - x[0][0]) + n[1] * (r[1] - x[0][1]) + n[2] * (r[2] - x[0][2]);
+  const double ah = fabs(h);
+  const double pr[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
+  double s = 0.0, om = 0.0, vin[3] = {0.0, 0.0, 0.0}, gin[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    const double *a = x[i], *b = x[(i + 1) % 3];
+    double t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double len = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    t[0] /= len;
+    t[1] /= len;
+    t[2] /= len;
+    const double m[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2],
+                         t[0] * n[1] - t[1] * n[0]};
+    const double ap[3] = {a[0] - pr[0], a[1] - pr[1], a[2] - pr[2]};
+    const double bp[3] = {b[0] - pr[0], b[1] - pr[1], b[2] - pr[2]};
+    const double sa = ap[0] * t[0] + ap[1] * t[1] + ap[2] * t[2];
+    const double sb = bp[0] * t[0] + bp[1] * t[1] + bp[2] * t[2];
+    const double p0 = ap[0] * m[0] + ap[1] * m[1] + ap[2] * m[2];
+    const double q2 = p0 * p0 + h * h;
+    const double Ra = sqrt((r[0] - a[0]) * (r[0] - a[0]) + (r[1] - a[1]) * (r[1] - a[1]) +
+                           (r[2] - a[2]) * (r[2] - a[2]));
+    const double Rb = sqrt((r[0] - b[0]) * (r[0] - b[0]) + (r[1] - b[1]) * (r[1] - b[1]) +
+                           (r[2] - b[2]) * (r[2] - b[2]));
+    double lg = 0.0, at = 0.0;
+    if (q2 > 0.0) {
+      const double fb = sb >= 0.0 ? Rb + sb : q2 / (Rb - sb);
+      const double fa = sa >= 0.0 ? Ra + sa : q2 / (Ra - sa);
+      lg = log(fb / fa);
+      at = atan(p0 * sb / (q2 + ah * Rb)) - atan(p0 * sa / (q2 + ah * Ra));
+    }
+    s += p0 * lg - ah * at;
+    om += at;
+    const double cv = 0.5 * (q2 * lg + sb * Rb - sa * Ra);
+    for (int c = 0; c < 3; ++c) {
+      vin[c] += cv * m[c];
+      gin[c] -= lg * m[c];
+    }
+  }
+  const double sg = h > 0.0 ? 1.0 : (h < 0.0 ? -1.0 : 0.0);
+  *S = s;
+  for (int c = 0; c < 3; ++c) {
+    Vv[c] = vin[c] - h * n[c] * s;
+    G[c] = gin[c] - sg * om * n[c];
+  }
+}
+
 // (exp(-jkR) - 1)/R, with its Taylor series for kR < 1e-4.
 __device__ inline void ghat(double k, double R, double &re, double &im) {
   const double x = k * R;

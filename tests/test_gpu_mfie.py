@@ -1,0 +1,232 @@
+"""GPU parity of the MFIE fill (K operator plus the identity term) and its
+plane-wave excitation against the FP64 oracle: full matrices of small
+meshes in both modes and both output types, sampled entries of the
+full-size sphere, the touching-only tetrahedron, and the sphere's RCS from
+the GPU solve against the Mie series."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import scatter
+from paper_1901_04162_amd import meshes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_04162_amd as m
+
+    m.lib()
+    return m
+
+
+def _maxrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+@pytest.fixture(scope="module")
+def ico2(orc):
+    V, F = meshes.icosphere(2)
+    V = meshes.jitter_uniform(V, F, 0.05, 61)
+    k, Q = 2 * np.pi, 6
+    E = orc.rwg(V, F)
+    Zd = orc.mfie_fill(V, F, k, Q, edges=E)
+    rmin, rmax = orc.r_range(V, F, Q)
+    Zt = {}
+    for tol in (1e-6, 1e-3):
+        G = orc.build_table(orc.GREEN, k, rmin, rmax, tol)
+        Zt[tol] = orc.mfie_fill(V, F, k, Q, edges=E, mode=orc.TABLE, gtable=G)
+    # entries whose four triangles touch nowhere: only the kernel from the
+    # table enters them (the identity term dominates max |Z| otherwise)
+    B = np.zeros((E.shape[0], V.shape[0]))
+    for e, (_, _, tp, tm, _, _) in enumerate(E):
+        B[e, F[tp]] = 1
+        B[e, F[tm]] = 1
+    return dict(V=V, F=F, k=k, Q=Q, E=E, Zd=Zd, Zt=Zt, reg=(B @ B.T) == 0)
+
+
+def _maxrel_on(a, b, mask):
+    a, b = np.asarray(a)[mask], np.asarray(b)[mask]
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_mfie_full_matrix_direct(mf, ico2, dtype):
+    import torch
+
+    c = ico2
+    say("mfie full ico2 direct", dtype)
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    Z = mf.fill_mfie(m, c["V"], c["k"], c["Q"], "direct", dtype=getattr(torch, dtype))
+    mf.sync_status(m)
+    e = _maxrel(Z.cpu().numpy(), c["Zd"])
+    say("max rel", e)
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("tol", [1e-6, 1e-3])
+def test_mfie_full_matrix_table(mf, ico2, dtype, tol):
+    """Against the oracle's table mode with the same table, on every entry
+    and on the regular entries alone.  At tolerance 1e-3 the table's own
+    error (1e-5 of the largest regular entry) stands well above the FP32
+    error, so the GPU must follow the table, not the exponential."""
+    import torch
+
+    c = ico2
+    say("mfie full ico2 table", dtype, tol)
+    m = mf.Mesh(c["F"], c["V"].shape[0])
+    lo, hi = mf.r_range(m, c["V"], c["Q"])
+    T = mf.build_tables(c["k"], lo, hi, tol)
+    Z = mf.fill_mfie(m, c["V"], c["k"], c["Q"], "table", T, dtype=getattr(torch, dtype))
+    mf.sync_status(m)
+    Z = Z.cpu().numpy()
+    e_t = _maxrel(Z, c["Zt"][tol])
+    r_t = _maxrel_on(Z, c["Zt"][tol], c["reg"])
+    r_d = _maxrel_on(Z, c["Zd"], c["reg"])
+    say("max rel vs oracle-table", e_t, "regular entries vs oracle-table", r_t,
+        "vs oracle-direct", r_d)
+    assert e_t <= 1e-6 and r_t <= 2e-6
+    if tol == 1e-3:
+        assert r_d > 3 * r_t
+
+
+def test_mfie_tetrahedron_touching_only(mf, orc):
+    import torch
+
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    F = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], dtype=np.int32)
+    say("mfie tetrahedron")
+    m = mf.Mesh(F, 4)
+    Z = mf.fill_mfie(m, V, 2.0, 7, "direct", dtype=torch.complex128).cpu().numpy()
+    assert _maxrel(Z, orc.mfie_fill(V, F, 2.0, 7)) < 1e-6
+
+
+@pytest.mark.parametrize("s", [0, 1])
+def test_mfie_single_ragged_tile(mf, orc, s):
+    import torch
+
+    V, F = meshes.icosphere(s)
+    V = meshes.jitter_uniform(V, F, 0.05, 70 + s)
+    say("mfie small mesh", s)
+    m = mf.Mesh(F, V.shape[0])
+    Z = mf.fill_mfie(m, V, 3.0, 7, "direct", dtype=torch.complex128).cpu().numpy()
+    assert _maxrel(Z, orc.mfie_fill(V, F, 3.0, 7)) < 1e-6
+
+
+def test_mfie_sampled_entries_full_size(mf, orc):
+    """The 20,480-triangle sphere at k = 17 (Q = 7), table mode at tolerance
+    1e-5 as the benchmark runs it: random entries and entries of touching
+    edge pairs against the oracle with the same table."""
+    import torch
+
+    V, F = meshes.icosphere(5)
+    k, Q, tol = 17.0, 7, 1e-5
+    m = mf.Mesh(F, V.shape[0])
+    E = m.edges()
+    lo, hi = mf.r_range(m, V, Q)
+    T = mf.build_tables(k, lo, hi, tol)
+    say("mfie ico5 table fill")
+    Z = mf.fill_mfie(m, V, k, Q, "table", T)
+    mf.sync_status(m)
+    rng = np.random.default_rng(17)
+    rows = rng.integers(0, E.shape[0], 1500)
+    cols = rng.integers(0, E.shape[0], 1500)
+    # touching pairs: a column edge sharing a triangle with the row edge
+    tr = rng.integers(0, E.shape[0], 300)
+    tc = np.array([int(rng.choice(np.nonzero(np.isin(E[:, 2], E[r, 2:4]) |
+                                             np.isin(E[:, 3], E[r, 2:4]))[0])) for r in tr])
+    rows, cols = np.concatenate([rows, tr]), np.concatenate([cols, tc])
+    got = Z[torch.tensor(rows, device=Z.device), torch.tensor(cols, device=Z.device)]
+    got = got.cpu().numpy().astype(np.complex128)
+    G = orc.build_table(orc.GREEN, k, lo, hi, tol)
+    want_t = orc.mfie_entries(V, F, E, k, Q, rows, cols, mode=orc.TABLE, gtable=G)
+    want_d = orc.mfie_entries(V, F, E, k, Q, rows, cols)
+    scale = np.abs(want_d).max()
+    e_t = np.abs(got - want_t).max() / scale
+    e_d = np.abs(got - want_d).max() / scale
+    # the random entries alone (almost all regular pairs), on their own scale
+    n = 1500
+    rs = np.abs(want_d[:n]).max()
+    r_t = np.abs(got[:n] - want_t[:n]).max() / rs
+    r_d = np.abs(got[:n] - want_d[:n]).max() / rs
+    say("sampled max rel vs oracle-table", e_t, "vs oracle-direct", e_d,
+        "random entries", r_t, r_d)
+    assert e_t <= 1e-6 and e_d <= 2e-5 and r_t <= 2e-6 and r_d <= 5e-5
+
+
+def test_mfie_rhs_matches_oracle(mf, orc):
+    import torch
+
+    V, F = meshes.icosphere(2)
+    V = meshes.jitter_uniform(V, F, 0.05, 8)
+    m = mf.Mesh(F, V.shape[0])
+    E = m.edges()
+    kh = np.array([0.3, -0.2, 0.93])
+    kh /= np.linalg.norm(kh)
+    E0 = np.array([1.0, 0.5j, -0.2])
+    b, w = orc.quad_rule(6)
+    got = mf.rhs_planewave_mfie(m, V, 2.5, 6, kh, E0, dtype=torch.complex128).cpu().numpy()
+    want = scatter.rhs_planewave_mfie(V, F, E, 2.5, b, w, kh, E0)
+    assert _maxrel(got, want) < 1e-12
+
+
+def test_mfie_sphere_rcs_vs_mie(mf, orc):
+    """ka = 1 unit sphere, 1,920 unknowns: the MFIE filled on the GPU (table
+    and direct), solved for an x-polarised wave along z, gives the Mie E-plane
+    RCS as the oracle's MFIE does (1.8 % on this mesh)."""
+    import torch
+
+    V, F = meshes.icosphere(3)
+    k, Q = 1.0, 6
+    m = mf.Mesh(F, V.shape[0])
+    lo, hi = mf.r_range(m, V, Q)
+    T = mf.build_tables(k, lo, hi, 1e-6)
+    rhs = mf.rhs_planewave_mfie(m, V, k, Q, [0, 0, 1.0], [1.0, 0, 0], dtype=torch.complex128)
+    th = np.linspace(0.0, np.pi, 37)
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    ref = scatter.mie_rcs(k, 1.0, th, "E")
+    sig = {}
+    for mode in ("table", "direct"):
+        Z = mf.fill_mfie(m, V, k, Q, mode, T if mode == "table" else None,
+                         dtype=torch.complex128)
+        mf.sync_status(m)
+        I = torch.linalg.solve(Z.cpu(), rhs.cpu()).to(Z.device)
+        _, s = mf.far_field(m, V, k, Q, I, dirs)
+        sig[mode] = s.cpu().numpy()
+        err = float(np.linalg.norm(sig[mode] - ref) / np.linalg.norm(ref))
+        say(mode, "rcs error vs Mie", err)
+        assert 0.01 < err < 0.025
+    assert _maxrel(sig["table"], sig["direct"]) < 1e-5
+
+
+def test_mfie_rejects_bad_arguments(mf):
+    import ctypes as C
+
+    import torch
+
+    V, F = meshes.icosphere(1)
+    m = mf.Mesh(F, V.shape[0])
+    E = m.n_edges
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+    args = lambda mode, tab, ldz: (m.handle, C.c_void_p(Vd.data_ptr()), 1.0, 6, mode, tab,
+                                   C.c_void_p(Z.data_ptr()), mf.MF_C64, ldz, None)
+    L = mf.lib()
+    assert L.mf_fill_mfie(*args(mf.MF_MODE_DIRECT | mf.MF_PART_A, None, E)) == mf._lib.MF_EINVAL
+    assert L.mf_fill_mfie(*args(mf.MF_MODE_TABLE, None, E)) == mf._lib.MF_EINVAL
+    assert L.mf_fill_mfie(*args(mf.MF_MODE_DIRECT, None, E - 1)) == mf._lib.MF_EINVAL
+    with pytest.raises(ValueError):
+        mf.fill_mfie(m, V, 1.0, 6, "direct", out=Z[:1])

@@ -185,3 +185,20 @@ def test_mfie_sphere_rcs_converges_to_mie(orc):
     print("mfie rcs error vs Mie: ico2", r2, "ico3", r3, "current vs efie", c2, c3)
     assert r2 < 0.07 and r3 < 0.025 and r3 < 0.5 * r2
     assert c2 < 0.025 and c3 < 0.01 and c3 < 0.6 * c2
+
+
+def test_table_mode_converges_to_direct(orc):
+    """The MFIE kernel taken from the Green table, (1/R + jk) G(R)/R, tends
+    to the direct kernel as the table tolerance tightens."""
+    V, F = meshes.icosphere(1)
+    V = meshes.jitter_uniform(V, F, 0.05, 5)
+    E = orc.rwg(V, F)
+    k, Q = 6.0, 6
+    Zd = orc.mfie_fill(V, F, k, Q, edges=E)
+    rmin, rmax = orc.r_range(V, F, Q)
+    errs = []
+    for tol in (1e-4, 1e-8):
+        G = orc.build_table(orc.GREEN, k, rmin, rmax, tol)
+        Zt = orc.mfie_fill(V, F, k, Q, edges=E, mode=orc.TABLE, gtable=G)
+        errs.append(np.abs(Zt - Zd).max() / np.abs(Zd).max())
+    assert errs[1] < 1e-8 and errs[1] < 1e-2 * errs[0]
