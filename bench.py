@@ -209,13 +209,63 @@ def near_timing(mf, mesh, V, Vd, k, Q, tables, steps):
     return out
 
 
+def mfie_timing(mf, mesh, Vd, k, Q, tables, steps):
+    """The MFIE (K operator) on the same sphere: table and direct fill times
+    (every entry computed: the operator is not symmetric) and the elementwise
+    relative error of the table fill's real and imaginary parts against the
+    direct fill (the paper's Fig. 3 measure), on a fixed sample of entries."""
+    import numpy as np
+    import torch
+
+    E = mesh.n_edges
+    out = {}
+    Zs = {}
+    for mode in ("table", "direct"):
+        Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+        tab = tables if mode == "table" else None
+        mf.fill_mfie(mesh, Vd, k, Q, mode, tab, out=Z)
+        torch.cuda.synchronize()
+        mf.set_timing(True)
+        ph = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mf.fill_mfie(mesh, Vd, k, Q, mode, tab, out=Z)
+            ph.append(mf.timings(mesh))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        mf.set_timing(False)
+        mf.sync_status(mesh)
+        ph = np.array(ph)
+        out[f"{mode}_ms"] = dt * 1e3
+        out[f"{mode}_fill_ms"] = float(ph[:, 2].mean())
+        out[f"{mode}_touching_fp64_ms"] = float(ph[:, 1].mean())
+        out[f"{mode}_z_entries_per_s"] = E * E / dt
+        Zs[mode] = Z
+    out["table_over_direct"] = out["direct_ms"] / out["table_ms"]
+    g = torch.Generator(device="cuda").manual_seed(5)
+    idx = torch.randint(0, E * E, (1 << 20,), device="cuda", generator=g)
+    zt = Zs["table"].view(-1)[idx].to(torch.complex128)
+    zd = Zs["direct"].view(-1)[idx].to(torch.complex128)
+    for part, f in (("real", torch.real), ("imag", torch.imag)):
+        rel = (torch.abs(f(zt) - f(zd)) / torch.abs(f(zd)).clamp_min(1e-30)).cpu().numpy()
+        out[f"rel_err_{part}_median"] = float(np.median(rel))
+        out[f"rel_err_{part}_p99"] = float(np.percentile(rel, 99))
+    out["max_abs_err_over_max_abs"] = float(
+        (Zs["table"] - Zs["direct"]).abs().max() / Zs["direct"].abs().max())
+    out["error_sample_entries"] = int(idx.numel())
+    del Zs
+    torch.cuda.empty_cache()
+    return out
+
+
 def scatter_timing(mf, steps):
     """The paper's scattering case: a PEC sphere of radius half a wavelength
     (ka = pi; icosphere with 4 subdivisions, 7,680 unknowns, 6-point rule)
     under an x-polarised plane wave along z: table fill (tol 1e-6),
     excitation, dense solve (library LU, complex128), far field in 361
-    E-plane directions; the RCS of the table fill against that of the direct
-    fill (the comparison with the Mie series is a test, not a benchmark)."""
+    E-plane directions, with the EFIE and with the MFIE; the RCS of each table
+    fill against that of its direct fill (the comparison with the Mie series
+    is a test, not a benchmark)."""
     import numpy as np
     import torch
 
@@ -231,32 +281,38 @@ def scatter_timing(mf, steps):
     dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
     out = {}
 
-    def run(mode):
-        Z = mf.fill_Z(m, Vd, k, Q, mode, T if mode == "table" else None, dtype=torch.complex64)
-        rhs = mf.rhs_planewave(m, Vd, k, Q, [0, 0, 1.0], [1.0, 0, 0], dtype=torch.complex128)
+    def run(mode, op):
+        fill = mf.fill_Z if op == "efie" else mf.fill_mfie
+        rhs_fn = mf.rhs_planewave if op == "efie" else mf.rhs_planewave_mfie
+        Z = fill(m, Vd, k, Q, mode, T if mode == "table" else None, dtype=torch.complex64)
+        rhs = rhs_fn(m, Vd, k, Q, [0, 0, 1.0], [1.0, 0, 0], dtype=torch.complex128)
         I = torch.linalg.solve(Z.to(torch.complex128), rhs.unsqueeze(1)).squeeze(1)
         return mf.far_field(m, Vd, k, Q, I, dirs)[1]
 
-    for mode in ("table", "direct"):
-        run(mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            sig = run(mode)
-        torch.cuda.synchronize()
-        out[f"{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
-        out[f"{mode}_rcs"] = sig.cpu().numpy()
-    st, sd = out.pop("table_rcs"), out.pop("direct_rcs")
-    out["rcs_rel_l2_table_vs_direct"] = float(np.linalg.norm(st - sd) / np.linalg.norm(sd))
+    for op in ("efie", "mfie"):
+        pre = "" if op == "efie" else "mfie_"
+        for mode in ("table", "direct"):
+            run(mode, op)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                sig = run(mode, op)
+            torch.cuda.synchronize()
+            out[f"{pre}{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+            out[f"{pre}{mode}_rcs"] = sig.cpu().numpy()
+        st, sd = out.pop(f"{pre}table_rcs"), out.pop(f"{pre}direct_rcs")
+        out[f"{pre}rcs_rel_l2_table_vs_direct"] = float(np.linalg.norm(st - sd) /
+                                                       np.linalg.norm(sd))
     out["workload"] = ("PEC sphere, radius half a wavelength (ka = pi), 5120 triangles, 7680 "
                        "unknowns, x-polarised plane wave along z; fill + excitation + solve + "
-                       "far field")
+                       "far field, EFIE and MFIE")
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--no-mfie", action="store_true")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--subdiv", type=int, default=5)
@@ -395,6 +451,9 @@ def main():
     }
     del Z
     torch.cuda.empty_cache()
+    if not args.no_mfie:
+        log("mfie ...")
+        out["mfie"] = mfie_timing(mf, mesh, Vd, k, Q, T, args.steps)
     if not args.no_near:
         log("near field ...")
         out["near_field"] = near_timing(mf, mesh, V, Vd, k, Q, T, args.steps)
