@@ -78,6 +78,11 @@ def lib():
         L.or_grad_potential.restype = None
         L.or_mfie_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
                                          C.c_int, dp, dp, C.c_int, dp]
+        L.or_angular_inner.argtypes = [dp, dp, dp, dp, C.c_double, C.c_int, C.c_int, vp, dp]
+        L.or_angular_entries.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double,
+                                         C.c_int, dp, dp, C.c_int, C.c_int, vp, C.c_int64, lp,
+                                         lp, dp]
+        L.or_angular_rmax.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, dp, dp, dp]
         L.or_mfie_entries.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
                                       dp, dp, C.c_int, vp, C.c_int64, lp, lp, dp]
         _lib = L
@@ -358,3 +363,46 @@ def mfie_fill(V, F, k, Q, edges=None, mode=DIRECT, gtable=None):
     E = edges.shape[0]
     rr, cc = np.meshgrid(np.arange(E), np.arange(E), indexing="ij")
     return mfie_entries(V, F, edges, k, Q, rr.ravel(), cc.ravel(), mode, gtable).reshape(E, E)
+
+
+def angular_inner(x0, x1, x2, r, k, n, mode=DIRECT, etable=None):
+    """(I0, I1): int_q exp(-jkR)/R dS' and int_q (r' - rho0) exp(-jkR)/R dS' by
+    the angular transformation with n points per edge."""
+    out = np.zeros(8)
+    a = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (x0, x1, x2, r)]
+    _check(lib().or_angular_inner(*[_pd(v) for v in a], float(k), int(n), int(mode),
+                                  etable.handle if etable is not None else None, _pd(out)),
+           "angular inner")
+    return complex(out[0], out[1]), out[2::2] + 1j * out[3::2]
+
+
+def angular_entries(V, F, edges, k, Q, n_edge, rows, cols, mode=DIRECT, etable=None):
+    """EFIE entries with every inner integral by the angular transformation."""
+    V, F, edges = _d(V), _i(F), _i(edges)
+    b, w = _rule(Q)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros(2 * rows.size)
+    _check(lib().or_angular_entries(V.shape[0], _pd(V), F.shape[0], _pi(F), edges.shape[0],
+                                    _pi(edges), float(k), len(w), _pd(b), _pd(w), int(n_edge),
+                                    int(mode), etable.handle if etable is not None else None,
+                                    rows.size, _pl(rows), _pl(cols), _pd(out)), "angular entries")
+    return out[0::2] + 1j * out[1::2]
+
+
+def angular_fill(V, F, k, Q, n_edge, edges=None, mode=DIRECT, etable=None):
+    if edges is None:
+        edges = rwg(V, F)
+    E = edges.shape[0]
+    rr, cc = np.meshgrid(np.arange(E), np.arange(E), indexing="ij")
+    return angular_entries(V, F, edges, k, Q, n_edge, rr.ravel(), cc.ravel(), mode,
+                           etable).reshape(E, E)
+
+
+def angular_rmax(V, F, Q):
+    V, F = _d(V), _i(F)
+    b, w = _rule(Q)
+    out = C.c_double()
+    _check(lib().or_angular_rmax(V.shape[0], _pd(V), F.shape[0], _pi(F), len(w), _pd(b), _pd(w),
+                                 C.byref(out)), "angular rmax")
+    return out.value

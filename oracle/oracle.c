@@ -620,7 +620,11 @@ static int table_fill(ortable *T, double t, int refine, int zeros, double mu, do
 int or_table_build(int kind, double k, double rmin, double rmax, double tol, double t, int refine,
                    int zeros, double mu, double win, double ratio, ortable **out) {
   if (!out || (kind != OR_TABLE_EXP && kind != OR_TABLE_GREEN)) return -1;
-  if (!(k > 0.0) || !isfinite(k) || !(rmin > 0.0) || !(rmax > rmin)) return -1;
+  /* Exp(-jkr) has no singularity at the origin (Section II-B): its table may
+   * start at r = 0; the Green function's may not */
+  if (!(k > 0.0) || !isfinite(k) || !(kind == OR_TABLE_EXP ? rmin >= 0.0 : rmin > 0.0) ||
+      !(rmax > rmin))
+    return -1;
   if (!(mu > 0.0) || !(win > 0.0) || !(ratio > mu)) return -1;
   if (!(t > 0.0) && !(tol >= 1e-12 && tol <= 1e-1)) return -1;
   ortable *T = (ortable *)calloc(1, sizeof(ortable));
@@ -1225,4 +1229,253 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
   }
   mesh_free(&M);
   return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* EFIE inner integrals by the angular transformation (Section II-A: n      */
+/* points on each of the three source edges, 3mn Exp evaluations per source  */
+/* triangle and m outer points).                                             */
+/*                                                                          */
+/* Observation point r, source triangle q with unit normal n, r = rho0 + h n */
+/* (rho0 in the plane).  Edge i runs from x_i to x_{i+1}; t_i is its unit    */
+/* tangent, m_i = t_i x n its outward in-plane normal, p_i = m_i.(x_i -      */
+/* rho0) the signed distance from rho0 (positive on the triangle's side),    */
+/* l runs along the edge from the foot of the perpendicular, and on the edge */
+/* R(l)^2 = d^2 + l^2 with d^2 = p_i^2 + h^2.                                */
+/*                                                                          */
+/*   I0 = int_q exp(-jkR)/R dS'                                              */
+/*   In polar coordinates about rho0 (the angular transformation), R dR =    */
+/*   rho drho makes the radial integral exact: int_0^{rho_e} exp(-jkR)/R     */
+/*   rho drho = (exp(-jk|h|) - exp(-jkR_e))/(jk).  The triangle is the       */
+/*   signed sum of the triangles (rho0, edge i), and the edge is seen under  */
+/*   dphi = |p_i| dl/(p_i^2 + l^2):                                          */
+/*   I0 = (1/jk) sum_i p_i int_edge [exp(-jk|h|) - exp(-jkR)] dl/(p_i^2 + l^2). */
+/*                                                                          */
+/*   I1 = int_q (r' - rho0) exp(-jkR)/R dS'                                  */
+/*   The in-plane gradient of exp(-jkR) is -jk exp(-jkR)(r' - rho0)/R, so    */
+/*   I1 = (j/k) int_q grad' exp(-jkR) dS' = (j/k) sum_i m_i int_edge          */
+/*   exp(-jkR) dl (surface divergence theorem).                              */
+/*                                                                          */
+/* Both edge integrals take the same n Gauss-Legendre points in u, l = d    */
+/* sinh(u), R = d cosh(u), dl = R du: the map is smooth through the foot of  */
+/* the perpendicular, where R(l) has its kink and the angular weight its    */
+/* peak, and exp(-jkR) is computed (or read from the linear Exp table, mode  */
+/* OR_MODE_TABLE) once per point for both integrals.  An edge with d = 0     */
+/* (r on the edge's line) takes the points in l and adds nothing to I0.      */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre polynomial P_n(z) and its derivative (three-term recurrence). */
+static void legendre(int n, double z, double *pn, double *dpn) {
+  double p0 = 1.0, p1 = z;
+  for (int j = 2; j <= n; ++j) {
+    const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = p1;
+  *dpn = n * (z * p1 - p0) / (z * z - 1.0);
+}
+
+/* Gauss-Legendre nodes and weights on [0, 1] (Newton's method on P_n). */
+static void gauss01(int n, double *x, double *w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), pn, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, z, &pn, &dp);
+      const double dz = pn / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    legendre(n, z, &pn, &dp);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static int exp_value(const ortable *E, double k, double R, cplx *v) {
+  if (!E) {
+    *v = cexp(-I * k * R);
+    return 0;
+  }
+  return table_value(E, R, v);
+}
+
+#define OR_MAX_EDGE_PTS 16
+
+/* I0 (one complex) and I1 (three complex) at r for the triangle x0 x1 x2. */
+static int angular_inner(const double *x0, const double *x1, const double *x2, const double *r,
+                         double k, int n, const double *gx, const double *gw, const ortable *E,
+                         cplx *I0, cplx *I1) {
+  const double *x[3] = {x0, x1, x2};
+  double e1[3], e2[3], nrm[3];
+  sub3(x1, x0, e1);
+  sub3(x2, x0, e2);
+  cross3(e1, e2, nrm);
+  const double nn = norm3(nrm);
+  for (int c = 0; c < 3; ++c) nrm[c] /= nn;
+  double rx0[3];
+  sub3(r, x0, rx0);
+  const double h = dot3(nrm, rx0), ah = fabs(h);
+  const double rho0[3] = {r[0] - h * nrm[0], r[1] - h * nrm[1], r[2] - h * nrm[2]};
+  const cplx eh = cexp(-I * k * ah);
+  cplx a0 = 0.0, a1[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    const double *xa = x[i], *xb = x[(i + 1) % 3];
+    double t[3], m[3], da[3], db[3];
+    sub3(xb, xa, t);
+    const double len = norm3(t);
+    for (int c = 0; c < 3; ++c) t[c] /= len;
+    cross3(t, nrm, m);
+    sub3(xa, rho0, da);
+    sub3(xb, rho0, db);
+    const double p = dot3(m, da), lm = dot3(t, da), lp = dot3(t, db);
+    const double d = sqrt(p * p + h * h);
+    cplx s0 = 0.0, s1 = 0.0; /* the two edge integrals */
+    if (d > 0.0) {
+      const double u0 = asinh(lm / d), du = asinh(lp / d) - u0;
+      for (int j = 0; j < n; ++j) {
+        const double u = u0 + du * gx[j];
+        const double l = d * sinh(u), R = d * cosh(u);
+        cplx ev;
+        int rc = exp_value(E, k, R, &ev);
+        if (rc) return rc;
+        s0 += gw[j] * du * R * (eh - ev) / (p * p + l * l);
+        s1 += gw[j] * du * R * ev;
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        const double l = lm + (lp - lm) * gx[j];
+        cplx ev;
+        int rc = exp_value(E, k, fabs(l), &ev);
+        if (rc) return rc;
+        s1 += gw[j] * (lp - lm) * ev;
+      }
+    }
+    a0 += p * s0;
+    for (int c = 0; c < 3; ++c) a1[c] += m[c] * s1;
+  }
+  *I0 = a0 / (I * k);
+  for (int c = 0; c < 3; ++c) I1[c] = (I / k) * a1[c];
+  return 0;
+}
+
+int or_angular_inner(const double *x0, const double *x1, const double *x2, const double *r,
+                     double k, int n, int mode, const ortable *etable, double *out8) {
+  if (!(k > 0.0) || n < 1 || n > OR_MAX_EDGE_PTS) return -1;
+  if (mode == OR_MODE_TABLE && (!etable || etable->kind != OR_TABLE_EXP)) return -1;
+  double gx[OR_MAX_EDGE_PTS], gw[OR_MAX_EDGE_PTS];
+  gauss01(n, gx, gw);
+  cplx I0, I1[3];
+  int rc = angular_inner(x0, x1, x2, r, k, n, gx, gw, mode == OR_MODE_TABLE ? etable : NULL, &I0,
+                         I1);
+  if (rc) return rc;
+  out8[0] = creal(I0);
+  out8[1] = cimag(I0);
+  for (int c = 0; c < 3; ++c) {
+    out8[2 + 2 * c] = creal(I1[c]);
+    out8[3 + 2 * c] = cimag(I1[c]);
+  }
+  return 0;
+}
+
+/* X(p,q;a,b) = (1/A_q) sum_i w_i [ (r_i - v_a).Psi_b(r_i)/4 - Phi(r_i)/k^2 ],
+ * Phi = I0, Psi_b = I1 + (rho0 - v_b) I0, for every pair (touching or not). */
+static int angular_pair(const mesh *M, double k, int n, const double *gx, const double *gw,
+                        const ortable *E, int p, int q, int a, int b, cplx *X) {
+  const double *va = vtx(M, p, a), *vb = vtx(M, q, b);
+  double e1[3], e2[3], nrm[3];
+  sub3(vtx(M, q, 1), vtx(M, q, 0), e1);
+  sub3(vtx(M, q, 2), vtx(M, q, 0), e2);
+  cross3(e1, e2, nrm);
+  const double nn = norm3(nrm);
+  for (int c = 0; c < 3; ++c) nrm[c] /= nn;
+  cplx acc = 0.0;
+  for (int i = 0; i < M->nq; ++i) {
+    const double *ri = qpt(M, p, i);
+    cplx I0, I1[3];
+    int rc = angular_inner(vtx(M, q, 0), vtx(M, q, 1), vtx(M, q, 2), ri, k, n, gx, gw, E, &I0, I1);
+    if (rc) return rc;
+    double rx0[3];
+    sub3(ri, vtx(M, q, 0), rx0);
+    const double h = dot3(nrm, rx0);
+    cplx dotv = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double rho0 = ri[c] - h * nrm[c];
+      dotv += (ri[c] - va[c]) * (I1[c] + (rho0 - vb[c]) * I0);
+    }
+    acc += M->w[i] * (0.25 * dotv - I0 / (k * k));
+  }
+  *X = acc / M->area[q];
+  return 0;
+}
+
+int or_angular_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                       const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                       int n_edge, int mode, const ortable *etable, int64_t ns,
+                       const int64_t *rows, const int64_t *cols, double *out) {
+  if (!(k > 0.0) || !isfinite(k) || ne <= 0 || n_edge < 1 || n_edge > OR_MAX_EDGE_PTS) return -1;
+  if (mode != OR_MODE_DIRECT && mode != OR_MODE_TABLE) return -1;
+  if (mode == OR_MODE_TABLE && (!etable || etable->kind != OR_TABLE_EXP)) return -1;
+  for (int64_t s = 0; s < ns; ++s)
+    if (rows[s] < 0 || rows[s] >= ne || cols[s] < 0 || cols[s] >= ne) return -1;
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  if (rc) {
+    mesh_free(&M);
+    return rc;
+  }
+  double gx[OR_MAX_EDGE_PTS], gw[OR_MAX_EDGE_PTS];
+  gauss01(n_edge, gx, gw);
+  const ortable *E = mode == OR_MODE_TABLE ? etable : NULL;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < ns; ++s) {
+    const int32_t *em = edges + 6 * rows[s], *en = edges + 6 * cols[s];
+    const double lm = dist3(V + 3 * (size_t)em[0], V + 3 * (size_t)em[1]);
+    const double ln = dist3(V + 3 * (size_t)en[0], V + 3 * (size_t)en[1]);
+    cplx acc = 0.0;
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        const int p = em[2 + u], a = em[4 + u], q = en[2 + v], b = en[4 + v];
+        const double sg = (u == 0 ? 1.0 : -1.0) * (v == 0 ? 1.0 : -1.0);
+        cplx X = 0.0;
+        int r2 = angular_pair(&M, k, n_edge, gx, gw, E, p, q, a, b, &X);
+        if (r2) {
+#pragma omp atomic write
+          err = r2;
+        }
+        acc += sg * X;
+      }
+    const cplx Z = (I * k * OR_ETA0 / (4.0 * M_PI)) * lm * ln * acc;
+    out[2 * s] = creal(Z);
+    out[2 * s + 1] = cimag(Z);
+  }
+  mesh_free(&M);
+  return err;
+}
+
+/* Largest distance from a quadrature point to a vertex of another triangle:
+ * the upper end of the Exp table for the angular scheme (the distance to a
+ * point of an edge never exceeds the distance to one of its ends). */
+int or_angular_rmax(int nv, const double *V, int nt, const int32_t *tri, int nq,
+                    const double *bary, const double *w, double *rmax) {
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  if (rc) {
+    mesh_free(&M);
+    return rc;
+  }
+  double best = 0.0;
+#pragma omp parallel for reduction(max : best) schedule(dynamic, 64)
+  for (int p = 0; p < nt; ++p)
+    for (int i = 0; i < nq; ++i) {
+      const double *ri = qpt(&M, p, i);
+      for (int v = 0; v < nv; ++v) {
+        const double d = dist3(ri, V + 3 * (size_t)v);
+        if (d > best) best = d;
+      }
+    }
+  *rmax = best;
+  mesh_free(&M);
+  return 0;
 }

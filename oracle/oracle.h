@@ -132,4 +132,20 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
 #ifdef __cplusplus
 }
 #endif
+
+/* EFIE inner integrals by the angular transformation (Section II-A):
+ * out8 = I0 = int_q exp(-jkR)/R dS' (re, im) and I1 = int_q (r' - rho0)
+ * exp(-jkR)/R dS' (three complex), rho0 the projection of r on the plane,
+ * n Gauss-Legendre points per edge (1..16); mode OR_MODE_TABLE reads
+ * exp(-jkR) from the linear Exp table etable. */
+int or_angular_inner(const double *x0, const double *x1, const double *x2, const double *r,
+                     double k, int n, int mode, const ortable *etable, double *out8);
+/* EFIE entries with every inner integral by the angular transformation. */
+int or_angular_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                       const int32_t *edges, double k, int nq, const double *bary, const double *w,
+                       int n_edge, int mode, const ortable *etable, int64_t ns,
+                       const int64_t *rows, const int64_t *cols, double *out);
+/* Largest quadrature-point-to-vertex distance (the Exp table's upper end). */
+int or_angular_rmax(int nv, const double *V, int nt, const int32_t *tri, int nq,
+                    const double *bary, const double *w, double *rmax);
 #endif
