@@ -1260,8 +1260,9 @@ int or_mfie_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
 /* sinh(u), R = d cosh(u), dl = R du: the map is smooth through the foot of  */
 /* the perpendicular, where R(l) has its kink and the angular weight its    */
 /* peak, and exp(-jkR) is computed (or read from the linear Exp table, mode  */
-/* OR_MODE_TABLE) once per point for both integrals.  An edge with d = 0     */
-/* (r on the edge's line) takes the points in l and adds nothing to I0.      */
+/* OR_MODE_TABLE) once per point for both integrals; exp(-jk|h|) comes from */
+/* the same source.  An edge with d = 0 (r on the edge's line) takes the    */
+/* points in l and adds nothing to I0.                                       */
 /* ------------------------------------------------------------------------ */
 
 /* Legendre polynomial P_n(z) and its derivative (three-term recurrence). */
@@ -1317,7 +1318,11 @@ static int angular_inner(const double *x0, const double *x1, const double *x2, c
   sub3(r, x0, rx0);
   const double h = dot3(nrm, rx0), ah = fabs(h);
   const double rho0[3] = {r[0] - h * nrm[0], r[1] - h * nrm[1], r[2] - h * nrm[2]};
-  const cplx eh = cexp(-I * k * ah);
+  /* exp(-jk|h|) from the same source as the edge values, so that the
+   * differences exp(-jk|h|) - exp(-jkR) carry one interpolant, not two */
+  cplx eh;
+  int rc0 = exp_value(E, k, ah, &eh);
+  if (rc0) return rc0;
   cplx a0 = 0.0, a1[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 3; ++i) {
     const double *xa = x[i], *xb = x[(i + 1) % 3];
