@@ -165,6 +165,39 @@ int mf_fill_mfie(mf_mesh *mesh, const double *vertices_dev, double k, int quad_o
                  const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
                  hipStream_t stream);
 
+/* ---- angular-transformation fill (Section II-A) --------------------------
+ * The paper's own inner scheme: for every test point r (the quad_order rule
+ * on the test triangle) and every source triangle, touching or not, the
+ * inner integrals I0 = int_q exp(-jkR)/R dS' and I1 = int_q (r' - rho0)
+ * exp(-jkR)/R dS' (rho0 the projection of r on the source plane) become sums
+ * over the three source edges: polar coordinates about rho0 make the radial
+ * integral exact (R dR = rho drho), and I1 is (j/k) times the boundary
+ * integral of exp(-jkR) times the outward edge normal.  Each edge takes
+ * n_edge (4, 6 or 8) Gauss-Legendre points in u, l = d sinh u along the edge
+ * (d the distance from r to the edge's line), and one exp(-jkR) per point
+ * serves both integrals: from the linear Exp table (MF_MODE_TABLE; built by
+ * mf_build_exp_table over [0, r_max] with r_max from mf_angular_rmax) or
+ * computed (MF_MODE_DIRECT; tables may be NULL).  The integrals are FP64;
+ * entries are accumulated in FP32 and written as z_dtype.  Z_dev receives all
+ * n_edges x n_edges entries of the EFIE matrix in the units of mf_fill_Z
+ * (the scheme is not symmetric, every entry is computed).  A distance beyond
+ * the table's r_max is reported as MF_ERANGE by mf_sync_status. */
+int mf_fill_angular(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order,
+                    int n_edge, int mode, const mf_tables *exp_table, void *Z_dev, int z_dtype,
+                    int64_t ldz, hipStream_t stream);
+/* Largest distance (FP64, exact) from a quadrature point of the quad_order
+ * rule to a mesh vertex: every distance the angular fill evaluates is at
+ * most this (the distance to a point of an edge never exceeds that to one of
+ * its ends).  *r_max is host memory; synchronises `stream`. */
+int mf_angular_rmax(mf_mesh *mesh, const double *vertices_dev, int quad_order, double *r_max,
+                    hipStream_t stream);
+/* The linear Exp(-jkr) table alone (Sections II-B, II-C) over [0, r_max]:
+ * Exp(-jkr) has no singularity at the origin, so the table starts at 0.
+ * Same placement, hash and probe check as mf_build_tables; the Green table
+ * is not built (mf_fill_Z, mf_fill_mfie, the batch, the near field and the
+ * adjoint reject such tables). */
+int mf_build_exp_table(double k, double r_max, double tol, mf_tables **out, hipStream_t stream);
+
 /* ---- batched fill (frequency sweeps, several meshes) --------------------
  * One persistent fill launch over n items, item i being (meshes[i],
  * vertices_dev[i], k[i], tables[i], Z_dev[i] with leading dimension

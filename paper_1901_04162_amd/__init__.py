@@ -60,7 +60,7 @@ class Mesh:
         check(lib().mf_mesh_plan(self._h, C.byref(nb), C.byref(nt), C.byref(mt)))
         return nb.value, nt.value, mt.value
 
-    def __del__(self):
+    def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_mesh_destroy(self._h)
             self._h = None
@@ -69,10 +69,16 @@ class Mesh:
 class Tables:
     """Device tables of Exp(-jkr) (linear) and Exp(-jkr)/r (cubic Lagrange)."""
 
-    def __init__(self, k: float, r_min: float, r_max: float, tol: float):
+    def __init__(self, k: float, r_min: float, r_max: float, tol: float, exp_only: bool = False):
         h = C.c_void_p()
-        check(lib().mf_build_tables(float(k), float(r_min), float(r_max), float(tol),
-                                    C.byref(h), _stream()))
+        if exp_only:
+            if r_min != 0.0:
+                raise ValueError("the Exp table alone starts at r = 0")
+            check(lib().mf_build_exp_table(float(k), float(r_max), float(tol), C.byref(h),
+                                           _stream()))
+        else:
+            check(lib().mf_build_tables(float(k), float(r_min), float(r_max), float(tol),
+                                        C.byref(h), _stream()))
         self._h = h
         self.k, self.r_min, self.r_max, self.tol = float(k), float(r_min), float(r_max), float(tol)
         ne, ng, me, mg = (C.c_int32() for _ in range(4))
@@ -108,7 +114,7 @@ class Tables:
                                    _stream()))
         return out
 
-    def __del__(self):
+    def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_tables_destroy(self._h)
             self._h = None
@@ -131,6 +137,35 @@ def r_range(mesh: Mesh, V, quad_order: int):
 
 def build_tables(k: float, r_min: float, r_max: float, tol: float) -> Tables:
     return Tables(k, r_min, r_max, tol)
+
+
+def angular_rmax(mesh: Mesh, V, quad_order: int) -> float:
+    """Largest quadrature-point-to-vertex distance (exact, FP64): the upper
+    end of the Exp table of the angular-transformation fill."""
+    Vd = _vertices(V)
+    out = C.c_double()
+    check(lib().mf_angular_rmax(mesh.handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
+                                C.byref(out), _stream()))
+    return out.value
+
+
+def build_exp_table(k: float, r_max: float, tol: float) -> Tables:
+    """The linear Exp(-jkr) table alone, over [0, r_max]."""
+    return Tables(k, 0.0, r_max, tol, exp_only=True)
+
+
+def fill_angular(mesh: Mesh, V, k: float, quad_order: int, n_edge: int = 8,
+                 mode: str = "table", table: Tables = None, dtype=torch.complex64,
+                 out: torch.Tensor = None) -> torch.Tensor:
+    """EFIE matrix with every inner integral by the angular transformation
+    (n_edge points per source edge, FP64 integrals)."""
+    Vd = _vertices(V)
+    out, zt = _z_out(mesh, dtype, out)
+    check(lib().mf_fill_angular(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
+                                int(quad_order), int(n_edge), MODES[mode],
+                                table.handle if table is not None else None,
+                                C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
+    return out
 
 
 def _z_out(mesh: Mesh, dtype, out):
@@ -245,7 +280,7 @@ class NearField:
                                  C.c_void_p(out.data_ptr()), zt, _stream()))
         return out
 
-    def __del__(self):
+    def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_near_destroy(self._h)
             self._h = None
@@ -297,7 +332,7 @@ class Batch:
     def fill(self):
         check(lib().mf_batch_fill(self._h, _stream()))
 
-    def __del__(self):
+    def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_batch_destroy(self._h)
             self._h = None

@@ -26,7 +26,7 @@ EXPORTS = [
     "mf_sync_status", "mf_set_timing", "mf_mesh_timings", "mf_batch_create", "mf_batch_fill",
     "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
     "mf_near_destroy", "mf_rhs_planewave", "mf_far_field", "mf_fill_mfie",
-    "mf_rhs_planewave_mfie",
+    "mf_rhs_planewave_mfie", "mf_fill_angular", "mf_angular_rmax", "mf_build_exp_table",
 ]
 
 
@@ -72,6 +72,10 @@ def lib():
         L.mf_rhs_planewave.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int, vp]
         L.mf_rhs_planewave_mfie.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int,
                                             vp]
+        L.mf_fill_angular.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp,
+                                      C.c_int, C.c_int64, vp]
+        L.mf_angular_rmax.argtypes = [vp, vp, C.c_int, dp, vp]
+        L.mf_build_exp_table.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(vp), vp]
         L.mf_fill_mfie.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, C.c_int,
                                    C.c_int64, vp]
         L.mf_far_field.argtypes = [vp, vp, C.c_double, C.c_int, vp, C.c_int, C.c_int32, vp,

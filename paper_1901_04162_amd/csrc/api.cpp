@@ -417,10 +417,33 @@ int mf_build_tables(double k, double rmin, double rmax, double tol, mf_tables **
   return MF_OK;
 }
 
+int mf_build_exp_table(double k, double rmax, double tol, mf_tables **out, hipStream_t s) {
+  if (!out) return fail(MF_EINVAL, "mf_build_exp_table: out is NULL");
+  *out = nullptr;
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_build_exp_table: k must be > 0");
+  if (!(rmax > 0.0) || !std::isfinite(rmax))
+    return fail(MF_EINVAL, "mf_build_exp_table: need r_max > 0");
+  if (!(tol >= 1e-12 && tol <= 1e-1))
+    return fail(MF_EINVAL, "mf_build_exp_table: tol must lie in [1e-12, 1e-1]");
+  mf_tables *t = new (std::nothrow) mf_tables;
+  if (!t) return fail(MF_ENOMEM, "mf_build_exp_table: out of host memory");
+  t->k = k;
+  t->rmin = 0.0;
+  t->rmax = rmax;
+  t->tol = tol;
+  int rc = build_tables_device(t, tol, s, false);
+  if (rc) {
+    mf_tables_destroy(t);
+    return rc;
+  }
+  *out = t;
+  return MF_OK;
+}
+
 void mf_tables_destroy(mf_tables *t) {
   if (!t) return;
   for (mf_tables::One *o : {&t->e, &t->g}) {
-    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef};
+    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef, o->rec64};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -458,6 +481,8 @@ int mf_tables_eval(const mf_tables *t, int which, int64_t n, const double *r, do
                    hipStream_t s) {
   if (!t || (which != 0 && which != 1) || n < 0 || (n > 0 && (!r || !out)))
     return fail(MF_EINVAL, "mf_tables_eval: bad argument");
+  if ((which == 0 ? t->e.n : t->g.n) == 0)
+    return fail(MF_EINVAL, "mf_tables_eval: this table was not built");
   if (n == 0) return MF_OK;
   return launch_table_eval(t, which, n, r, out, s);
 }
@@ -472,7 +497,8 @@ int mf_fill_Z(mf_mesh *m, const double *V, double k, int quad_order, int mode,
   if ((base != MF_MODE_TABLE && base != MF_MODE_DIRECT) || (mode & ~0x3f) ||
       part == (MF_PART_A | MF_PART_PHI))
     return fail(MF_EINVAL, "mf_fill_Z: unknown mode");
-  if (base == MF_MODE_TABLE && !tab) return fail(MF_EINVAL, "mf_fill_Z: table mode needs tables");
+  if (base == MF_MODE_TABLE && (!tab || tab->g.n == 0))
+    return fail(MF_EINVAL, "mf_fill_Z: table mode needs a Green table");
   if (base == MF_MODE_TABLE && std::fabs(tab->k - k) > 1e-12 * k)
     return fail(MF_EINVAL, "mf_fill_Z: tables were built for another k");
   if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_fill_Z: unknown z_dtype");
@@ -502,7 +528,8 @@ int mf_fill_mfie(mf_mesh *m, const double *V, double k, int quad_order, int mode
   if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_mfie: k must be > 0");
   if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
     return fail(MF_EINVAL, "mf_fill_mfie: unknown mode");
-  if (mode == MF_MODE_TABLE && !tab) return fail(MF_EINVAL, "mf_fill_mfie: table mode needs tables");
+  if (mode == MF_MODE_TABLE && (!tab || tab->g.n == 0))
+    return fail(MF_EINVAL, "mf_fill_mfie: table mode needs a Green table");
   if (mode == MF_MODE_TABLE && std::fabs(tab->k - k) > 1e-12 * k)
     return fail(MF_EINVAL, "mf_fill_mfie: tables were built for another k");
   if (z_dtype != MF_C64 && z_dtype != MF_C128)
@@ -519,6 +546,53 @@ int mf_fill_mfie(mf_mesh *m, const double *V, double k, int quad_order, int mode
   if ((rc = launch_singular_mfie(m, V, r, k, s))) return rc;
   if (timed) MF_HIP(hipEventRecord(m->ev[2], s));
   if ((rc = launch_fill(m, r, k, mode | kModeMfie, tab, Z, z_dtype, ldz, s))) return rc;
+  if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
+  m->timed = timed;
+  return MF_OK;
+}
+
+int mf_angular_rmax(mf_mesh *m, const double *V, int quad_order, double *rmax, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !rmax) return fail(MF_EINVAL, "mf_angular_rmax: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_angular_rmax: quad_order must be 3, 6 or 7");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  return launch_range_angular(m, V, r, rmax, s);
+}
+
+int mf_fill_angular(mf_mesh *m, const double *V, double k, int quad_order, int n_edge, int mode,
+                    const mf_tables *tab, void *Z, int z_dtype, int64_t ldz, hipStream_t s) {
+  Rule r;
+  if (!m || !V || !Z) return fail(MF_EINVAL, "mf_fill_angular: NULL argument");
+  if (!make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_fill_angular: quad_order must be 3, 6 or 7");
+  if (n_edge != 4 && n_edge != 6 && n_edge != 8)
+    return fail(MF_EINVAL, "mf_fill_angular: points per edge must be 4, 6 or 8");
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_angular: k must be > 0");
+  if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
+    return fail(MF_EINVAL, "mf_fill_angular: unknown mode");
+  if (mode == MF_MODE_TABLE &&
+      (!tab || tab->e.n < 2 || !tab->e.rec64 || tab->rmin != 0.0 ||
+       std::fabs(tab->k - k) > 1e-12 * k))
+    return fail(MF_EINVAL,
+                "mf_fill_angular: table mode needs an Exp table from r = 0 built for this k");
+  if (z_dtype != MF_C64 && z_dtype != MF_C128)
+    return fail(MF_EINVAL, "mf_fill_angular: unknown z_dtype");
+  if (ldz < m->ne) return fail(MF_EINVAL, "mf_fill_angular: ldz < number of edges");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  const bool timed = g_timing;
+  if (timed && !m->ev[0])
+    for (hipEvent_t &e : m->ev) MF_HIP(hipEventCreate(&e));
+  if (timed) MF_HIP(hipEventRecord(m->ev[0], s));
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  if (timed) {
+    MF_HIP(hipEventRecord(m->ev[1], s));
+    MF_HIP(hipEventRecord(m->ev[2], s));  // no separate touching-pair phase
+  }
+  if ((rc = launch_fill_angular(m, V, r, k, n_edge, mode, tab, Z, z_dtype, ldz, s))) return rc;
   if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
   m->timed = timed;
   return MF_OK;
@@ -545,8 +619,9 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, c
     const std::string at = "mf_batch_create: item " + std::to_string(i) + ": ";
     if (!meshes[i] || !V[i] || !Z[i]) return fail(MF_EINVAL, at + "NULL argument");
     if (!(k[i] > 0.0) || !std::isfinite(k[i])) return fail(MF_EINVAL, at + "k must be > 0");
-    if (base == MF_MODE_TABLE && (!tab[i] || std::fabs(tab[i]->k - k[i]) > 1e-12 * k[i]))
-      return fail(MF_EINVAL, at + "tables missing or built for another k");
+    if (base == MF_MODE_TABLE &&
+        (!tab[i] || tab[i]->g.n == 0 || std::fabs(tab[i]->k - k[i]) > 1e-12 * k[i]))
+      return fail(MF_EINVAL, at + "tables missing, without a Green table or built for another k");
     if (ldz[i] < meshes[i]->ne) return fail(MF_EINVAL, at + "ldz < number of edges");
     for (int j = 0; j < i; ++j)
       if (meshes[j] == meshes[i] && V[j] != V[i])
@@ -707,8 +782,8 @@ int mf_fill_near(mf_mesh *m, mf_near *nf, const double *V, double k, int quad_or
   if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_near: k must be > 0");
   if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
     return fail(MF_EINVAL, "mf_fill_near: unknown mode");
-  if (mode == MF_MODE_TABLE && (!tab || std::fabs(tab->k - k) > 1e-12 * k))
-    return fail(MF_EINVAL, "mf_fill_near: tables missing or built for another k");
+  if (mode == MF_MODE_TABLE && (!tab || tab->g.n == 0 || std::fabs(tab->k - k) > 1e-12 * k))
+    return fail(MF_EINVAL, "mf_fill_near: tables missing, without a Green table or built for another k");
   if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_fill_near: unknown z_dtype");
   int rc = ensure_device(m);
   if (rc) return rc;
@@ -800,8 +875,8 @@ int mf_fill_Z_backward(mf_mesh *m, const double *V, double k, int quad_order, in
   if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_fill_Z_backward: k must be > 0");
   if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
     return fail(MF_EINVAL, "mf_fill_Z_backward: unknown mode");
-  if (mode == MF_MODE_TABLE && !tab)
-    return fail(MF_EINVAL, "mf_fill_Z_backward: table mode needs tables");
+  if (mode == MF_MODE_TABLE && (!tab || tab->g.n == 0))
+    return fail(MF_EINVAL, "mf_fill_Z_backward: table mode needs the Green and Exp tables");
   if (z_dtype != MF_C64 && z_dtype != MF_C128)
     return fail(MF_EINVAL, "mf_fill_Z_backward: unknown z_dtype");
   if (ldz < m->ne) return fail(MF_EINVAL, "mf_fill_Z_backward: ldz < number of edges");

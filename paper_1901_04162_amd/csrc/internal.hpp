@@ -56,6 +56,9 @@ struct mf_tables {
     int mb = 0;
     float binv = 0.0f, bbias = 0.0f, btop = 0.0f;
     float4 *coef = nullptr;
+    // FP64 interval records of the Exp table (n-1 records of 6 doubles:
+    // r_i, E_i (re, im), slope (re, im), r_{i+1}) for the FP64 lookup
+    double *rec64 = nullptr;
   } e, g;
 };
 
@@ -135,7 +138,13 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
                        const float *const *sing, FillLaunch **out);
 int fill_launch_run(FillLaunch *L, hipStream_t s);
 void fill_launch_destroy(FillLaunch *L);
-int build_tables_device(mf_tables *t, double tol, hipStream_t s);
+int build_tables_device(mf_tables *t, double tol, hipStream_t s, bool green = true);
+// Angular-transformation fill (FP64 inner integrals on every pair).
+int launch_range_angular(mf_mesh *m, const double *V, const Rule &r, double *rmax,
+                         hipStream_t s);
+int launch_fill_angular(mf_mesh *m, const double *V, const Rule &r, double k, int n_edge,
+                        int mode, const mf_tables *tab, void *Z, int z_dtype, int64_t ldz,
+                        hipStream_t s);
 int launch_table_eval(const mf_tables *t, int which, int64_t n, const double *r, double *out,
                       hipStream_t s);
 int launch_backward(mf_mesh *m, const double *V, const Rule &r, double k, int mode,

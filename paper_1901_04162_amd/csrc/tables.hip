@@ -330,6 +330,20 @@ __global__ void k_pack_exp(const double *r, const double *f, int n, float4 *coef
   coef[i] = make_float4((float)vr, (float)vi, (float)sr, (float)si);
 }
 
+// FP64 interval records of the linear Exp table: {r_i, E_i, slope, r_{i+1}}.
+__global__ void k_pack_exp64(const double *r, const double *f, int n, double *rec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const double h = r[i + 1] - r[i];
+  double *o = rec + 6 * (size_t)i;
+  o[0] = r[i];
+  o[1] = f[2 * i];
+  o[2] = f[2 * i + 1];
+  o[3] = (f[2 * i + 2] - f[2 * i]) / h;
+  o[4] = (f[2 * i + 3] - f[2 * i + 1]) / h;
+  o[5] = r[i + 1];
+}
+
 // ---- host driver ---------------------------------------------------------
 
 static unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -353,13 +367,14 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef};
+  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef, o.rec64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   o.r = o.f = nullptr;
   o.hash = nullptr;
   o.look = nullptr;
   o.coef = nullptr;
+  o.rec64 = nullptr;
 }
 
 static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStream_t s) {
@@ -480,6 +495,15 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_pack_exp, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
                        o.coef);
+  if (kind == kExp) {
+    e = hipMalloc((void **)&o.rec64, sizeof(double) * 6 * (o.n - 1));
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "FP64 Exp records");
+    }
+    hipLaunchKernelGGL(k_pack_exp64, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
+                       o.rec64);
+  }
   int hbad = 0;
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -493,8 +517,9 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   return MF_OK;
 }
 
-int build_tables_device(mf_tables *T, double tol, hipStream_t s) {
+int build_tables_device(mf_tables *T, double tol, hipStream_t s, bool green) {
   for (int kind : {kGreen, kExp}) {
+    if (kind == kGreen && !green) continue;
     mf_tables::One &o = kind == kGreen ? T->g : T->e;
     double t = interval_from_tol(kind, T->k, T->rmin, tol);
     bool ok = false;
