@@ -258,6 +258,53 @@ def mfie_timing(mf, mesh, Vd, k, Q, tables, steps):
     return out
 
 
+def angular_timing(mf, steps):
+    """The paper's own inner scheme (angular transformation, n = 8 points on
+    each source edge, FP64 integrals) on the 5,120-triangle sphere at k = 10
+    with the 6-point rule: the linear Exp table (from r = 0, tol 1e-6) against
+    computed exponentials; 3 n Q Exp(-jkr) per ordered triangle pair plus one
+    per test point and source triangle."""
+    import numpy as np
+    import torch
+
+    from paper_1901_04162_amd import meshes
+
+    V, F = meshes.icosphere(4)
+    k, Q, n = 10.0, 6, 8
+    m = mf.Mesh(F, V.shape[0])
+    E, T_ = m.n_edges, F.shape[0]
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    rmax = mf.angular_rmax(m, Vd, Q)
+    tab = mf.build_exp_table(k, rmax, 1e-6)
+    out = {"workload": "icosphere 4 subdivisions (5120 triangles, 7680 unknowns), k=10 rad/m, "
+                       "6-point rule, 8 points per source edge, complex64 Z",
+           "exp_table_samples": tab.n_exp, "r_max": rmax}
+    exps = T_ * T_ * Q * (3 * n + 1)
+    Zs = {}
+    for mode in ("table", "direct"):
+        Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+        mf.fill_angular(m, Vd, k, Q, n, mode, tab, out=Z)
+        torch.cuda.synchronize()
+        mf.set_timing(True)
+        ph = []
+        for _ in range(steps):
+            mf.fill_angular(m, Vd, k, Q, n, mode, tab, out=Z)
+            ph.append(mf.timings(m)[2])
+        mf.set_timing(False)
+        mf.sync_status(m)
+        fill = float(np.mean(ph))
+        out[f"{mode}_fill_ms"] = fill
+        out[f"{mode}_z_entries_per_s"] = E * E / (fill * 1e-3)
+        out[f"{mode}_exp_evals_per_s"] = exps / (fill * 1e-3)
+        Zs[mode] = Z
+    out["table_over_direct"] = out["direct_fill_ms"] / out["table_fill_ms"]
+    out["max_abs_err_over_max_abs"] = float(
+        (Zs["table"] - Zs["direct"]).abs().max() / Zs["direct"].abs().max())
+    del Zs
+    torch.cuda.empty_cache()
+    return out
+
+
 def scatter_timing(mf, steps):
     """The paper's scattering case: a PEC sphere of radius half a wavelength
     (ka = pi; icosphere with 4 subdivisions, 7,680 unknowns, 6-point rule)
@@ -313,6 +360,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--no-mfie", action="store_true")
+    ap.add_argument("--no-angular", action="store_true")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--subdiv", type=int, default=5)
@@ -454,6 +502,9 @@ def main():
     if not args.no_mfie:
         log("mfie ...")
         out["mfie"] = mfie_timing(mf, mesh, Vd, k, Q, T, args.steps)
+    if not args.no_angular:
+        log("angular transformation ...")
+        out["angular"] = angular_timing(mf, max(1, min(args.steps, 3)))
     if not args.no_near:
         log("near field ...")
         out["near_field"] = near_timing(mf, mesh, V, Vd, k, Q, T, args.steps)

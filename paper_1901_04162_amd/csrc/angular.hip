@@ -50,21 +50,20 @@ struct AngArgs {
   long long ldz;
   double w[kMaxQ];
   double k, ik2, pref;
-  // Exp table (FP64): interval records {r_i, E_i, slope, r_{i+1}}, the hash
-  // array of Eq. (6) with its bucket width delta, the range [0, rmax]
-  const double *erec;
-  const int32_t *ehash;
-  int en, em;
-  double edelta_inv, ermax;
+  // Exp table (FP64 bucket records, see mf_tables) and its range [0, rmax]
+  const double *elook;
+  int em;
+  double einv, ermax;
   void *Z;
   int *status;
 };
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// exp(-jkR): the linear table of Eq. (4) found through the hash of Eq. (6),
-// or sincos.  A table distance beyond r_max (by more than rounding) raises
-// the status flag.
+// exp(-jkR): the linear table of Eq. (4), one 80-byte bucket record per
+// lookup (the bucket of a coarsened Eq. (6) hash holds both candidate
+// intervals and the sample between them), or sincos.  A table distance
+// beyond r_max (by more than rounding) raises the status flag.
 template <int MODE>
 __device__ __forceinline__ void exp_jkr(const AngArgs &A, double R, double &re, double &im,
                                         bool &bad) {
@@ -76,16 +75,14 @@ __device__ __forceinline__ void exp_jkr(const AngArgs &A, double R, double &re, 
     return;
   }
   bad |= !(R <= A.ermax * (1.0 + 1e-12));
-  int b = (int)(R * A.edelta_inv);
+  int b = (int)(R * A.einv);
   b = b < 0 ? 0 : (b > A.em - 1 ? A.em - 1 : b);
-  int i = A.ehash[b];
-  i = i > A.en - 2 ? A.en - 2 : i;
-  const double *o = A.erec + 6 * (size_t)i;
-  if (R < o[0] && i > 0) o -= 6;
-  else if (R >= o[5] && i < A.en - 2) o += 6;
-  const double u = R - o[0];
-  re = fma(o[3], u, o[1]);
-  im = fma(o[4], u, o[2]);
+  const double2 *o = reinterpret_cast<const double2 *>(A.elook + 10 * (size_t)b);
+  const double2 h = o[0], lv = o[1], ls = o[2], rv = o[3], rs = o[4];
+  const bool right = R >= h.x;
+  const double u = R - h.y;
+  re = fma(right ? rs.x : ls.x, u, right ? rv.x : lv.x);
+  im = fma(right ? rs.y : ls.y, u, right ? rv.y : lv.y);
 }
 
 // Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on P_n,
@@ -160,7 +157,7 @@ __device__ void inner_integrals(const AngArgs &A, const double *gxs, const doubl
     if (d > 0.0) {
       const double u0 = asinh(lm / d), du = asinh(lp / d) - u0;
       if (MODE == MF_MODE_TABLE) {
-        // pairs of points: two table gathers in flight
+        // pairs of points: two table reads in flight
 #pragma unroll 2
         for (int j = 0; j < NE; ++j)
           edge_point<MODE>(A, u0, du, gxs[j], gws[j], d, p, ehr, ehi, s0r, s0i, s1r, s1i, bad);
@@ -432,11 +429,9 @@ int launch_fill_angular(mf_mesh *m, const double *V, const Rule &r, double k, in
   A.pref = k * kEta0 / (4.0 * M_PI);
   if (mode == MF_MODE_TABLE) {
     const mf_tables::One &e = tab->e;
-    A.erec = e.rec64;
-    A.ehash = e.hash;
-    A.en = e.n;
-    A.em = e.m;
-    A.edelta_inv = 1.0 / e.delta;
+    A.elook = e.look64;
+    A.em = e.m64;
+    A.einv = e.inv64;
     A.ermax = tab->rmax;
   }
   A.Z = Z;

@@ -443,7 +443,7 @@ int mf_build_exp_table(double k, double rmax, double tol, mf_tables **out, hipSt
 void mf_tables_destroy(mf_tables *t) {
   if (!t) return;
   for (mf_tables::One *o : {&t->e, &t->g}) {
-    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef, o->rec64};
+    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef, o->look64};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
   }
@@ -574,7 +574,7 @@ int mf_fill_angular(mf_mesh *m, const double *V, double k, int quad_order, int n
   if (mode != MF_MODE_TABLE && mode != MF_MODE_DIRECT)
     return fail(MF_EINVAL, "mf_fill_angular: unknown mode");
   if (mode == MF_MODE_TABLE &&
-      (!tab || tab->e.n < 2 || !tab->e.rec64 || tab->rmin != 0.0 ||
+      (!tab || tab->e.n < 2 || !tab->e.look64 || tab->rmin != 0.0 ||
        std::fabs(tab->k - k) > 1e-12 * k))
     return fail(MF_EINVAL,
                 "mf_fill_angular: table mode needs an Exp table from r = 0 built for this k");

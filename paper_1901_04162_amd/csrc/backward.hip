@@ -390,13 +390,12 @@ __device__ double touching_share(const double xp[3][3], const double xq[3][3], c
       Oi[3 * a + b] = -f * wi;
     }
   }
-  double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+  // only the imaginary part of the contraction enters Re[j c (sr + j si)]
+  double s1i = 0.0, s2i = 0.0;
   const double A1 = oneway_terms(xp, xq, R, k, 0, [&](int a, int b, double re, double im) {
-    s1r += Or[3 * a + b] * re - Oi[3 * a + b] * im;
     s1i += Or[3 * a + b] * im + Oi[3 * a + b] * re;
   });
   const double A2 = oneway_terms(xq, xp, R, k, 0, [&](int b, int a, double re, double im) {
-    s2r += Or[3 * a + b] * re - Oi[3 * a + b] * im;
     s2i += Or[3 * a + b] * im + Oi[3 * a + b] * re;
   });
   const double si = 0.5 * (s1i / A1 + s2i / A2);

@@ -56,9 +56,14 @@ struct mf_tables {
     int mb = 0;
     float binv = 0.0f, bbias = 0.0f, btop = 0.0f;
     float4 *coef = nullptr;
-    // FP64 interval records of the Exp table (n-1 records of 6 doubles:
-    // r_i, E_i (re, im), slope (re, im), r_{i+1}) for the FP64 lookup
-    double *rec64 = nullptr;
+    // FP64 lookup of the Exp table: m64 bucket records of 10 doubles, bucket
+    // b = (int)(r * inv64) of width just under the smallest sample interval,
+    // so at most one sample (split) lies inside a bucket: {split, x_b, the
+    // interval left of split as E + slope (r - x_b) (4 doubles), the
+    // interval right of it likewise (4 doubles)}
+    double *look64 = nullptr;
+    int m64 = 0;
+    double inv64 = 0.0;
   } e, g;
 };
 

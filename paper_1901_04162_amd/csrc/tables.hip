@@ -330,18 +330,55 @@ __global__ void k_pack_exp(const double *r, const double *f, int n, float4 *coef
   coef[i] = make_float4((float)vr, (float)vi, (float)sr, (float)si);
 }
 
-// FP64 interval records of the linear Exp table: {r_i, E_i, slope, r_{i+1}}.
-__global__ void k_pack_exp64(const double *r, const double *f, int n, double *rec) {
+// FP64 bucket records of the linear Exp table (a coarsened form of the hash
+// of Eq. (6) for a table that starts at r = 0): bucket b = (int)(r * inv)
+// with width just under the smallest sample interval holds at most one
+// sample; its record carries that sample (split, +inf if none), the bucket
+// start x_b and both candidate intervals as value-at-x_b and slope, so one
+// 80-byte read answers a lookup.  Sample buckets use the lookup's own formula.
+__global__ void k_node_bucket64(const double *r, int n, double inv, int *nb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n - 1) return;
+  if (i < n) nb[i] = (int)(r[i] * inv);
+}
+
+__device__ inline void linear_at(const double *r, const double *f, int i, double x, double *o) {
   const double h = r[i + 1] - r[i];
-  double *o = rec + 6 * (size_t)i;
-  o[0] = r[i];
-  o[1] = f[2 * i];
-  o[2] = f[2 * i + 1];
-  o[3] = (f[2 * i + 2] - f[2 * i]) / h;
-  o[4] = (f[2 * i + 3] - f[2 * i + 1]) / h;
-  o[5] = r[i + 1];
+  const double sr = (f[2 * i + 2] - f[2 * i]) / h, si = (f[2 * i + 3] - f[2 * i + 1]) / h;
+  o[0] = f[2 * i] + sr * (x - r[i]);
+  o[1] = f[2 * i + 1] + si * (x - r[i]);
+  o[2] = sr;
+  o[3] = si;
+}
+
+__global__ void k_pack_look64(const double *r, const double *f, const int *nb, int n, int m,
+                              double inv, double *look, int *bad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= m) return;
+  int lo = 0, hi = n;  // first sample whose bucket is >= b
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (nb[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const int c = lo;
+  int iL = c - 1, iR = c;
+  double split = __longlong_as_double(0x7ff0000000000000ll);
+  if (c < n && nb[c] == b) {
+    split = r[c];
+    if (c + 1 < n && nb[c + 1] == b) atomicOr(bad, 1);
+  } else {
+    iR = iL;
+  }
+  iL = iL < 0 ? 0 : (iL > n - 2 ? n - 2 : iL);
+  iR = iR < 0 ? 0 : (iR > n - 2 ? n - 2 : iR);
+  const double xb = (double)b / inv;
+  double *o = look + 10 * (size_t)b;
+  o[0] = split;
+  o[1] = xb;
+  linear_at(r, f, iL, xb, o + 2);
+  linear_at(r, f, iR, xb, o + 6);
 }
 
 // ---- host driver ---------------------------------------------------------
@@ -367,14 +404,14 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef, o.rec64};
+  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef, o.look64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   o.r = o.f = nullptr;
   o.hash = nullptr;
   o.look = nullptr;
   o.coef = nullptr;
-  o.rec64 = nullptr;
+  o.look64 = nullptr;
 }
 
 static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStream_t s) {
@@ -495,14 +532,19 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_pack_exp, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
                        o.coef);
-  if (kind == kExp) {
-    e = hipMalloc((void **)&o.rec64, sizeof(double) * 6 * (o.n - 1));
+  if (kind == kExp && T->rmin == 0.0) {
+    const double w = 0.999 * o.delta;
+    o.inv64 = 1.0 / w;
+    o.m64 = (int)(T->rmax * o.inv64) + 1;
+    e = hipMalloc((void **)&o.look64, sizeof(double) * 10 * (size_t)o.m64);
     if (e != hipSuccess) {
       cleanup();
-      return hip_fail(e, "FP64 Exp records");
+      return hip_fail(e, "FP64 Exp lookup");
     }
-    hipLaunchKernelGGL(k_pack_exp64, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
-                       o.rec64);
+    hipLaunchKernelGGL(k_node_bucket64, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n,
+                       o.inv64, nb);
+    hipLaunchKernelGGL(k_pack_look64, dim3(blocks(o.m64, 256)), dim3(256), 0, s, o.r, o.f, nb,
+                       o.n, o.m64, o.inv64, o.look64, bad);
   }
   int hbad = 0;
   e = hipGetLastError();
