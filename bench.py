@@ -127,7 +127,9 @@ def sweep_timing(mf, steps, group=8, tol=1e-5):
     unknowns) x 32 wavenumbers in [4, 20], 6-point rule, per-(mesh, k)
     tables.  The 96 items run as 4 batched launches of 3 meshes x 8
     wavenumbers, captured together in one CUDA graph; the groups share one
-    set of complex64 outputs (64 GB), as a consumer would reuse them."""
+    set of complex64 outputs (64 GB), as a consumer would reuse them.  The
+    first batch's creation runs the tile-shape tuner (the others reuse its
+    choice); its timings are reported."""
     import torch
 
     from paper_1901_04162_amd import meshes
@@ -174,10 +176,13 @@ def sweep_timing(mf, steps, group=8, tol=1e-5):
     for md in mesh_data:
         mf.sync_status(md[0])
     entries = sum(md[0].n_edges ** 2 for md in mesh_data) * len(ks)
+    threads, tune_ms = batches[0].tuning()
     return {
         "workload": "3 jittered icospheres (1280/5120/20480 triangles) x 32 k in [4, 20] rad/m, "
                     "6-point rule, table tol 1e-5, complex64; 4 launches of 24 items in one graph",
         "items": len(mesh_data) * len(ks),
+        "tuned_threads": threads,
+        "tuning_ms_512_768_1024": tune_ms,
         "ms_per_sweep": dt * 1e3,
         "z_entries_per_s": entries / dt,
         "table_build_ms_per_sweep": t_tables * 1e3,

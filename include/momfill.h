@@ -217,6 +217,17 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *vert
  * touching-pair blocks of every item, then the single fill launch.  It
  * allocates nothing and copies nothing, so a HIP graph can capture it. */
 int mf_batch_fill(mf_batch *batch, hipStream_t stream);
+/* Tile-shape tuner.  mf_batch_create, before returning, fills the batch once
+ * on the null stream and times the persistent launch with 512, 768 and 1024
+ * threads per workgroup (2, 3 or 4 waves per SIMD, trading each lane's
+ * register budget against the latency hiding of the table gathers), keeping
+ * the fastest for the batch; the choice is cached per (quad_order, mode,
+ * table placement, z_dtype) for the life of the process, so later batches of
+ * the same kind skip the timing.  The outputs hold the batch's result when
+ * mf_batch_create returns.  mf_batch_info reports the choice (*threads) and
+ * the three timings in milliseconds (tune_ms3, zeros when the cache
+ * answered); either pointer may be NULL. */
+int mf_batch_info(const mf_batch *batch, int32_t *threads, float *tune_ms3);
 void mf_batch_destroy(mf_batch *batch);
 
 /* ---- near-field fill (Section II-A) --------------------------------------

@@ -332,6 +332,14 @@ class Batch:
     def fill(self):
         check(lib().mf_batch_fill(self._h, _stream()))
 
+    def tuning(self):
+        """(threads per workgroup picked by the tuner, its three timings in ms
+        for 512/768/1024 threads; zeros when an earlier batch's choice was reused)."""
+        t = C.c_int32()
+        ms = (C.c_float * 3)()
+        check(lib().mf_batch_info(self._h, C.byref(t), ms))
+        return t.value, [float(v) for v in ms]
+
     def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:
             _L._lib.mf_batch_destroy(self._h)

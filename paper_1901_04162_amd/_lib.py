@@ -27,6 +27,7 @@ EXPORTS = [
     "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
     "mf_near_destroy", "mf_rhs_planewave", "mf_far_field", "mf_fill_mfie",
     "mf_rhs_planewave_mfie", "mf_fill_angular", "mf_angular_rmax", "mf_build_exp_table",
+    "mf_batch_info",
 ]
 
 
@@ -72,6 +73,7 @@ def lib():
         L.mf_rhs_planewave.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int, vp]
         L.mf_rhs_planewave_mfie.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int,
                                             vp]
+        L.mf_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
         L.mf_fill_angular.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp,
                                       C.c_int, C.c_int64, vp]
         L.mf_angular_rmax.argtypes = [vp, vp, C.c_int, dp, vp]

@@ -315,6 +315,8 @@ struct mf_batch {
   std::vector<double> k;
   std::vector<float *> sing;  // per-item touching-pair blocks (owned)
   mf::FillLaunch *launch = nullptr;
+  int threads = 0;             // workgroup size picked by the tuner
+  float tune_ms[3] = {0.0f, 0.0f, 0.0f};
 };
 
 using namespace mf;
@@ -647,11 +649,31 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, c
     rc = fill_launch_create(n, meshes, k, tab, r, mode, Z, z_dtype, ldz, sing.data(),
                             &b->launch);
   }
+  // tile-shape tuning on the real inputs: geometry and touching blocks first,
+  // then the launch variants (writing the outputs); all on the null stream
+  if (!rc) {
+    *out = b;
+    rc = mf_batch_fill(b, nullptr);
+    if (!rc) rc = fill_launch_autotune(b->launch, nullptr, b->tune_ms, &b->threads);
+    if (!rc) {
+      hipError_t e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) rc = hip_fail(e, "mf_batch_create: tuning");
+    }
+  }
   if (rc) {
+    *out = nullptr;
     mf_batch_destroy(b);
     return rc;
   }
   *out = b;
+  return MF_OK;
+}
+
+int mf_batch_info(const mf_batch *b, int32_t *threads, float *tune_ms3) {
+  if (!b) return fail(MF_EINVAL, "mf_batch_info: batch is NULL");
+  if (threads) *threads = b->threads;
+  if (tune_ms3)
+    for (int i = 0; i < 3; ++i) tune_ms3[i] = b->tune_ms[i];
   return MF_OK;
 }
 

@@ -31,7 +31,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -577,11 +580,10 @@ __attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE
 // Several items in one persistent launch: the workgroups stride through the
 // concatenated tile list, so every workgroup visits the items in order and
 // loads each item's table once.
-template <int Q, int MODE, bool kLDS, typename ZT>
-__global__ __launch_bounds__(fill_threads<MODE>())
-__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill_batch(
+template <int Q, int MODE, bool kLDS, typename ZT, int kFillThreads>
+__global__ __launch_bounds__(kFillThreads)
+__attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) void k_fill_batch(
     const FillItem *__restrict__ items, int n_items, FillRule W) {
-  constexpr int kFillThreads = fill_threads<MODE>();
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
   const int G = gridDim.x;
@@ -610,6 +612,7 @@ struct FillLaunch {
   int total_tiles = 0, n = 0;
   size_t lds = 0;
   int nq = 0, base = 0, part = 0, z_dtype = 0, op = MF_OP_EFIE;
+  int threads = 0;  // workgroup size of a batched launch (0: the mode's default)
   bool lds_tab = false, sparse = false;
   long long grid = 0;
 };
@@ -632,6 +635,21 @@ static int plan_grid(FillLaunch &L, K kern, int threads) {
   if (getenv("MOMFILL_VERBOSE"))
     fprintf(stderr, "[momfill] k_fill Q=%d mode=%d lds_table=%d items=%d grid=%lld x %d lds=%zu B\n",
             L.nq, L.base, (int)L.lds_tab, L.n, L.grid, threads, L.lds);
+  return MF_OK;
+}
+
+// Batched launch with a given workgroup size (the variants the tuner times).
+template <int Q, int MODE, bool kLDS, typename ZT, int kThreads>
+static int launch_batch(FillLaunch &L, bool plan_only, hipStream_t s) {
+  auto kern = k_fill_batch<Q, MODE, kLDS, ZT, kThreads>;
+  if (L.grid == 0) {
+    const int rc = plan_grid(L, kern, kThreads);
+    if (rc) return rc;
+  }
+  if (plan_only || L.total_tiles == 0) return MF_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kThreads), L.lds, s, L.d_items, L.n,
+                     L.rule);
+  MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
@@ -671,14 +689,11 @@ static int launch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
     hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.first,
                        L.rule);
   } else {
-    auto kern = k_fill_batch<Q, MODE, kLDS, ZT>;
-    if (L.grid == 0) {
-      const int rc = plan_grid(L, kern, kFillThreads);
-      if (rc) return rc;
+    switch (L.threads ? L.threads : kFillThreads) {
+      case 512: return launch_batch<Q, MODE, kLDS, ZT, 512>(L, plan_only, s);
+      case 1024: return launch_batch<Q, MODE, kLDS, ZT, 1024>(L, plan_only, s);
+      default: return launch_batch<Q, MODE, kLDS, ZT, 768>(L, plan_only, s);
     }
-    if (plan_only || L.total_tiles == 0) return MF_OK;
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.d_items,
-                       L.n, L.rule);
   }
   MF_HIP(hipGetLastError());
   return MF_OK;
@@ -817,6 +832,73 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
 }
 
 int fill_launch_run(FillLaunch *L, hipStream_t s) { return dispatch(*L, false, s); }
+
+// Tile-shape tuner of batched launches: the workgroup size sets the waves per
+// SIMD (2, 3 or 4) and with them the register budget of a lane (256, 168 or
+// 128 VGPRs) against the latency hiding of the LDS gathers.  Each candidate
+// runs the whole launch once to warm up and once timed with HIP events; the
+// fastest is kept for every later launch with the same rule, mode, table
+// placement and output type in this process.
+int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads) {
+  static const int kCand[3] = {512, 768, 1024};
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> cache;
+  if (ms3)
+    for (int i = 0; i < 3; ++i) ms3[i] = 0.0f;
+  if (L->n < 2 || L->op != MF_OP_EFIE || L->sparse) {  // single fills keep the defaults
+    if (threads) *threads = L->threads ? L->threads : (L->base == MF_MODE_TABLE ? 768 : 1024);
+    return MF_OK;
+  }
+  const auto key = std::make_tuple(L->nq, L->base, (int)L->lds_tab, L->z_dtype);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      L->threads = it->second;
+      L->grid = 0;
+      if (threads) *threads = L->threads;
+      return dispatch(*L, true, nullptr);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MF_HIP(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(he, "tuner events");
+  }
+  int rc = MF_OK, best = 768;
+  float best_ms = INFINITY;
+  for (int c = 0; c < 3 && !rc; ++c) {
+    L->threads = kCand[c];
+    L->grid = 0;
+    rc = dispatch(*L, false, s);  // warm-up (and grid plan)
+    if (rc) break;
+    he = hipEventRecord(e0, s);
+    if (he == hipSuccess) rc = dispatch(*L, false, s);
+    if (!rc && he == hipSuccess) he = hipEventRecord(e1, s);
+    if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) rc = hip_fail(he, "tuner timing");
+    if (ms3) ms3[c] = ms;
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = kCand[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  L->threads = best;
+  L->grid = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = best;
+  }
+  if (threads) *threads = best;
+  return dispatch(*L, true, nullptr);
+}
 
 void fill_launch_destroy(FillLaunch *L) {
   if (!L) return;

@@ -142,6 +142,10 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
                        const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
                        const float *const *sing, FillLaunch **out);
 int fill_launch_run(FillLaunch *L, hipStream_t s);
+// Times the workgroup-size variants of a batched launch (running it), keeps
+// the fastest; ms3 (may be NULL) receives the three timings (512, 768, 1024
+// threads), *threads the choice.
+int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads);
 void fill_launch_destroy(FillLaunch *L);
 int build_tables_device(mf_tables *t, double tol, hipStream_t s, bool green = true);
 // Angular-transformation fill (FP64 inner integrals on every pair).

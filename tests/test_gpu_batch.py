@@ -183,3 +183,26 @@ def test_sweep_meshes_sampled(mf, orc):
         err = _rel(z, ref)
         say(f"  E={E.shape[0]} k={k} sampled rel {err:.2e}")
         assert err <= 1e-5
+
+
+def test_batch_tuner(mf):
+    """The tile-shape tuner runs at creation: it picks one of the three
+    workgroup sizes, leaves the batch's result in the outputs, and a second
+    batch of the same kind reuses the choice without timing again."""
+    import torch
+
+    Q = 3  # a rule no other test batches, so the first batch here is timed
+    say("batch tuner")
+    specs = _items(mf, "table", Q)
+    b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
+    torch.cuda.synchronize()
+    threads, ms = b.tuning()
+    say("  threads", threads, "ms", ms)
+    assert threads in (512, 768, 1024)
+    assert all(t > 0 for t in ms) and min(ms) == ms[(512, 768, 1024).index(threads)]
+    for s in specs:
+        ref = mf.fill_Z(s["mesh"], s["Vd"], s["k"], Q, "table", s["T"]).cpu().numpy()
+        assert _rel(s["Z"].cpu().numpy(), ref) <= 1e-6  # result present after creation
+    b2 = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs[:2]], Q, "table")
+    t2, ms2 = b2.tuning()
+    assert t2 == threads and ms2 == [0.0, 0.0, 0.0]
