@@ -19,8 +19,9 @@
 // beta_b = c_q - v_b:
 //   X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + alpha_a.beta_b S0)/4 - S0/k^2.
 // Touching pairs take their FP64 blocks from the singular kernel.  The
-// Green-function table sits in LDS when it fits and is read from global
-// memory otherwise.
+// Green-function table's interval coefficients sit in LDS when they fit (read
+// from global memory otherwise); its bucket records are read from global
+// memory through the vector L1.
 //
 // Distances: D = c_p - c_q is formed in FP64 and split into FP32 hi + lo;
 // each test point's offset hi + (lo + rho_i) is rounded once in FP32, then
@@ -315,15 +316,17 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
   }
 }
 
-// The item's Green table: copied into LDS after the accumulator when it
-// fits, read from global memory otherwise.
+// The item's Green table: the interval coefficients are copied into LDS
+// after the accumulator when they fit, the bucket records stay in global
+// memory (read through the vector L1).  Splitting the two gathers of a lookup
+// between the LDS and the vector-memory path measured 5 % faster than both in
+// LDS, whose bank conflicts bind the kernel (and 9 % faster than the bucket
+// records in LDS with the coefficients in global memory).
 template <bool kLDS, int kThreads>
 __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coef) {
   if (!kLDS) return TabPtrs{S.look, S.coef, S.coef + (S.tn - 1)};
-  int4 *b = reinterpret_cast<int4 *>(lds_coef + 2 * (S.tn - 1));
   for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kThreads) lds_coef[i] = S.coef[i];
-  for (int i = threadIdx.x; i < S.tm; i += kThreads) b[i] = S.look[i];
-  return TabPtrs{b, lds_coef, lds_coef + (S.tn - 1)};
+  return TabPtrs{S.look, lds_coef, lds_coef + (S.tn - 1)};
 }
 
 // One tile of one item: accumulate it in LDS, then write it and its mirror.
@@ -728,8 +731,7 @@ static int dispatch(FillLaunch &L, bool plan_only, hipStream_t s) {
 }
 
 static size_t table_lds_bytes(const mf_tables *tab) {
-  const mf_tables::One &g = tab->g;
-  return sizeof(float4) * 2 * (size_t)(g.n - 1) + sizeof(int4) * (size_t)g.mb;
+  return sizeof(float4) * 2 * (size_t)(tab->g.n - 1);  // the coefficients (load_table)
 }
 
 static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
