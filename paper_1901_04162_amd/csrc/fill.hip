@@ -53,6 +53,12 @@ template <int MODE>
 constexpr int fill_threads() {
   return MODE == MF_MODE_TABLE ? 768 : 1024;
 }
+// The MFIE kernel holds both directions' moments and two accumulators: 512
+// threads (2 waves per SIMD, 256 VGPRs per lane), one workgroup per CU.
+template <int MODE, int OP>
+constexpr int fill_threads_op() {
+  return OP == MF_OP_MFIE ? 512 : fill_threads<MODE>();
+}
 
 // One fill item: a mesh, a wavenumber, its table and its output.  A launch
 // walks the global tile list of one or more items (tiles tile_begin ..
@@ -67,7 +73,7 @@ struct FillItem {
   float lo_ok, hi_ok;
   long long ldz;
   const float *rec;
-  const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q;
+  const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q, *touch_rev;
   const float *sing;
   const int4 *look;
   const float4 *coef;
@@ -136,14 +142,26 @@ __device__ __forceinline__ void zero(Moments &M) {
 //   Md = sum w_i (a_i T0 - T1),       Mx = sum w_i a_i x T1,
 //   Ms = sum w_i sigma_i x (a_i T0 - T1),  M0 = sum w_i sigma_i.(a_i x T1),
 //   X_ab = (beta_b.(tau_a x Md + Ms) + tau_a.Mx + M0)/4.
+// The operator is not symmetric, but K(R) is: the same kernel values give the
+// reverse block (test triangle q, source p) too.  With n' the unit normal of
+// q, tau'_b = beta_b x n' and the third inner sum T2 = sum_j w_j K |rho'_j|^2
+// (rho'_j lies in q's plane, so the terms quadratic in rho'_j reduce to it),
+//   Md' = -Md,   Mx' = -sum w_i (a_i T0 - T1) x rho_i,
+//   Ms' = -sum w_i [ (T1 x n') x a_i - n' T2 ],
+//   M0' = -sum w_i [ (T1 x n').(a_i x rho_i) - T2 (n'.rho_i) ],
+//   X'_ba = (alpha_a.(tau'_b x Md' + Ms') + tau'_b.Mx' + M0')/4.
 struct MomentsM {
-  float dr[3], di[3], xr[3], xi[3], sr[3], si[3], m0r, m0i;
+  float dr[3], di[3], xr[3], xi[3], sr[3], si[3], m0r, m0i;  // p tested against q
+  float qxr[3], qxi[3], qsr[3], qsi[3], q0r, q0i;             // q tested against p
 };
 
 __device__ __forceinline__ void zero(MomentsM &M) {
-  M.m0r = M.m0i = 0.0f;
+  M.m0r = M.m0i = M.q0r = M.q0i = 0.0f;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) M.dr[c] = M.di[c] = M.xr[c] = M.xi[c] = M.sr[c] = M.si[c] = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    M.dr[c] = M.di[c] = M.xr[c] = M.xi[c] = M.sr[c] = M.si[c] = 0.0f;
+    M.qxr[c] = M.qxi[c] = M.qsr[c] = M.qsi[c] = 0.0f;
+  }
 }
 
 __device__ __forceinline__ void cross3(const float *u, const float *v, float *o) {
@@ -157,8 +175,9 @@ __device__ __forceinline__ float dot3(const float *u, const float *v) {
 }
 
 __device__ __forceinline__ void add_point(MomentsM &M, float wi, const float *pri, const float *a,
-                                          const float *nrm, float t0r, float t0i,
-                                          const float *t1r, const float *t1i) {
+                                          const float *nrm, const float *nq, float t0r, float t0i,
+                                          const float *t1r, const float *t1i, float t2r,
+                                          float t2i) {
   float vr[3], vi[3], cr[3], ci[3], sg[3], u[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -188,6 +207,30 @@ __device__ __forceinline__ void add_point(MomentsM &M, float wi, const float *pr
   cross3(sg, vi, u);
 #pragma unroll
   for (int c = 0; c < 3; ++c) M.si[c] += u[c];
+  // reverse direction
+  cross3(vr, pri, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.qxr[c] -= u[c];
+  cross3(vi, pri, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.qxi[c] -= u[c];
+  float axr[3], cw[3];
+  cross3(a, pri, axr);
+  const float nr = dot3(nq, pri), w2r = wi * t2r, w2i = wi * t2i;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wt[c] = wi * t1r[c];
+  cross3(wt, nq, cw);
+  cross3(cw, a, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.qsr[c] -= fmaf(-nq[c], w2r, u[c]);
+  M.q0r -= fmaf(-w2r, nr, dot3(cw, axr));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wt[c] = wi * t1i[c];
+  cross3(wt, nq, cw);
+  cross3(cw, a, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) M.qsi[c] -= fmaf(-nq[c], w2i, u[c]);
+  M.q0i -= fmaf(-w2i, nr, dot3(cw, axr));
 }
 
 // g -> K = (1/R + jk) g / R (MFIE kernel from the Green-function value).
@@ -211,9 +254,9 @@ template <int Q, int OP>
 __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
                                               const FillScalars &S, const FillRule &W,
                                               const float (&prho)[Q][3], const float *nrm,
-                                              float hx, float hy, float hz, float lx, float ly,
-                                              float lz, const float *qr, float &rlo,
-                                              float &rhi) {
+                                              const float *nq, float hx, float hy, float hz,
+                                              float lx, float ly, float lz, const float *qr,
+                                              float &rlo, float &rhi) {
   zero(M);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -222,6 +265,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     const float ax = hx + (prho[i][0] + lx), ay = hy + (prho[i][1] + ly),
                 az = hz + (prho[i][2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+    float t2r = 0.f, t2i = 0.f;
     // batches of source points keep fewer lookups live at once (three for
     // the MFIE, whose moments hold more registers)
     constexpr int kG = OP == MF_OP_MFIE ? 3 : 2;
@@ -261,14 +305,89 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
           t1r[c] = fmaf(wq, gr, t1r[c]);
           t1i[c] = fmaf(wq, gi, t1i[c]);
         }
+        if constexpr (OP == MF_OP_MFIE) {
+          const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
+                                 fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
+                                      qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
+          t2r = fmaf(wr2, gr, t2r);
+          t2i = fmaf(wr2, gi, t2i);
+        }
       }
     }
     if constexpr (OP == MF_OP_MFIE) {
       const float a[3] = {ax, ay, az};
-      add_point(M, W.w[i], prho[i], a, nrm, t0r, t0i, t1r, t1i);
+      add_point(M, W.w[i], prho[i], a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
     } else {
       add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);
     }
+  }
+}
+
+// MFIE, table mode: the same grouped lookups with the test-point loop
+// rolled and rho_i read from the record (the moments of both directions take
+// the registers the EFIE path spends on the unrolled test points).
+template <int Q>
+__device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &tab,
+                                                   const FillScalars &S, const FillRule &W,
+                                                   const float *pr, const float *nrm,
+                                                   const float *nq, float hx, float hy, float hz,
+                                                   float lx, float ly, float lz, const float *qr,
+                                                   float &rlo, float &rhi) {
+  zero(M);
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    float pri[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
+    const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
+    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+    float t2r = 0.f, t2i = 0.f;
+    constexpr int kG = 2;
+#pragma unroll
+    for (int grp = 0; grp < kG; ++grp) {
+      const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
+      float r[Q];
+      int4 w[Q];
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        const float dx = ax - qr[kRecRho + 3 * j + 0];
+        const float dy = ay - qr[kRecRho + 3 * j + 1];
+        const float dz = az - qr[kRecRho + 3 * j + 2];
+        r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        rlo = fminf(rlo, r[j]);
+        rhi = fmaxf(rhi, r[j]);
+        w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
+      }
+      float u[Q];
+      float4 A[Q], B[Q];
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        const int ii = look_interval(w[j], r[j], u[j]);
+        A[j] = tab.c01[ii];
+        B[j] = tab.c23[ii];
+      }
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        const float2 g = cubic(A[j], B[j], u[j]);
+        float gr = g.x, gi = g.y;
+        green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
+        t0r = fmaf(W.w[j], gr, t0r);
+        t0i = fmaf(W.w[j], gi, t0i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float wq = qr[kRecWRho + 3 * j + c];
+          t1r[c] = fmaf(wq, gr, t1r[c]);
+          t1i[c] = fmaf(wq, gi, t1i[c]);
+        }
+        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
+                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
+                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
+        t2r = fmaf(wr2, gr, t2r);
+        t2i = fmaf(wr2, gi, t2i);
+      }
+    }
+    const float a[3] = {ax, ay, az};
+    add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
   }
 }
 
@@ -277,7 +396,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
 template <int Q, int OP>
 __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScalars &S,
                                                const FillRule &W, const float *pr,
-                                               const float *nrm, float hx, float hy, float hz, float lx, float ly,
+                                               const float *nrm, const float *nq, float hx, float hy, float hz, float lx, float ly,
                                                float lz, const float *qr) {
   zero(M);
 #pragma unroll 1
@@ -287,6 +406,7 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
     for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
     const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+    float t2r = 0.f, t2i = 0.f;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const float dx = ax - qr[kRecRho + 3 * j + 0];
@@ -306,10 +426,17 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
         t1r[c] = fmaf(wq, gr, t1r[c]);
         t1i[c] = fmaf(wq, gi, t1i[c]);
       }
+      if constexpr (OP == MF_OP_MFIE) {
+        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
+                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
+                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
+        t2r = fmaf(wr2, gr, t2r);
+        t2i = fmaf(wr2, gi, t2i);
+      }
     }
     if constexpr (OP == MF_OP_MFIE) {
       const float a[3] = {ax, ay, az};
-      add_point(M, W.w[i], pri, a, nrm, t0r, t0i, t1r, t1i);
+      add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
     } else {
       add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
     }
@@ -333,12 +460,7 @@ __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coe
 // The item's arrays come in as separate __restrict__ parameters: once the
 // function is inlined they carry no-alias scopes, which lets the
 // wave-uniform source records go through scalar loads into SGPRs.
-//
-// The MFIE operator is not symmetric: a tile (I, J) with I != J is then
-// accumulated twice, rows I against columns J and rows J against columns I,
-// each written once.
-template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false,
-          int OP = MF_OP_EFIE>
+template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false>
 __device__ __forceinline__ void fill_tile(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
@@ -346,15 +468,11 @@ __device__ __forceinline__ void fill_tile(
     const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
     const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
     const float *__restrict__ sing, ZT *__restrict__ Z) {
-  constexpr bool kM = OP == MF_OP_MFIE;
   constexpr int kWaves = kFillThreads / 64;
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
   const int tij = tiles[local];
-  const int I0 = tij >> 16, J0 = tij & 0xffff;
-  const int ndir = kM && I0 != J0 ? 2 : 1;
-  for (int dir = 0; dir < ndir; ++dir) {
-  const int I = dir ? J0 : I0, J = dir ? I0 : J0;
+  const int I = tij >> 16, J = tij & 0xffff;
   for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   __syncthreads();
   const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
@@ -378,28 +496,6 @@ __device__ __forceinline__ void fill_tile(
       for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
       psig[a] = pr[kRecSigma + a];
     }
-    // MFIE: unit normal of p (alpha_0 - alpha_a = v_a - v_0) and tau_a =
-    // alpha_a x n, held in place of alpha
-    float nrm[3] = {0.0f, 0.0f, 0.0f};
-    if constexpr (kM) {
-      float e1[3], e2[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        e1[c] = palpha[0][c] - palpha[1][c];
-        e2[c] = palpha[0][c] - palpha[2][c];
-      }
-      cross3(e1, e2, nrm);
-      const float inv = __builtin_amdgcn_rsqf(dot3(nrm, nrm));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) nrm[c] *= inv;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float t[3];
-        cross3(palpha[a], nrm, t);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) palpha[a][c] = t[c];
-      }
-    }
     const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
     const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
     const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
@@ -420,32 +516,13 @@ __device__ __forceinline__ void fill_tile(
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
-        MomentsOf<OP> M;
+        Moments M;
         if (MODE == MF_MODE_TABLE)
-          moments_table<Q, OP>(M, tab, S, W, prho, nrm, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          moments_table<Q, MF_OP_EFIE>(M, tab, S, W, prho, nullptr, nullptr, hx, hy, hz, lx, ly,
+                                       lz, qr, rlo, rhi);
         else
-          moments_direct<Q, OP>(M, S, W, pr, nrm, hx, hy, hz, lx, ly, lz, qr);
-        if constexpr (kM) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            float Yr[3], Yi[3];
-            cross3(palpha[a], M.dr, Yr);
-            cross3(palpha[a], M.di, Yi);
-            const float yr = dot3(palpha[a], M.xr) + M.m0r;
-            const float yi = dot3(palpha[a], M.xi) + M.m0i;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              Yr[c] += M.sr[c];
-              Yi[c] += M.si[c];
-            }
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const float *beta = qr + kRecAlpha + 3 * b;
-              Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
-              Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
-            }
-          }
-        } else {
+          moments_direct<Q, MF_OP_EFIE>(M, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
+                                        qr);
         const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
         const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
@@ -474,7 +551,6 @@ __device__ __forceinline__ void fill_tile(
             Xr[a][b] = vr;
             Xi[a][b] = vi;
           }
-        }
       } else {
         int s = touch_off[p];
         const int s1 = touch_off[p + 1];
@@ -520,63 +596,259 @@ __device__ __forceinline__ void fill_tile(
       Z[en.y] = v;
       if (en.z >= 0) Z[en.z] = v;
     }
-  } else if (kM) {
-    // Z = acc/(4 pi), rows of block I, columns of block J
-    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
-    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
-    for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
-      const int r = e / nj, c = e % nj;
-      ZT v;
-      v.x = S.pref * acc[r * kAccStride + 2 * c];
-      v.y = S.pref * acc[r * kAccStride + 2 * c + 1];
-      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
-    }
   } else {
     // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
     const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
     const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
       const int r = e / nj, c = e % nj;
-      {
-        const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
-        ZT v;
-        v.x = -S.pref * ai;
-        v.y = S.pref * ar;
-        Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
-      }
+      const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+      ZT v;
+      v.x = -S.pref * ai;
+      v.y = S.pref * ar;
+      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
     }
     if (I != J) {
       for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
         const int c = e / ni, r = e % ni;
+        const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+        ZT v;
+        v.x = -S.pref * ai;
+        v.y = S.pref * ar;
+        Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// One MFIE tile.  The operator is not symmetric: a tile (I, J) with I != J
+// accumulates rows I against columns J in acc and, from the same kernel
+// values, rows J against columns I in acc2, each written once.  The test
+// points are read from the record per test point (the moments of both
+// directions hold the registers the EFIE tile gives to them).
+template <int Q, int MODE, typename ZT, int kFillThreads>
+__device__ __forceinline__ void fill_tile_mfie(
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float *acc2, int local,
+    float &rlo, float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
+    const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
+    const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
+    const int32_t *__restrict__ touch_rev, const float *__restrict__ sing, ZT *__restrict__ Z) {
+  constexpr int kWaves = kFillThreads / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int tij = tiles[local];
+  const int I = tij >> 16, J = tij & 0xffff;
+  const bool rev = I != J;  // also the block (J, I)
+  for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
+  if (rev)
+    for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc2[i] = 0.0f;
+  __syncthreads();
+  const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
+  const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
+  for (int pc = 0; pc < np; pc += 64) {
+    const bool pv = pc + lane < np;
+    const int pidx = pv ? pc + lane : pc;
+    const int p = blk_tri[p0 + pidx];
+    const int prow = pv ? blk_pos[p0 + pidx] : -1;
+    const float *pr = rec + (size_t)p * kRecFloats;
+    float palpha[3][3], psig[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+      psig[a] = pr[kRecSigma + a];
+    }
+    // unit normal of p (alpha_0 - alpha_a = v_a - v_0)
+    float nrm[3];
+    {
+      float e1[3], e2[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e1[c] = palpha[0][c] - palpha[1][c];
+        e2[c] = palpha[0][c] - palpha[2][c];
+      }
+      cross3(e1, e2, nrm);
+      const float inv = __builtin_amdgcn_rsqf(dot3(nrm, nrm));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nrm[c] *= inv;
+    }
+    const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
+    const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
+    const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
+    const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
+
+    for (int qi = wave; qi < nq; qi += kWaves) {
+      const int q = uniform(blk_tri[q0 + qi]);
+      const int qcol = uniform(blk_pos[q0 + qi]);
+      const float *qr = rec + (size_t)q * kRecFloats;
+      const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
+      const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
+      const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
+                         pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
+      float Xr[3][3], Xi[3][3];
+      float Rr[3][3], Ri[3][3];  // reverse block [b][a] (q tested against p)
+      if (!touch) {
+        const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
+        const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
+        const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
+        const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                    lz = (float)(Dz - (double)hz);
+        // unit normal of q (from its record, wave-uniform)
+        float qn[3];
         {
-          const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
-          ZT v;
-          v.x = -S.pref * ai;
-          v.y = S.pref * ar;
-          Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+          float e1[3], e2[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            e1[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 3 + c];
+            e2[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 6 + c];
+          }
+          cross3(e1, e2, qn);
+          const float inv = __builtin_amdgcn_rsqf(dot3(qn, qn));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) qn[c] *= inv;
+        }
+        MomentsM M;
+        if (MODE == MF_MODE_TABLE)
+          moments_table_mfie<Q>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+        else
+          moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float tau[3], Yr[3], Yi[3];
+          cross3(palpha[a], nrm, tau);
+          cross3(tau, M.dr, Yr);
+          cross3(tau, M.di, Yi);
+          const float yr = dot3(tau, M.xr) + M.m0r;
+          const float yi = dot3(tau, M.xi) + M.m0i;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Yr[c] += M.sr[c];
+            Yi[c] += M.si[c];
+          }
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const float *beta = qr + kRecAlpha + 3 * b;
+            Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
+            Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
+          }
+        }
+        if (rev) {
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            float tau[3], Yr[3], Yi[3];
+            cross3(qr + kRecAlpha + 3 * b, qn, tau);
+            cross3(M.dr, tau, Yr);  // tau x Md' = Md x tau (Md' = -Md)
+            cross3(M.di, tau, Yi);
+            const float yr = dot3(tau, M.qxr) + M.q0r;
+            const float yi = dot3(tau, M.qxi) + M.q0i;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              Yr[c] += M.qsr[c];
+              Yi[c] += M.qsi[c];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              Rr[b][a] = 0.25f * (dot3(palpha[a], Yr) + yr);
+              Ri[b][a] = 0.25f * (dot3(palpha[a], Yi) + yi);
+            }
+          }
+        }
+      } else {
+        int s = touch_off[p];
+        const int s1 = touch_off[p + 1];
+        while (s < s1 && touch_q[s] != q) ++s;
+        const bool found = s < s1;  // always: touching pairs are listed both ways
+        const float *x = sing + (size_t)(found ? s : 0) * 18;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
+            Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
+          }
+        if (rev) {  // the pair (q, p), block [b][a]
+          const float *y = sing + (size_t)(found ? touch_rev[s] : 0) * 18;
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              Rr[b][a] = found ? y[2 * (3 * b + a)] : 0.0f;
+              Ri[b][a] = found ? y[2 * (3 * b + a) + 1] : 0.0f;
+            }
+        }
+      }
+      if (pv) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int row = (prow >> (8 * a)) & 0xff;
+          if (row == 0xff) continue;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const int col = (qcol >> (8 * b)) & 0xff;
+            if (col == 0xff) continue;
+            const float sg = psig[a] * qr[kRecSigma + b];
+            float *dst = acc + row * kAccStride + 2 * col;
+            atomicAdd(dst, sg * Xr[a][b]);
+            atomicAdd(dst + 1, sg * Xi[a][b]);
+            if (rev) {
+              float *dst2 = acc2 + col * kAccStride + 2 * row;
+              atomicAdd(dst2, sg * Rr[b][a]);
+              atomicAdd(dst2 + 1, sg * Ri[b][a]);
+            }
+          }
         }
       }
     }
   }
   __syncthreads();
+  // Z = acc/(4 pi): rows of block I, columns of block J; and the reverse
+  const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+  const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
+  for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+    const int r = e / nj, c = e % nj;
+    ZT v;
+    v.x = S.pref * acc[r * kAccStride + 2 * c];
+    v.y = S.pref * acc[r * kAccStride + 2 * c + 1];
+    Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
   }
+  if (rev) {
+    for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+      const int r = e / ni, c = e % ni;
+      ZT v;
+      v.x = S.pref * acc2[r * kAccStride + 2 * c];
+      v.y = S.pref * acc2[r * kAccStride + 2 * c + 1];
+      Z[(size_t)(j0 + r) * S.ldz + (i0 + c)] = v;
+    }
+  }
+  __syncthreads();
 }
 
 template <int Q, int MODE, bool kLDS, int PART, typename ZT, bool kSparse, int OP = MF_OP_EFIE>
-__global__ __launch_bounds__(fill_threads<MODE>())
-__attribute__((amdgpu_waves_per_eu(fill_threads<MODE>() / 256, fill_threads<MODE>() / 256))) void k_fill(
+__global__ __launch_bounds__((fill_threads_op<MODE, OP>()))
+__attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
+                                   fill_threads_op<MODE, OP>() / 256))) void k_fill(
     FillItem S, FillRule W) {
-  constexpr int kFillThreads = fill_threads<MODE>();
+  constexpr int kFillThreads = fill_threads_op<MODE, OP>();
+  constexpr int kAccs = OP == MF_OP_MFIE ? 2 : 1;
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
-  const TabPtrs tab =
-      load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + kAccFloats / 4 + 1);
+  float *acc2 = OP == MF_OP_MFIE ? acc + kAccFloats : nullptr;
+  const TabPtrs tab = load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(
+      S, smem4 + kAccs * kAccFloats / 4 + 1);
   float rlo = INFINITY, rhi = 0.0f;
   const int ntiles = S.tile_end - S.tile_begin;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse, OP>(
-        S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
-        S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if constexpr (OP == MF_OP_MFIE)
+      fill_tile_mfie<Q, MODE, ZT, kFillThreads>(
+          S, W, tab, acc, acc2, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri,
+          S.blk_pos, S.touch_off, S.touch_q, S.touch_rev, S.sing, reinterpret_cast<ZT *>(S.Z));
+    else
+      fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse>(
+          S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
+          S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
+  }
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
@@ -661,14 +933,14 @@ static int launch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
   constexpr int kFillThreads = fill_threads<MODE>();
   if (L.op == MF_OP_MFIE) {
     if constexpr (PART == 0) {
+      constexpr int kThr = fill_threads_op<MODE, MF_OP_MFIE>();
       auto kern = k_fill<Q, MODE, kLDS, 0, ZT, false, MF_OP_MFIE>;
       if (L.grid == 0) {
-        const int rc = plan_grid(L, kern, kFillThreads);
+        const int rc = plan_grid(L, kern, kThr);
         if (rc) return rc;
       }
       if (plan_only || L.total_tiles == 0) return MF_OK;
-      hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kFillThreads), L.lds, s, L.first,
-                         L.rule);
+      hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kThr), L.lds, s, L.first, L.rule);
     } else {
       set_error("the MFIE fill has no partial modes");
       return MF_EINVAL;
@@ -753,6 +1025,7 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.blk_pos = m->d_blk_pos;
   S.touch_off = m->d_touch_off;
   S.touch_q = m->d_touch_q;
+  S.touch_rev = m->d_touch_rev;
   S.sing = sing;
   S.Z = Z;
   S.status = m->d_status;
@@ -789,7 +1062,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->op = (mode & kModeMfie) ? MF_OP_MFIE : MF_OP_EFIE;
   L->z_dtype = z_dtype;
   for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
-  L->lds = sizeof(float) * kAccFloats + 16;
+  L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 2 : 1) + 16;
   std::vector<FillItem> items(n);
   size_t tmax = 0;
   int tiles = 0;
