@@ -211,7 +211,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
               float ei;
               if (MODE == MF_MODE_TABLE) {
                 float u;
-                const int ii = look_interval(S.gl[look_bucket(R, S.ginv, S.gbias, S.gmax)], R, u);
+                const int ii = look_interval(
+                    look_record(S.gl, look_bucket(R, S.ginv, S.gbias, S.gmax)), R, u);
                 const float4 A = S.g01[ii], B = S.g23[ii];
                 // g = c0 + c1 u + c2 u^2 + c3 u^3, g' = c1 + 2 c2 u + 3 c3 u^2
                 const float der = fmaf(3.0f * B.z, u, 2.0f * B.x);
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
                 gr = g.x;
                 gi = g.y;
                 float ue;
-                const int ie = look_interval(S.el[look_bucket(R, S.einv, S.ebias, S.emax)], R, ue);
+                const int ie = look_interval(
+                    look_record(S.el, look_bucket(R, S.einv, S.ebias, S.emax)), R, ue);
                 const float4 Ec = S.ec[ie];
                 er = fmaf(Ec.z, ue, Ec.x);
                 ei = fmaf(Ec.w, ue, Ec.y);

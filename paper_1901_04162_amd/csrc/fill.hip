@@ -47,11 +47,13 @@ namespace mf {
 constexpr int kBM = kMaxBlockEdges;
 constexpr int kAccStride = 2 * kBM + 1;  // odd stride: rows fall in different banks
 constexpr int kAccFloats = kBM * kAccStride;
-// Table mode runs 768 threads (3 waves per SIMD, room for the batched
-// lookups of one test point in registers); direct mode 1024.
+// The EFIE kernels run 1024 threads (4 waves per SIMD, at most 128 VGPRs):
+// the source records sit in SGPRs and the test triangle's data is read from
+// its record where it is used.  Sixteen waves also split a block's source
+// triangles (at most 64) evenly.
 template <int MODE>
 constexpr int fill_threads() {
-  return MODE == MF_MODE_TABLE ? 768 : 1024;
+  return 1024;
 }
 // The MFIE kernel holds both directions' moments and two accumulators: 512
 // threads (2 waves per SIMD, 256 VGPRs per lane), one workgroup per CU.
@@ -98,6 +100,15 @@ struct TabPtrs {
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wave-uniform read-only data (the source triangle's record, the block
+// lists) is read through the constant address space: the loads then go to
+// the scalar unit and the values live in SGPRs.
+typedef __attribute__((address_space(4))) const float cfloat;
+typedef __attribute__((address_space(4))) const int32_t cint32;
+typedef __attribute__((address_space(4))) const double cdouble;
+__device__ __forceinline__ cfloat *as_const(const float *p) { return (cfloat *)p; }
+__device__ __forceinline__ cint32 *as_const(const int32_t *p) { return (cint32 *)p; }
 
 // The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
 struct Moments {
@@ -243,32 +254,32 @@ __device__ __forceinline__ void green_to_k(float k, float ri, float &gr, float &
 template <int OP>
 using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>::type;
 
-// Table mode.  The lookups of one test point go in groups of source
-// points, each in three steps (distances and bucket-record reads, then
-// coefficient reads, then the cubic and the sums), so that the dependent LDS
-// reads of a group overlap each other.  The interval search is the bucket lookup of Eq. (6)
-// in the record form of lookup.hpp (one 16-byte read gives the interval and
-// its first sample), and the cubic of Eq. (5) is evaluated in Horner form
-// about that sample.
+// Table mode.  The test-point loop stays rolled and reads rho_i from the
+// record; the lookups of one test point go in two groups of source points,
+// each in three steps (distances and bucket-record reads, then coefficient
+// reads, then the cubic and the sums), so that the dependent reads of a
+// group overlap each other.  The interval search is the bucket lookup of
+// Eq. (6) in the record form of lookup.hpp (one gather gives the interval
+// and its first sample), and the cubic of Eq. (5) is evaluated in Horner
+// form about that sample.  The MFIE takes K = (1/R + jk) g/R from the same
+// value and adds the third inner sum T2.
 template <int Q, int OP>
 __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
-                                              const FillScalars &S, const FillRule &W,
-                                              const float (&prho)[Q][3], const float *nrm,
-                                              const float *nq, float hx, float hy, float hz,
-                                              float lx, float ly, float lz, const float *qr,
-                                              float &rlo, float &rhi) {
+                                                     const FillScalars &S, const FillRule &W,
+                                                     const float *pr, const float *nrm,
+                                                     const float *nq, float hx, float hy,
+                                                     float hz, float lx, float ly, float lz,
+                                                     cfloat *qr, float &rlo, float &rhi) {
   zero(M);
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < Q; ++i) {
-    // test point relative to the source centroid: the FP64 centroid offset
-    // enters as hi + (lo + rho), one FP32 rounding at the size of R
-    const float ax = hx + (prho[i][0] + lx), ay = hy + (prho[i][1] + ly),
-                az = hz + (prho[i][2] + lz);
+    float pri[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
+    const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
     float t2r = 0.f, t2i = 0.f;
-    // batches of source points keep fewer lookups live at once (three for
-    // the MFIE, whose moments hold more registers)
-    constexpr int kG = OP == MF_OP_MFIE ? 3 : 2;
+    constexpr int kG = 2;
 #pragma unroll
     for (int grp = 0; grp < kG; ++grp) {
       const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
@@ -282,7 +293,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
         r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         rlo = fminf(rlo, r[j]);
         rhi = fmaxf(rhi, r[j]);
-        w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
+        w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
       }
       float u[Q];
       float4 A[Q], B[Q];
@@ -316,78 +327,10 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     }
     if constexpr (OP == MF_OP_MFIE) {
       const float a[3] = {ax, ay, az};
-      add_point(M, W.w[i], prho[i], a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
+      add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
     } else {
-      add_point(M, W.w[i], prho[i], t0r, t0i, t1r, t1i);
+      add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
     }
-  }
-}
-
-// MFIE, table mode: the same grouped lookups with the test-point loop
-// rolled and rho_i read from the record (the moments of both directions take
-// the registers the EFIE path spends on the unrolled test points).
-template <int Q>
-__device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &tab,
-                                                   const FillScalars &S, const FillRule &W,
-                                                   const float *pr, const float *nrm,
-                                                   const float *nq, float hx, float hy, float hz,
-                                                   float lx, float ly, float lz, const float *qr,
-                                                   float &rlo, float &rhi) {
-  zero(M);
-#pragma unroll 1
-  for (int i = 0; i < Q; ++i) {
-    float pri[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
-    const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
-    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
-    float t2r = 0.f, t2i = 0.f;
-    constexpr int kG = 2;
-#pragma unroll
-    for (int grp = 0; grp < kG; ++grp) {
-      const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
-      float r[Q];
-      int4 w[Q];
-#pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const float dx = ax - qr[kRecRho + 3 * j + 0];
-        const float dy = ay - qr[kRecRho + 3 * j + 1];
-        const float dz = az - qr[kRecRho + 3 * j + 2];
-        r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        rlo = fminf(rlo, r[j]);
-        rhi = fmaxf(rhi, r[j]);
-        w[j] = tab.look[look_bucket(r[j], S.tinv, S.tbias, S.tmax)];
-      }
-      float u[Q];
-      float4 A[Q], B[Q];
-#pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const int ii = look_interval(w[j], r[j], u[j]);
-        A[j] = tab.c01[ii];
-        B[j] = tab.c23[ii];
-      }
-#pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const float2 g = cubic(A[j], B[j], u[j]);
-        float gr = g.x, gi = g.y;
-        green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
-        t0r = fmaf(W.w[j], gr, t0r);
-        t0i = fmaf(W.w[j], gi, t0i);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float wq = qr[kRecWRho + 3 * j + c];
-          t1r[c] = fmaf(wq, gr, t1r[c]);
-          t1i[c] = fmaf(wq, gi, t1i[c]);
-        }
-        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
-                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
-                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
-        t2r = fmaf(wr2, gr, t2r);
-        t2i = fmaf(wr2, gi, t2i);
-      }
-    }
-    const float a[3] = {ax, ay, az};
-    add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
   }
 }
 
@@ -397,7 +340,7 @@ template <int Q, int OP>
 __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScalars &S,
                                                const FillRule &W, const float *pr,
                                                const float *nrm, const float *nq, float hx, float hy, float hz, float lx, float ly,
-                                               float lz, const float *qr) {
+                                               float lz, cfloat *qr) {
   zero(M);
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
@@ -451,9 +394,10 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
 // records in LDS with the coefficients in global memory).
 template <bool kLDS, int kThreads>
 __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coef) {
-  if (!kLDS) return TabPtrs{S.look, S.coef, S.coef + (S.tn - 1)};
-  for (int i = threadIdx.x; i < 2 * (S.tn - 1); i += kThreads) lds_coef[i] = S.coef[i];
-  return TabPtrs{S.look, lds_coef, lds_coef + (S.tn - 1)};
+  const int ne = S.tn - 1;
+  if (!kLDS) return TabPtrs{S.look, S.coef, S.coef + ne};
+  for (int i = threadIdx.x; i < 2 * ne; i += kThreads) lds_coef[i] = S.coef[i];
+  return TabPtrs{S.look, lds_coef, lds_coef + ne};
 }
 
 // One tile of one item: accumulate it in LDS, then write it and its mirror.
@@ -483,43 +427,31 @@ __device__ __forceinline__ void fill_tile(
     const int p = blk_tri[p0 + pidx];
     const int prow = pv ? blk_pos[p0 + pidx] : -1;
     const float *pr = rec + (size_t)p * kRecFloats;
-    float prho[Q][3], palpha[3][3], psig[3];
-    if (MODE == MF_MODE_TABLE) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) prho[i][c] = pr[kRecRho + 3 * i + c];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
-      psig[a] = pr[kRecSigma + a];
-    }
+    float palpha[3][3], psig[3];  // read from the record where they are used
     const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
     const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
     const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
     const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
 
     for (int qi = wave; qi < nq; qi += kWaves) {
-      const int q = uniform(blk_tri[q0 + qi]);
-      const int qcol = uniform(blk_pos[q0 + qi]);
-      const float *qr = rec + (size_t)q * kRecFloats;
-      const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
+      const int q = uniform(as_const(blk_tri)[q0 + qi]);
+      const int qcol = uniform(as_const(blk_pos)[q0 + qi]);
+      cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
+      cint32 *qvi = (cint32 *)(qr + kRecVid);
       const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
       const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
                          pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
       float Xr[3][3], Xi[3][3];
       if (!touch) {
-        const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
+        cdouble *qcd = (cdouble *)(qr + kRecCent);
         const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
         Moments M;
         if (MODE == MF_MODE_TABLE)
-          moments_table<Q, MF_OP_EFIE>(M, tab, S, W, prho, nullptr, nullptr, hx, hy, hz, lx, ly,
-                                       lz, qr, rlo, rhi);
+          moments_table<Q, MF_OP_EFIE>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
+                                       qr, rlo, rhi);
         else
           moments_direct<Q, MF_OP_EFIE>(M, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
                                         qr);
@@ -528,10 +460,15 @@ __device__ __forceinline__ void fill_tile(
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
+          for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
           for (int b = 0; b < 3; ++b) {
             float vr = 0.f, vi = 0.f;
             if (!(PART & MF_PART_PHI)) {
-              const float *beta = qr + kRecAlpha + 3 * b;
+              const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
+                                     qr[kRecAlpha + 3 * b + 2]};
               const float ab = palpha[a][0] * beta[0] + palpha[a][1] * beta[1] +
                                palpha[a][2] * beta[2];
               vr = fmaf(ab, s0r, srr);
@@ -566,6 +503,8 @@ __device__ __forceinline__ void fill_tile(
           }
       }
       if (pv) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) psig[a] = pr[kRecSigma + a];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const int row = (prow >> (8 * a)) & 0xff;
@@ -680,17 +619,17 @@ __device__ __forceinline__ void fill_tile_mfie(
     const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
 
     for (int qi = wave; qi < nq; qi += kWaves) {
-      const int q = uniform(blk_tri[q0 + qi]);
-      const int qcol = uniform(blk_pos[q0 + qi]);
-      const float *qr = rec + (size_t)q * kRecFloats;
-      const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
+      const int q = uniform(as_const(blk_tri)[q0 + qi]);
+      const int qcol = uniform(as_const(blk_pos)[q0 + qi]);
+      cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
+      cint32 *qvi = (cint32 *)(qr + kRecVid);
       const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
       const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
                          pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
       float Xr[3][3], Xi[3][3];
       float Rr[3][3], Ri[3][3];  // reverse block [b][a] (q tested against p)
       if (!touch) {
-        const double *qcd = reinterpret_cast<const double *>(qr + kRecCent);
+        cdouble *qcd = (cdouble *)(qr + kRecCent);
         const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
@@ -711,7 +650,7 @@ __device__ __forceinline__ void fill_tile_mfie(
         }
         MomentsM M;
         if (MODE == MF_MODE_TABLE)
-          moments_table_mfie<Q>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          moments_table<Q, MF_OP_MFIE>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
         else
           moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
 #pragma unroll
@@ -729,7 +668,8 @@ __device__ __forceinline__ void fill_tile_mfie(
           }
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
-            const float *beta = qr + kRecAlpha + 3 * b;
+            const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
+                                   qr[kRecAlpha + 3 * b + 2]};
             Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
             Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
           }
@@ -738,7 +678,9 @@ __device__ __forceinline__ void fill_tile_mfie(
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             float tau[3], Yr[3], Yi[3];
-            cross3(qr + kRecAlpha + 3 * b, qn, tau);
+            const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
+                                   qr[kRecAlpha + 3 * b + 2]};
+            cross3(beta, qn, tau);
             cross3(M.dr, tau, Yr);  // tau x Md' = Md x tau (Md' = -Md)
             cross3(M.di, tau, Yi);
             const float yr = dot3(tau, M.qxr) + M.q0r;

@@ -26,6 +26,13 @@ __device__ __forceinline__ int look_bucket(float r, float inv, float bias, float
   return (int)__builtin_amdgcn_fmed3f(fmaf(r, inv, bias), 0.0f, top);
 }
 
+// Bucket record b; the 32-bit byte offset lets the load take its base from
+// scalar registers.
+__device__ __forceinline__ int4 look_record(const int4 *look, int b) {
+  return *reinterpret_cast<const int4 *>(reinterpret_cast<const char *>(look) +
+                                         ((unsigned)b << 4));
+}
+
 // Interval of r from its bucket record; u receives r minus the interval's
 // first sample.
 __device__ __forceinline__ int look_interval(const int4 &w, float r, float &u) {

@@ -599,7 +599,7 @@ __global__ void k_table_eval(const int4 *look, const float4 *coef, int tn, float
   }
   const float rf = (float)x;
   float u;
-  const int ii = look_interval(look[look_bucket(rf, binv, bbias, btop)], rf, u);
+  const int ii = look_interval(look_record(look, look_bucket(rf, binv, bbias, btop)), rf, u);
   float2 v;
   if (kind == kGreen) {
     v = cubic(coef[ii], coef[(tn - 1) + ii], u);
