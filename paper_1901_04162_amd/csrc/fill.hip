@@ -255,21 +255,20 @@ template <int OP>
 using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>::type;
 
 // Table mode.  The test-point loop stays rolled and reads rho_i from the
-// record; the lookups of one test point go in two groups of source points,
-// each in three steps (distances and bucket-record reads, then coefficient
-// reads, then the cubic and the sums), so that the dependent reads of a
-// group overlap each other.  The interval search is the bucket lookup of
+// record; the lookups of one test point go in three steps (distances and
+// bucket-record reads, then coefficient reads, then the cubic and the sums)
+// over all source points at once for the EFIE, in two groups for the MFIE
+// (whose moments hold more registers), so that the dependent reads overlap.  The interval search is the bucket lookup of
 // Eq. (6) in the record form of lookup.hpp (one gather gives the interval
 // and its first sample), and the cubic of Eq. (5) is evaluated in Horner
 // form about that sample.  The MFIE takes K = (1/R + jk) g/R from the same
 // value and adds the third inner sum T2.
 template <int Q, int OP>
 __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
-                                                     const FillScalars &S, const FillRule &W,
-                                                     const float *pr, const float *nrm,
-                                                     const float *nq, float hx, float hy,
-                                                     float hz, float lx, float ly, float lz,
-                                                     cfloat *qr, float &rlo, float &rhi) {
+                                              const FillScalars &S, const FillRule &W,
+                                              const float *pr, const float *nrm, const float *nq,
+                                              float hx, float hy, float hz, float lx, float ly,
+                                              float lz, cfloat *qr, float &rlo, float &rhi) {
   zero(M);
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
@@ -279,7 +278,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
     float t2r = 0.f, t2i = 0.f;
-    constexpr int kG = 2;
+    constexpr int kG = OP == MF_OP_MFIE ? 2 : 1;
 #pragma unroll
     for (int grp = 0; grp < kG; ++grp) {
       const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
