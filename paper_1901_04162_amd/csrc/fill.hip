@@ -41,6 +41,7 @@
 
 #include "internal.hpp"
 #include "lookup.hpp"
+#include "uniform.hpp"
 
 namespace mf {
 
@@ -101,14 +102,6 @@ struct TabPtrs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Wave-uniform read-only data (the source triangle's record, the block
-// lists) is read through the constant address space: the loads then go to
-// the scalar unit and the values live in SGPRs.
-typedef __attribute__((address_space(4))) const float cfloat;
-typedef __attribute__((address_space(4))) const int32_t cint32;
-typedef __attribute__((address_space(4))) const double cdouble;
-__device__ __forceinline__ cfloat *as_const(const float *p) { return (cfloat *)p; }
-__device__ __forceinline__ cint32 *as_const(const int32_t *p) { return (cint32 *)p; }
 
 // The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
 struct Moments {
