@@ -119,6 +119,7 @@ int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
 
 constexpr int kRangeBlock = 256;
 constexpr int kRangeChunk = 256;  // equal to kRangeBlock: one sphere list serves both
+constexpr int kRangeScreen = 32;  // source triangles screened per round
 
 struct RangeTri {
   double c[3];
@@ -193,17 +194,44 @@ __device__ inline void flush_extremes(double lo, double hi, unsigned long long *
   }
 }
 
+// Farthest centroid from the centroid of triangle `from` (or, when from < 0,
+// of the triangle whose index sits in the low half of *from_slot): *out keeps
+// the maximum of (float bits of the squared distance) << 32 | index.  Two
+// such sweeps give an approximate diameter pair of the mesh, the witnesses
+// for the largest distance.
+__global__ void k_range_far(const float *__restrict__ rec, int nt, int from,
+                            const unsigned long long *__restrict__ from_slot,
+                            unsigned long long *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = from >= 0 ? from : (int)(unsigned)(*from_slot & 0xffffffffull);
+  const double *fc = reinterpret_cast<const double *>(rec + (size_t)f * kRecFloats + kRecCent);
+  unsigned long long v = 0ull;
+  if (t < nt) {
+    const double *tc = reinterpret_cast<const double *>(rec + (size_t)t * kRecFloats + kRecCent);
+    const float d2 = (float)sq_dist(tc, fc);
+    v = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)t;
+  }
+  v = wave_max_u64(v);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
 // Witnesses: each triangle against a few index neighbours (close in space for
-// meshes numbered with locality) and a few pseudo-random partners.
+// meshes numbered with locality), a few pseudo-random partners and the two
+// ends of the approximate diameter (far[0], far[1]).
 __global__ void k_range_seed(const double *__restrict__ qp64, const float *__restrict__ rec, int nt,
-                             int nq, unsigned long long *__restrict__ out) {
+                             int nq, unsigned long long *__restrict__ out,
+                             const unsigned long long *__restrict__ far) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   double lo = INFINITY, hi = 0.0;
   if (p < nt) {
     const int *pv = reinterpret_cast<const int *>(rec + (size_t)p * kRecFloats + kRecVid);
-    for (int j = 0; j < 24; ++j) {
-      const int q = j < 16 ? (p + 2 + j) % nt
-                           : (int)(((long long)p * 7919 + (long long)j * 104729) % nt);
+    const int f0 = (int)(unsigned)(far[0] & 0xffffffffull);
+    const int f1 = (int)(unsigned)(far[1] & 0xffffffffull);
+    for (int j = 0; j < 26; ++j) {
+      const int q = j < 16   ? (p + 2 + j) % nt
+                    : j < 24 ? (int)(((long long)p * 7919 + (long long)j * 104729) % nt)
+                    : j == 24 ? f0
+                              : f1;
       const int *qv = reinterpret_cast<const int *>(rec + (size_t)q * kRecFloats + kRecVid);
       if (q == p || share_vertex(pv, qv)) continue;
       pair_extremes(qp64, nq, p, q, lo, hi);
@@ -212,20 +240,22 @@ __global__ void k_range_seed(const double *__restrict__ qp64, const float *__res
   flush_extremes(lo, hi, out);
 }
 
-// Bounding sphere of every run of kRangeBlock triangles (centre, radius
-// covering all their quadrature points), for skipping whole block pairs.
-__global__ __launch_bounds__(kRangeBlock) void k_range_spheres(const double *__restrict__ brad,
-                                                               const float *__restrict__ rec,
-                                                               int nt, double *__restrict__ sph) {
-  __shared__ double red[kRangeBlock][3];
+// Bounding sphere of every run of kRun triangles (centre, radius covering all
+// their quadrature points), for skipping whole block pairs (runs of
+// kRangeBlock) and, per test triangle, whole rounds of kRangeScreen sources.
+template <int kRun>
+__global__ __launch_bounds__(kRun) void k_range_spheres(const double *__restrict__ brad,
+                                                        const float *__restrict__ rec, int nt,
+                                                        double *__restrict__ sph) {
+  __shared__ double red[kRun][3];
   __shared__ double cen[3];
-  const int t = blockIdx.x * kRangeBlock + threadIdx.x;
-  const int n = min(kRangeBlock, nt - (int)blockIdx.x * kRangeBlock);
+  const int t = blockIdx.x * kRun + threadIdx.x;
+  const int n = min(kRun, nt - (int)blockIdx.x * kRun);
   RangeTri T{};
   if (t < nt) load_range_tri(brad, rec, t, T);
   for (int d = 0; d < 3; ++d) red[threadIdx.x][d] = t < nt ? T.c[d] : 0.0;
   __syncthreads();
-  for (int h = kRangeBlock / 2; h > 0; h >>= 1) {
+  for (int h = kRun / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h)
       for (int d = 0; d < 3; ++d) red[threadIdx.x][d] += red[threadIdx.x + h][d];
     __syncthreads();
@@ -238,7 +268,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_spheres(const double *__r
   __syncthreads();
   red[threadIdx.x][0] = r;
   __syncthreads();
-  for (int h = kRangeBlock / 2; h > 0; h >>= 1) {
+  for (int h = kRun / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x][0] = fmax(red[threadIdx.x][0], red[threadIdx.x + h][0]);
     __syncthreads();
   }
@@ -255,6 +285,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
                                                        const double *__restrict__ brad,
                                                        const float *__restrict__ rec, int nt,
                                                        int nq, const double *__restrict__ sph,
+                                                       const double *__restrict__ sph_round,
                                                        unsigned long long *out) {
   const int p0 = blockIdx.x * kRangeBlock, q0 = blockIdx.y * kRangeChunk;
   if (q0 + kRangeChunk <= p0) return;  // unordered pairs: q > p only
@@ -272,29 +303,63 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
   __syncthreads();
   if (skip) return;
   __shared__ RangeTri sq[kRangeChunk];
+  // pairs that pass the screen, {test lane << 16 | source index}, evaluated
+  // by the whole block so that no wave idles behind a few passing lanes
+  __shared__ int list[kRangeBlock * kRangeScreen];
+  __shared__ int nlist;
   const int p = p0 + threadIdx.x;
   const int nqc = min(kRangeChunk, nt - q0);
   for (int i = threadIdx.x; i < nqc; i += kRangeBlock) load_range_tri(brad, rec, q0 + i, sq[i]);
-  __syncthreads();
-  double lo = INFINITY, hi = 0.0;
-  if (p < nt) {
-    RangeTri P;
-    load_range_tri(brad, rec, p, P);
-    lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
-    hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
-    for (int j = max(0, p + 1 - q0); j < nqc; ++j) {
-      const RangeTri &Q = sq[j];
-      if (share_vertex(P.v, Q.v)) continue;
-      const double D[3] = {Q.c[0] - P.c[0], Q.c[1] - P.c[1], Q.c[2] - P.c[2]};
-      const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d = sqrt(d2);
-      const double cp = (D[0] * P.n[0] + D[1] * P.n[1] + D[2] * P.n[2]) / d;
-      const double cq = (D[0] * Q.n[0] + D[1] * Q.n[1] + D[2] * Q.n[2]) / d;
-      const double hh = P.rb * sqrt(fmax(0.0, 1.0 - cp * cp)) + Q.rb * sqrt(fmax(0.0, 1.0 - cq * cq));
-      const double rr = P.rb + Q.rb;
-      const double lo_b = (d2 - 2.0 * d * hh) * (1.0 - 1e-9);
-      const double hi_b = (d2 + 2.0 * d * hh + rr * rr) * (1.0 + 1e-9);
-      if (lo_b <= lo || hi_b >= hi) pair_extremes(qp64, nq, p, q0 + j, lo, hi);
+  double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
+  double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
+  RangeTri P{};
+  if (p < nt) load_range_tri(brad, rec, p, P);
+  // The pair bounds are screened in FP32 and made conservative: the centre
+  // offset is formed in FP64 before rounding, the sine of each normal angle
+  // is bounded from above (+1e-5 under the root), the bounds are widened by
+  // 1e-5 of their size and the running extremes by 1e-6, all far above the
+  // FP32 rounding, so a pair that could move an extreme is never screened
+  // out.  The pairs that pass are evaluated exactly in FP64.
+  const float pn[3] = {(float)P.n[0], (float)P.n[1], (float)P.n[2]};
+  const float prb = (float)P.rb;
+  for (int jc = 0; jc < nqc; jc += kRangeScreen) {
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    // this round's sources lie in one bounding sphere: skip them when no
+    // point of them can move an extreme against this test triangle
+    bool near_or_far = p < nt;
+    if (near_or_far) {
+      const double *b = sph_round + 4 * ((q0 + jc) / kRangeScreen);
+      const double dc = sqrt(sq_dist(P.c, b)), rr = P.rb + b[3];
+      const double dmin = fmax(0.0, dc - rr), dmax = dc + rr;
+      near_or_far = !(dmin * dmin * (1.0 - 1e-9) > lo && dmax * dmax * (1.0 + 1e-9) < hi);
     }
+    if (near_or_far) {
+      const float lo_f = (float)lo * 1.000001f, hi_f = (float)hi * 0.999999f;
+      const int j1 = min(jc + kRangeScreen, nqc);
+      for (int j = max(jc, p + 1 - q0); j < j1; ++j) {
+        const RangeTri &Q = sq[j];
+        if (share_vertex(P.v, Q.v)) continue;
+        const float D[3] = {(float)(Q.c[0] - P.c[0]), (float)(Q.c[1] - P.c[1]),
+                            (float)(Q.c[2] - P.c[2])};
+        const float d2 = fmaf(D[0], D[0], fmaf(D[1], D[1], D[2] * D[2]));
+        const float id2 = 1.0f / fmaxf(d2, 1e-30f);
+        const float dp = D[0] * pn[0] + D[1] * pn[1] + D[2] * pn[2];
+        const float dq = D[0] * (float)Q.n[0] + D[1] * (float)Q.n[1] + D[2] * (float)Q.n[2];
+        const float sp = sqrtf(fmaxf(0.0f, 1.0f - dp * dp * id2) + 1e-5f);
+        const float sqq = sqrtf(fmaxf(0.0f, 1.0f - dq * dq * id2) + 1e-5f);
+        const float qrb = (float)Q.rb;
+        const float d = sqrtf(d2), dh = 2.0f * d * (prb * sp + qrb * sqq), rr = prb + qrb;
+        const float lo_b = (d2 - dh) - 1e-5f * (d2 + dh);
+        const float hi_b = (d2 + dh + rr * rr) * 1.00001f;
+        if (lo_b <= lo_f || hi_b >= hi_f) list[atomicAdd(&nlist, 1)] = (threadIdx.x << 16) | j;
+      }
+    }
+    __syncthreads();
+    const int n = nlist;
+    for (int e = threadIdx.x; e < n; e += kRangeBlock)
+      pair_extremes(qp64, nq, p0 + (list[e] >> 16), q0 + (list[e] & 0xffff), lo, hi);
+    __syncthreads();
   }
   flush_extremes(lo, hi, out);
 }
@@ -302,19 +367,27 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s) {
   (void)V;
-  unsigned long long init[2] = {~0ull, 0ull};
+  unsigned long long init[4] = {~0ull, 0ull, 0ull, 0ull};
   MF_HIP(hipMemcpyAsync(m->d_scratch, init, sizeof(init), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_range_seed, dim3((m->nt + 255) / 256), dim3(256), 0, s, m->d_qp64,
-                     m->d_rec, m->nt, r.nq, m->d_scratch);
+  const dim3 tgrid((m->nt + 255) / 256);
+  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, 0, m->d_scratch,
+                     m->d_scratch + 2);
+  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, -1,
+                     m->d_scratch + 2, m->d_scratch + 3);
+  hipLaunchKernelGGL(k_range_seed, tgrid, dim3(256), 0, s, m->d_qp64, m->d_rec, m->nt, r.nq,
+                     m->d_scratch, m->d_scratch + 2);
   MF_HIP(hipGetLastError());
   const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
+  const int nr = (m->nt + kRangeScreen - 1) / kRangeScreen;
   double *sph = nullptr;
-  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * nb, s));
-  hipLaunchKernelGGL(k_range_spheres, dim3(nb), dim3(kRangeBlock), 0, s, m->d_brad, m->d_rec,
-                     m->nt, sph);
+  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * (nb + nr), s));
+  hipLaunchKernelGGL(k_range_spheres<kRangeBlock>, dim3(nb), dim3(kRangeBlock), 0, s,
+                     m->d_brad, m->d_rec, m->nt, sph);
+  hipLaunchKernelGGL(k_range_spheres<kRangeScreen>, dim3(nr), dim3(kRangeScreen), 0, s,
+                     m->d_brad, m->d_rec, m->nt, sph + 4 * nb);
   dim3 grid(nb, (m->nt + kRangeChunk - 1) / kRangeChunk);
   hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
-                     m->nt, r.nq, sph, m->d_scratch);
+                     m->nt, r.nq, sph, sph + 4 * nb, m->d_scratch);
   MF_HIP(hipGetLastError());
   MF_HIP(hipFreeAsync(sph, s));
   MF_HIP(hipGetLastError());
