@@ -36,9 +36,17 @@ def _rel(a, b):
 
 # ---- distance range and tables -------------------------------------------
 
-@pytest.mark.parametrize("name,s,q", [("ico", 2, 3), ("ico", 3, 6), ("plate", 12, 7), ("ico", 1, 7)])
+@pytest.mark.parametrize("name,s,q", [("ico", 2, 3), ("ico", 3, 6), ("plate", 12, 7), ("ico", 1, 7),
+                                      ("ico", 5, 7), ("plate", 100, 7)])
 def test_r_range_matches_oracle(mf, orc, name, s, q):
-    V, F = meshes.icosphere(s) if name == "ico" else meshes.plate(n=s, h=0.1, jitter=0.005, seed=9)
+    # the last two are the benchmark sphere and the jittered plate of the
+    # precision study (about 6 s of oracle time each)
+    if name == "ico":
+        V, F = meshes.icosphere(s)
+    elif s == 100:
+        V, F = meshes.plate()
+    else:
+        V, F = meshes.plate(n=s, h=0.1, jitter=0.005, seed=9)
     say("r_range", name, s, q)
     m = mf.Mesh(F, V.shape[0])
     lo, hi = mf.r_range(m, V, q)
