@@ -248,10 +248,9 @@ template <int OP>
 using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>::type;
 
 // Table mode.  The test-point loop stays rolled and reads rho_i from the
-// record; the lookups of one test point go in three steps (distances and
-// bucket-record reads, then coefficient reads, then the cubic and the sums)
-// over all source points at once for the EFIE, in two groups for the MFIE
-// (whose moments hold more registers), so that the dependent reads overlap.  The interval search is the bucket lookup of
+// record; the lookups of one test point go in three steps over all source
+// points at once (distances and bucket-record reads, then coefficient reads,
+// then the cubic and the sums), so that the dependent reads overlap.  The interval search is the bucket lookup of
 // Eq. (6) in the record form of lookup.hpp (one gather gives the interval
 // and its first sample), and the cubic of Eq. (5) is evaluated in Horner
 // form about that sample.  The MFIE takes K = (1/R + jk) g/R from the same
@@ -271,50 +270,45 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
     float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
     float t2r = 0.f, t2i = 0.f;
-    constexpr int kG = OP == MF_OP_MFIE ? 2 : 1;
+    float r[Q];
+    int4 w[Q];
 #pragma unroll
-    for (int grp = 0; grp < kG; ++grp) {
-      const int j0 = (grp * Q + kG - 1) / kG, j1 = ((grp + 1) * Q + kG - 1) / kG;
-      float r[Q];
-      int4 w[Q];
+    for (int j = 0; j < Q; ++j) {
+      const float dx = ax - qr[kRecRho + 3 * j + 0];
+      const float dy = ay - qr[kRecRho + 3 * j + 1];
+      const float dz = az - qr[kRecRho + 3 * j + 2];
+      r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      rlo = fminf(rlo, r[j]);
+      rhi = fmaxf(rhi, r[j]);
+      w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
+    }
+    float u[Q];
+    float4 A[Q], B[Q];
 #pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const float dx = ax - qr[kRecRho + 3 * j + 0];
-        const float dy = ay - qr[kRecRho + 3 * j + 1];
-        const float dz = az - qr[kRecRho + 3 * j + 2];
-        r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        rlo = fminf(rlo, r[j]);
-        rhi = fmaxf(rhi, r[j]);
-        w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
+    for (int j = 0; j < Q; ++j) {
+      const int ii = look_interval(w[j], r[j], u[j]);
+      A[j] = tab.c01[ii];
+      B[j] = tab.c23[ii];
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float2 g = cubic(A[j], B[j], u[j]);
+      float gr = g.x, gi = g.y;
+      if constexpr (OP == MF_OP_MFIE) green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
+      t0r = fmaf(W.w[j], gr, t0r);
+      t0i = fmaf(W.w[j], gi, t0i);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float wq = qr[kRecWRho + 3 * j + c];
+        t1r[c] = fmaf(wq, gr, t1r[c]);
+        t1i[c] = fmaf(wq, gi, t1i[c]);
       }
-      float u[Q];
-      float4 A[Q], B[Q];
-#pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const int ii = look_interval(w[j], r[j], u[j]);
-        A[j] = tab.c01[ii];
-        B[j] = tab.c23[ii];
-      }
-#pragma unroll
-      for (int j = j0; j < j1; ++j) {
-        const float2 g = cubic(A[j], B[j], u[j]);
-        float gr = g.x, gi = g.y;
-        if constexpr (OP == MF_OP_MFIE) green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
-        t0r = fmaf(W.w[j], gr, t0r);
-        t0i = fmaf(W.w[j], gi, t0i);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float wq = qr[kRecWRho + 3 * j + c];
-          t1r[c] = fmaf(wq, gr, t1r[c]);
-          t1i[c] = fmaf(wq, gi, t1i[c]);
-        }
-        if constexpr (OP == MF_OP_MFIE) {
-          const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
-                                 fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
-                                      qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
-          t2r = fmaf(wr2, gr, t2r);
-          t2i = fmaf(wr2, gi, t2i);
-        }
+      if constexpr (OP == MF_OP_MFIE) {
+        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
+                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
+                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
+        t2r = fmaf(wr2, gr, t2r);
+        t2i = fmaf(wr2, gi, t2i);
       }
     }
     if constexpr (OP == MF_OP_MFIE) {
