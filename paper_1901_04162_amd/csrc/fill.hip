@@ -403,7 +403,7 @@ __device__ __forceinline__ void fill_tile(
   const int wave = uniform(threadIdx.x >> 6);
   const int tij = tiles[local];
   const int I = tij >> 16, J = tij & 0xffff;
-  for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
+  for (int i = threadIdx.x; i < 2 * kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   __syncthreads();
   const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
   const int q0 = blk_off[J], nq = blk_off[J + 1] - q0;
@@ -491,20 +491,30 @@ __device__ __forceinline__ void fill_tile(
       if (pv) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) psig[a] = pr[kRecSigma + a];
+        // Accumulation without atomics.  Each entry is kept in two halves,
+        // by the sign of the source triangle in the column's RWG function;
+        // a source triangle belongs to one wave, so no other wave writes the
+        // halves it adds to.  Within the wave the two triangles of a row's
+        // RWG function are two lanes: rows of the plus triangle are added in
+        // a first pass and rows of the minus triangle in a second, so no two
+        // lanes of one instruction share an address.
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int row = (prow >> (8 * a)) & 0xff;
-          if (row == 0xff) continue;
+        for (int pass = 0; pass < 2; ++pass)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int col = (qcol >> (8 * b)) & 0xff;
-            if (col == 0xff) continue;
-            const float sg = psig[a] * qr[kRecSigma + b];
-            float *dst = acc + row * kAccStride + 2 * col;
-            atomicAdd(dst, sg * Xr[a][b]);
-            atomicAdd(dst + 1, sg * Xi[a][b]);
+          for (int a = 0; a < 3; ++a) {
+            const int row = (prow >> (8 * a)) & 0xff;
+            if (row == 0xff || (psig[a] < 0.0f) != (pass == 1)) continue;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const int col = (qcol >> (8 * b)) & 0xff;
+              if (col == 0xff) continue;
+              const float qs = qr[kRecSigma + b];
+              const float sg = psig[a] * qs;
+              float *dst = acc + (qs < 0.0f ? kAccFloats : 0) + row * kAccStride + 2 * col;
+              dst[0] += sg * Xr[a][b];
+              dst[1] += sg * Xi[a][b];
+            }
           }
-        }
       }
     }
   }
@@ -514,7 +524,8 @@ __device__ __forceinline__ void fill_tile(
     for (int e = S.sp_off[local] + threadIdx.x; e < S.sp_off[local + 1]; e += kFillThreads) {
       const int4 en = S.sp_ent[e];
       const int r = en.x >> 8, c = en.x & 0xff;
-      const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+      const int o = r * kAccStride + 2 * c;
+      const float ar = acc[o] + acc[kAccFloats + o], ai = acc[o + 1] + acc[kAccFloats + o + 1];
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
@@ -527,7 +538,8 @@ __device__ __forceinline__ void fill_tile(
     const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
       const int r = e / nj, c = e % nj;
-      const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+      const int o = r * kAccStride + 2 * c;
+      const float ar = acc[o] + acc[kAccFloats + o], ai = acc[o + 1] + acc[kAccFloats + o + 1];
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
@@ -536,7 +548,8 @@ __device__ __forceinline__ void fill_tile(
     if (I != J) {
       for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
         const int c = e / ni, r = e % ni;
-        const float ar = acc[r * kAccStride + 2 * c], ai = acc[r * kAccStride + 2 * c + 1];
+        const int o = r * kAccStride + 2 * c;
+        const float ar = acc[o] + acc[kAccFloats + o], ai = acc[o + 1] + acc[kAccFloats + o + 1];
         ZT v;
         v.x = -S.pref * ai;
         v.y = S.pref * ar;
@@ -759,7 +772,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
                                    fill_threads_op<MODE, OP>() / 256))) void k_fill(
     FillItem S, FillRule W) {
   constexpr int kFillThreads = fill_threads_op<MODE, OP>();
-  constexpr int kAccs = OP == MF_OP_MFIE ? 2 : 1;
+  constexpr int kAccs = 2;  // the MFIE's two directions, or the EFIE's two halves
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
   float *acc2 = OP == MF_OP_MFIE ? acc + kAccFloats : nullptr;
@@ -796,7 +809,7 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
     int t = S.tile_begin + (((int)blockIdx.x - S.tile_begin) % G + G) % G;
     if (t >= S.tile_end) continue;
     const TabPtrs tab =
-        load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + kAccFloats / 4 + 1);
+        load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + 2 * kAccFloats / 4 + 1);
     float rlo = INFINITY, rhi = 0.0f;
     for (; t < S.tile_end; t += G)
       fill_tile<Q, MODE, 0, ZT, kFillThreads>(
@@ -990,7 +1003,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->op = (mode & kModeMfie) ? MF_OP_MFIE : MF_OP_EFIE;
   L->z_dtype = z_dtype;
   for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
-  L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 2 : 1) + 16;
+  L->lds = sizeof(float) * kAccFloats * 2 + 16;
   std::vector<FillItem> items(n);
   size_t tmax = 0;
   int tiles = 0;
@@ -1010,7 +1023,9 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
     if (e == hipSuccess)
       e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) rc = hip_fail(e, "device attributes");
-    if (!rc && L->lds + tmax <= (size_t)maxlds) {
+    // the MFIE reads its table through the vector L1: with the table in LDS
+    // its fill measured slower (bank conflicts against its longer moments)
+    if (!rc && L->op != MF_OP_MFIE && L->lds + tmax <= (size_t)maxlds) {
       L->lds_tab = true;
       L->lds += tmax;
     }
