@@ -118,7 +118,7 @@ int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
 // monotone, so this gives the same extreme as comparing distances.
 
 constexpr int kRangeBlock = 256;
-constexpr int kRangeChunk = 256;  // equal to kRangeBlock: one sphere list serves both
+constexpr int kRangeChunk = 256;  // equal to kRangeBlock (the run tests assume it)
 constexpr int kRangeScreen = 32;  // source triangles screened per round
 
 struct RangeTri {
@@ -241,8 +241,8 @@ __global__ void k_range_seed(const double *__restrict__ qp64, const float *__res
 }
 
 // Bounding sphere of every run of kRun triangles (centre, radius covering all
-// their quadrature points), for skipping whole block pairs (runs of
-// kRangeBlock) and, per test triangle, whole rounds of kRangeScreen sources.
+// their quadrature points), for skipping whole block pairs and, per test
+// triangle, whole rounds of sources.
 template <int kRun>
 __global__ __launch_bounds__(kRun) void k_range_spheres(const double *__restrict__ brad,
                                                         const float *__restrict__ rec, int nt,
@@ -284,24 +284,33 @@ __global__ __launch_bounds__(kRun) void k_range_spheres(const double *__restrict
 __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict__ qp64,
                                                        const double *__restrict__ brad,
                                                        const float *__restrict__ rec, int nt,
-                                                       int nq, const double *__restrict__ sph,
-                                                       const double *__restrict__ sph_round,
+                                                       int nq, const double *__restrict__ sph_round,
                                                        unsigned long long *out) {
   const int p0 = blockIdx.x * kRangeBlock, q0 = blockIdx.y * kRangeChunk;
   if (q0 + kRangeChunk <= p0) return;  // unordered pairs: q > p only
   // Skip the block pair when no point pair in it can lower the running
-  // minimum or raise the running maximum (one thread decides for all).
-  __shared__ int skip;
-  if (threadIdx.x == 0) {
-    const double *a = sph + 4 * blockIdx.x, *b = sph + 4 * blockIdx.y;
-    const double dc = sqrt(sq_dist(a, b)), rr = a[3] + b[3];
-    const double dmin = fmax(0.0, dc - rr), dmax = dc + rr;
-    const double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
-    const double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
-    skip = dmin * dmin * (1.0 - 1e-9) > lo && dmax * dmax * (1.0 + 1e-9) < hi;
+  // minimum or raise the running maximum: 64 threads test the 8 x 8 pairs of
+  // its 32-triangle runs' bounding spheres.
+  __shared__ int keep;
+  if (threadIdx.x == 0) keep = 0;
+  __syncthreads();
+  constexpr int kRuns = kRangeBlock / kRangeScreen;
+  if (threadIdx.x < kRuns * kRuns) {
+    const int ra = p0 / kRangeScreen + (int)threadIdx.x / kRuns;
+    const int rb = q0 / kRangeScreen + (int)threadIdx.x % kRuns;
+    const int nr = (nt + kRangeScreen - 1) / kRangeScreen;
+    if (ra < nr && rb < nr && rb >= ra) {
+      const double *a = sph_round + 4 * ra, *b = sph_round + 4 * rb;
+      const double dc = sqrt(sq_dist(a, b)), rr = a[3] + b[3];
+      const double dmin = fmax(0.0, dc - rr), dmax = dc + rr;
+      const double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
+      const double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
+      if (!(dmin * dmin * (1.0 - 1e-9) > lo && dmax * dmax * (1.0 + 1e-9) < hi))
+        atomicOr(&keep, 1);
+    }
   }
   __syncthreads();
-  if (skip) return;
+  if (!keep) return;
   __shared__ RangeTri sq[kRangeChunk];
   // pairs that pass the screen, {test lane << 16 | source index}, evaluated
   // by the whole block so that no wave idles behind a few passing lanes
@@ -380,14 +389,12 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
   const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
   const int nr = (m->nt + kRangeScreen - 1) / kRangeScreen;
   double *sph = nullptr;
-  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * (nb + nr), s));
-  hipLaunchKernelGGL(k_range_spheres<kRangeBlock>, dim3(nb), dim3(kRangeBlock), 0, s,
-                     m->d_brad, m->d_rec, m->nt, sph);
+  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * nr, s));
   hipLaunchKernelGGL(k_range_spheres<kRangeScreen>, dim3(nr), dim3(kRangeScreen), 0, s,
-                     m->d_brad, m->d_rec, m->nt, sph + 4 * nb);
+                     m->d_brad, m->d_rec, m->nt, sph);
   dim3 grid(nb, (m->nt + kRangeChunk - 1) / kRangeChunk);
   hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
-                     m->nt, r.nq, sph, sph + 4 * nb, m->d_scratch);
+                     m->nt, r.nq, sph, m->d_scratch);
   MF_HIP(hipGetLastError());
   MF_HIP(hipFreeAsync(sph, s));
   MF_HIP(hipGetLastError());
