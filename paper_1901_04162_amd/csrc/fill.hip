@@ -95,7 +95,7 @@ struct FillRule {
 };
 
 struct TabPtrs {
-  const int4 *look;     // bucket records {i0, x(i0), s1, s2}
+  const int4 *look;     // one-sample bucket records {i0, x(i0), x(i0 + 1), -}
   const float4 *c01;    // per interval (c0, c1) about its first sample
   const float4 *c23;    // per interval (c2, c3)
 };
@@ -286,7 +286,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     float4 A[Q], B[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const int ii = look_interval(w[j], r[j], u[j]);
+      const int ii = look_interval1(w[j], r[j], u[j]);
       A[j] = tab.c01[ii];
       B[j] = tab.c23[ii];
     }
@@ -972,13 +972,13 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.status = m->d_status;
   if (base == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g;
-    S.look = g.look;
+    S.look = g.look1;
     S.coef = g.coef;
     S.tn = g.n;
-    S.tm = g.mb;
-    S.tinv = g.binv;
-    S.tbias = g.bbias;
-    S.tmax = g.btop;
+    S.tm = g.mb1;
+    S.tinv = g.binv1;
+    S.tbias = g.bbias1;
+    S.tmax = g.btop1;
     S.lo_ok = (float)(tab->rmin * (1.0 - 1e-6));
     S.hi_ok = (float)(tab->rmax * (1.0 + 1e-6));
   }

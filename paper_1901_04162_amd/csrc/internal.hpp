@@ -55,6 +55,11 @@ struct mf_tables {
     int4 *look = nullptr;
     int mb = 0;
     float binv = 0.0f, bbias = 0.0f, btop = 0.0f;
+    // Green table only: the one-sample bucket records the fill kernels read
+    // (look_interval1 in lookup.hpp), width just under the smallest interval
+    int4 *look1 = nullptr;
+    int mb1 = 0;
+    float binv1 = 0.0f, bbias1 = 0.0f, btop1 = 0.0f;
     float4 *coef = nullptr;
     // FP64 lookup of the Exp table: m64 bucket records of 10 doubles, bucket
     // b = (int)(r * inv64) of width just under the smallest sample interval,

@@ -42,6 +42,21 @@ __device__ __forceinline__ int look_interval(const int4 &w, float r, float &u) {
   return w.x + (int)a1 + (int)a2;
 }
 
+// The fill kernels read a second set of records whose buckets are just
+// narrower than the smallest sample interval, the width of the paper's hash:
+// such a bucket holds at most one sample, and its record
+//   { i0, x(i0), x(i0 + 1), unused }
+// gives the interval as i0 + [r >= x(i0 + 1)] (x(i0 + 1) = +inf when i0 is the
+// last interval).  Either x(i0 + 1) lies in the bucket, or beyond it and then
+// no r of the bucket reaches it.  One compare and one select fewer per lookup,
+// for twice the records.
+__device__ __forceinline__ int look_interval1(const int4 &w, float r, float &u) {
+  const float x1 = __int_as_float(w.z);
+  const bool a1 = r >= x1;
+  u = r - (a1 ? x1 : __int_as_float(w.y));
+  return w.x + (int)a1;
+}
+
 // Cubic of interval i in Horner form, (c0, c1) and (c2, c3) complex.
 __device__ __forceinline__ float2 cubic(const float4 &A, const float4 &B, float u) {
   float re = fmaf(B.z, u, B.x), im = fmaf(B.w, u, B.y);

@@ -282,6 +282,32 @@ __global__ void k_pack_look(const double *r, const int *nb, int n, int mb, int4 
   look[b] = make_int4(i0, __float_as_int((float)r[i0]), __float_as_int(s1), __float_as_int(s2));
 }
 
+// One-sample bucket records (look_interval1 in lookup.hpp): the interval
+// containing the bucket's first point, its first sample and the next sample
+// (+inf after the last interval).  Two samples in one bucket set *bad.
+__global__ void k_pack_look1(const double *r, const int *nb, int n, int mb, int4 *look,
+                             int *bad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= mb) return;
+  int lo = 0, hi = n;  // first sample whose bucket is >= b
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (nb[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int i0 = lo - 1, c = lo;
+  if (i0 < 0) {
+    i0 = 0;
+    c = 1;
+  }
+  if (i0 > n - 2) i0 = n - 2;
+  if (c < n - 1 && nb[c] == b && c + 1 < n - 1 && nb[c + 1] == b) atomicOr(bad, 1);
+  const float x1 = i0 + 1 < n - 1 ? (float)r[i0 + 1] : __int_as_float(0x7f800000);
+  look[b] = make_int4(i0, __float_as_int((float)r[i0]), __float_as_int(x1), 0);
+}
+
 // Cubic Lagrange polynomial of interval i (stencil s..s+3) re-expanded in
 // powers of u = r - float(r_i): sum_k c_k u^k, coefficients in FP64, stored
 // as two arrays of n-1 records, (c0, c1) then (c2, c3).
@@ -404,12 +430,13 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.coef, o.look64};
+  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.look1, o.coef, o.look64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   o.r = o.f = nullptr;
   o.hash = nullptr;
   o.look = nullptr;
+  o.look1 = nullptr;
   o.coef = nullptr;
   o.look64 = nullptr;
 }
@@ -501,6 +528,8 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
 // interval, so that FP32 rounding of the bucket coordinate can never put
 // three samples in one bucket.
 constexpr double kBucketWidth = 1.99;
+// the fill's one-sample buckets: just under the smallest interval
+constexpr double kBucketWidth1 = 0.99;
 
 static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   const double bw = kBucketWidth * o.delta;
@@ -526,9 +555,24 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
                      o.bbias, o.btop, nb);
   hipLaunchKernelGGL(k_pack_look, dim3(blocks(o.mb, 256)), dim3(256), 0, s, o.r, nb, o.n, o.mb,
                      o.look, bad);
-  if (kind == kGreen)
+  if (kind == kGreen) {
     hipLaunchKernelGGL(k_pack_green, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
                        o.coef);
+    const double bw1 = kBucketWidth1 * o.delta;
+    o.mb1 = (int)std::floor((T->rmax - T->rmin) / bw1) + 1;
+    o.binv1 = (float)(1.0 / bw1);
+    o.bbias1 = (float)(-T->rmin / bw1);
+    o.btop1 = (float)(o.mb1 - 1);
+    e = hipMalloc((void **)&o.look1, sizeof(int4) * o.mb1);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "one-sample lookup");
+    }
+    hipLaunchKernelGGL(k_node_bucket, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n, o.binv1,
+                       o.bbias1, o.btop1, nb);
+    hipLaunchKernelGGL(k_pack_look1, dim3(blocks(o.mb1, 256)), dim3(256), 0, s, o.r, nb, o.n,
+                       o.mb1, o.look1, bad);
+  }
   else
     hipLaunchKernelGGL(k_pack_exp, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
                        o.coef);
@@ -553,7 +597,7 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   cleanup();
   if (e != hipSuccess) return hip_fail(e, "table packing");
   if (hbad) {
-    set_error("mf_build_tables: a lookup bucket holds more than two samples");
+    set_error("mf_build_tables: a lookup bucket holds more samples than its record");
     return MF_EINVAL;
   }
   return MF_OK;
