@@ -102,6 +102,11 @@ struct TabPtrs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// In LDS the (c2, c3) array starts a fixed kLdsCoefHalf records after the
+// (c0, c1) array, so that one address serves both reads of a lookup (the
+// second through the instruction's offset field).
+constexpr int kLdsCoefHalf = 1570;  // with the two accumulator halves: 163,824 B of LDS
+
 
 // The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
 struct Moments {
@@ -255,7 +260,7 @@ using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>
 // and its first sample), and the cubic of Eq. (5) is evaluated in Horner
 // form about that sample.  The MFIE takes K = (1/R + jk) g/R from the same
 // value and adds the third inner sum T2.
-template <int Q, int OP>
+template <int Q, int OP, bool kLDS>
 __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
                                               const FillScalars &S, const FillRule &W,
                                               const float *pr, const float *nrm, const float *nq,
@@ -288,7 +293,7 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
     for (int j = 0; j < Q; ++j) {
       const int ii = look_interval1(w[j], r[j], u[j]);
       A[j] = tab.c01[ii];
-      B[j] = tab.c23[ii];
+      B[j] = kLDS ? tab.c01[ii + kLdsCoefHalf] : tab.c23[ii];
     }
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -382,15 +387,17 @@ template <bool kLDS, int kThreads>
 __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coef) {
   const int ne = S.tn - 1;
   if (!kLDS) return TabPtrs{S.look, S.coef, S.coef + ne};
-  for (int i = threadIdx.x; i < 2 * ne; i += kThreads) lds_coef[i] = S.coef[i];
-  return TabPtrs{S.look, lds_coef, lds_coef + ne};
+  for (int i = threadIdx.x; i < 2 * ne; i += kThreads)
+    lds_coef[i < ne ? i : kLdsCoefHalf + (i - ne)] = S.coef[i];
+  return TabPtrs{S.look, lds_coef, lds_coef + kLdsCoefHalf};
 }
 
 // One tile of one item: accumulate it in LDS, then write it and its mirror.
 // The item's arrays come in as separate __restrict__ parameters: once the
 // function is inlined they carry no-alias scopes, which lets the
 // wave-uniform source records go through scalar loads into SGPRs.
-template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false>
+template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false,
+          bool kLDS = false>
 __device__ __forceinline__ void fill_tile(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
@@ -436,8 +443,8 @@ __device__ __forceinline__ void fill_tile(
                     lz = (float)(Dz - (double)hz);
         Moments M;
         if (MODE == MF_MODE_TABLE)
-          moments_table<Q, MF_OP_EFIE>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
-                                       qr, rlo, rhi);
+          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx,
+                                             ly, lz, qr, rlo, rhi);
         else
           moments_direct<Q, MF_OP_EFIE>(M, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
                                         qr);
@@ -565,7 +572,7 @@ __device__ __forceinline__ void fill_tile(
 // values, rows J against columns I in acc2, each written once.  The test
 // points are read from the record per test point (the moments of both
 // directions hold the registers the EFIE tile gives to them).
-template <int Q, int MODE, typename ZT, int kFillThreads>
+template <int Q, int MODE, typename ZT, int kFillThreads, bool kLDS = false>
 __device__ __forceinline__ void fill_tile_mfie(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float *acc2, int local,
     float &rlo, float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
@@ -649,7 +656,7 @@ __device__ __forceinline__ void fill_tile_mfie(
         }
         MomentsM M;
         if (MODE == MF_MODE_TABLE)
-          moments_table<Q, MF_OP_MFIE>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          moments_table<Q, MF_OP_MFIE, kLDS>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
         else
           moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
 #pragma unroll
@@ -782,11 +789,11 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
   const int ntiles = S.tile_end - S.tile_begin;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     if constexpr (OP == MF_OP_MFIE)
-      fill_tile_mfie<Q, MODE, ZT, kFillThreads>(
+      fill_tile_mfie<Q, MODE, ZT, kFillThreads, MODE == MF_MODE_TABLE && kLDS>(
           S, W, tab, acc, acc2, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri,
           S.blk_pos, S.touch_off, S.touch_q, S.touch_rev, S.sing, reinterpret_cast<ZT *>(S.Z));
     else
-      fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse>(
+      fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse, MODE == MF_MODE_TABLE && kLDS>(
           S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
           S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
   }
@@ -812,7 +819,7 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
         load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + 2 * kAccFloats / 4 + 1);
     float rlo = INFINITY, rhi = 0.0f;
     for (; t < S.tile_end; t += G)
-      fill_tile<Q, MODE, 0, ZT, kFillThreads>(
+      fill_tile<Q, MODE, 0, ZT, kFillThreads, false, MODE == MF_MODE_TABLE && kLDS>(
           S, W, tab, acc, t - S.tile_begin, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off,
           S.blk_tri, S.blk_pos, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
     if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
@@ -944,7 +951,9 @@ static int dispatch(FillLaunch &L, bool plan_only, hipStream_t s) {
 }
 
 static size_t table_lds_bytes(const mf_tables *tab) {
-  return sizeof(float4) * 2 * (size_t)(tab->g.n - 1);  // the coefficients (load_table)
+  // the coefficients (load_table); longer tables stay in global memory
+  return tab->g.n - 1 <= kLdsCoefHalf ? sizeof(float4) * 2 * (size_t)kLdsCoefHalf
+                                      : ((size_t)1 << 30);
 }
 
 static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
