@@ -7,11 +7,11 @@
 // Z[I,J] and, transposed, to Z[J,I].
 //
 // One workgroup owns a tile at a time (persistent grid) and accumulates it
-// in LDS.  A tile needs every triangle carrying one of its row edges (list
-// I) against every triangle carrying one of its column edges (list J).  Lane
-// l of a wave takes test triangle I[l] (record in VGPRs); the wave walks the
-// source triangles of J, whose records are wave-uniform and so live in
-// SGPRs.  Per triangle pair the Q x Q point pairs are reduced to four
+// in LDS, without atomics (fill_tile).  A tile needs every triangle carrying
+// one of its row edges (list I) against every triangle carrying one of its
+// column edges (list J).  Lane l of a wave takes test triangle I[l] (its
+// record read where used); the wave walks the source triangles of J, whose
+// records are wave-uniform and so come through scalar loads into SGPRs.  Per triangle pair the Q x Q point pairs are reduced to four
 // moments of g = exp(-jkR)/R,
 //   S0 = sum w_i w_j g, Srho = sum w_i w_j g rho_i, Srho' = sum w_i w_j g rho'_j,
 //   Srr = sum w_i w_j g rho_i.rho'_j,
@@ -454,29 +454,46 @@ __device__ __forceinline__ void fill_tile(
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+        // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2,
+        // with the parts that depend on a or b alone formed once
+        float c0r = 0.f, c0i = 0.f;
+        if (!(PART & MF_PART_PHI)) {
+          c0r = 0.25f * srr;
+          c0i = 0.25f * sri;
+        }
+        if (!(PART & MF_PART_A)) {
+          c0r = fmaf(-S.ik2, s0r, c0r);
+          c0i = fmaf(-S.ik2, s0i, c0i);
+        }
+        float Ar[3], Ai[3], Br[3], Bi[3], beta[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Ar[a] = c0r;
+          Ai[a] = c0i;
+          Br[a] = Bi[a] = 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) beta[a][c] = qr[kRecAlpha + 3 * a + c];
+          if (!(PART & MF_PART_PHI)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
+              Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
+              Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
+              Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+            }
+          }
+        }
+        const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
-            float vr = 0.f, vi = 0.f;
+            float vr = Ar[a] + Br[b], vi = Ai[a] + Bi[b];
             if (!(PART & MF_PART_PHI)) {
-              const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
-                                     qr[kRecAlpha + 3 * b + 2]};
-              const float ab = palpha[a][0] * beta[0] + palpha[a][1] * beta[1] +
-                               palpha[a][2] * beta[2];
-              vr = fmaf(ab, s0r, srr);
-              vi = fmaf(ab, s0i, sri);
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                vr = fmaf(palpha[a][c], sqr[c], fmaf(beta[c], spr[c], vr));
-                vi = fmaf(palpha[a][c], sqi[c], fmaf(beta[c], spi[c], vi));
-              }
-              vr *= 0.25f;
-              vi *= 0.25f;
-            }
-            if (!(PART & MF_PART_A)) {
-              vr = fmaf(-S.ik2, s0r, vr);
-              vi = fmaf(-S.ik2, s0i, vi);
+              const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
+                               palpha[a][2] * beta[b][2];
+              vr = fmaf(ab, q0r, vr);
+              vi = fmaf(ab, q0i, vi);
             }
             Xr[a][b] = vr;
             Xi[a][b] = vi;
