@@ -54,6 +54,20 @@ def test_r_range_matches_oracle(mf, orc, name, s, q):
     assert lo == rlo and hi == rhi
 
 
+def test_r_range_unordered_triangles(mf, orc):
+    """The range scan's witnesses (index neighbours, the diameter ends) only
+    speed it up: with the triangles in random order the extremes are still the
+    oracle's, bit for bit."""
+    V, F = meshes.icosphere(3)
+    F = F[np.random.default_rng(5).permutation(F.shape[0])]
+    say("r_range permuted ico3")
+    m = mf.Mesh(F, V.shape[0])
+    for q in (3, 6):
+        lo, hi = mf.r_range(m, V, q)
+        rlo, rhi = orc.r_range(V, F, q)
+        assert lo == rlo and hi == rhi
+
+
 @pytest.mark.parametrize("k,rmin,rmax,tol", [
     (2 * np.pi, 0.31621617599108715, 1.9801182897103815, 1e-8),
     (2 * np.pi, 0.31621617599108715, 1.9801182897103815, 1e-4),
