@@ -105,7 +105,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // In LDS the (c2, c3) array starts a fixed kLdsCoefHalf records after the
 // (c0, c1) array, so that one address serves both reads of a lookup (the
 // second through the instruction's offset field).
-constexpr int kLdsCoefHalf = 1570;  // with the two accumulator halves: 163,824 B of LDS
+constexpr int kLdsCoefHalf = 1899;  // with the two accumulator halves: 163,824 B of LDS
 
 
 // The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
@@ -603,7 +603,7 @@ __device__ __forceinline__ void fill_tile_mfie(
   const int tij = tiles[local];
   const int I = tij >> 16, J = tij & 0xffff;
   const bool rev = I != J;  // also the block (J, I)
-  for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
+  for (int i = threadIdx.x; i < 2 * kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   if (rev)
     for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc2[i] = 0.0f;
   __syncthreads();
@@ -745,25 +745,32 @@ __device__ __forceinline__ void fill_tile_mfie(
         }
       }
       if (pv) {
+        // The forward block as in the EFIE tile: halves by the sign of the
+        // source triangle, rows in two passes by the sign of the test
+        // triangle, plain adds.  The reverse block (rows of the source
+        // triangle's edges) would need halves of its own and keeps atomics.
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int row = (prow >> (8 * a)) & 0xff;
-          if (row == 0xff) continue;
+        for (int pass = 0; pass < 2; ++pass)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int col = (qcol >> (8 * b)) & 0xff;
-            if (col == 0xff) continue;
-            const float sg = psig[a] * qr[kRecSigma + b];
-            float *dst = acc + row * kAccStride + 2 * col;
-            atomicAdd(dst, sg * Xr[a][b]);
-            atomicAdd(dst + 1, sg * Xi[a][b]);
-            if (rev) {
-              float *dst2 = acc2 + col * kAccStride + 2 * row;
-              atomicAdd(dst2, sg * Rr[b][a]);
-              atomicAdd(dst2 + 1, sg * Ri[b][a]);
+          for (int a = 0; a < 3; ++a) {
+            const int row = (prow >> (8 * a)) & 0xff;
+            if (row == 0xff || (psig[a] < 0.0f) != (pass == 1)) continue;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const int col = (qcol >> (8 * b)) & 0xff;
+              if (col == 0xff) continue;
+              const float qs = qr[kRecSigma + b];
+              const float sg = psig[a] * qs;
+              float *dst = acc + (qs < 0.0f ? kAccFloats : 0) + row * kAccStride + 2 * col;
+              dst[0] += sg * Xr[a][b];
+              dst[1] += sg * Xi[a][b];
+              if (rev) {
+                float *dst2 = acc2 + col * kAccStride + 2 * row;
+                atomicAdd(dst2, sg * Rr[b][a]);
+                atomicAdd(dst2 + 1, sg * Ri[b][a]);
+              }
             }
           }
-        }
       }
     }
   }
@@ -774,8 +781,9 @@ __device__ __forceinline__ void fill_tile_mfie(
   for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
     const int r = e / nj, c = e % nj;
     ZT v;
-    v.x = S.pref * acc[r * kAccStride + 2 * c];
-    v.y = S.pref * acc[r * kAccStride + 2 * c + 1];
+    const int o = r * kAccStride + 2 * c;
+    v.x = S.pref * (acc[o] + acc[kAccFloats + o]);
+    v.y = S.pref * (acc[o + 1] + acc[kAccFloats + o + 1]);
     Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
   }
   if (rev) {
@@ -796,10 +804,12 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
                                    fill_threads_op<MODE, OP>() / 256))) void k_fill(
     FillItem S, FillRule W) {
   constexpr int kFillThreads = fill_threads_op<MODE, OP>();
-  constexpr int kAccs = 2;  // the MFIE's two directions, or the EFIE's two halves
+  // the EFIE's two halves; the MFIE's two halves of its forward block and its
+  // reverse block
+  constexpr int kAccs = OP == MF_OP_MFIE ? 3 : 2;
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
-  float *acc2 = OP == MF_OP_MFIE ? acc + kAccFloats : nullptr;
+  float *acc2 = OP == MF_OP_MFIE ? acc + 2 * kAccFloats : nullptr;
   const TabPtrs tab = load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(
       S, smem4 + kAccs * kAccFloats / 4 + 1);
   float rlo = INFINITY, rhi = 0.0f;
@@ -1029,7 +1039,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->op = (mode & kModeMfie) ? MF_OP_MFIE : MF_OP_EFIE;
   L->z_dtype = z_dtype;
   for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
-  L->lds = sizeof(float) * kAccFloats * 2 + 16;
+  L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 3 : 2) + 16;
   std::vector<FillItem> items(n);
   size_t tmax = 0;
   int tiles = 0;

@@ -17,7 +17,7 @@ constexpr int kMaxQ = 7;
 // identity term).  kModeMfie marks an MFIE fill in the internal mode word.
 enum { MF_OP_EFIE = 0, MF_OP_MFIE = 1 };
 constexpr int kModeMfie = 0x100;
-constexpr int kMaxBlockEdges = 84;  // RWG edges per row/column block of a tile
+constexpr int kMaxBlockEdges = 80;  // RWG edges per row/column block of a tile
 constexpr int kMaxBlockTris = 64;   // triangles carrying a block's edges (one per lane)
 
 // Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
