@@ -444,11 +444,7 @@ int mf_build_exp_table(double k, double rmax, double tol, mf_tables **out, hipSt
 
 void mf_tables_destroy(mf_tables *t) {
   if (!t) return;
-  for (mf_tables::One *o : {&t->e, &t->g}) {
-    void *ptrs[] = {o->r, o->f, o->hash, o->look, o->coef, o->look64};
-    for (void *p : ptrs)
-      if (p) (void)hipFree(p);
-  }
+  release_tables(t);
   delete t;
 }
 

@@ -153,6 +153,8 @@ int fill_launch_run(FillLaunch *L, hipStream_t s);
 int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads);
 void fill_launch_destroy(FillLaunch *L);
 int build_tables_device(mf_tables *t, double tol, hipStream_t s, bool green = true);
+// Frees every device array of both tables (safe on partly built ones).
+void release_tables(mf_tables *t);
 // Angular-transformation fill (FP64 inner integrals on every pair).
 int launch_range_angular(mf_mesh *m, const double *V, const Rule &r, double *rmax,
                          hipStream_t s);

@@ -430,7 +430,8 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  void *ptrs[] = {o.r, o.f, o.hash, o.look, o.look1, o.coef, o.look64};
+  // o.f lives in the allocation of o.r
+  void *ptrs[] = {o.r, o.hash, o.look, o.look1, o.coef, o.look64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   o.r = o.f = nullptr;
@@ -496,8 +497,10 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
     return MF_EINVAL;
   }
   o.n = n;
-  CK(hipMalloc((void **)&o.r, sizeof(double) * n));
-  CK(hipMalloc((void **)&o.f, sizeof(double) * 2 * n));
+  // samples and values in one allocation, the values 256-byte aligned
+  const size_t n_pad = ((size_t)n + 31) & ~(size_t)31;
+  CK(hipMalloc((void **)&o.r, sizeof(double) * (n_pad + 2 * (size_t)n)));
+  o.f = o.r + n_pad;
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(kScanThreads), 0, s, cells, P.ncell, o.r, d_count);
   hipLaunchKernelGGL(k_values, dim3(blocks(n, 256)), dim3(256), 0, s, o.r, n, T->k, kind, o.f);
   unsigned long long init[2] = {~0ull, 0ull};
@@ -601,6 +604,11 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
     return MF_EINVAL;
   }
   return MF_OK;
+}
+
+void release_tables(mf_tables *t) {
+  release(t->e);
+  release(t->g);
 }
 
 int build_tables_device(mf_tables *T, double tol, hipStream_t s, bool green) {
