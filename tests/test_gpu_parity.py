@@ -113,6 +113,32 @@ def test_table_fp32_evaluation(mf, orc, k, rmin, rmax, tol):
     assert np.all(np.isnan(v))
 
 
+def test_tables_destroy_frees_device_memory(mf):
+    """Build and destroy tables many times: the device's free memory must not
+    shrink (every lookup array of both tables is released)."""
+    import gc
+
+    import torch
+
+    say("tables build/destroy cycles")
+    # about 73,000 Green samples: each build holds some 10 MB of device arrays
+    k, rmin, rmax, tol = 17.0, 0.01, 1.99979, 1e-10
+    for _ in range(3):
+        T = mf.build_tables(k, rmin, rmax, tol)
+        del T
+    gc.collect()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(30):
+        T = mf.build_tables(k, rmin, rmax, tol)
+        del T
+    gc.collect()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    say("free bytes before", free0, "after", free1)
+    assert free0 - free1 < 16 << 20
+
+
 # ---- full matrices --------------------------------------------------------
 
 @pytest.fixture(scope="module")
