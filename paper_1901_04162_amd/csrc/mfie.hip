@@ -40,9 +40,11 @@ __device__ inline void krem(double k, double R, double &re, double &im) {
   im = (x * cx - sx) / r3;
 }
 
-__global__ void k_singular_mfie(const double *__restrict__ V, const int32_t *__restrict__ tri,
-                                const int32_t *__restrict__ tp, const int32_t *__restrict__ tq,
-                                int64_t npair, RuleArg R, double k, float *__restrict__ out) {
+// 255 VGPRs at two waves per SIMD; the default bound of 128 spills the FP64
+// state of the pair.
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void k_singular_mfie(
+    const double *__restrict__ V, const int32_t *__restrict__ tri, const int32_t *__restrict__ tp,
+    const int32_t *__restrict__ tq, int64_t npair, RuleArg R, double k, float *__restrict__ out) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= npair) return;
   const int p = tp[s], q = tq[s];

@@ -158,17 +158,19 @@ __device__ inline void ghat(double k, double R, double &re, double &im) {
 //   Psi_b = V_q + (r_i - v_b) S_q + A_q sum_j w_j (r_j - v_b) ghat(R_ij).
 // Quadrature points are b0 x0 + b1 x1 + b2 x2 as in the rest of the path.
 // oneway_terms hands every term w_i [...] of the sum to sink(a, b, re, im)
-// and returns A_q; the caller applies the 1/A_q.
+// and returns A_q; the caller applies the 1/A_q.  Only the outer points
+// i_begin <= i < i_end are taken (all of them by default).
 template <class Sink>
 __device__ inline double oneway_terms(const double xp[3][3], const double xq[3][3],
-                                      const RuleArg &R, double k, int part, Sink &&sink) {
+                                      const RuleArg &R, double k, int part, Sink &&sink,
+                                      int i_begin = 0, int i_end = kMaxQ) {
   const double e1[3] = {xq[1][0] - xq[0][0], xq[1][1] - xq[0][1], xq[1][2] - xq[0][2]};
   const double e2[3] = {xq[2][0] - xq[0][0], xq[2][1] - xq[0][1], xq[2][2] - xq[0][2]};
   const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
                cz = e1[0] * e2[1] - e1[1] * e2[0];
   const double Aq = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
   const double ik2 = 1.0 / (k * k);
-  for (int i = 0; i < R.nq; ++i) {
+  for (int i = i_begin; i < R.nq && i < i_end; ++i) {
     double ri[3];
     for (int c = 0; c < 3; ++c)
       ri[c] = R.b[i][0] * xp[0][c] + R.b[i][1] * xp[1][c] + R.b[i][2] * xp[2][c];
@@ -214,20 +216,6 @@ __device__ inline double oneway_terms(const double xp[3][3], const double xq[3][
     }
   }
   return Aq;
-}
-
-// The one-way block X[a][b] of the pair (row-major, 9 complex).
-__device__ inline void oneway_block(const double xp[3][3], const double xq[3][3], const RuleArg &R,
-                                    double k, int part, double *accr, double *acci) {
-  for (int i = 0; i < 9; ++i) accr[i] = acci[i] = 0.0;
-  const double Aq = oneway_terms(xp, xq, R, k, part, [&](int a, int b, double re, double im) {
-    accr[3 * a + b] += re;
-    acci[3 * a + b] += im;
-  });
-  for (int i = 0; i < 9; ++i) {
-    accr[i] /= Aq;
-    acci[i] /= Aq;
-  }
 }
 
 }  // namespace mf
