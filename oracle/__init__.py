@@ -67,6 +67,8 @@ def lib():
         L.or_table_eval.argtypes = [vp, C.c_int, dp, dp]
         L.or_fill_entries.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
                                       dp, dp, C.c_int, C.c_int, vp, C.c_int64, lp, lp, dp]
+        L.or_fill_rows.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
+                                   dp, dp, C.c_int, C.c_int, vp, C.c_int, C.c_int, dp]
         L.or_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
                                     C.c_int, dp, dp, C.c_int, C.c_int, vp, dp]
         L.or_loss.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int, dp,
@@ -74,6 +76,8 @@ def lib():
         L.or_loss_local.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, ip, C.c_double, C.c_int,
                                     dp, dp, dp, C.c_int, dp]
         L.or_max_threads.argtypes = []
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         L.or_grad_potential.argtypes = [dp, dp, dp, dp, dp]
         L.or_grad_potential.restype = None
         L.or_mfie_pair_block.argtypes = [C.c_int, dp, C.c_int, ip, C.c_int, C.c_int, C.c_double,
@@ -92,6 +96,11 @@ def lib():
 def max_threads() -> int:
     """Threads the oracle's OpenMP loops run on."""
     return int(lib().or_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on (timing runs)."""
+    lib().or_set_threads(int(n))
 
 
 class OracleError(RuntimeError):
@@ -239,6 +248,20 @@ def fill_entries(V, F, edges, k, Q, rows, cols, mode=DIRECT, part=PART_ALL, gtab
                                  gtable.handle if gtable is not None else None, rows.size,
                                  _pl(rows), _pl(cols), _pd(out)), "fill entries")
     return out[0::2] + 1j * out[1::2]
+
+
+def fill_rows(V, F, edges, k, Q, r0, r1, mode=DIRECT, part=PART_ALL, gtable=None):
+    """Rows [r0, r1) of Z in triangle-pair order (each pair's kernel values
+    once for its nine local entries): the CPU baseline of the fill."""
+    V, F, edges = _d(V), _i(F), _i(edges)
+    b, w = _rule(Q)
+    ne = edges.shape[0]
+    out = np.zeros(2 * (r1 - r0) * ne)
+    _check(lib().or_fill_rows(V.shape[0], _pd(V), F.shape[0], _pi(F), ne, _pi(edges), float(k),
+                              len(w), _pd(b), _pd(w), mode, part,
+                              gtable.handle if gtable is not None else None, int(r0), int(r1),
+                              _pd(out)), "fill rows")
+    return (out[0::2] + 1j * out[1::2]).reshape(r1 - r0, ne)
 
 
 def fill(V, F, k, Q, mode=DIRECT, part=PART_ALL, gtable=None, edges=None):

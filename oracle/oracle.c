@@ -914,6 +914,178 @@ int or_fill_entries(int nv, const double *V, int nt, const int32_t *tri, int ne,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Row block of Z in triangle-pair order (the CPU baseline of the fill): each */
+/* triangle pair evaluates its kernel values once and forms all nine local   */
+/* entries from them, by the same rules as pair_value; the entries are then  */
+/* scattered with the RWG signs and lengths.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Regular pair, all (a, b): one g(R_ij) per point pair. */
+static int regular_block9(const fillctx *C, int p, int q, cplx X[3][3]) {
+  const mesh *M = C->M;
+  const double k = C->k;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X[a][b] = 0.0;
+  for (int i = 0; i < M->nq; ++i) {
+    const double *ri = qpt(M, p, i);
+    double ua[3][3]; /* r_i - v_a */
+    for (int a = 0; a < 3; ++a) sub3(ri, vtx(M, p, a), ua[a]);
+    for (int j = 0; j < M->nq; ++j) {
+      const double *rj = qpt(M, q, j);
+      double ub[3][3]; /* r_j - v_b */
+      for (int b = 0; b < 3; ++b) sub3(rj, vtx(M, q, b), ub[b]);
+      const double R = dist3(ri, rj);
+      cplx g;
+      if (C->mode == OR_MODE_DIRECT) {
+        g = cexp(-I * k * R) / R;
+      } else {
+        int rc = table_value(C->G, R, &g);
+        if (rc) return rc;
+      }
+      const cplx wg = M->w[i] * M->w[j] * g;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double br = 0.0;
+          if (C->part != OR_PART_PHI) br += 0.25 * dot3(ua[a], ub[b]);
+          if (C->part != OR_PART_A) br -= 1.0 / (k * k);
+          X[a][b] += wg * br;
+        }
+    }
+  }
+  return 0;
+}
+
+/* Touching pair, one way, all (a, b): the closed-form potentials and the
+ * remainder sums once per outer point (pair_touching_oneway's rule). */
+static void touching_block9(const fillctx *C, int p, int q, cplx X[3][3]) {
+  const mesh *M = C->M;
+  const double k = C->k, Aq = M->area[q];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X[a][b] = 0.0;
+  for (int i = 0; i < M->nq; ++i) {
+    const double *ri = qpt(M, p, i);
+    double S, Vv[3];
+    or_tri_potentials(vtx(M, q, 0), vtx(M, q, 1), vtx(M, q, 2), ri, &S, Vv);
+    cplx phi = S, s1[3] = {0.0, 0.0, 0.0}; /* s1 = A_q sum_j w_j r_j ghat */
+    cplx s0 = 0.0;                        /* s0 = A_q sum_j w_j ghat */
+    for (int j = 0; j < M->nq; ++j) {
+      const double *rj = qpt(M, q, j);
+      const cplx gh = ghat(k, dist3(ri, rj));
+      s0 += Aq * M->w[j] * gh;
+      for (int c = 0; c < 3; ++c) s1[c] += Aq * M->w[j] * rj[c] * gh;
+    }
+    phi += s0;
+    for (int b = 0; b < 3; ++b) {
+      const double *vb = vtx(M, q, b);
+      double rb[3];
+      sub3(ri, vb, rb);
+      cplx psi[3];
+      for (int c = 0; c < 3; ++c) psi[c] = Vv[c] + rb[c] * S + (s1[c] - vb[c] * s0);
+      for (int a = 0; a < 3; ++a) {
+        double ua[3];
+        sub3(ri, vtx(M, p, a), ua);
+        cplx br = 0.0;
+        if (C->part != OR_PART_PHI) br += 0.25 * (ua[0] * psi[0] + ua[1] * psi[1] + ua[2] * psi[2]);
+        if (C->part != OR_PART_A) br -= phi / (k * k);
+        X[a][b] += M->w[i] * br;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X[a][b] /= Aq;
+}
+
+static int pair_block9(const fillctx *C, int p, int q, cplx X[3][3]) {
+  if (touching(C->M, p, q)) {
+    cplx A[3][3], B[3][3];
+    touching_block9(C, p, q, A);
+    touching_block9(C, q, p, B);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) X[a][b] = 0.5 * (A[a][b] + B[b][a]);
+    return 0;
+  }
+  return regular_block9(C, p, q, X);
+}
+
+int or_fill_rows(int nv, const double *V, int nt, const int32_t *tri, int ne, const int32_t *edges,
+                 double k, int nq, const double *bary, const double *w, int mode, int part,
+                 const ortable *gtable, int r0, int r1, double *out) {
+  if (!(k > 0.0) || !isfinite(k) || ne <= 0 || r0 < 0 || r1 > ne || r0 >= r1) return -1;
+  if (mode != OR_MODE_DIRECT && mode != OR_MODE_TABLE) return -1;
+  if (mode == OR_MODE_TABLE && (!gtable || gtable->kind != OR_TABLE_GREEN)) return -1;
+  mesh M;
+  int rc = mesh_init(&M, nv, V, nt, tri, nq, bary, w);
+  /* per triangle and local vertex a: the edge opposite a (-1: none) and its sign */
+  int32_t *ted = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)nt);
+  int8_t *tsg = (int8_t *)malloc(3 * (size_t)nt);
+  int32_t *plist = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)(r1 - r0));
+  char *seen = (char *)calloc((size_t)nt, 1);
+  if (!rc && (!ted || !tsg || !plist || !seen)) rc = -4;
+  int np = 0;
+  if (!rc) {
+    for (size_t i = 0; i < 3 * (size_t)nt; ++i) {
+      ted[i] = -1;
+      tsg[i] = 0;
+    }
+    for (int m = 0; m < ne; ++m)
+      for (int s = 0; s < 2; ++s) {
+        const int t = edges[6 * (size_t)m + 2 + s], a = edges[6 * (size_t)m + 4 + s];
+        ted[3 * (size_t)t + a] = m;
+        tsg[3 * (size_t)t + a] = s == 0 ? 1 : -1;
+      }
+    for (int m = r0; m < r1; ++m)
+      for (int s = 0; s < 2; ++s) {
+        const int t = edges[6 * (size_t)m + 2 + s];
+        if (!seen[t]) {
+          seen[t] = 1;
+          plist[np++] = t;
+        }
+      }
+    for (size_t i = 0; i < 2 * (size_t)(r1 - r0) * (size_t)ne; ++i) out[i] = 0.0;
+  }
+  int err = rc;
+  if (!rc) {
+    fillctx C = {&M, k, mode, part, gtable, 0};
+    const cplx pref = I * k * OR_ETA0 / (4.0 * M_PI);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ip = 0; ip < np; ++ip) {
+      const int p = plist[ip];
+      for (int q = 0; q < nt; ++q) {
+        cplx X[3][3];
+        int r2 = pair_block9(&C, p, q, X);
+        if (r2) {
+#pragma omp atomic write
+          err = r2;
+          continue;
+        }
+        for (int a = 0; a < 3; ++a) {
+          const int m = ted[3 * (size_t)p + a];
+          if (m < r0 || m >= r1) continue;
+          const double lm = dist3(V + 3 * (size_t)edges[6 * (size_t)m], V + 3 * (size_t)edges[6 * (size_t)m + 1]);
+          for (int b = 0; b < 3; ++b) {
+            const int n = ted[3 * (size_t)q + b];
+            if (n < 0) continue;
+            const double ln = dist3(V + 3 * (size_t)edges[6 * (size_t)n], V + 3 * (size_t)edges[6 * (size_t)n + 1]);
+            const cplx v = pref * (tsg[3 * (size_t)p + a] * tsg[3 * (size_t)q + b]) * lm * ln * X[a][b];
+            double *o = out + 2 * ((size_t)(m - r0) * ne + n);
+#pragma omp atomic
+            o[0] += creal(v);
+#pragma omp atomic
+            o[1] += cimag(v);
+          }
+        }
+      }
+    }
+  }
+  free(ted);
+  free(tsg);
+  free(plist);
+  free(seen);
+  mesh_free(&M);
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Loss L = Re sum_mn conj(W_mn) Z_mn (direct mode), for finite differences   */
 /* of the adjoint: the full sum, or only the entries whose row or column     */
 /* edge lies on a triangle containing vertex v (the only entries that move   */
@@ -979,6 +1151,16 @@ int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
                   const double *W, int v, double *L) {
   if (v < 0 || v >= nv) return -1;
   return loss_impl(nv, V, nt, tri, ne, edges, k, nq, bary, w, W, v, L);
+}
+
+/* Sets the threads of the OpenMP loops (a timing hook; no effect without
+ * OpenMP). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 /* Threads the OpenMP loops of this library use (1 without OpenMP). */

@@ -93,6 +93,15 @@ int or_fill_entries(int nv, const double *V, int nt, const int32_t *tri,
                     const ortable *gtable, int64_t ns, const int64_t *rows,
                     const int64_t *cols, double *out);
 
+/* Rows [r0, r1) of Z (out: (r1-r0) x ne complex, interleaved) in triangle-
+ * pair order: every pair's kernel values are evaluated once for its nine
+ * local entries (the CPU baseline of the fill; same values as
+ * or_fill_entries up to rounding order). */
+int or_fill_rows(int nv, const double *V, int nt, const int32_t *tri, int ne,
+                 const int32_t *edges, double k, int nq, const double *bary,
+                 const double *w, int mode, int part, const ortable *gtable, int r0,
+                 int r1, double *out);
+
 /* Normalised local 3x3 block of one ordered triangle pair (p,q):
  * X[a][b] = (1/(A_p A_q)) int_p int_q [(r-v_a).(r'-v_b)/4 - 1/k^2] g dS' dS
  * by the quadrature of the fill (symmetrised for touching pairs). */
@@ -111,6 +120,7 @@ int or_loss_local(int nv, const double *V, int nt, const int32_t *tri, int ne,
                   const double *W, int v, double *L);
 
 /* Number of threads the OpenMP loops use. */
+void or_set_threads(int n);
 int or_max_threads(void);
 
 /* MFIE (magnetic-field) operator, FP64 direct exponential.

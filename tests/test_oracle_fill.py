@@ -200,3 +200,24 @@ def test_fill_entries_match_full(orc, ico2):
     rows, cols = meshes.entry_sample(E.shape[0], 500, 1)
     z = orc.fill_entries(V, F, E, k, 3, rows, cols)
     np.testing.assert_array_equal(z, Z[rows, cols])
+
+
+@pytest.mark.parametrize("part", [0, 1, 2])
+def test_fill_rows_triangle_pair_order_matches_entries(orc, ico2, part):
+    """The triangle-pair-order row fill (the CPU baseline) forms each pair's
+    nine entries from one set of kernel values; it must give the per-entry
+    definition up to rounding order, in every part and for any row block."""
+    V, F, E, k, Z = ico2
+    Zp = Z if part == 0 else orc.fill(V, F, k, 3, part=part, edges=E)
+    for r0, r1 in ((0, E.shape[0]), (37, 161)):
+        Zr = orc.fill_rows(V, F, E, k, 3, r0, r1, part=part)
+        assert np.linalg.norm(Zr - Zp[r0:r1]) <= 1e-13 * np.linalg.norm(Zp[r0:r1])
+
+
+def test_fill_rows_table_mode(orc, ico2):
+    V, F, E, k, Z = ico2
+    rmin, rmax = orc.r_range(V, F, 3)
+    G = orc.build_table(orc.GREEN, k, rmin, rmax, 1e-6)
+    Zt = orc.fill(V, F, k, 3, mode=orc.TABLE, gtable=G, edges=E)
+    Zr = orc.fill_rows(V, F, E, k, 3, 100, 300, mode=orc.TABLE, gtable=G)
+    assert np.linalg.norm(Zr - Zt[100:300]) <= 1e-13 * np.linalg.norm(Zt[100:300])
