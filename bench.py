@@ -53,37 +53,98 @@ def _traffic():
         return None
 
 
-def cpu_baseline(V, F, edges, k, Q, seconds):
-    """The oracle, untuned, on a sample of entries of the same matrix: a short
-    calibration run, then a sample sized to take about `seconds`."""
+def _lscpu():
+    """Host CPU description (model, sockets, cores, threads) from lscpu."""
+    import subprocess
+
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+            "CPU max MHz", "L3 cache")
+    out = {}
+    for line in txt.splitlines():
+        if ":" in line:
+            key, val = line.split(":", 1)
+            if key.strip() in keep:
+                out[key.strip()] = val.strip()
+    return out
+
+
+def cpu_baseline(V, F, edges, k, Q, tol, seconds, sample=None):
+    """The oracle, untuned, timed on the host cores, and the parity of the
+    timed GPU fills.
+
+    Rate: rows of the same matrix filled in triangle-pair order (each pair's
+    kernel values evaluated once for its nine local entries), FP64 direct
+    exponential, on all cores; a contiguous row block sized from a short
+    calibration to take about `seconds`/2.  The same block in table mode (the
+    oracle's Lagrange table, tol as the GPU) gives the oracle's own
+    table-versus-direct ratio, and a smaller block on one thread the rate to
+    set beside the paper's single-threaded CPU.
+
+    Parity: `sample` = (flat indices, {mode: GPU values}); the oracle's
+    entries at those indices give the relative Frobenius error of each timed
+    fill and the element-wise relative errors of the real and imaginary
+    parts."""
     import numpy as np
 
     import oracle
 
     E = edges.shape[0]
-    rng = np.random.default_rng(101)
+    threads = oracle.max_threads()
 
-    def run(n):
-        rows = rng.integers(0, E, n, dtype=np.int64)
-        cols = rng.integers(0, E, n, dtype=np.int64)
+    def rate(r0, r1, mode=oracle.DIRECT, G=None):
         t0 = time.perf_counter()
-        oracle.fill_entries(V, F, edges, k, Q, rows, cols)
+        oracle.fill_rows(V, F, edges, k, Q, r0, r1, mode=mode, gtable=G)
         return time.perf_counter() - t0
 
-    n = 100_000
-    dt = run(n)
-    n2 = int(min(200_000_000, max(n, n * seconds / max(dt, 1e-6))))
-    dt = run(n2)
-    return {
-        "value": n2 / dt,
+    dt = rate(0, 32)
+    rows = int(min(E, max(32, 32 * 0.5 * seconds / max(dt, 1e-6))))
+    dt = rate(0, rows)
+    lo, hi = oracle.r_range(V, F, Q)
+    G = oracle.build_table(oracle.GREEN, k, lo, hi, tol)
+    dt_table = rate(0, rows, oracle.TABLE, G)
+    rows1 = max(8, rows // (4 * threads))
+    oracle.set_threads(1)
+    try:
+        dt1 = rate(0, rows1)
+    finally:
+        oracle.set_threads(threads)
+    base = {
+        "value": rows * E / dt,
         "unit": "Z entries/s",
-        "cores": oracle.max_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{n2} entries drawn uniformly with replacement from the same {E}x{E} matrix "
-                  f"(seed 101), FP64 direct exp, one entry at a time (4 triangle pairs x "
-                  f"{Q * Q} point pairs each), {dt:.1f} s",
-        "green_evals_per_s": n2 * 4 * Q * Q / dt,
+        "sample": f"rows 0..{rows - 1} of the same {E}x{E} matrix ({rows * E} entries) in "
+                  f"triangle-pair order, FP64 direct exp, {threads} threads, {dt:.1f} s",
+        # point pairs the block evaluates: its test triangles x all triangles x Q^2
+        "green_evals_per_s": np.unique(edges[:rows, 2:4]).size * F.shape[0] * Q * Q / dt,
+        "table_mode": {"value": rows * E / dt_table, "seconds": dt_table, "tol": tol,
+                       "table_over_direct": dt / dt_table},
+        "one_thread": {"value": rows1 * E / dt1, "rows": rows1, "seconds": dt1},
+        "lscpu": _lscpu(),
     }
+    parity = None
+    if sample is not None:
+        flat, vals = sample
+        t0 = time.perf_counter()
+        ref = oracle.fill_entries(V, F, edges, k, Q, flat // E, flat % E)
+        t_ref = time.perf_counter() - t0
+        parity = {"sample": f"{flat.size} distinct flat indices of the {E}x{E} matrix "
+                            f"(numpy default_rng(2), 1 %), FP64 oracle per entry, {t_ref:.1f} s"}
+        for mode, z in vals.items():
+            z = z.astype(np.complex128)
+            nz_r, nz_i = ref.real != 0.0, ref.imag != 0.0
+            er = np.abs(z.real - ref.real)[nz_r] / np.abs(ref.real[nz_r])
+            ei = np.abs(z.imag - ref.imag)[nz_i] / np.abs(ref.imag[nz_i])
+            parity[mode] = {
+                "rel_frobenius": float(np.linalg.norm(z - ref) / np.linalg.norm(ref)),
+                "re_rel_median": float(np.median(er)), "re_rel_p99": float(np.percentile(er, 99)),
+                "im_rel_median": float(np.median(ei)), "im_rel_p99": float(np.percentile(ei, 99)),
+            }
+    return base, parity
 
 
 def adjoint_timing(mf, steps):
@@ -372,7 +433,7 @@ def main():
     ap.add_argument("--k", type=float, default=17.0)
     ap.add_argument("--q", type=int, default=7)
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -441,7 +502,12 @@ def main():
         mf.sync_status(mesh)
         return wall / steps, np.array(fill_ms)
 
+    # uniform 1 % sample of the matrix for the parity of the timed fills
+    flat = np.sort(np.random.default_rng(2).choice(E * E, size=E * E // 100, replace=False))
+    flat_d = torch.tensor(flat, device="cuda")
+    gathered = {}
     s_table, ph_table = timed(step_table, args.steps, args.warmup)
+    gathered["table"] = Z.view(-1)[flat_d].cpu().numpy()
     log(f"table step {s_table*1e3:.2f} ms; phases (geom, touching, fill) ms "
         f"{ph_table.mean(0).round(3).tolist()}")
     T = tabs["T"]
@@ -479,6 +545,7 @@ def main():
     }
     if not args.no_direct:
         s_direct, ph_direct = timed(step_direct, args.steps, args.warmup)
+        gathered["direct"] = Z.view(-1)[flat_d].cpu().numpy()
         log(f"direct step {s_direct*1e3:.2f} ms; phases {ph_direct.mean(0).round(3).tolist()}")
         out["direct"] = {
             "ms_per_step": s_direct * 1e3,
@@ -502,7 +569,7 @@ def main():
         "flops_per_launch": FLOPS_PER_EVAL * evals_alg,
         "launch_ms": fill_s * 1e3,
     }
-    del Z
+    del Z, flat_d
     torch.cuda.empty_cache()
     if not args.no_mfie:
         log("mfie ...")
@@ -527,7 +594,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(V, F, mesh.edges(), k, Q, args.cpu_seconds)
+        out["cpu_baseline"], out["rel_err"] = cpu_baseline(V, F, mesh.edges(), k, Q, args.tol,
+                                                           args.cpu_seconds, (flat, gathered))
     print(json.dumps(out), flush=True)
 
 

@@ -87,7 +87,7 @@ int mf_mesh_edges(const mf_mesh *mesh, int32_t *edges);
 /* Number of ordered touching triangle pairs (p, q sharing a vertex). */
 int mf_mesh_n_touching(const mf_mesh *mesh, int64_t *n_pairs);
 /* The tile plan of the regular fill: the RWG edges are cut into n_blocks
- * blocks of consecutive edges (at most 88 edges and 64 carrying triangles
+ * blocks of consecutive edges (at most 80 edges and 64 carrying triangles
  * each); every block pair I <= J is one tile, n_tiles = n_blocks (n_blocks
  * + 1)/2, and an off-diagonal tile also writes its transpose (Z = Z^T).
  * max_block_triangles is the largest number of triangles one block needs. */

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kAngThreads) void k_fill_angular(AngArgs A) {
   ZT *Z = reinterpret_cast<ZT *>(A.Z);
   for (int tl = blockIdx.x; tl < A.ntiles; tl += gridDim.x) {
     const int tij = A.tiles[tl];
-    const int I0 = tij >> 16, J0 = tij & 0xffff;
+    const int I0 = (int)((unsigned)tij >> 16), J0 = tij & 0xffff;
     for (int dir = 0; dir < (I0 != J0 ? 2 : 1); ++dir) {
       const int I = dir ? J0 : I0, J = dir ? I0 : J0;
       for (int i = threadIdx.x; i < kAngAccFloats; i += kAngThreads) acc[i] = 0.0f;

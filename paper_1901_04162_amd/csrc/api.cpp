@@ -212,6 +212,7 @@ static void build_blocks(mf_mesh *m) {
   m->blk_off.assign(m->nblk + 1, 0);
   m->blk_tri.clear();
   m->blk_pos.clear();
+  m->blk_rt.assign((size_t)m->nblk * kMaxBlockEdges, 0);
   m->max_blk_tris = 0;
   std::vector<int32_t> tl;
   for (int b = 0; b < m->nblk; ++b) {
@@ -233,13 +234,24 @@ static void build_blocks(mf_mesh *m) {
       m->blk_tri.push_back(t);
       m->blk_pos.push_back((int32_t)pk);
     }
+    for (int e = e0; e < e1; ++e) {
+      const auto pos = [&](int32_t t) {
+        return (int32_t)(std::lower_bound(tl.begin(), tl.end(), t) - tl.begin());
+      };
+      m->blk_rt[(size_t)b * kMaxBlockEdges + (e - e0)] =
+          pos(E[6 * (size_t)e + 2]) | (pos(E[6 * (size_t)e + 3]) << 8);
+    }
     m->blk_off[b + 1] = (int32_t)m->blk_tri.size();
     m->max_blk_tris = std::max(m->max_blk_tris, (int)tl.size());
   }
-  // Z is symmetric (Galerkin reciprocity): only block pairs I <= J are filled
+  // Z is symmetric (Galerkin reciprocity): only block pairs I <= J are filled.
+  // Tiles pack I and J into 16 bits each (unsigned); with at most 65535
+  // blocks there are fewer than 2^31 tiles.  Larger plans are refused by the
+  // caller before any tile is listed.
   m->tiles.clear();
+  if (m->nblk > 65535) return;
   for (int I = 0; I < m->nblk; ++I)
-    for (int J = I; J < m->nblk; ++J) m->tiles.push_back((I << 16) | J);
+    for (int J = I; J < m->nblk; ++J) m->tiles.push_back((int32_t)(((uint32_t)I << 16) | (uint32_t)J));
 }
 
 template <class T>
@@ -258,6 +270,7 @@ static void free_mesh(mf_mesh *m) {
     if (e) (void)hipEventDestroy(e);
   void *ptrs[] = {m->d_tri,       m->d_tedge,   m->d_tsign,   m->d_touch_off, m->d_touch_q,
                   m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos, m->d_tiles, m->d_blk_e0,
+                  m->d_blk_rt,    m->d_elen,
                   m->d_rec,       m->d_sing1,   m->d_sing,    m->d_scratch,   m->d_status,
                   m->d_qp64,      m->d_brad,    m->d_edges};
   for (void *p : ptrs)
@@ -280,8 +293,10 @@ static int ensure_device(mf_mesh *m) {
       (rc = upload(&m->d_touch_q, m->touch_q)) || (rc = upload(&m->d_touch_rev, m->touch_rev)) ||
       (rc = upload(&m->d_touch_p, touch_p)) || (rc = upload(&m->d_blk_off, m->blk_off)) ||
       (rc = upload(&m->d_blk_tri, m->blk_tri)) || (rc = upload(&m->d_blk_pos, m->blk_pos)) ||
-      (rc = upload(&m->d_tiles, m->tiles)) || (rc = upload(&m->d_blk_e0, m->blk_e0)))
+      (rc = upload(&m->d_tiles, m->tiles)) || (rc = upload(&m->d_blk_e0, m->blk_e0)) ||
+      (rc = upload(&m->d_blk_rt, m->blk_rt)))
     return rc;
+  MF_HIP(hipMalloc((void **)&m->d_elen, sizeof(float) * (size_t)m->ne));
   MF_HIP(hipMalloc((void **)&m->d_sing1, sizeof(double) * 18 * std::max<size_t>(npair, 1)));
   MF_HIP(hipMalloc((void **)&m->d_sing, sizeof(float) * 18 * std::max<size_t>(npair, 1)));
   MF_HIP(hipMalloc((void **)&m->d_scratch, sizeof(unsigned long long) * 16));
@@ -765,7 +780,7 @@ int mf_near_create(mf_mesh *m, const double *V, double r_near, mf_near **out) {
       if (I > J) continue;  // taken as the mirror of (f, e)
       const int r = e - m->blk_e0[I], c = f - m->blk_e0[J];
       // on a diagonal tile both orders are computed, so no mirror write
-      per_tile[(I << 16) | J].push_back({(r << 8) | c, (int32_t)s, I == J ? -1 : pos(f, e), 0});
+      per_tile[(int32_t)(((uint32_t)I << 16) | (uint32_t)J)].push_back({(r << 8) | c, (int32_t)s, I == J ? -1 : pos(f, e), 0});
     }
   nf->toff.push_back(0);
   for (auto &kv : per_tile) {

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
 
   for (int tile = blockIdx.x; tile < S.ntiles; tile += gridDim.x) {
     const int tij = tiles[tile];
-    const int I = tij >> 16, J = tij & 0xffff;
+    const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
     const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
     const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
     __syncthreads();

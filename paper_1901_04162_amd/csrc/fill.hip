@@ -27,6 +27,19 @@
 // each test point's offset hi + (lo + rho_i) is rounded once in FP32, then
 // the source offsets are subtracted: R carries a few FP32 roundings at its
 // own size and no cancellation error of the centroids.
+//
+// Direct mode keeps FP64 accuracy where the RWG sum cancels.  For distant
+// edges the four triangle-pair terms of an entry are tens of times larger
+// than their sum (the div-div terms of the two charge dipoles cancel), so
+// FP32 rounding of the terms, and the FP32 phase error k dR ~ 1e-6 of each
+// point pair at kR ~ 30, would reach the entry at the 1e-6 level.  The
+// direct tile therefore splits every phase about the FP64 centroid distance
+// d (exp(-jkR) = exp(-jkd) exp(-jku), u = R - d formed without
+// cancellation), accumulates the moments as deviations from the reference
+// exp(-jkd)/d of the pair, and keeps that reference (rounded to FP32) per
+// triangle pair in LDS; the write-out adds the second difference of the
+// references over the four triangle pairs of each entry in FP64, where the
+// cancellation is exact.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -69,6 +82,7 @@ constexpr int fill_threads_op() {
 struct FillItem {
   int tile_begin, tile_end;
   int ne;
+  double kd;  // wavenumber (FP64: the per-pair reference phase of direct mode)
   float k, ik2;
   float pref;  // k eta0 / (4 pi)
   int tn, tm;
@@ -77,6 +91,8 @@ struct FillItem {
   long long ldz;
   const float *rec;
   const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q, *touch_rev;
+  const int32_t *blk_rt;  // per block row: positions of its T+ and T- in the block's list
+  const float *elen;      // edge lengths
   const float *sing;
   const int4 *look;
   const float4 *coef;
@@ -106,6 +122,11 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // (c0, c1) array, so that one address serves both reads of a lookup (the
 // second through the instruction's offset field).
 constexpr int kLdsCoefHalf = 1899;  // with the two accumulator halves: 163,824 B of LDS
+
+// Direct mode: the per-triangle-pair references exp(-jkd)/d of a tile,
+// indexed [source position][test position] with an odd stride of float2.
+constexpr int kRefStride = kMaxBlockTris + 1;
+constexpr int kRefFloat2 = kMaxBlockTris * kRefStride;
 
 
 // The four moments of one triangle pair (S0, Srho, Srho', Srr), complex.
@@ -377,6 +398,76 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
   }
 }
 
+// Direct mode, EFIE, with the phase split about the centroid distance d of
+// the pair (FP64, passed as dn = d, d2 = d^2, rd = 1/d rounded to FP32).
+// With delta = rho_i - rho'_j, R^2 = d^2 + num, num = 2 D.delta + |delta|^2,
+// and u = R - d = num/(R + d) has no cancellation.  The moments accumulate
+// g'' = exp(-jku)/R - 1/d = (cos ku - 1)/R - u/(R d) - j sin(ku)/R; the
+// caller rotates them by exp(-jkd) and adds exp(-jkd)/d to S0.  With
+// one = 1 and rd = 0 (a pair whose centroids coincide) g'' is exp(-jku)/R
+// and u = R: no reference.
+template <int Q>
+__device__ __forceinline__ void moments_direct_split(Moments &M, const FillScalars &S,
+                                                     const FillRule &W, const float *pr, float hx,
+                                                     float hy, float hz, float dn, float d2,
+                                                     float rd, float one, cfloat *qr) {
+  zero(M);
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    float pri[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
+    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float ex = pri[0] - qr[kRecRho + 3 * j + 0];
+      const float ey = pri[1] - qr[kRecRho + 3 * j + 1];
+      const float ez = pri[2] - qr[kRecRho + 3 * j + 2];
+      const float ee = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+      const float de = fmaf(hx, ex, fmaf(hy, ey, hz * ez));
+      const float num = fmaf(2.0f, de, ee);
+      const float r2 = d2 + num;
+      const float ri = __builtin_amdgcn_rsqf(r2);
+      const float u = num * __builtin_amdgcn_rcpf(fmaf(r2, ri, dn));
+      float sn, cs;
+      sincosf(S.k * u, &sn, &cs);
+      const float gr = fmaf((cs - 1.0f) + one, ri, -(u * ri) * rd), gi = -sn * ri;
+      t0r = fmaf(W.w[j], gr, t0r);
+      t0i = fmaf(W.w[j], gi, t0i);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float wq = qr[kRecWRho + 3 * j + c];
+        t1r[c] = fmaf(wq, gr, t1r[c]);
+        t1i[c] = fmaf(wq, gi, t1i[c]);
+      }
+    }
+    add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
+  }
+}
+
+// Complex product (xr + j xi)(er + j ei) in place.
+__device__ __forceinline__ void crot(float &xr, float &xi, float er, float ei) {
+  const float yr = fmaf(xr, er, -xi * ei);
+  xi = fmaf(xr, ei, xi * er);
+  xr = yr;
+}
+
+// Second difference of the per-pair references over the four triangle pairs
+// of entry (row r of block I, column c of block J), in FP64, times
+// -l_m l_n / k^2: the reference part of the entry's div-div term.
+__device__ __forceinline__ void ref_part(const FillItem &S, const float2 *gref, int I, int J,
+                                         int r, int c, int em, int en, float &vr, float &vi) {
+  const int rtI = S.blk_rt[I * kMaxBlockEdges + r], rtJ = S.blk_rt[J * kMaxBlockEdges + c];
+  const int pp = rtI & 0xff, pm = (rtI >> 8) & 0xff, qp = rtJ & 0xff, qm = (rtJ >> 8) & 0xff;
+  const float2 a = gref[qp * kRefStride + pp], b = gref[qm * kRefStride + pp];
+  const float2 c2 = gref[qp * kRefStride + pm], d = gref[qm * kRefStride + pm];
+  const double sr = ((double)a.x - (double)b.x) - ((double)c2.x - (double)d.x);
+  const double si = ((double)a.y - (double)b.y) - ((double)c2.y - (double)d.y);
+  const double f = -((double)S.elen[em] * (double)S.elen[en]) / (S.kd * S.kd);
+  vr = (float)(f * sr);
+  vi = (float)(f * si);
+}
+
 // The item's Green table: the interval coefficients are copied into LDS
 // after the accumulator when they fit, the bucket records stay in global
 // memory (read through the vector L1).  Splitting the two gathers of a lookup
@@ -399,17 +490,19 @@ __device__ __forceinline__ TabPtrs load_table(const FillItem &S, float4 *lds_coe
 template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse = false,
           bool kLDS = false>
 __device__ __forceinline__ void fill_tile(
-    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
-    float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref, int local,
+    float &rlo, float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
     const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
     const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
     const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
     const float *__restrict__ sing, ZT *__restrict__ Z) {
   constexpr int kWaves = kFillThreads / 64;
+  // direct mode: reference of the div-div term per triangle pair (see top)
+  constexpr bool kRef = MODE == MF_MODE_DIRECT && !(PART & MF_PART_A);
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
   const int tij = tiles[local];
-  const int I = tij >> 16, J = tij & 0xffff;
+  const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
   for (int i = threadIdx.x; i < 2 * kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   __syncthreads();
   const int p0 = blk_off[I], np = blk_off[I + 1] - p0;
@@ -442,13 +535,46 @@ __device__ __forceinline__ void fill_tile(
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
         Moments M;
-        if (MODE == MF_MODE_TABLE)
+        // s0r/s0i: S0 for the vector terms; scr/sci: S0 for the div-div term,
+        // less the reference the write-out adds back in FP64 (direct mode)
+        float s0r, s0i, scr, sci;
+        if (MODE == MF_MODE_TABLE) {
           moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx,
                                              ly, lz, qr, rlo, rhi);
-        else
-          moments_direct<Q, MF_OP_EFIE>(M, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly, lz,
-                                        qr);
-        const float s0r = M.s0r, s0i = M.s0i, srr = M.srr, sri = M.sri;
+          s0r = scr = M.s0r;
+          s0i = sci = M.s0i;
+        } else {
+          const double d2 = Dx * Dx + Dy * Dy + Dz * Dz;
+          const double d = sqrt(d2);
+          const bool has_ref = d > 0.0;
+          const double id = has_ref ? 1.0 / d : 0.0;
+          moments_direct_split<Q>(M, S, W, pr, hx, hy, hz, (float)d, (float)d2, (float)id,
+                                  has_ref ? 0.0f : 1.0f, qr);
+          double sn, cs;
+          sincos(S.kd * d, &sn, &cs);
+          const float er = (float)cs, ei = (float)-sn;  // exp(-jkd)
+          crot(M.s0r, M.s0i, er, ei);
+          crot(M.srr, M.sri, er, ei);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            crot(M.spr[c], M.spi[c], er, ei);
+            crot(M.sqr[c], M.sqi[c], er, ei);
+          }
+          // reference exp(-jkd)/d: its FP32 rounding g and the remainder
+          const double gcr = cs * id, gci = -sn * id;
+          const float gr = (float)gcr, gi = (float)gci;
+          scr = M.s0r + (float)(gcr - (double)gr);
+          sci = M.s0i + (float)(gci - (double)gi);
+          if (kRef) {
+            if (pv) gref[qi * kRefStride + pidx] = make_float2(gr, gi);
+            s0r = gr + scr;
+            s0i = gi + sci;
+          } else {
+            s0r = scr = gr + scr;
+            s0i = sci = gi + sci;
+          }
+        }
+        const float srr = M.srr, sri = M.sri;
         const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -462,8 +588,8 @@ __device__ __forceinline__ void fill_tile(
           c0i = 0.25f * sri;
         }
         if (!(PART & MF_PART_A)) {
-          c0r = fmaf(-S.ik2, s0r, c0r);
-          c0i = fmaf(-S.ik2, s0i, c0i);
+          c0r = fmaf(-S.ik2, scr, c0r);
+          c0i = fmaf(-S.ik2, sci, c0i);
         }
         float Ar[3], Ai[3], Br[3], Bi[3], beta[3][3];
 #pragma unroll
@@ -511,6 +637,7 @@ __device__ __forceinline__ void fill_tile(
             Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
             Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
           }
+        if (kRef && pv) gref[qi * kRefStride + pidx] = make_float2(0.0f, 0.0f);
       }
       if (pv) {
 #pragma unroll
@@ -543,13 +670,21 @@ __device__ __forceinline__ void fill_tile(
     }
   }
   __syncthreads();
+  const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
+  const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
   if (kSparse) {
     // near-field entries only, into the CSR values (Z) at their positions
     for (int e = S.sp_off[local] + threadIdx.x; e < S.sp_off[local + 1]; e += kFillThreads) {
       const int4 en = S.sp_ent[e];
       const int r = en.x >> 8, c = en.x & 0xff;
       const int o = r * kAccStride + 2 * c;
-      const float ar = acc[o] + acc[kAccFloats + o], ai = acc[o + 1] + acc[kAccFloats + o + 1];
+      float ar = acc[o] + acc[kAccFloats + o], ai = acc[o + 1] + acc[kAccFloats + o + 1];
+      if (kRef) {
+        float vr, vi;
+        ref_part(S, gref, I, J, r, c, i0 + r, j0 + c, vr, vi);
+        ar += vr;
+        ai += vi;
+      }
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
@@ -557,9 +692,19 @@ __device__ __forceinline__ void fill_tile(
       if (en.z >= 0) Z[en.z] = v;
     }
   } else {
+    if (kRef) {
+      // the reference part of every entry, into the first half
+      for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
+        const int r = e / nj, c = e % nj;
+        const int o = r * kAccStride + 2 * c;
+        float vr, vi;
+        ref_part(S, gref, I, J, r, c, i0 + r, j0 + c, vr, vi);
+        acc[o] += vr;
+        acc[o + 1] += vi;
+      }
+      __syncthreads();
+    }
     // Z = j k eta/(4 pi) * acc, and its transpose below the diagonal
-    const int i0 = blk_e0[I], ni = blk_e0[I + 1] - i0;
-    const int j0 = blk_e0[J], nj = blk_e0[J + 1] - j0;
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
       const int r = e / nj, c = e % nj;
       const int o = r * kAccStride + 2 * c;
@@ -601,7 +746,7 @@ __device__ __forceinline__ void fill_tile_mfie(
   const int lane = threadIdx.x & 63;
   const int wave = uniform(threadIdx.x >> 6);
   const int tij = tiles[local];
-  const int I = tij >> 16, J = tij & 0xffff;
+  const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
   const bool rev = I != J;  // also the block (J, I)
   for (int i = threadIdx.x; i < 2 * kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   if (rev)
@@ -812,6 +957,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
   float *acc2 = OP == MF_OP_MFIE ? acc + 2 * kAccFloats : nullptr;
   const TabPtrs tab = load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(
       S, smem4 + kAccs * kAccFloats / 4 + 1);
+  float2 *gref = reinterpret_cast<float2 *>(acc + 2 * kAccFloats + 4);  // direct mode
   float rlo = INFINITY, rhi = 0.0f;
   const int ntiles = S.tile_end - S.tile_begin;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -821,7 +967,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
           S.blk_pos, S.touch_off, S.touch_q, S.touch_rev, S.sing, reinterpret_cast<ZT *>(S.Z));
     else
       fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse, MODE == MF_MODE_TABLE && kLDS>(
-          S, W, tab, acc, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
+          S, W, tab, acc, gref, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
           S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
   }
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
@@ -836,6 +982,7 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
     const FillItem *__restrict__ items, int n_items, FillRule W) {
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
+  float2 *gref = reinterpret_cast<float2 *>(acc + 2 * kAccFloats + 4);  // direct mode
   const int G = gridDim.x;
   for (int it = 0; it < n_items; ++it) {
     const FillItem &S = items[it];
@@ -847,7 +994,7 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
     float rlo = INFINITY, rhi = 0.0f;
     for (; t < S.tile_end; t += G)
       fill_tile<Q, MODE, 0, ZT, kFillThreads, false, MODE == MF_MODE_TABLE && kLDS>(
-          S, W, tab, acc, t - S.tile_begin, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off,
+          S, W, tab, acc, gref, t - S.tile_begin, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off,
           S.blk_tri, S.blk_pos, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
     if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
   }
@@ -990,6 +1137,7 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.tile_begin = tile_begin;
   S.tile_end = tile_begin + (int)m->tiles.size();
   S.ne = m->ne;
+  S.kd = k;
   S.k = (float)k;
   S.ik2 = (float)(1.0 / (k * k));
   S.pref = (float)(k * kEta0 / (4.0 * M_PI));
@@ -1000,6 +1148,8 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.blk_off = m->d_blk_off;
   S.blk_tri = m->d_blk_tri;
   S.blk_pos = m->d_blk_pos;
+  S.blk_rt = m->d_blk_rt;
+  S.elen = m->d_elen;
   S.touch_off = m->d_touch_off;
   S.touch_q = m->d_touch_q;
   S.touch_rev = m->d_touch_rev;
@@ -1040,6 +1190,9 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->z_dtype = z_dtype;
   for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
   L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 3 : 2) + 16;
+  // direct EFIE: the per-pair references of the div-div term
+  if (L->op == MF_OP_EFIE && L->base == MF_MODE_DIRECT && !(L->part & MF_PART_A))
+    L->lds += sizeof(float2) * kRefFloat2;
   std::vector<FillItem> items(n);
   size_t tmax = 0;
   int tiles = 0;
@@ -1100,7 +1253,10 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
   if (ms3)
     for (int i = 0; i < 3; ++i) ms3[i] = 0.0f;
   if (L->n < 2 || L->op != MF_OP_EFIE || L->sparse) {  // single fills keep the defaults
-    if (threads) *threads = L->threads ? L->threads : (L->base == MF_MODE_TABLE ? 768 : 1024);
+    if (threads)
+      *threads = L->threads ? L->threads
+                            : (L->op == MF_OP_MFIE ? fill_threads_op<MF_MODE_TABLE, MF_OP_MFIE>()
+                                                   : fill_threads<MF_MODE_TABLE>());
     return MF_OK;
   }
   const auto key = std::make_tuple(L->nq, L->base, (int)L->lds_tab, L->z_dtype);

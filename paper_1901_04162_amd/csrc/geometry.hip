@@ -39,7 +39,8 @@ __device__ inline double exact_dist(const double *a, const double *b) {
 __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restrict__ tri,
                            const int32_t *__restrict__ tedge, const int8_t *__restrict__ tsign,
                            int nt, RuleArg R, float *__restrict__ rec, double *__restrict__ qp64,
-                           double *__restrict__ brad, int *__restrict__ status) {
+                           double *__restrict__ brad, float *__restrict__ elen,
+                           int *__restrict__ status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
   double x[3][3];
@@ -82,6 +83,7 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
     const double l = sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
                           (u[2] - v[2]) * (u[2] - v[2]));
     o[kRecSigma + a] = tedge[3 * t + a] >= 0 ? (float)(tsign[3 * t + a] * l) : 0.0f;
+    if (elen && tedge[3 * t + a] >= 0 && tsign[3 * t + a] > 0) elen[tedge[3 * t + a]] = (float)l;
   }
   double *cd = reinterpret_cast<double *>(o + kRecCent);
   cd[0] = c[0];
@@ -97,7 +99,8 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {
   RuleArg R = rule_arg(r);
   hipLaunchKernelGGL(k_geometry, dim3((m->nt + 127) / 128), dim3(128), 0, s, V, m->d_tri,
-                     m->d_tedge, m->d_tsign, m->nt, R, m->d_rec, m->d_qp64, m->d_brad, m->d_status);
+                     m->d_tedge, m->d_tsign, m->nt, R, m->d_rec, m->d_qp64, m->d_brad, m->d_elen,
+                     m->d_status);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

@@ -85,6 +85,9 @@ struct mf_mesh {
   std::vector<int32_t> blk_off;    // nblk+1: triangles needed by each edge block
   std::vector<int32_t> blk_tri;
   std::vector<int32_t> blk_pos;    // packed local-edge positions inside the block
+  // nblk*kMaxBlockEdges: for row r of block b, the positions in the block's
+  // triangle list of the row edge's T+ (bits 0-7) and T- (bits 8-15)
+  std::vector<int32_t> blk_rt;
   std::vector<int32_t> tiles;      // (I << 16) | J for every block pair I <= J
   int nblk = 0, max_blk_tris = 0;
 
@@ -95,7 +98,8 @@ struct mf_mesh {
   int32_t *d_touch_off = nullptr, *d_touch_q = nullptr, *d_touch_rev = nullptr;
   int32_t *d_touch_p = nullptr;    // p of each touching pair
   int32_t *d_blk_off = nullptr, *d_blk_tri = nullptr, *d_blk_pos = nullptr;
-  int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr;
+  int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr, *d_blk_rt = nullptr;
+  float *d_elen = nullptr;         // ne edge lengths (FP32, from the FP64 vertices)
   float *d_rec = nullptr;          // nt * kRecFloats
   double *d_qp64 = nullptr;        // nt * kMaxQ * 3 quadrature points (FP64)
   double *d_brad = nullptr;        // nt*4: radius of the quadrature points about the centroid, unit normal

@@ -269,19 +269,33 @@ def _near_sample(E, count, seed):
     return rows.astype(np.int64), np.array(cols, dtype=np.int64)
 
 
-def _sampled_check(mf, orc, V, F, k, Q, tol, n_far, seed, modes=("direct", "table"),
+def _touching_entries(E, F, rows, cols):
+    """Mask of the sampled entries with at least one touching triangle pair."""
+    vs = [set(int(v) for v in f) for f in F]
+    out = np.zeros(len(rows), dtype=bool)
+    for i, (r, c) in enumerate(zip(rows, cols)):
+        out[i] = any(vs[int(p)] & vs[int(q)] for p in E[r, 2:4] for q in E[c, 2:4])
+    return out
+
+
+def _sampled_check(mf, orc, V, F, k, Q, tol, n_uniform, seed, modes=("direct", "table"),
                    bound_direct=1e-6, bound_table=1e-5):
+    """Relative Frobenius error of a uniform entry sample (the estimate of the
+    full-matrix error, asserted), and separately of 200 edge-adjacent entries
+    (touching pairs, asserted to the same bar)."""
     import torch
 
     m = mf.Mesh(F, V.shape[0])
     E = m.edges()
-    rows, cols = meshes.entry_sample(E.shape[0], n_far, seed)
+    rows, cols = meshes.entry_sample(E.shape[0], n_uniform, seed)
     nr, nc = _near_sample(E, 200, seed + 1)
-    rows, cols = np.concatenate([rows, nr]), np.concatenate([cols, nc])
+    touch = _touching_entries(E, F, rows, cols)
     ref = orc.fill_entries(V, F, E, k, Q, rows, cols)
+    ref_n = orc.fill_entries(V, F, E, k, Q, nr, nc)
     lo, hi = mf.r_range(m, V, Q)
     Z = torch.empty((E.shape[0], E.shape[0]), dtype=torch.complex64, device="cuda")
     ri, ci = torch.tensor(rows, device="cuda"), torch.tensor(cols, device="cuda")
+    nri, nci = torch.tensor(nr, device="cuda"), torch.tensor(nc, device="cuda")
     out = {}
     for mode in modes:
         T = mf.build_tables(k, lo, hi, tol) if mode == "table" else None
@@ -289,11 +303,14 @@ def _sampled_check(mf, orc, V, F, k, Q, tol, n_far, seed, modes=("direct", "tabl
         mf.fill_Z(m, V, k, Q, mode, T, out=Z)
         mf.sync_status(m)
         z = Z[ri, ci].cpu().numpy().astype(np.complex128)
-        e_all, e_near = _rel(z, ref), _rel(z[-200:], ref[-200:])
-        e_far = _rel(z[:-200], ref[:-200])
-        say(mode, "sample rel err all", e_all, "far", e_far, "near", e_near)
+        zn = Z[nri, nci].cpu().numpy().astype(np.complex128)
+        e_all, e_near = _rel(z, ref), _rel(zn, ref_n)
+        e_far = _rel(z[~touch], ref[~touch])
+        say(mode, "uniform sample rel err", e_all, "(non-touching entries", e_far,
+            "); adjacent entries", e_near)
         out[mode] = e_all
-        assert e_all <= (bound_direct if mode == "direct" else bound_table)
+        bound = bound_direct if mode == "direct" else bound_table
+        assert e_all <= bound and e_near <= bound
     return out
 
 
@@ -304,9 +321,48 @@ def test_sampled_ico4_q6(mf, orc):
 
 
 def test_sampled_ico5_q7_full_size(mf, orc):
-    """The 30,720-unknown workload at its launch configuration."""
+    """The 30,720-unknown workload with a longer table (tol 1e-6: 2,488
+    intervals, coefficients read from global memory)."""
     V, F = meshes.icosphere(5)
-    _sampled_check(mf, orc, V, F, 17.0, 7, 1e-6, 3000, 2)
+    _sampled_check(mf, orc, V, F, 17.0, 7, 1e-6, 20000, 2)
+
+
+def test_benchmark_one_percent_sample(mf, orc):
+    """The benchmark fill as it is timed (30,720 unknowns, k = 17, 7-point
+    rule, complex64; table tol 1e-5, whose 1,441 intervals put the cubic's
+    coefficients in LDS) against the FP64 oracle on a uniform 1 % sample of the
+    matrix: 9,437,184 distinct flat indices drawn by default_rng(2).  The
+    relative Frobenius error of the sample estimates that of the matrix; the
+    bars are 1e-5 for table mode and 1e-6 for direct mode.  The element-wise
+    relative errors of the real and imaginary parts (the measure of the
+    paper's Fig. 3) are reported."""
+    import torch
+
+    V, F = meshes.icosphere(5)
+    k, Q, tol = 17.0, 7, 1e-5
+    m = mf.Mesh(F, V.shape[0])
+    E = m.edges()
+    ne = E.shape[0]
+    flat = np.sort(np.random.default_rng(2).choice(ne * ne, size=ne * ne // 100, replace=False))
+    rows, cols = flat // ne, flat % ne
+    say("oracle on", flat.size, "entries")
+    ref = orc.fill_entries(V, F, E, k, Q, rows, cols)
+    lo, hi = mf.r_range(m, V, Q)
+    T = mf.build_tables(k, lo, hi, tol)
+    assert T.n_green - 1 <= 1899  # the coefficients-in-LDS instantiation
+    Z = torch.empty((ne, ne), dtype=torch.complex64, device="cuda")
+    idx = torch.tensor(flat, device="cuda")
+    for mode, bound in (("table", 1e-5), ("direct", 1e-6)):
+        say("fill", mode)
+        mf.fill_Z(m, V, k, Q, mode, T if mode == "table" else None, out=Z)
+        mf.sync_status(m)
+        z = Z.view(-1)[idx].cpu().numpy().astype(np.complex128)
+        e = _rel(z, ref)
+        er = np.abs(z.real - ref.real) / np.abs(ref.real)
+        ei = np.abs(z.imag - ref.imag) / np.abs(ref.imag)
+        say(mode, "1% sample rel Frobenius err", e, "| element-wise Re median/p99",
+            np.median(er), np.percentile(er, 99), "Im", np.median(ei), np.percentile(ei, 99))
+        assert e <= bound
 
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-6, 1e-8])

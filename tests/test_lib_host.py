@@ -104,7 +104,7 @@ def test_tile_plan_shape(s):
     nb, nt, mt = m.plan()
     assert nt == nb * (nb + 1) // 2
     assert 1 <= mt <= 64
-    assert nb * 88 >= m.n_edges
+    assert nb * 80 >= m.n_edges
 
 
 @pytest.mark.parametrize("s,r", [(2, 0.25), (3, 0.12)])
