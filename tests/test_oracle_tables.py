@@ -144,6 +144,50 @@ def test_zeros_are_samples_and_merge_rule(tabs, key):
         assert np.allclose(np.diff(near), 0.5 * T.t, rtol=1e-9)
 
 
+def _placement_by_definition(k, rmin, rmax, t, mu=0.25, half_window=2.0, ratio=0.5):
+    """The sample positions of Section II-B written out plainly (readings:
+    zeros of Re and Im at r = m pi / (2k) strictly inside the range; windows of
+    half-width 2t about each zero sampled every t/2; uniform samples every t
+    from r_min, dropped inside an open window; candidates visited as zeros,
+    the two ends, refined samples, uniform samples, each kept only if it lies
+    at least mu t from every sample kept before it).  A sorted list and
+    bisection find the nearest kept sample; nothing is binned."""
+    import bisect
+
+    c = np.pi / (2.0 * k)
+    m = np.arange(int(np.floor(rmin / c)) - 1, int(np.ceil(rmax / c)) + 2)
+    zeros = [float(mm) * c for mm in m if rmin < float(mm) * c < rmax]
+    nref = int(round(half_window / ratio))
+    refined = [z + float(s) * (ratio * t) for z in zeros for s in range(-nref, nref + 1)
+               if s != 0 and rmin < z + float(s) * (ratio * t) < rmax]
+    uniform = []
+    i = 0
+    while rmin + float(i) * t < rmax:
+        x = rmin + float(i) * t
+        if not any(abs(x - z) < half_window * t for z in zeros):
+            uniform.append(x)
+        i += 1
+    kept = []
+    for x in zeros + [rmin, rmax] + refined + uniform:
+        j = bisect.bisect_left(kept, x)
+        near = [kept[jj] for jj in (j - 1, j) if 0 <= jj < len(kept)]
+        if all(abs(x - y) >= mu * t for y in near):
+            kept.insert(j, x)
+    return np.array(kept)
+
+
+@pytest.mark.parametrize("kind,k,rmin,rmax,tol", [
+    (1, K2, 0.316, 1.98, 1e-4), (1, K2, 0.316, 1.98, 1e-8), (0, K2, 0.316, 1.98, 1e-6),
+    (1, 17.0, 0.0331, 1.9998, 1e-5), (1, K2, 0.02977, 5.64474, 1e-6), (0, 10.0, 0.0, 2.0, 1e-6)])
+def test_placement_matches_its_definition(orc, kind, k, rmin, rmax, tol):
+    """The oracle's placement (a binned greedy merge) equals the plain
+    definition sample for sample, at the spacing the probe check settled on."""
+    T = orc.build_table(kind, k, rmin, rmax, tol)
+    ref = _placement_by_definition(k, rmin, rmax, T.t)
+    assert T.r.size == ref.size
+    np.testing.assert_array_equal(T.r, ref)
+
+
 def test_tables_reject_bad_arguments(orc):
     for args in [(0.0, 0.1, 1.0, 1e-6), (K2, 0.0, 1.0, 1e-6), (K2, 1.0, 0.5, 1e-6), (K2, 0.1, 1.0, 1.0)]:
         with pytest.raises(orc.OracleError):
