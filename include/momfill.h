@@ -25,9 +25,13 @@
  *
  * Memory and streams
  *  - Arguments named *_dev are device pointers on the current HIP device;
- *    the others are host pointers.  The caller owns vertices, Z, gradients
- *    and the stream.  A mesh or table handle owns the device memory it
- *    allocates when it is created and frees it in its destroy call.
+ *    the others are host pointers.  The caller owns every byte of device
+ *    memory: vertices, Z, gradients, and one workspace per mesh, per table
+ *    set, per batch and per near-field pattern, each sized by its
+ *    *_workspace_bytes query and handed over 256-byte aligned.  The library
+ *    never allocates or frees device memory; a handle is host memory that
+ *    views its workspace, which must outlive the handle's use, and its
+ *    destroy call frees only the handle.
  *  - Every call enqueues its kernels on `stream` and returns without
  *    synchronising, except where it says it copies a result to the host.
  *
@@ -69,9 +73,10 @@ typedef struct mf_tables mf_tables;
 const char *mf_last_error(void);
 
 /* ---- mesh -------------------------------------------------------------
- * Validates the triangle list (host, n_triangles*3 vertex indices), builds
- * the RWG edge table, the touching-pair lists and the tile plan on the host
- * and uploads them.  Only topology is fixed here: vertex coordinates are
+ * Validates the triangle list (host, n_triangles*3 vertex indices) and
+ * builds the RWG edge table, the touching-pair lists and the tile plan on
+ * the host (mf_mesh_set_workspace uploads them).  Only topology is fixed
+ * here: vertex coordinates are
  * passed to every fill call (device, FP64), so one handle serves perturbed
  * geometries.  MF_EMESH for a repeated or out-of-range vertex index, an edge
  * shared by more than two triangles or two triangles running an edge the
@@ -94,6 +99,17 @@ int mf_mesh_n_touching(const mf_mesh *mesh, int64_t *n_pairs);
 int mf_mesh_plan(const mf_mesh *mesh, int32_t *n_blocks, int64_t *n_tiles,
                  int32_t *max_block_triangles);
 
+/* Device workspace of a mesh: the topology, the tile plan, the per-triangle
+ * records and FP64 quadrature points the kernels read, the touching-pair
+ * blocks and small reduction and status words.  mf_mesh_set_workspace binds
+ * workspace_dev (at least mf_mesh_workspace_bytes bytes, 256-byte aligned,
+ * owned by the caller and kept until the mesh is destroyed or rebound) and
+ * uploads the plan on `stream` (synchronises it).  Every call below that
+ * runs on the GPU needs a bound workspace: MF_EINVAL otherwise, and for a
+ * workspace that is too small or misaligned. */
+int mf_mesh_workspace_bytes(const mf_mesh *mesh, size_t *bytes);
+int mf_mesh_set_workspace(mf_mesh *mesh, void *workspace_dev, size_t bytes, hipStream_t stream);
+
 /* ---- distance range (abstract; Section II-C) ---------------------------
  * Exact FP64 minimum and maximum of |r_{p,i} - r_{q,j}| over all vertex-
  * disjoint triangle pairs (p,q) and all pairs of quadrature points of the
@@ -115,11 +131,18 @@ int mf_r_range(mf_mesh *mesh, const double *vertices_dev, int quad_order, double
  * smallest sample interval, and a probe check (8 points per interval and
  * r_max) that halves t^2 and rebuilds, at most 8 times, until the maximum
  * relative error is below tol.  Synchronises `stream` (the probe result
- * decides the loop).  MF_EINVAL: k <= 0 or not finite, r_min <= 0,
- * r_max <= r_min, tol outside [1e-12, 1e-1]; MF_ENOTCONV if the probe check
- * still fails. */
-int mf_build_tables(double k, double r_min, double r_max, double tol, mf_tables **out,
-                    hipStream_t stream);
+ * decides the loop).  The tables and the build's temporaries live in
+ * workspace_dev (caller-owned, 256-byte aligned, at least
+ * mf_tables_workspace_bytes(k, r_min, r_max, tol) bytes: a bound over the
+ * eight possible refinements, a few MB for the benchmark sphere), which must
+ * outlive the handle's use.  MF_EINVAL: k <= 0 or not finite, r_min <= 0,
+ * r_max <= r_min, tol outside [1e-12, 1e-1], a NULL or misaligned workspace;
+ * MF_ENOMEM if the workspace is smaller than the build needs; MF_ENOTCONV if
+ * the probe check still fails. */
+int mf_tables_workspace_bytes(double k, double r_min, double r_max, double tol, size_t *bytes);
+int mf_build_tables(double k, double r_min, double r_max, double tol, void *workspace_dev,
+                    size_t bytes, mf_tables **out, hipStream_t stream);
+/* Frees the handle; the workspace is the caller's. */
 void mf_tables_destroy(mf_tables *tables);
 /* Sizes and parameters: samples of the Exp and Green tables, hash buckets
  * of each, their uniform intervals and the probe errors reached. */
@@ -137,8 +160,16 @@ int mf_tables_get(const mf_tables *tables, int which, double *r, double *values,
 int mf_tables_eval(const mf_tables *tables, int which, int64_t n, const double *r_dev,
                    double *out_dev, hipStream_t stream);
 
-/* ---- fill ---------------------------------------------------------------
- * Z (device) receives all n_edges x n_edges entries.  mode: MF_MODE_TABLE
+/* ---- fill (Section II-A: the MoM matrix fill the tables accelerate) ------
+ * Z (device) receives all n_edges x n_edges entries of the EFIE matrix in
+ * the convention above: every regular point pair takes exp(-jkR)/R (Eq. (1))
+ * from the cubic Lagrange table of Eq. (5), located through the hash of
+ * Eq. (6) (MF_MODE_TABLE), or computed (MF_MODE_DIRECT, the plain method the
+ * paper compares against); touching pairs use singularity cancellation in
+ * FP64 (Section II-C).  Direct mode keeps the cancellation of the four
+ * triangle-pair terms of distant entries exact: each pair's phase is split
+ * about its FP64 centroid distance d and the reference exp(-jkd)/d of the
+ * div-div term is summed over the four pairs in FP64.  mode: MF_MODE_TABLE
  * (Green function from `tables`, which must cover the mesh's distance
  * range) or MF_MODE_DIRECT (exp(-jkR)/R evaluated per point pair; tables
  * may be NULL), optionally OR-ed with MF_PART_A or MF_PART_PHI.  A regular
@@ -196,7 +227,9 @@ int mf_angular_rmax(mf_mesh *mesh, const double *vertices_dev, int quad_order, d
  * Same placement, hash and probe check as mf_build_tables; the Green table
  * is not built (mf_fill_Z, mf_fill_mfie, the batch, the near field and the
  * adjoint reject such tables). */
-int mf_build_exp_table(double k, double r_max, double tol, mf_tables **out, hipStream_t stream);
+int mf_exp_table_workspace_bytes(double k, double r_max, double tol, size_t *bytes);
+int mf_build_exp_table(double k, double r_max, double tol, void *workspace_dev, size_t bytes,
+                       mf_tables **out, hipStream_t stream);
 
 /* ---- batched fill (frequency sweeps, several meshes) --------------------
  * One persistent fill launch over n items, item i being (meshes[i],
@@ -205,14 +238,18 @@ int mf_build_exp_table(double k, double r_max, double tol, mf_tables **out, hipS
  * of uneven size share the GPU without a tail per item.  All items share
  * quad_order, mode and z_dtype; items that share a mesh handle must share
  * its vertex pointer (one geometry pass per mesh).  mf_batch_create checks
- * the items as mf_fill_Z does, allocates the per-item touching-pair blocks
- * and copies the item list to the device (synchronous); the meshes, tables,
- * vertices and outputs must outlive the batch.  MF_EINVAL for n < 1, a
- * NULL array or any item mf_fill_Z would reject. */
+ * the items as mf_fill_Z does, places the per-item touching-pair blocks and
+ * the item list in workspace_dev (caller-owned, 256-byte aligned, at least
+ * mf_batch_workspace_bytes(n, meshes) bytes) and copies the item list there
+ * (synchronous); the meshes, tables, vertices, outputs and workspace must
+ * outlive the batch.  MF_EINVAL for n < 1, a NULL array, a short or
+ * misaligned workspace or any item mf_fill_Z would reject. */
 typedef struct mf_batch mf_batch;
+int mf_batch_workspace_bytes(int32_t n, mf_mesh *const *meshes, size_t *bytes);
 int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *vertices_dev,
                     const double *k, const mf_tables *const *tables, int quad_order, int mode,
-                    void *const *Z_dev, int z_dtype, const int64_t *ldz, mf_batch **out);
+                    void *const *Z_dev, int z_dtype, const int64_t *ldz, void *workspace_dev,
+                    size_t workspace_bytes, mf_batch **out);
 /* Enqueues the batch on `stream`: geometry once per distinct mesh, the
  * touching-pair blocks of every item, then the single fill launch.  It
  * allocates nothing and copies nothing, so a HIP graph can capture it. */
@@ -236,11 +273,16 @@ void mf_batch_destroy(mf_batch *batch);
  * of their edges are at most r_near apart (every unknown is near itself).
  * mf_near_create builds, on the host, the CSR pattern of those pairs from
  * the host vertex array (n_vertices*3 doubles) and the list of edge-block
- * tiles that hold a near pair; the first mf_fill_near uploads the tile
- * lists.  The pattern keeps the mesh handle, which must outlive it.
+ * tiles that hold a near pair; mf_near_set_workspace uploads the tile lists
+ * into workspace_dev (caller-owned, 256-byte aligned, at least
+ * mf_near_workspace_bytes bytes; synchronises `stream`) before the first
+ * mf_fill_near.  The pattern keeps the mesh handle, which must outlive it.
  * MF_EINVAL for r_near <= 0 or more than 2^31 pairs. */
 typedef struct mf_near mf_near;
 int mf_near_create(mf_mesh *mesh, const double *vertices_host, double r_near, mf_near **out);
+int mf_near_workspace_bytes(const mf_near *pattern, size_t *bytes);
+int mf_near_set_workspace(mf_near *pattern, void *workspace_dev, size_t bytes,
+                          hipStream_t stream);
 /* Number of near pairs and of tiles the near fill runs over. */
 int mf_near_info(const mf_near *pattern, int64_t *nnz, int64_t *n_tiles);
 /* Host copy of the pattern: row_ptr (n_edges + 1 int64), col (nnz int32,

@@ -43,6 +43,20 @@ class Mesh:
     def handle(self):
         return self._h
 
+    @property
+    def device_handle(self):
+        """The handle with its device workspace bound: a torch tensor of the
+        size the library asks for, made on first use (the library allocates
+        no device memory itself)."""
+        if getattr(self, "_ws", None) is None:
+            n = C.c_size_t()
+            check(lib().mf_mesh_workspace_bytes(self._h, C.byref(n)))
+            ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+            check(lib().mf_mesh_set_workspace(self._h, C.c_void_p(ws.data_ptr()), n.value,
+                                              _stream()))
+            self._ws = ws
+        return self._h
+
     def edges(self) -> np.ndarray:
         out = np.zeros((self.n_edges, 6), dtype=np.int32)
         check(lib().mf_mesh_edges(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))))
@@ -71,14 +85,24 @@ class Tables:
 
     def __init__(self, k: float, r_min: float, r_max: float, tol: float, exp_only: bool = False):
         h = C.c_void_p()
+        n = C.c_size_t()
         if exp_only:
             if r_min != 0.0:
                 raise ValueError("the Exp table alone starts at r = 0")
-            check(lib().mf_build_exp_table(float(k), float(r_max), float(tol), C.byref(h),
-                                           _stream()))
+            check(lib().mf_exp_table_workspace_bytes(float(k), float(r_max), float(tol),
+                                                     C.byref(n)))
         else:
-            check(lib().mf_build_tables(float(k), float(r_min), float(r_max), float(tol),
-                                        C.byref(h), _stream()))
+            check(lib().mf_tables_workspace_bytes(float(k), float(r_min), float(r_max),
+                                                  float(tol), C.byref(n)))
+        # the tables live in this tensor (the library allocates no device memory)
+        self._ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        wsp = C.c_void_p(self._ws.data_ptr())
+        if exp_only:
+            check(lib().mf_build_exp_table(float(k), float(r_max), float(tol), wsp, n.value,
+                                           C.byref(h), _stream()))
+        else:
+            check(lib().mf_build_tables(float(k), float(r_min), float(r_max), float(tol), wsp,
+                                        n.value, C.byref(h), _stream()))
         self._h = h
         self.k, self.r_min, self.r_max, self.tol = float(k), float(r_min), float(r_max), float(tol)
         ne, ng, me, mg = (C.c_int32() for _ in range(4))
@@ -130,7 +154,7 @@ def r_range(mesh: Mesh, V, quad_order: int):
     """Exact FP64 (r_min, r_max) over regular quadrature-point pairs."""
     Vd = _vertices(V)
     lo, hi = C.c_double(), C.c_double()
-    check(lib().mf_r_range(mesh.handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
+    check(lib().mf_r_range(mesh.device_handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
                            C.byref(lo), C.byref(hi), _stream()))
     return lo.value, hi.value
 
@@ -144,7 +168,7 @@ def angular_rmax(mesh: Mesh, V, quad_order: int) -> float:
     end of the Exp table of the angular-transformation fill."""
     Vd = _vertices(V)
     out = C.c_double()
-    check(lib().mf_angular_rmax(mesh.handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
+    check(lib().mf_angular_rmax(mesh.device_handle, C.c_void_p(Vd.data_ptr()), int(quad_order),
                                 C.byref(out), _stream()))
     return out.value
 
@@ -161,7 +185,7 @@ def fill_angular(mesh: Mesh, V, k: float, quad_order: int, n_edge: int = 8,
     (n_edge points per source edge, FP64 integrals)."""
     Vd = _vertices(V)
     out, zt = _z_out(mesh, dtype, out)
-    check(lib().mf_fill_angular(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
+    check(lib().mf_fill_angular(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k),
                                 int(quad_order), int(n_edge), MODES[mode],
                                 table.handle if table is not None else None,
                                 C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
@@ -184,7 +208,7 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     Vd = _vertices(V)
     out, zt = _z_out(mesh, dtype, out)
     m = MODES[mode] | part
-    check(lib().mf_fill_Z(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order), m,
+    check(lib().mf_fill_Z(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order), m,
                           tables.handle if tables is not None else None,
                           C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
     return out
@@ -196,7 +220,7 @@ def fill_mfie(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table",
     """MFIE matrix <f_m, f_n>/2 - K_mn (n_edges x n_edges) on the current device."""
     Vd = _vertices(V)
     out, zt = _z_out(mesh, dtype, out)
-    check(lib().mf_fill_mfie(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+    check(lib().mf_fill_mfie(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
                              MODES[mode], tables.handle if tables is not None else None,
                              C.c_void_p(out.data_ptr()), zt, out.stride(0), _stream()))
     return out
@@ -209,7 +233,7 @@ def _rhs(fn, mesh: Mesh, V, k, quad_order, khat, E0, dtype):
     e0 = np.ascontiguousarray(np.stack([e0.real, e0.imag], 1).ravel())
     out = torch.empty(mesh.n_edges, dtype=dtype, device="cuda")
     dp = C.POINTER(C.c_double)
-    check(fn(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+    check(fn(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
              kh.ctypes.data_as(dp), e0.ctypes.data_as(dp), C.c_void_p(out.data_ptr()),
              MF_C64 if dtype == torch.complex64 else MF_C128, _stream()))
     return out
@@ -235,7 +259,7 @@ def far_field(mesh: Mesh, V, k: float, quad_order: int, I: torch.Tensor, dirs, e
     n = d.shape[0]
     F = torch.empty((n, 3), dtype=torch.complex128, device="cuda")
     sig = torch.empty(n, dtype=torch.float64, device="cuda")
-    check(lib().mf_far_field(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
+    check(lib().mf_far_field(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k), int(quad_order),
                              C.c_void_p(I.data_ptr()),
                              MF_C64 if I.dtype == torch.complex64 else MF_C128, n,
                              C.c_void_p(d.data_ptr()), float(e0_norm),
@@ -274,7 +298,13 @@ class NearField:
                 not out.is_contiguous():
             raise ValueError("out must be a contiguous complex vector of nnz values")
         zt = MF_C64 if out.dtype == torch.complex64 else MF_C128
-        check(lib().mf_fill_near(self.mesh.handle, self._h, C.c_void_p(Vd.data_ptr()), float(k),
+        if getattr(self, "_ws", None) is None:
+            n = C.c_size_t()
+            check(lib().mf_near_workspace_bytes(self._h, C.byref(n)))
+            self._ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+            check(lib().mf_near_set_workspace(self._h, C.c_void_p(self._ws.data_ptr()), n.value,
+                                              _stream()))
+        check(lib().mf_fill_near(self.mesh.device_handle, self._h, C.c_void_p(Vd.data_ptr()), float(k),
                                  int(quad_order), MODES[mode],
                                  tables.handle if tables is not None else None,
                                  C.c_void_p(out.data_ptr()), zt, _stream()))
@@ -314,7 +344,7 @@ class Batch:
             if zt is not None and t != zt:
                 raise ValueError("all outputs of a batch share one dtype")
             zt = t
-            meshes.append(mesh.handle.value)
+            meshes.append(mesh.device_handle.value)
             vps.append(Vd.data_ptr())
             ks.append(float(k))
             tps.append(tables.handle.value if tables is not None else None)
@@ -323,9 +353,13 @@ class Batch:
             self._keep += [mesh, Vd, tables, Z]
         arr = C.c_void_p * n
         self._h = C.c_void_p()
+        nb = C.c_size_t()
+        check(lib().mf_batch_workspace_bytes(n, arr(*meshes), C.byref(nb)))
+        self._ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
         check(lib().mf_batch_create(n, arr(*meshes), arr(*vps), (C.c_double * n)(*ks),
                                     arr(*tps) if mode == "table" else None, int(quad_order),
                                     MODES[mode], arr(*zps), zt, (C.c_int64 * n)(*lds),
+                                    C.c_void_p(self._ws.data_ptr()), nb.value,
                                     C.byref(self._h)))
         self.n = n
 
@@ -353,12 +387,12 @@ def set_timing(on: bool):
 def timings(mesh: Mesh):
     """(geometry, touching pairs, regular fill) milliseconds of the last timed fill."""
     ms = (C.c_float * 3)()
-    check(lib().mf_mesh_timings(mesh.handle, ms))
+    check(lib().mf_mesh_timings(mesh.device_handle, ms))
     return tuple(float(x) for x in ms)
 
 
 def sync_status(mesh: Mesh):
-    check(lib().mf_sync_status(mesh.handle, _stream()))
+    check(lib().mf_sync_status(mesh.device_handle, _stream()))
 
 
 def fill_Z_backward(mesh: Mesh, V, k: float, quad_order: int, mode: str, tables: Tables,
@@ -369,7 +403,7 @@ def fill_Z_backward(mesh: Mesh, V, k: float, quad_order: int, mode: str, tables:
     zt = MF_C64 if W.dtype == torch.complex64 else MF_C128
     dV = torch.empty_like(Vd)
     dk = torch.empty(1, dtype=torch.float64, device="cuda")
-    check(lib().mf_fill_Z_backward(mesh.handle, C.c_void_p(Vd.data_ptr()), float(k),
+    check(lib().mf_fill_Z_backward(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k),
                                    int(quad_order), MODES[mode],
                                    tables.handle if tables is not None else None,
                                    C.c_void_p(W.data_ptr()), zt, W.stride(0),

@@ -27,7 +27,9 @@ EXPORTS = [
     "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
     "mf_near_destroy", "mf_rhs_planewave", "mf_far_field", "mf_fill_mfie",
     "mf_rhs_planewave_mfie", "mf_fill_angular", "mf_angular_rmax", "mf_build_exp_table",
-    "mf_batch_info",
+    "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
+    "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
+    "mf_near_workspace_bytes", "mf_near_set_workspace",
 ]
 
 
@@ -57,10 +59,19 @@ def lib():
         L.mf_mesh_n_edges.argtypes = [vp, ip]
         L.mf_mesh_edges.argtypes = [vp, ip]
         L.mf_mesh_n_touching.argtypes = [vp, C.POINTER(C.c_int64)]
+        sp = C.POINTER(C.c_size_t)
+        L.mf_mesh_workspace_bytes.argtypes = [vp, sp]
+        L.mf_mesh_set_workspace.argtypes = [vp, vp, C.c_size_t, vp]
+        L.mf_tables_workspace_bytes.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                                sp]
+        L.mf_exp_table_workspace_bytes.argtypes = [C.c_double, C.c_double, C.c_double, sp]
+        L.mf_batch_workspace_bytes.argtypes = [C.c_int32, C.POINTER(vp), sp]
+        L.mf_near_workspace_bytes.argtypes = [vp, sp]
+        L.mf_near_set_workspace.argtypes = [vp, vp, C.c_size_t, vp]
         L.mf_batch_create.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(C.c_double), C.POINTER(vp), C.c_int, C.c_int,
-                                      C.POINTER(vp), C.c_int, C.POINTER(C.c_int64),
-                                      C.POINTER(vp)]
+                                      C.POINTER(vp), C.c_int, C.POINTER(C.c_int64), vp,
+                                      C.c_size_t, C.POINTER(vp)]
         L.mf_batch_fill.argtypes = [vp, vp]
         L.mf_batch_destroy.argtypes = [vp]
         L.mf_batch_destroy.restype = None
@@ -77,7 +88,8 @@ def lib():
         L.mf_fill_angular.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp,
                                       C.c_int, C.c_int64, vp]
         L.mf_angular_rmax.argtypes = [vp, vp, C.c_int, dp, vp]
-        L.mf_build_exp_table.argtypes = [C.c_double, C.c_double, C.c_double, C.POINTER(vp), vp]
+        L.mf_build_exp_table.argtypes = [C.c_double, C.c_double, C.c_double, vp, C.c_size_t,
+                                         C.POINTER(vp), vp]
         L.mf_fill_mfie.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, C.c_int,
                                    C.c_int64, vp]
         L.mf_far_field.argtypes = [vp, vp, C.c_double, C.c_int, vp, C.c_int, C.c_int32, vp,
@@ -85,8 +97,8 @@ def lib():
         L.mf_mesh_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]
         L.mf_r_range.argtypes = [vp, vp, C.c_int, dp, dp, vp]
-        L.mf_build_tables.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
-                                      C.POINTER(vp), vp]
+        L.mf_build_tables.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, vp,
+                                      C.c_size_t, C.POINTER(vp), vp]
         L.mf_tables_destroy.argtypes = [vp]
         L.mf_tables_destroy.restype = None
         L.mf_tables_info.argtypes = [vp, ip, ip, ip, ip, dp, dp, dp, dp]

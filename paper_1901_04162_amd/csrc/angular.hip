@@ -351,8 +351,7 @@ __global__ __launch_bounds__(kRangeThreads) void k_range_angular(const double *_
 
 int launch_range_angular(mf_mesh *m, const double *V, const Rule &r, double *rmax,
                          hipStream_t s) {
-  unsigned long long *d = nullptr;
-  MF_HIP(hipMallocAsync((void **)&d, sizeof(unsigned long long), s));
+  unsigned long long *d = m->d_scratch + 8;  // one word of the mesh's scratch
   hipError_t e = hipMemsetAsync(d, 0, sizeof(unsigned long long), s);
   const int npts = m->nt * r.nq;
   if (e == hipSuccess) {
@@ -363,7 +362,6 @@ int launch_range_angular(mf_mesh *m, const double *V, const Rule &r, double *rma
   unsigned long long h = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFreeAsync(d, s);
   if (e != hipSuccess) return hip_fail(e, "angular distance range");
   double v;
   static_assert(sizeof(v) == sizeof(h), "bit pattern");

@@ -169,6 +169,9 @@ static void build_touching(mf_mesh *m) {
       auto b = m->touch_q.begin() + m->touch_off[q], e = m->touch_q.begin() + m->touch_off[q + 1];
       m->touch_rev[s] = (int32_t)(std::lower_bound(b, e, p) - m->touch_q.begin());
     }
+  m->touch_p.resize(m->touch_q.size());
+  for (int p = 0; p < nt; ++p)
+    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) m->touch_p[s] = p;
 }
 
 // Row/column blocks of the tiled fill: runs of consecutive edges (so every
@@ -255,10 +258,37 @@ static void build_blocks(mf_mesh *m) {
 }
 
 template <class T>
-static int upload(T **dst, const std::vector<T> &src) {
-  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
-  MF_HIP(hipMalloc((void **)dst, bytes));
-  if (!src.empty()) MF_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+static bool take(Arena &A, T **dst, size_t n) {
+  T *p = nullptr;
+  if (!A.bottom(&p, n)) return false;
+  if (dst) *dst = p;
+  return true;
+}
+
+// Every device array of a mesh, carved from its workspace in a fixed order
+// (d == nullptr: count only).
+static bool carve_mesh(const mf_mesh *m, Arena &A, mf_mesh *d) {
+  const size_t npair = std::max<size_t>(m->touch_q.size(), 1);
+  const size_t nt = (size_t)m->nt;
+#define MF_TAKE(field, n) take(A, d ? &d->field : nullptr, (n))
+  return MF_TAKE(d_tri, m->tri.size()) && MF_TAKE(d_tedge, m->tedge.size()) &&
+         MF_TAKE(d_edges, m->edges.size()) && MF_TAKE(d_tsign, m->tsign.size()) &&
+         MF_TAKE(d_touch_off, m->touch_off.size()) && MF_TAKE(d_touch_q, m->touch_q.size()) &&
+         MF_TAKE(d_touch_rev, m->touch_rev.size()) && MF_TAKE(d_touch_p, m->touch_p.size()) &&
+         MF_TAKE(d_blk_off, m->blk_off.size()) && MF_TAKE(d_blk_tri, m->blk_tri.size()) &&
+         MF_TAKE(d_blk_pos, m->blk_pos.size()) && MF_TAKE(d_tiles, m->tiles.size()) &&
+         MF_TAKE(d_blk_e0, m->blk_e0.size()) && MF_TAKE(d_blk_rt, m->blk_rt.size()) &&
+         MF_TAKE(d_elen, (size_t)m->ne) && MF_TAKE(d_sing1, 18 * npair) &&
+         MF_TAKE(d_sing, 18 * npair) && MF_TAKE(d_scratch, 16) && MF_TAKE(d_status, 4) &&
+         MF_TAKE(d_qp64, 3 * kMaxQ * nt) && MF_TAKE(d_brad, 4 * nt) &&
+         MF_TAKE(d_rec, (size_t)kRecFloats * nt) && MF_TAKE(d_sph, 4 * (size_t)range_runs(m->nt));
+#undef MF_TAKE
+}
+
+template <class T>
+static int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+  if (!src.empty())
+    MF_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return MF_OK;
 }
 
@@ -268,45 +298,14 @@ static void free_mesh(mf_mesh *m) {
   if (!m) return;
   for (hipEvent_t &e : m->ev)
     if (e) (void)hipEventDestroy(e);
-  void *ptrs[] = {m->d_tri,       m->d_tedge,   m->d_tsign,   m->d_touch_off, m->d_touch_q,
-                  m->d_touch_rev, m->d_touch_p, m->d_blk_off, m->d_blk_tri,   m->d_blk_pos, m->d_tiles, m->d_blk_e0,
-                  m->d_blk_rt,    m->d_elen,
-                  m->d_rec,       m->d_sing1,   m->d_sing,    m->d_scratch,   m->d_status,
-                  m->d_qp64,      m->d_brad,    m->d_edges};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  delete m;
+  delete m;  // the device workspace belongs to the caller
 }
 
-// Device copies of the plan, made on the first call that needs the GPU so
-// that topology can be built and inspected without one.
+// Calls that run on the GPU need the caller's workspace bound to the mesh.
 static int ensure_device(mf_mesh *m) {
-  if (m->d_rec) return MF_OK;
-  std::vector<int32_t> touch_p(m->touch_q.size());
-  for (int p = 0; p < m->nt; ++p)
-    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) touch_p[s] = p;
-  const size_t npair = m->touch_q.size();
-  int rc;
-  if ((rc = upload(&m->d_tri, m->tri)) || (rc = upload(&m->d_tedge, m->tedge)) ||
-      (rc = upload(&m->d_edges, m->edges)) ||
-      (rc = upload(&m->d_tsign, m->tsign)) || (rc = upload(&m->d_touch_off, m->touch_off)) ||
-      (rc = upload(&m->d_touch_q, m->touch_q)) || (rc = upload(&m->d_touch_rev, m->touch_rev)) ||
-      (rc = upload(&m->d_touch_p, touch_p)) || (rc = upload(&m->d_blk_off, m->blk_off)) ||
-      (rc = upload(&m->d_blk_tri, m->blk_tri)) || (rc = upload(&m->d_blk_pos, m->blk_pos)) ||
-      (rc = upload(&m->d_tiles, m->tiles)) || (rc = upload(&m->d_blk_e0, m->blk_e0)) ||
-      (rc = upload(&m->d_blk_rt, m->blk_rt)))
-    return rc;
-  MF_HIP(hipMalloc((void **)&m->d_elen, sizeof(float) * (size_t)m->ne));
-  MF_HIP(hipMalloc((void **)&m->d_sing1, sizeof(double) * 18 * std::max<size_t>(npair, 1)));
-  MF_HIP(hipMalloc((void **)&m->d_sing, sizeof(float) * 18 * std::max<size_t>(npair, 1)));
-  MF_HIP(hipMalloc((void **)&m->d_scratch, sizeof(unsigned long long) * 16));
-  MF_HIP(hipMalloc((void **)&m->d_status, sizeof(int) * 4));
-  MF_HIP(hipMalloc((void **)&m->d_qp64, sizeof(double) * 3 * kMaxQ * (size_t)m->nt));
-  MF_HIP(hipMalloc((void **)&m->d_brad, sizeof(double) * 4 * (size_t)m->nt));
-  MF_HIP(hipMemset(m->d_status, 0, sizeof(int) * 4));
-  // d_rec last: its presence marks a complete upload
-  MF_HIP(hipMalloc((void **)&m->d_rec, sizeof(float) * kRecFloats * (size_t)m->nt));
-  return MF_OK;
+  if (m->ws) return MF_OK;
+  set_error("mesh has no device workspace (mf_mesh_workspace_bytes, mf_mesh_set_workspace)");
+  return MF_EINVAL;
 }
 
 }  // namespace mf
@@ -399,6 +398,45 @@ int mf_mesh_plan(const mf_mesh *m, int32_t *n_blocks, int64_t *n_tiles,
   return MF_OK;
 }
 
+int mf_mesh_workspace_bytes(const mf_mesh *m, size_t *bytes) {
+  if (!m || !bytes) return fail(MF_EINVAL, "mf_mesh_workspace_bytes: bad argument");
+  Arena A = Arena::counter();
+  carve_mesh(m, A, nullptr);
+  *bytes = A.lo;
+  return MF_OK;
+}
+
+int mf_mesh_set_workspace(mf_mesh *m, void *ws, size_t bytes, hipStream_t s) {
+  if (!m || !ws) return fail(MF_EINVAL, "mf_mesh_set_workspace: bad argument");
+  if ((uintptr_t)ws & 255) return fail(MF_EINVAL, "mf_mesh_set_workspace: workspace not 256-byte aligned");
+  Arena A(ws, bytes);
+  mf_mesh view;  // carve into a scratch handle first: a short workspace leaves m unchanged
+  if (!carve_mesh(m, A, &view)) return fail(MF_EINVAL, "mf_mesh_set_workspace: workspace too small");
+  carve_mesh(m, A = Arena(ws, bytes), m);
+  m->ws = ws;
+  m->ws_bytes = bytes;
+  int rc;
+  if ((rc = upload(m->d_tri, m->tri, s)) || (rc = upload(m->d_tedge, m->tedge, s)) ||
+      (rc = upload(m->d_edges, m->edges, s)) || (rc = upload(m->d_tsign, m->tsign, s)) ||
+      (rc = upload(m->d_touch_off, m->touch_off, s)) ||
+      (rc = upload(m->d_touch_q, m->touch_q, s)) ||
+      (rc = upload(m->d_touch_rev, m->touch_rev, s)) ||
+      (rc = upload(m->d_touch_p, m->touch_p, s)) || (rc = upload(m->d_blk_off, m->blk_off, s)) ||
+      (rc = upload(m->d_blk_tri, m->blk_tri, s)) || (rc = upload(m->d_blk_pos, m->blk_pos, s)) ||
+      (rc = upload(m->d_tiles, m->tiles, s)) || (rc = upload(m->d_blk_e0, m->blk_e0, s)) ||
+      (rc = upload(m->d_blk_rt, m->blk_rt, s))) {
+    m->ws = nullptr;
+    return rc;
+  }
+  hipError_t e = hipMemsetAsync(m->d_status, 0, sizeof(int) * 4, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    m->ws = nullptr;
+    return hip_fail(e, "mf_mesh_set_workspace");
+  }
+  return MF_OK;
+}
+
 int mf_r_range(mf_mesh *m, const double *V, int quad_order, double *rmin, double *rmax,
                hipStream_t s) {
   Rule r;
@@ -410,22 +448,50 @@ int mf_r_range(mf_mesh *m, const double *V, int quad_order, double *rmin, double
   return launch_r_range(m, V, r, rmin, rmax, s);
 }
 
-int mf_build_tables(double k, double rmin, double rmax, double tol, mf_tables **out,
-                    hipStream_t s) {
-  if (!out) return fail(MF_EINVAL, "mf_build_tables: out is NULL");
+static int check_table_args(const char *who, double k, double rmin, double rmax, double tol,
+                            bool green) {
+  const std::string w = who;
+  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, w + ": k must be > 0");
+  if (green && (!(rmin > 0.0) || !(rmax > rmin) || !std::isfinite(rmax)))
+    return fail(MF_EINVAL, w + ": need 0 < r_min < r_max");
+  if (!green && (!(rmax > 0.0) || !std::isfinite(rmax)))
+    return fail(MF_EINVAL, w + ": need r_max > 0");
+  if (!(tol >= 1e-12 && tol <= 1e-1)) return fail(MF_EINVAL, w + ": tol must lie in [1e-12, 1e-1]");
+  return MF_OK;
+}
+
+int mf_tables_workspace_bytes(double k, double rmin, double rmax, double tol, size_t *bytes) {
+  if (!bytes) return fail(MF_EINVAL, "mf_tables_workspace_bytes: bytes is NULL");
+  int rc = check_table_args("mf_tables_workspace_bytes", k, rmin, rmax, tol, true);
+  if (rc) return rc;
+  *bytes = tables_workspace_bytes(k, rmin, rmax, tol, true);
+  return MF_OK;
+}
+
+int mf_exp_table_workspace_bytes(double k, double rmax, double tol, size_t *bytes) {
+  if (!bytes) return fail(MF_EINVAL, "mf_exp_table_workspace_bytes: bytes is NULL");
+  int rc = check_table_args("mf_exp_table_workspace_bytes", k, 0.0, rmax, tol, false);
+  if (rc) return rc;
+  *bytes = tables_workspace_bytes(k, 0.0, rmax, tol, false);
+  return MF_OK;
+}
+
+static int build_into(const char *who, double k, double rmin, double rmax, double tol, bool green,
+                      void *ws, size_t bytes, mf_tables **out, hipStream_t s) {
+  if (!out) return fail(MF_EINVAL, std::string(who) + ": out is NULL");
   *out = nullptr;
-  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_build_tables: k must be > 0");
-  if (!(rmin > 0.0) || !(rmax > rmin) || !std::isfinite(rmax))
-    return fail(MF_EINVAL, "mf_build_tables: need 0 < r_min < r_max");
-  if (!(tol >= 1e-12 && tol <= 1e-1))
-    return fail(MF_EINVAL, "mf_build_tables: tol must lie in [1e-12, 1e-1]");
+  int rc = check_table_args(who, k, rmin, rmax, tol, green);
+  if (rc) return rc;
+  if (!ws || ((uintptr_t)ws & 255))
+    return fail(MF_EINVAL, std::string(who) + ": workspace NULL or not 256-byte aligned");
   mf_tables *t = new (std::nothrow) mf_tables;
-  if (!t) return fail(MF_ENOMEM, "mf_build_tables: out of host memory");
+  if (!t) return fail(MF_ENOMEM, std::string(who) + ": out of host memory");
   t->k = k;
   t->rmin = rmin;
   t->rmax = rmax;
   t->tol = tol;
-  int rc = build_tables_device(t, tol, s);
+  t->arena = Arena(ws, bytes);
+  rc = build_tables_device(t, tol, s, green);
   if (rc) {
     mf_tables_destroy(t);
     return rc;
@@ -434,27 +500,14 @@ int mf_build_tables(double k, double rmin, double rmax, double tol, mf_tables **
   return MF_OK;
 }
 
-int mf_build_exp_table(double k, double rmax, double tol, mf_tables **out, hipStream_t s) {
-  if (!out) return fail(MF_EINVAL, "mf_build_exp_table: out is NULL");
-  *out = nullptr;
-  if (!(k > 0.0) || !std::isfinite(k)) return fail(MF_EINVAL, "mf_build_exp_table: k must be > 0");
-  if (!(rmax > 0.0) || !std::isfinite(rmax))
-    return fail(MF_EINVAL, "mf_build_exp_table: need r_max > 0");
-  if (!(tol >= 1e-12 && tol <= 1e-1))
-    return fail(MF_EINVAL, "mf_build_exp_table: tol must lie in [1e-12, 1e-1]");
-  mf_tables *t = new (std::nothrow) mf_tables;
-  if (!t) return fail(MF_ENOMEM, "mf_build_exp_table: out of host memory");
-  t->k = k;
-  t->rmin = 0.0;
-  t->rmax = rmax;
-  t->tol = tol;
-  int rc = build_tables_device(t, tol, s, false);
-  if (rc) {
-    mf_tables_destroy(t);
-    return rc;
-  }
-  *out = t;
-  return MF_OK;
+int mf_build_tables(double k, double rmin, double rmax, double tol, void *ws, size_t bytes,
+                    mf_tables **out, hipStream_t s) {
+  return build_into("mf_build_tables", k, rmin, rmax, tol, true, ws, bytes, out, s);
+}
+
+int mf_build_exp_table(double k, double rmax, double tol, void *ws, size_t bytes, mf_tables **out,
+                       hipStream_t s) {
+  return build_into("mf_build_exp_table", k, 0.0, rmax, tol, false, ws, bytes, out, s);
 }
 
 void mf_tables_destroy(mf_tables *t) {
@@ -611,12 +664,38 @@ int mf_fill_angular(mf_mesh *m, const double *V, double k, int quad_order, int n
   return MF_OK;
 }
 
+// The batch's device arrays: per item its touching-pair blocks, then the
+// item list of the launch (d == nullptr: count only).
+static bool carve_batch(int n, mf_mesh *const *meshes, Arena &A, std::vector<float *> *sing,
+                        void **items) {
+  for (int i = 0; i < n; ++i) {
+    float *p = nullptr;
+    if (!A.bottom(&p, 18 * std::max<size_t>(meshes[i]->touch_q.size(), 1))) return false;
+    if (sing) (*sing)[i] = p;
+  }
+  char *it = nullptr;
+  if (!A.bottom(&it, fill_items_bytes(n))) return false;
+  if (items) *items = it;
+  return true;
+}
+
+int mf_batch_workspace_bytes(int32_t n, mf_mesh *const *meshes, size_t *bytes) {
+  if (n < 1 || !meshes || !bytes) return fail(MF_EINVAL, "mf_batch_workspace_bytes: bad argument");
+  for (int i = 0; i < n; ++i)
+    if (!meshes[i]) return fail(MF_EINVAL, "mf_batch_workspace_bytes: NULL mesh");
+  Arena A = Arena::counter();
+  carve_batch(n, meshes, A, nullptr, nullptr);
+  *bytes = A.lo;
+  return MF_OK;
+}
+
 int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, const double *k,
                     const mf_tables *const *tab, int quad_order, int mode, void *const *Z,
-                    int z_dtype, const int64_t *ldz, mf_batch **out) {
+                    int z_dtype, const int64_t *ldz, void *ws, size_t ws_bytes, mf_batch **out) {
   Rule r;
-  if (n < 1 || !meshes || !V || !k || !Z || !ldz || !out)
+  if (n < 1 || !meshes || !V || !k || !Z || !ldz || !out || !ws)
     return fail(MF_EINVAL, "mf_batch_create: bad argument");
+  if ((uintptr_t)ws & 255) return fail(MF_EINVAL, "mf_batch_create: workspace not 256-byte aligned");
   *out = nullptr;
   if (!make_rule(quad_order, &r))
     return fail(MF_EINVAL, "mf_batch_create: quad_order must be 3, 6 or 7");
@@ -650,14 +729,13 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, c
   int rc = MF_OK;
   for (int i = 0; i < n && !rc; ++i) rc = ensure_device(meshes[i]);
   b->sing.assign(n, nullptr);
-  for (int i = 0; i < n && !rc; ++i) {
-    const size_t np = std::max<size_t>(meshes[i]->touch_q.size(), 1);
-    hipError_t e = hipMalloc((void **)&b->sing[i], sizeof(float) * 18 * np);
-    if (e != hipSuccess) rc = hip_fail(e, "mf_batch_create: touching-pair blocks");
-  }
+  void *items = nullptr;
+  Arena A(ws, ws_bytes);
+  if (!rc && !carve_batch(n, meshes, A, &b->sing, &items))
+    rc = fail(MF_EINVAL, "mf_batch_create: workspace too small (mf_batch_workspace_bytes)");
   if (!rc) {
     std::vector<const float *> sing(b->sing.begin(), b->sing.end());
-    rc = fill_launch_create(n, meshes, k, tab, r, mode, Z, z_dtype, ldz, sing.data(),
+    rc = fill_launch_create(n, meshes, k, tab, r, mode, Z, z_dtype, ldz, sing.data(), items,
                             &b->launch);
   }
   // tile-shape tuning on the real inputs: geometry and touching blocks first,
@@ -706,9 +784,7 @@ int mf_batch_fill(mf_batch *b, hipStream_t s) {
 void mf_batch_destroy(mf_batch *b) {
   if (!b) return;
   fill_launch_destroy(b->launch);
-  for (float *p : b->sing)
-    if (p) (void)hipFree(p);
-  delete b;
+  delete b;  // the device workspace belongs to the caller
 }
 
 int mf_near_create(mf_mesh *m, const double *V, double r_near, mf_near **out) {
@@ -806,6 +882,46 @@ int mf_near_pattern(const mf_near *nf, int64_t *row_ptr, int32_t *col) {
   return MF_OK;
 }
 
+static bool carve_near(const mf_near *nf, Arena &A, mf_near *d) {
+  int32_t *a = nullptr, *b = nullptr, *c = nullptr;
+  if (!A.bottom(&a, nf->tiles.size()) || !A.bottom(&b, nf->toff.size()) ||
+      !A.bottom(&c, nf->ent.size()))
+    return false;
+  if (d) {
+    d->d_tiles = a;
+    d->d_toff = b;
+    d->d_ent = c;
+  }
+  return true;
+}
+
+int mf_near_workspace_bytes(const mf_near *nf, size_t *bytes) {
+  if (!nf || !bytes) return fail(MF_EINVAL, "mf_near_workspace_bytes: bad argument");
+  Arena A = Arena::counter();
+  carve_near(nf, A, nullptr);
+  *bytes = A.lo;
+  return MF_OK;
+}
+
+int mf_near_set_workspace(mf_near *nf, void *ws, size_t bytes, hipStream_t s) {
+  if (!nf || !ws) return fail(MF_EINVAL, "mf_near_set_workspace: bad argument");
+  if ((uintptr_t)ws & 255) return fail(MF_EINVAL, "mf_near_set_workspace: workspace not 256-byte aligned");
+  Arena A(ws, bytes);
+  mf_near view;
+  if (!carve_near(nf, A, &view)) return fail(MF_EINVAL, "mf_near_set_workspace: workspace too small");
+  nf->d_tiles = view.d_tiles;
+  nf->d_toff = view.d_toff;
+  nf->d_ent = view.d_ent;
+  int rc;
+  if ((rc = upload(nf->d_tiles, nf->tiles, s)) || (rc = upload(nf->d_toff, nf->toff, s)) ||
+      (rc = upload(nf->d_ent, nf->ent, s))) {
+    nf->d_ent = nullptr;
+    return rc;
+  }
+  MF_HIP(hipStreamSynchronize(s));
+  return MF_OK;
+}
+
 int mf_fill_near(mf_mesh *m, mf_near *nf, const double *V, double k, int quad_order,
                  int mode, const mf_tables *tab, void *values, int z_dtype, hipStream_t s) {
   Rule r;
@@ -820,9 +936,8 @@ int mf_fill_near(mf_mesh *m, mf_near *nf, const double *V, double k, int quad_or
   if (z_dtype != MF_C64 && z_dtype != MF_C128) return fail(MF_EINVAL, "mf_fill_near: unknown z_dtype");
   int rc = ensure_device(m);
   if (rc) return rc;
-  if (!nf->d_ent && ((rc = upload(&nf->d_tiles, nf->tiles)) ||
-                     (rc = upload(&nf->d_toff, nf->toff)) || (rc = upload(&nf->d_ent, nf->ent))))
-    return rc;
+  if (!nf->d_ent)
+    return fail(MF_EINVAL, "mf_fill_near: pattern has no device workspace (mf_near_set_workspace)");
   if ((rc = launch_geometry(m, V, r, s))) return rc;
   if ((rc = launch_singular(m, V, r, k, 0, s))) return rc;
   if (nf->tiles.empty()) return MF_OK;
@@ -830,12 +945,7 @@ int mf_fill_near(mf_mesh *m, mf_near *nf, const double *V, double k, int quad_or
                           reinterpret_cast<const int4 *>(nf->d_ent), values, z_dtype, s);
 }
 
-void mf_near_destroy(mf_near *nf) {
-  if (!nf) return;
-  for (int32_t *p : {nf->d_tiles, nf->d_toff, nf->d_ent})
-    if (p) (void)hipFree(p);
-  delete nf;
-}
+void mf_near_destroy(mf_near *nf) { delete nf; }  // the device workspace belongs to the caller
 
 int mf_rhs_planewave(mf_mesh *m, const double *V, double k, int quad_order, const double *khat,
                      const double *E0, void *out, int z_dtype, hipStream_t s) {

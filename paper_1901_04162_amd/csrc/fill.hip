@@ -1005,7 +1005,7 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
 struct FillLaunch {
   FillItem first;
   FillRule rule;
-  FillItem *d_items = nullptr;  // owned; null for a single item
+  FillItem *d_items = nullptr;  // in the batch's workspace; null for a single item
   int total_tiles = 0, n = 0;
   size_t lds = 0;
   int nq = 0, base = 0, part = 0, z_dtype = 0, op = MF_OP_EFIE;
@@ -1174,9 +1174,11 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
 // Builds the launch of n items (all with the same rule, mode and Z type).
 // With more than one item the item list is copied to the device here
 // (synchronously); running the launch afterwards only enqueues the kernel.
+size_t fill_items_bytes(int n) { return sizeof(FillItem) * (size_t)n; }
+
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
                        const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
-                       const float *const *sing, FillLaunch **out) {
+                       const float *const *sing, void *items_dev, FillLaunch **out) {
   FillLaunch *L = new (std::nothrow) FillLaunch;
   if (!L) {
     set_error("out of host memory");
@@ -1224,10 +1226,15 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
     rc = MF_EINVAL;
   }
   if (!rc && n > 1) {
-    hipError_t e = hipMalloc((void **)&L->d_items, sizeof(FillItem) * n);
-    if (e == hipSuccess)
-      e = hipMemcpy(L->d_items, items.data(), sizeof(FillItem) * n, hipMemcpyHostToDevice);
-    if (e != hipSuccess) rc = hip_fail(e, "fill item list");
+    if (!items_dev) {
+      set_error("internal: a batched launch needs device memory for its item list");
+      rc = MF_EINVAL;
+    } else {
+      L->d_items = reinterpret_cast<FillItem *>(items_dev);
+      hipError_t e =
+          hipMemcpy(L->d_items, items.data(), sizeof(FillItem) * n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) rc = hip_fail(e, "fill item list");
+    }
   }
   if (!rc) rc = dispatch(*L, true, nullptr);
   if (rc) {
@@ -1310,11 +1317,7 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
   return dispatch(*L, true, nullptr);
 }
 
-void fill_launch_destroy(FillLaunch *L) {
-  if (!L) return;
-  if (L->d_items) (void)hipFree(L->d_items);
-  delete L;
-}
+void fill_launch_destroy(FillLaunch *L) { delete L; }
 
 int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab,
                      const int32_t *tiles, int ntiles, const int32_t *sp_off, const int4 *sp_ent,
@@ -1322,7 +1325,7 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
   FillLaunch *L = nullptr;
   const float *sing = m->d_sing;
   int64_t ld = m->ne;
-  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &values, z_dtype, &ld, &sing, &L);
+  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &values, z_dtype, &ld, &sing, nullptr, &L);
   if (rc) return rc;
   L->sparse = true;
   L->first.tiles = tiles;
@@ -1341,7 +1344,7 @@ int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *
                 int z_dtype, int64_t ldz, hipStream_t s) {
   FillLaunch *L = nullptr;
   const float *sing = m->d_sing;
-  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &Z, z_dtype, &ldz, &sing, &L);
+  int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &Z, z_dtype, &ldz, &sing, nullptr, &L);
   if (rc) return rc;
   rc = fill_launch_run(L, s);
   fill_launch_destroy(L);

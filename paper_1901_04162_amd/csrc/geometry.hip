@@ -376,6 +376,8 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
   flush_extremes(lo, hi, out);
 }
 
+int range_runs(int nt) { return (nt + kRangeScreen - 1) / kRangeScreen; }
+
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s) {
   (void)V;
@@ -390,16 +392,13 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
                      m->d_scratch, m->d_scratch + 2);
   MF_HIP(hipGetLastError());
   const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
-  const int nr = (m->nt + kRangeScreen - 1) / kRangeScreen;
-  double *sph = nullptr;
-  MF_HIP(hipMallocAsync((void **)&sph, sizeof(double) * 4 * nr, s));
+  const int nr = range_runs(m->nt);
+  double *sph = m->d_sph;
   hipLaunchKernelGGL(k_range_spheres<kRangeScreen>, dim3(nr), dim3(kRangeScreen), 0, s,
                      m->d_brad, m->d_rec, m->nt, sph);
   dim3 grid(nb, (m->nt + kRangeChunk - 1) / kRangeChunk);
   hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
                      m->nt, r.nq, sph, m->d_scratch);
-  MF_HIP(hipGetLastError());
-  MF_HIP(hipFreeAsync(sph, s));
   MF_HIP(hipGetLastError());
   unsigned long long res[2];
   int st[4];

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -31,6 +32,37 @@ constexpr int kRecFloats = 64;
 constexpr int kRecRho = 0, kRecWRho = 21, kRecAlpha = 42, kRecSigma = 51, kRecCent = 54,
               kRecVid = 60;
 
+// Carves a caller-owned device workspace into arrays: `bottom` takes space
+// from the low end (arrays that outlive a call), `top` from the high end
+// (temporaries, released by restoring `hi`).  Every array starts on a
+// 256-byte boundary of the workspace (whose base must be 256-byte aligned).
+// With base == nullptr and size == SIZE_MAX it only counts: `lo` then ends
+// as the bytes a workspace needs for the same sequence of bottom calls.
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0, lo = 0, hi = 0;
+  Arena() = default;
+  Arena(void *b, size_t n) : base((char *)b), size(n), lo(0), hi(n) {}
+  static Arena counter() { return Arena(nullptr, SIZE_MAX); }
+  static size_t up(size_t x) { return (x + 255) & ~(size_t)255; }
+  template <class T>
+  bool bottom(T **p, size_t count) {
+    const size_t a = up(lo), b = up(sizeof(T) * (count ? count : 1));
+    if (a > hi || b > hi - a) return false;
+    lo = a + b;
+    *p = base ? (T *)(base + a) : nullptr;
+    return true;
+  }
+  template <class T>
+  bool top(T **p, size_t count) {
+    const size_t b = up(sizeof(T) * (count ? count : 1));
+    if (b > hi || hi - b < up(lo)) return false;
+    hi = (hi - b) & ~(size_t)255;
+    *p = base ? (T *)(base + hi) : nullptr;
+    return true;
+  }
+};
+
 struct Rule {
   int nq = 0;
   double bary[kMaxQ][3] = {};
@@ -42,6 +74,7 @@ bool make_rule(int q, Rule *r);
 
 struct mf_tables {
   double k = 0, rmin = 0, rmax = 0, tol = 0;
+  mf::Arena arena;  // over the caller's workspace; the arrays below live in it
   struct One {
     int n = 0, m = 0, iters = 0;
     double t = 0, delta = 0, err = 0;
@@ -81,6 +114,7 @@ struct mf_mesh {
   std::vector<int32_t> touch_off;  // nt+1 CSR of touching q per p (sorted)
   std::vector<int32_t> touch_q;
   std::vector<int32_t> touch_rev;  // index of (q,p) for pair (p,q)
+  std::vector<int32_t> touch_p;    // p of each touching pair
   std::vector<int32_t> blk_e0;     // nblk+1: first edge of each block
   std::vector<int32_t> blk_off;    // nblk+1: triangles needed by each edge block
   std::vector<int32_t> blk_tri;
@@ -107,6 +141,9 @@ struct mf_mesh {
   float *d_sing = nullptr;         // symmetrised, FP32 complex: npairs*9*2
   unsigned long long *d_scratch = nullptr;  // small reductions and flags
   int *d_status = nullptr;
+  double *d_sph = nullptr;         // range scan: bounding spheres of 32-triangle runs
+  void *ws = nullptr;              // the caller's device workspace (mf_mesh_set_workspace)
+  size_t ws_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
 };
@@ -124,6 +161,8 @@ int hip_fail(hipError_t e, const char *what);
 struct RuleArg;
 RuleArg rule_arg(const Rule &r);
 
+// Runs of 32 triangles the range scan bounds by spheres (4 doubles each).
+int range_runs(int nt);
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s);
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s);
@@ -147,9 +186,12 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
                      void *values, int z_dtype, hipStream_t s);
 // Several items (meshes x wavenumbers) in one persistent fill launch.
 struct FillLaunch;
+// items_dev: device memory of fill_items_bytes(n) for the item list of a
+// batched launch (n > 1), owned by the caller; may be null for one item.
+size_t fill_items_bytes(int n);
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
                        const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
-                       const float *const *sing, FillLaunch **out);
+                       const float *const *sing, void *items_dev, FillLaunch **out);
 int fill_launch_run(FillLaunch *L, hipStream_t s);
 // Times the workgroup-size variants of a batched launch (running it), keeps
 // the fastest; ms3 (may be NULL) receives the three timings (512, 768, 1024
@@ -157,6 +199,9 @@ int fill_launch_run(FillLaunch *L, hipStream_t s);
 int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads);
 void fill_launch_destroy(FillLaunch *L);
 int build_tables_device(mf_tables *t, double tol, hipStream_t s, bool green = true);
+// Upper bound of the device workspace a table build needs (both tables, or
+// the Exp table alone).
+size_t tables_workspace_bytes(double k, double rmin, double rmax, double tol, bool green);
 // Frees every device array of both tables (safe on partly built ones).
 void release_tables(mf_tables *t);
 // Angular-transformation fill (FP64 inner integrals on every pair).

@@ -430,10 +430,7 @@ static double interval_from_tol(int kind, double k, double rmin, double tol) {
 }
 
 static void release(mf_tables::One &o) {
-  // o.f lives in the allocation of o.r
-  void *ptrs[] = {o.r, o.hash, o.look, o.look1, o.coef, o.look64};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  // the arrays live in the caller's workspace: forget them
   o.r = o.f = nullptr;
   o.hash = nullptr;
   o.look = nullptr;
@@ -442,13 +439,12 @@ static void release(mf_tables::One &o) {
   o.look64 = nullptr;
 }
 
-static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStream_t s) {
-  release(o);
+static Plan make_plan(double k, double rmin, double rmax, double t) {
   Plan P{};
-  P.rmin = T->rmin;
-  P.rmax = T->rmax;
+  P.rmin = rmin;
+  P.rmax = rmax;
   P.t = t;
-  P.c = M_PI / (2.0 * T->k);
+  P.c = M_PI / (2.0 * k);
   P.mind = kMu * t;
   P.win_t = kWin * t;
   P.step_ref = kRatio * t;
@@ -457,27 +453,34 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
   while ((double)(P.mz0 + P.nz) * P.c < P.rmax) ++P.nz;
   P.nu = (long)std::floor((P.rmax - P.rmin) / t) + 2;
   P.ncell = (long)std::floor((P.rmax - P.rmin) / P.mind) + 3;
+  return P;
+}
 
+// Arrays of one table in the workspace arena: samples and values, hash
+// (bottom) and the placement cells and counters (top, released on return).
+static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStream_t s) {
+  release(o);
+  const Plan P = make_plan(T->k, T->rmin, T->rmax, t);
+  Arena &A = T->arena;
+  const size_t top0 = A.hi;
   double *cells = nullptr;
   int *d_count = nullptr;
   unsigned long long *d_u = nullptr;
-  int rc = MF_OK;
-  auto cleanup = [&]() {
-    if (cells) (void)hipFree(cells);
-    if (d_count) (void)hipFree(d_count);
-    if (d_u) (void)hipFree(d_u);
+  auto out_of_space = [&]() {
+    A.hi = top0;
+    set_error("mf_build_tables: table workspace too small");
+    return MF_ENOMEM;
   };
+  if (!A.top(&cells, 2 * (size_t)P.ncell) || !A.top(&d_count, 1) || !A.top(&d_u, 2))
+    return out_of_space();
 #define CK(call)                   \
   do {                             \
     hipError_t e_ = (call);        \
     if (e_ != hipSuccess) {        \
-      cleanup();                   \
+      A.hi = top0;                 \
       return hip_fail(e_, #call);  \
     }                              \
   } while (0)
-  CK(hipMalloc((void **)&cells, sizeof(double) * 2 * P.ncell));
-  CK(hipMalloc((void **)&d_count, sizeof(int)));
-  CK(hipMalloc((void **)&d_u, sizeof(unsigned long long) * 2));
   hipLaunchKernelGGL(k_fill_nan, dim3(blocks(2 * P.ncell, 256)), dim3(256), 0, s, cells,
                      2 * P.ncell);
   const long ncand[4] = {P.nz, 2, P.nz * 2 * kNRef, P.nu};
@@ -492,14 +495,14 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
   CK(hipMemcpyAsync(&n, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   if (n < (kind == kExp ? 2 : 4)) {
-    cleanup();
+    A.hi = top0;
     set_error("mf_build_tables: range too short for the interpolation stencil");
     return MF_EINVAL;
   }
   o.n = n;
-  // samples and values in one allocation, the values 256-byte aligned
+  // samples and values in one array, the values 256-byte aligned
   const size_t n_pad = ((size_t)n + 31) & ~(size_t)31;
-  CK(hipMalloc((void **)&o.r, sizeof(double) * (n_pad + 2 * (size_t)n)));
+  if (!A.bottom(&o.r, n_pad + 2 * (size_t)n)) return out_of_space();
   o.f = o.r + n_pad;
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(kScanThreads), 0, s, cells, P.ncell, o.r, d_count);
   hipLaunchKernelGGL(k_values, dim3(blocks(n, 256)), dim3(256), 0, s, o.r, n, T->k, kind, o.f);
@@ -516,15 +519,16 @@ static int build_one(mf_tables *T, int kind, double t, mf_tables::One &o, hipStr
   std::memcpy(&o.err, &res[1], 8);
   o.t = t;
   o.m = (int)std::floor((T->rmax - T->rmin) / o.delta) + 1;
-  CK(hipMalloc((void **)&o.hash, sizeof(int32_t) * o.m));
+  if (!A.bottom(&o.hash, (size_t)o.m)) return out_of_space();
   hipLaunchKernelGGL(k_hash_init, dim3(blocks(o.m, 256)), dim3(256), 0, s, o.hash, o.m);
   hipLaunchKernelGGL(k_hash_scatter, dim3(blocks(n, 256)), dim3(256), 0, s, o.r, n, T->rmin,
                      o.delta, o.m, o.hash);
   hipLaunchKernelGGL(k_hash_fill, dim3(1), dim3(kScanThreads), 0, s, o.hash, o.m);
   CK(hipGetLastError());
-  cleanup();
+  // the caller's stream has used the temporaries; later work on it may reuse them
+  A.hi = top0;
 #undef CK
-  return rc;
+  return MF_OK;
 }
 
 // Bucket width of the FP32 lookup: just under twice the smallest sample
@@ -535,24 +539,27 @@ constexpr double kBucketWidth = 1.99;
 constexpr double kBucketWidth1 = 0.99;
 
 static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
+  Arena &A = T->arena;
+  const size_t top0 = A.hi;
+  auto out_of_space = [&]() {
+    A.hi = top0;
+    set_error("mf_build_tables: table workspace too small");
+    return MF_ENOMEM;
+  };
   const double bw = kBucketWidth * o.delta;
   o.mb = (int)std::floor((T->rmax - T->rmin) / bw) + 1;
   o.binv = (float)(1.0 / bw);
   o.bbias = (float)(-T->rmin / bw);
   o.btop = (float)(o.mb - 1);
-  MF_HIP(hipMalloc((void **)&o.look, sizeof(int4) * o.mb));
-  MF_HIP(hipMalloc((void **)&o.coef, sizeof(float4) * (kind == kGreen ? 2 : 1) * (o.n - 1)));
   int *nb = nullptr, *bad = nullptr;
-  auto cleanup = [&]() {
-    if (nb) (void)hipFree(nb);
-    if (bad) (void)hipFree(bad);
-  };
-  hipError_t e = hipMalloc((void **)&nb, sizeof(int) * (o.n + 1));
-  if (e == hipSuccess) e = hipMalloc((void **)&bad, sizeof(int));
-  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), s);
+  if (!A.bottom(&o.look, (size_t)o.mb) ||
+      !A.bottom(&o.coef, (kind == kGreen ? 2 : 1) * (size_t)(o.n - 1)) ||
+      !A.top(&nb, (size_t)o.n + 1) || !A.top(&bad, 1))
+    return out_of_space();
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
   if (e != hipSuccess) {
-    cleanup();
-    return hip_fail(e, "table packing buffers");
+    A.hi = top0;
+    return hip_fail(e, "table packing");
   }
   hipLaunchKernelGGL(k_node_bucket, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n, o.binv,
                      o.bbias, o.btop, nb);
@@ -566,28 +573,20 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
     o.binv1 = (float)(1.0 / bw1);
     o.bbias1 = (float)(-T->rmin / bw1);
     o.btop1 = (float)(o.mb1 - 1);
-    e = hipMalloc((void **)&o.look1, sizeof(int4) * o.mb1);
-    if (e != hipSuccess) {
-      cleanup();
-      return hip_fail(e, "one-sample lookup");
-    }
+    if (!A.bottom(&o.look1, (size_t)o.mb1)) return out_of_space();
     hipLaunchKernelGGL(k_node_bucket, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n, o.binv1,
                        o.bbias1, o.btop1, nb);
     hipLaunchKernelGGL(k_pack_look1, dim3(blocks(o.mb1, 256)), dim3(256), 0, s, o.r, nb, o.n,
                        o.mb1, o.look1, bad);
-  }
-  else
+  } else {
     hipLaunchKernelGGL(k_pack_exp, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.f, o.n,
                        o.coef);
+  }
   if (kind == kExp && T->rmin == 0.0) {
     const double w = 0.999 * o.delta;
     o.inv64 = 1.0 / w;
     o.m64 = (int)(T->rmax * o.inv64) + 1;
-    e = hipMalloc((void **)&o.look64, sizeof(double) * 10 * (size_t)o.m64);
-    if (e != hipSuccess) {
-      cleanup();
-      return hip_fail(e, "FP64 Exp lookup");
-    }
+    if (!A.bottom(&o.look64, 10 * (size_t)o.m64)) return out_of_space();
     hipLaunchKernelGGL(k_node_bucket64, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n,
                        o.inv64, nb);
     hipLaunchKernelGGL(k_pack_look64, dim3(blocks(o.m64, 256)), dim3(256), 0, s, o.r, o.f, nb,
@@ -597,7 +596,7 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  cleanup();
+  A.hi = top0;
   if (e != hipSuccess) return hip_fail(e, "table packing");
   if (hbad) {
     set_error("mf_build_tables: a lookup bucket holds more samples than its record");
@@ -606,9 +605,48 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
   return MF_OK;
 }
 
+// Workspace bound of one table: every array at the largest size the probe
+// loop can reach (t down to t0/16 after eight refinements).  Counts of a
+// plan never grow with t, and kept samples are at least mu t apart, so the
+// bucket counts are bounded through the smallest interval mu t.
+static void count_table(Arena &A, int kind, double k, double rmin, double rmax, double tol,
+                        size_t &top_max) {
+  const double t0 = interval_from_tol(kind, k, rmin, tol);
+  const double tmin = t0 / 16.0 * (1.0 - 1e-9);
+  const Plan P = make_plan(k, rmin, rmax, tmin);
+  const size_t n = (size_t)(P.nz * (1 + 2 * kNRef) + 2 + P.nu) + 2;
+  const double dmin = kMu * tmin;
+  const size_t m = (size_t)std::floor((rmax - rmin) / dmin) + 3;
+  double *r = nullptr;
+  int32_t *h = nullptr;
+  int4 *look = nullptr;
+  float4 *coef = nullptr;
+  A.bottom(&r, ((n + 31) & ~(size_t)31) + 2 * n);
+  A.bottom(&h, m);
+  A.bottom(&look, (size_t)std::floor((rmax - rmin) / (kBucketWidth * dmin)) + 3);
+  A.bottom(&coef, (kind == kGreen ? 2 : 1) * n);
+  if (kind == kGreen)
+    A.bottom(&look, (size_t)std::floor((rmax - rmin) / (kBucketWidth1 * dmin)) + 3);
+  if (kind == kExp && rmin == 0.0) A.bottom(&r, 10 * ((size_t)(rmax / (0.999 * dmin)) + 3));
+  // temporaries: placement cells and counters, or the packing's bucket list
+  const size_t place = Arena::up(sizeof(double) * 2 * (size_t)P.ncell) + 2 * 256;
+  const size_t packing = Arena::up(sizeof(int) * (n + 1)) + 256;
+  top_max = std::max(top_max, std::max(place, packing) + 256);
+}
+
+size_t tables_workspace_bytes(double k, double rmin, double rmax, double tol, bool green) {
+  Arena A = Arena::counter();
+  size_t top = 0;
+  if (green) count_table(A, kGreen, k, rmin, rmax, tol, top);
+  count_table(A, kExp, k, rmin, rmax, tol, top);
+  return A.lo + top + 512;
+}
+
 void release_tables(mf_tables *t) {
   release(t->e);
   release(t->g);
+  t->arena.lo = 0;
+  t->arena.hi = t->arena.size;
 }
 
 int build_tables_device(mf_tables *T, double tol, hipStream_t s, bool green) {
@@ -617,7 +655,9 @@ int build_tables_device(mf_tables *T, double tol, hipStream_t s, bool green) {
     mf_tables::One &o = kind == kGreen ? T->g : T->e;
     double t = interval_from_tol(kind, T->k, T->rmin, tol);
     bool ok = false;
+    const size_t mark = T->arena.lo;  // each attempt reuses this table's space
     for (int it = 0; it <= 8; ++it) {
+      T->arena.lo = mark;
       int rc = build_one(T, kind, t, o, s);
       if (rc) return rc;
       o.iters = it;

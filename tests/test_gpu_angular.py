@@ -195,7 +195,7 @@ def test_angular_error_paths(mf, ico2):
     EINVAL = mf._lib.MF_EINVAL
 
     def call(n, mode, tab, k=c["k"]):
-        return L.mf_fill_angular(m.handle, C.c_void_p(Vd.data_ptr()), k, c["Q"], n, mode, tab,
+        return L.mf_fill_angular(m.device_handle, C.c_void_p(Vd.data_ptr()), k, c["Q"], n, mode, tab,
                                  C.c_void_p(Z.data_ptr()), mf.MF_C64, E, None)
 
     rmax = mf.angular_rmax(m, Vd, c["Q"])

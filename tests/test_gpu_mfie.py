@@ -222,7 +222,7 @@ def test_mfie_rejects_bad_arguments(mf):
     E = m.n_edges
     Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
     Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
-    args = lambda mode, tab, ldz: (m.handle, C.c_void_p(Vd.data_ptr()), 1.0, 6, mode, tab,
+    args = lambda mode, tab, ldz: (m.device_handle, C.c_void_p(Vd.data_ptr()), 1.0, 6, mode, tab,
                                    C.c_void_p(Z.data_ptr()), mf.MF_C64, ldz, None)
     L = mf.lib()
     assert L.mf_fill_mfie(*args(mf.MF_MODE_DIRECT | mf.MF_PART_A, None, E)) == mf._lib.MF_EINVAL

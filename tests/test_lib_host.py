@@ -79,10 +79,14 @@ def test_argument_errors_without_gpu():
 
     L = mf.lib()
     h = C.c_void_p()
+    ws = C.c_void_p(1 << 20)  # never dereferenced: every call below fails its checks first
     assert L.mf_mesh_create(0, 1, None, C.byref(h)) == mf._lib.MF_EINVAL
-    assert L.mf_build_tables(-1.0, 0.1, 1.0, 1e-6, C.byref(h), None) == mf._lib.MF_EINVAL
-    assert L.mf_build_tables(1.0, 0.5, 0.1, 1e-6, C.byref(h), None) == mf._lib.MF_EINVAL
-    assert L.mf_build_tables(1.0, 0.1, 1.0, 0.5, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(-1.0, 0.1, 1.0, 1e-6, ws, 1 << 20, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.5, 0.1, 1e-6, ws, 1 << 20, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.1, 1.0, 0.5, ws, 1 << 20, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.1, 1.0, 1e-6, None, 1 << 20, C.byref(h), None) == mf._lib.MF_EINVAL
+    assert L.mf_build_tables(1.0, 0.1, 1.0, 1e-6, C.c_void_p((1 << 20) + 8), 1 << 20, C.byref(h),
+                             None) == mf._lib.MF_EINVAL
     V, F = meshes.icosphere(1)
     m = mf.Mesh(F, V.shape[0])
     z = C.c_void_p(1)
@@ -126,3 +130,40 @@ def test_near_pattern_brute_force(s, r):
         np.testing.assert_array_equal(col[rp[e]:rp[e + 1]], np.nonzero(near[e])[0])
     nb, nt, _ = m.plan()
     assert 1 <= nf.n_tiles <= nt
+
+
+def test_workspaces_without_gpu():
+    """The device memory model: sizes are queried, a mesh without a bound
+    workspace refuses GPU work (no fallback allocation), a short or misaligned
+    workspace is refused before anything touches it."""
+    import paper_1901_04162_amd as mf
+
+    L = mf.lib()
+    V, F = meshes.icosphere(2)
+    m = mf.Mesh(F, V.shape[0])
+    n = C.c_size_t()
+    assert L.mf_mesh_workspace_bytes(m.handle, C.byref(n)) == mf._lib.MF_OK
+    # at least the 256-byte records and the FP64 quadrature points of every triangle
+    assert n.value >= F.shape[0] * (256 + 3 * 7 * 8)
+    fake = C.c_void_p(1 << 30)
+    assert L.mf_mesh_set_workspace(m.handle, fake, n.value - 1, None) == mf._lib.MF_EINVAL
+    assert b"too small" in L.mf_last_error()
+    assert L.mf_mesh_set_workspace(m.handle, C.c_void_p((1 << 30) + 64), n.value, None) == \
+        mf._lib.MF_EINVAL
+    lo, hi = C.c_double(), C.c_double()
+    assert L.mf_r_range(m.handle, fake, 3, C.byref(lo), C.byref(hi), None) == mf._lib.MF_EINVAL
+    assert b"workspace" in L.mf_last_error()
+    # table bounds grow as the tolerance tightens and cover the Exp table alone
+    b = []
+    for tol in (1e-4, 1e-6, 1e-8):
+        t = C.c_size_t()
+        assert L.mf_tables_workspace_bytes(17.0, 0.0331, 1.9998, tol, C.byref(t)) == mf._lib.MF_OK
+        b.append(t.value)
+    assert b[0] < b[1] < b[2]
+    t = C.c_size_t()
+    assert L.mf_exp_table_workspace_bytes(10.0, 2.0, 1e-6, C.byref(t)) == mf._lib.MF_OK
+    assert t.value > 0
+    arr = (C.c_void_p * 2)(m.handle.value, m.handle.value)
+    assert L.mf_batch_workspace_bytes(2, arr, C.byref(t)) == mf._lib.MF_OK
+    nf = mf.NearField(m, V, 0.2)
+    assert L.mf_near_workspace_bytes(nf._h, C.byref(t)) == mf._lib.MF_OK and t.value > 0
