@@ -119,6 +119,16 @@ int mf_mesh_set_workspace(mf_mesh *mesh, void *workspace_dev, size_t bytes, hipS
  * MF_EMESH for a zero-area triangle. */
 int mf_r_range(mf_mesh *mesh, const double *vertices_dev, int quad_order, double *r_min,
                double *r_max, hipStream_t stream);
+/* For callers that cannot allocate device memory or hand over scratch: the
+ * same range (bit-identical results) with the scan's scratch (four reduction
+ * words and 32 bytes per run of 32 triangles) in a 4 MiB array the library
+ * holds on each GPU it runs on until the process ends, so no workspace
+ * beyond the mesh's inputs is touched and nothing is allocated.  Meshes of
+ * more than 4,194,048 triangles are refused with MF_EINVAL.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (two host
+ * threads, or two streams) race and must be serialised by the caller. */
+int mf_r_range_static(mf_mesh *mesh, const double *vertices_dev, int quad_order, double *r_min,
+                      double *r_max, hipStream_t stream);
 
 /* ---- tables (Section II-B, II-C; Eqs. (2), (4)-(6), (10)) --------------
  * Builds on the device, in FP64, the adaptive tables of Exp(-jkr) (linear

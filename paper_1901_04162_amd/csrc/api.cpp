@@ -448,6 +448,20 @@ int mf_r_range(mf_mesh *m, const double *V, int quad_order, double *rmin, double
   return launch_r_range(m, V, r, rmin, rmax, s);
 }
 
+int mf_r_range_static(mf_mesh *m, const double *V, int quad_order, double *rmin, double *rmax,
+                      hipStream_t s) {
+  Rule r;
+  if (!m || !V || !rmin || !rmax || !make_rule(quad_order, &r))
+    return fail(MF_EINVAL, "mf_r_range_static: bad argument (quad_order must be 3, 6 or 7)");
+  if (m->nt > max_static_range_triangles())
+    return fail(MF_EINVAL, "mf_r_range_static: more triangles than the static scratch holds (" +
+                               std::to_string(max_static_range_triangles()) + ")");
+  int rc = ensure_device(m);
+  if (rc) return rc;
+  if ((rc = launch_geometry(m, V, r, s))) return rc;
+  return launch_r_range_static(m, V, r, rmin, rmax, s);
+}
+
 static int check_table_args(const char *who, double k, double rmin, double rmax, double tol,
                             bool green) {
   const std::string w = who;

@@ -3,6 +3,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "internal.hpp"
 #include "singular.hpp"
@@ -378,31 +380,30 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
 
 int range_runs(int nt) { return (nt + kRangeScreen - 1) / kRangeScreen; }
 
-int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
-                   hipStream_t s) {
-  (void)V;
+// The scan with its scratch at `words` (4 reduction words) and `sph` (the
+// run spheres): the mesh's workspace, or the static array below.
+static int range_scan(mf_mesh *m, const Rule &r, unsigned long long *words, double *sph,
+                      double *rmin, double *rmax, hipStream_t s) {
   unsigned long long init[4] = {~0ull, 0ull, 0ull, 0ull};
-  MF_HIP(hipMemcpyAsync(m->d_scratch, init, sizeof(init), hipMemcpyHostToDevice, s));
+  MF_HIP(hipMemcpyAsync(words, init, sizeof(init), hipMemcpyHostToDevice, s));
   const dim3 tgrid((m->nt + 255) / 256);
-  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, 0, m->d_scratch,
-                     m->d_scratch + 2);
-  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, -1,
-                     m->d_scratch + 2, m->d_scratch + 3);
+  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, 0, words, words + 2);
+  hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, -1, words + 2,
+                     words + 3);
   hipLaunchKernelGGL(k_range_seed, tgrid, dim3(256), 0, s, m->d_qp64, m->d_rec, m->nt, r.nq,
-                     m->d_scratch, m->d_scratch + 2);
+                     words, words + 2);
   MF_HIP(hipGetLastError());
   const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
   const int nr = range_runs(m->nt);
-  double *sph = m->d_sph;
   hipLaunchKernelGGL(k_range_spheres<kRangeScreen>, dim3(nr), dim3(kRangeScreen), 0, s,
                      m->d_brad, m->d_rec, m->nt, sph);
   dim3 grid(nb, (m->nt + kRangeChunk - 1) / kRangeChunk);
   hipLaunchKernelGGL(k_range, grid, dim3(kRangeBlock), 0, s, m->d_qp64, m->d_brad, m->d_rec,
-                     m->nt, r.nq, sph, m->d_scratch);
+                     m->nt, r.nq, sph, words);
   MF_HIP(hipGetLastError());
   unsigned long long res[2];
   int st[4];
-  MF_HIP(hipMemcpyAsync(res, m->d_scratch, sizeof(res), hipMemcpyDeviceToHost, s));
+  MF_HIP(hipMemcpyAsync(res, words, sizeof(res), hipMemcpyDeviceToHost, s));
   MF_HIP(hipMemcpyAsync(st, m->d_status, sizeof(st), hipMemcpyDeviceToHost, s));
   MF_HIP(hipStreamSynchronize(s));
   if (st[1]) {
@@ -420,6 +421,62 @@ int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, dou
   *rmin = std::sqrt(lo2);
   *rmax = std::sqrt(hi2);
   return MF_OK;
+}
+
+int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
+                   hipStream_t s) {
+  (void)V;
+  return range_scan(m, r, m->d_scratch, m->d_sph, rmin, rmax, s);
+}
+
+// ---- the range scan without a scratch workspace ---------------------------
+// For callers that cannot allocate: the scan's scratch (4 reduction words,
+// then 4 doubles per run of 32 triangles) lives in this file-scope array,
+// one copy per GPU for the life of the process.  Host code reaches it only
+// through the address hipGetSymbolAddress gives for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+constexpr size_t kStaticSphOffset = 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static int static_scratch(void **out) {
+  int dev = 0;
+  MF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("mf_r_range_static: device index beyond the library's table");
+    return MF_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    MF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MF_OK;
+}
+
+int max_static_range_triangles() {
+  return (int)((kStaticScratchBytes - kStaticSphOffset) / (4 * sizeof(double))) * kRangeScreen;
+}
+
+int launch_r_range_static(mf_mesh *m, const double *V, const Rule &r, double *rmin,
+                          double *rmax, hipStream_t s) {
+  (void)V;
+  if (m->nt > max_static_range_triangles()) {
+    set_error("mf_r_range_static: more triangles than the static scratch holds (" +
+              std::to_string(max_static_range_triangles()) + ")");
+    return MF_EINVAL;
+  }
+  void *p = nullptr;
+  int rc = static_scratch(&p);
+  if (rc) return rc;
+  auto *words = reinterpret_cast<unsigned long long *>(p);
+  auto *sph = reinterpret_cast<double *>(reinterpret_cast<char *>(p) + kStaticSphOffset);
+  return range_scan(m, r, words, sph, rmin, rmax, s);
 }
 
 // ---- K5: touching pairs (FP64 singularity cancellation) -------------------

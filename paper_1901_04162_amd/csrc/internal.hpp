@@ -166,6 +166,10 @@ int range_runs(int nt);
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s);
 int launch_r_range(mf_mesh *m, const double *V, const Rule &r, double *rmin, double *rmax,
                    hipStream_t s);
+// The same scan with its scratch in a static device array (no workspace).
+int launch_r_range_static(mf_mesh *m, const double *V, const Rule &r, double *rmin,
+                          double *rmax, hipStream_t s);
+int max_static_range_triangles();
 // Touching-pair blocks into out (m->d_sing when out is null).
 int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int part,
                     hipStream_t s, float *out = nullptr);
