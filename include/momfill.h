@@ -98,6 +98,17 @@ int mf_mesh_n_touching(const mf_mesh *mesh, int64_t *n_pairs);
  * max_block_triangles is the largest number of triangles one block needs. */
 int mf_mesh_plan(const mf_mesh *mesh, int32_t *n_blocks, int64_t *n_tiles,
                  int32_t *max_block_triangles);
+/* The triangle-block plan of the table-mode fill (mf_fill_Z with
+ * MF_MODE_TABLE and no MF_PART_ flag): blocks of at most 64 consecutive
+ * triangles and 112 edges with a triangle in the block, one tile per block
+ * pair I <= J (each unordered triangle pair evaluated once), the source
+ * triangles of a block in rounds of at most 16 of which no two share an
+ * edge.  n_cut edges have their two triangles in different blocks: their
+ * entries are completed from a side buffer in the mesh workspace.  All four
+ * outputs are 0 when the mesh has no such plan (then the edge-block plan
+ * above serves table mode too). */
+int mf_mesh_tb_plan(const mf_mesh *mesh, int32_t *n_blocks, int64_t *n_tiles, int32_t *n_cut,
+                    int32_t *max_rounds);
 
 /* Device workspace of a mesh: the topology, the tile plan, the per-triangle
  * records and FP64 quadrature points the kernels read, the touching-pair

@@ -67,6 +67,14 @@ class Mesh:
         check(lib().mf_mesh_n_touching(self._h, C.byref(n)))
         return n.value
 
+    def tb_plan(self):
+        """(blocks, tiles, cut edges, largest number of rounds) of the
+        triangle-block plan of the table-mode fill (zeros: no such plan)."""
+        nb, nc, mr = C.c_int32(), C.c_int32(), C.c_int32()
+        nt = C.c_int64()
+        check(lib().mf_mesh_tb_plan(self._h, C.byref(nb), C.byref(nt), C.byref(nc), C.byref(mr)))
+        return nb.value, nt.value, nc.value, mr.value
+
     def plan(self):
         """(blocks, tiles, largest triangles per block) of the regular fill."""
         nb, mt = C.c_int32(), C.c_int32()

@@ -29,7 +29,7 @@ EXPORTS = [
     "mf_rhs_planewave_mfie", "mf_fill_angular", "mf_angular_rmax", "mf_build_exp_table",
     "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
     "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
-    "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static",
+    "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static", "mf_mesh_tb_plan",
 ]
 
 
@@ -96,6 +96,8 @@ def lib():
                                    C.c_double, vp, vp, vp]
         L.mf_mesh_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]
+        L.mf_mesh_tb_plan.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.mf_r_range.argtypes = [vp, vp, C.c_int, dp, dp, vp]
         L.mf_r_range_static.argtypes = [vp, vp, C.c_int, dp, dp, vp]
         L.mf_build_tables.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, vp,

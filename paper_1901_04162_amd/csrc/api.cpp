@@ -257,6 +257,189 @@ static void build_blocks(mf_mesh *m) {
     for (int J = I; J < m->nblk; ++J) m->tiles.push_back((int32_t)(((uint32_t)I << 16) | (uint32_t)J));
 }
 
+// Triangle-block plan of the table-mode fill.  Blocks are runs of
+// consecutive triangles (at most kTBTris), closed before their block-edge
+// count would pass kTBEdges.  Edges are numbered by first appearance, so the
+// edges a block owns (first seen in its triangles) form one run of edge ids.
+// An edge with its two triangles in different blocks is cut: the block of
+// its lower triangle owns it, the other holds its non-owner half.  The
+// source triangles of each block are put in rounds of at most kTBRound
+// triangles of which no two share an edge (greedy, in index order).
+static void build_tb_plan(mf_mesh *m) {
+  m->tb_ok = false;
+  const int nt = m->nt, ne = m->ne;
+  const int32_t *E = m->edges.data();
+  std::vector<int32_t> blk(nt, -1);
+  m->tb_t0.assign(1, 0);
+  {
+    int t0 = 0, cnt = 0;
+    for (int t = 0; t < nt; ++t) {
+      int add = 0;
+      for (int a = 0; a < 3; ++a) {
+        const int e = m->tedge[3 * (size_t)t + a];
+        if (e < 0) continue;
+        const int o = E[6 * (size_t)e + 2] == t ? E[6 * (size_t)e + 3] : E[6 * (size_t)e + 2];
+        if (!(o >= t0 && o < t)) ++add;
+      }
+      if (t > t0 && (t - t0 == kTBTris || cnt + add > kTBEdges)) {
+        m->tb_t0.push_back(t);
+        t0 = t;
+        cnt = 0;
+        add = 0;
+        for (int a = 0; a < 3; ++a) add += m->tedge[3 * (size_t)t + a] >= 0;
+      }
+      if (add > kTBEdges) return;  // cannot happen for triangles (at most 3 edges)
+      cnt += add;
+      blk[t] = (int)m->tb_t0.size() - 1;
+    }
+    m->tb_t0.push_back(nt);
+  }
+  const int nb = (int)m->tb_t0.size() - 1;
+  if (nb > 65535) return;
+  m->tb_nblk = nb;
+  // owned edge runs, cut indices
+  m->tb_e0.assign(nb + 1, ne);
+  m->cut_idx.assign(ne, -1);
+  m->cut_edge.clear();
+  for (int e = ne - 1; e >= 0; --e) {
+    const int tp = E[6 * (size_t)e + 2], tm = E[6 * (size_t)e + 3];
+    m->tb_e0[blk[std::min(tp, tm)]] = e;
+  }
+  for (int b = nb - 1; b >= 0; --b)
+    if (m->tb_e0[b] > m->tb_e0[b + 1]) m->tb_e0[b] = m->tb_e0[b + 1];  // a block owning none
+  for (int e = 0; e < ne; ++e) {
+    const int tp = E[6 * (size_t)e + 2], tm = E[6 * (size_t)e + 3];
+    const int lo = std::min(tp, tm);
+    if (e < m->tb_e0[blk[lo]] || e >= m->tb_e0[blk[lo] + 1]) return;  // runs must hold
+    if (blk[tp] != blk[tm]) {
+      m->cut_idx[e] = (int)m->cut_edge.size();
+      m->cut_edge.push_back(e);
+    }
+  }
+  m->n_cut = (int)m->cut_edge.size();
+  // non-owner halves per block (in edge order) and their local indices
+  std::vector<std::vector<int32_t>> half(nb);
+  for (int e = 0; e < ne; ++e) {
+    if (m->cut_idx[e] < 0) continue;
+    const int hi = std::max(E[6 * (size_t)e + 2], E[6 * (size_t)e + 3]);
+    half[blk[hi]].push_back(e);
+  }
+  m->tb_nbe.assign(nb, 0);
+  m->tb_be_off.assign(nb + 1, 0);
+  m->tb_be_cut.clear();
+  std::vector<int32_t> local(ne, -1);  // local index of a non-owner half in its block
+  for (int b = 0; b < nb; ++b) {
+    const int nown = m->tb_e0[b + 1] - m->tb_e0[b];
+    for (size_t k = 0; k < half[b].size(); ++k) {
+      local[half[b][k]] = nown + (int)k;
+      m->tb_be_cut.push_back(m->cut_idx[half[b][k]]);
+    }
+    m->tb_nbe[b] = nown + (int)half[b].size();
+    m->tb_be_off[b + 1] = (int32_t)m->tb_be_cut.size();
+    if (m->tb_nbe[b] > kTBEdges) return;
+  }
+  m->tb_pos.assign(nt, -1);
+  for (int t = 0; t < nt; ++t) {
+    const int b = blk[t];
+    uint32_t pk = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int e = m->tedge[3 * (size_t)t + a];
+      uint32_t r = 0xffu;
+      if (e >= 0) r = (e >= m->tb_e0[b] && e < m->tb_e0[b + 1]) ? (uint32_t)(e - m->tb_e0[b])
+                                                                   : (uint32_t)local[e];
+      pk |= r << (8 * a);
+    }
+    m->tb_pos[t] = (int32_t)pk;
+  }
+  // rounds: first fit into rounds of at most kTBRound triangles with no two
+  // neighbours in one round, over a few orders of the block's triangles: the
+  // two classes of a breadth-first two-colouring of its triangle adjacency
+  // (a triangulated patch is mostly bipartite, then the rounds come out full),
+  // index order, and seeded shuffles; the order with the fewest rounds wins.
+  m->tb_order.assign(nt, 0);
+  m->tb_rounds.assign((size_t)nb * (kTBMaxRounds + 1), 0);
+  std::vector<int> round_of(nt, -1), par(nt, -1), best_round(nt, -1);
+  std::vector<int32_t> order, queue;
+  uint64_t seed = 0x9e3779b97f4a7c15ull;
+  for (int b = 0; b < nb; ++b) {
+    const int t0 = m->tb_t0[b], t1 = m->tb_t0[b + 1], n = t1 - t0;
+    auto nbr = [&](int t, int a) -> int {
+      const int e = m->tedge[3 * (size_t)t + a];
+      if (e < 0) return -1;
+      const int o = E[6 * (size_t)e + 2] == t ? E[6 * (size_t)e + 3] : E[6 * (size_t)e + 2];
+      return o >= t0 && o < t1 ? o : -1;
+    };
+    for (int s0 = t0; s0 < t1; ++s0) {  // two-colouring, breadth first
+      if (par[s0] >= 0) continue;
+      par[s0] = 0;
+      queue.assign(1, s0);
+      for (size_t h = 0; h < queue.size(); ++h)
+        for (int a = 0; a < 3; ++a) {
+          const int o = nbr(queue[h], a);
+          if (o >= 0 && par[o] < 0) {
+            par[o] = 1 - par[queue[h]];
+            queue.push_back(o);
+          }
+        }
+    }
+    auto first_fit = [&](const std::vector<int32_t> &ord) -> int {
+      int cnt[kTBMaxRounds] = {};
+      int nr = 0;
+      for (int t : ord) round_of[t] = -1;
+      for (int t : ord) {
+        int r = 0;
+        for (; r < kTBMaxRounds; ++r) {
+          if (cnt[r] >= kTBRound) continue;
+          bool clash = false;
+          for (int a = 0; a < 3 && !clash; ++a) {
+            const int o = nbr(t, a);
+            clash = o >= 0 && round_of[o] == r;
+          }
+          if (!clash) break;
+        }
+        if (r == kTBMaxRounds) return kTBMaxRounds + 1;
+        round_of[t] = r;
+        ++cnt[r];
+        nr = std::max(nr, r + 1);
+      }
+      return nr;
+    };
+    const int ideal = (n + kTBRound - 1) / kTBRound;
+    int best = kTBMaxRounds + 1;
+    for (int trial = 0; trial < 36 && best > ideal; ++trial) {
+      order.resize(n);
+      for (int i = 0; i < n; ++i) order[i] = t0 + i;
+      if (trial < 2)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return (par[x] ^ trial) < (par[y] ^ trial); });
+      else if (trial > 2)
+        for (int i = n - 1; i > 0; --i) {  // seeded shuffle
+          seed = seed * 6364136223846793005ull + 1442695040888963407ull;
+          std::swap(order[i], order[(int)((seed >> 33) % (uint64_t)(i + 1))]);
+        }
+      const int nr = first_fit(order);
+      if (nr < best) {
+        best = nr;
+        for (int t = t0; t < t1; ++t) best_round[t] = round_of[t];
+      }
+    }
+    if (best > kTBMaxRounds) return;
+    int32_t *rs = &m->tb_rounds[(size_t)b * (kTBMaxRounds + 1)];
+    int pos = 0;
+    for (int r = 0; r <= kTBMaxRounds; ++r) {
+      rs[r] = pos;
+      if (r < best)
+        for (int t = t0; t < t1; ++t)
+          if (best_round[t] == r) m->tb_order[t0 + pos++] = t;
+    }
+  }
+  m->tb_tiles.clear();
+  for (int I = 0; I < nb; ++I)
+    for (int J = I; J < nb; ++J)
+      m->tb_tiles.push_back((int32_t)(((uint32_t)I << 16) | (uint32_t)J));
+  m->tb_ok = true;
+}
+
 template <class T>
 static bool take(Arena &A, T **dst, size_t n) {
   T *p = nullptr;
@@ -281,7 +464,14 @@ static bool carve_mesh(const mf_mesh *m, Arena &A, mf_mesh *d) {
          MF_TAKE(d_elen, (size_t)m->ne) && MF_TAKE(d_sing1, 18 * npair) &&
          MF_TAKE(d_sing, 18 * npair) && MF_TAKE(d_scratch, 16) && MF_TAKE(d_status, 4) &&
          MF_TAKE(d_qp64, 3 * kMaxQ * nt) && MF_TAKE(d_brad, 4 * nt) &&
-         MF_TAKE(d_rec, (size_t)kRecFloats * nt) && MF_TAKE(d_sph, 4 * (size_t)range_runs(m->nt));
+         MF_TAKE(d_rec, (size_t)kRecFloats * nt) && MF_TAKE(d_sph, 4 * (size_t)range_runs(m->nt)) &&
+         MF_TAKE(d_tb_t0, m->tb_t0.size()) && MF_TAKE(d_tb_e0, m->tb_e0.size()) &&
+         MF_TAKE(d_tb_nbe, m->tb_nbe.size()) && MF_TAKE(d_tb_be_off, m->tb_be_off.size()) &&
+         MF_TAKE(d_tb_be_cut, m->tb_be_cut.size()) && MF_TAKE(d_tb_pos, m->tb_pos.size()) &&
+         MF_TAKE(d_tb_order, m->tb_order.size()) && MF_TAKE(d_tb_rounds, m->tb_rounds.size()) &&
+         MF_TAKE(d_tb_tiles, m->tb_tiles.size()) && MF_TAKE(d_cut_idx, m->cut_idx.size()) &&
+         MF_TAKE(d_cut_edge, m->cut_edge.size()) &&
+         MF_TAKE(d_side, m->tb_ok ? 2 * (size_t)m->n_cut * ((size_t)m->ne + m->n_cut) : 0);
 #undef MF_TAKE
 }
 
@@ -356,6 +546,7 @@ int mf_mesh_create(int32_t n_vertices, int32_t n_triangles, const int32_t *trian
   }
   build_touching(m);
   build_blocks(m);
+  build_tb_plan(m);
   if (m->nblk > 65535) {
     free_mesh(m);
     return fail(MF_EINVAL, "mf_mesh_create: too many RWG edges for the tile plan");
@@ -398,6 +589,24 @@ int mf_mesh_plan(const mf_mesh *m, int32_t *n_blocks, int64_t *n_tiles,
   return MF_OK;
 }
 
+int mf_mesh_tb_plan(const mf_mesh *m, int32_t *n_blocks, int64_t *n_tiles, int32_t *n_cut,
+                    int32_t *max_rounds) {
+  if (!m || !n_blocks || !n_tiles || !n_cut || !max_rounds)
+    return fail(MF_EINVAL, "mf_mesh_tb_plan: bad argument");
+  *n_blocks = m->tb_ok ? m->tb_nblk : 0;
+  *n_tiles = m->tb_ok ? (int64_t)m->tb_tiles.size() : 0;
+  *n_cut = m->tb_ok ? m->n_cut : 0;
+  int mr = 0;
+  for (int b = 0; m->tb_ok && b < m->tb_nblk; ++b) {
+    const int32_t *rs = &m->tb_rounds[(size_t)b * (kTBMaxRounds + 1)];
+    int r = 0;
+    while (r < kTBMaxRounds && rs[r + 1] > rs[r]) ++r;
+    mr = std::max(mr, r);
+  }
+  *max_rounds = mr;
+  return MF_OK;
+}
+
 int mf_mesh_workspace_bytes(const mf_mesh *m, size_t *bytes) {
   if (!m || !bytes) return fail(MF_EINVAL, "mf_mesh_workspace_bytes: bad argument");
   Arena A = Arena::counter();
@@ -424,7 +633,14 @@ int mf_mesh_set_workspace(mf_mesh *m, void *ws, size_t bytes, hipStream_t s) {
       (rc = upload(m->d_touch_p, m->touch_p, s)) || (rc = upload(m->d_blk_off, m->blk_off, s)) ||
       (rc = upload(m->d_blk_tri, m->blk_tri, s)) || (rc = upload(m->d_blk_pos, m->blk_pos, s)) ||
       (rc = upload(m->d_tiles, m->tiles, s)) || (rc = upload(m->d_blk_e0, m->blk_e0, s)) ||
-      (rc = upload(m->d_blk_rt, m->blk_rt, s))) {
+      (rc = upload(m->d_blk_rt, m->blk_rt, s)) || (rc = upload(m->d_tb_t0, m->tb_t0, s)) ||
+      (rc = upload(m->d_tb_e0, m->tb_e0, s)) || (rc = upload(m->d_tb_nbe, m->tb_nbe, s)) ||
+      (rc = upload(m->d_tb_be_off, m->tb_be_off, s)) ||
+      (rc = upload(m->d_tb_be_cut, m->tb_be_cut, s)) || (rc = upload(m->d_tb_pos, m->tb_pos, s)) ||
+      (rc = upload(m->d_tb_order, m->tb_order, s)) ||
+      (rc = upload(m->d_tb_rounds, m->tb_rounds, s)) ||
+      (rc = upload(m->d_tb_tiles, m->tb_tiles, s)) || (rc = upload(m->d_cut_idx, m->cut_idx, s)) ||
+      (rc = upload(m->d_cut_edge, m->cut_edge, s))) {
     m->ws = nullptr;
     return rc;
   }

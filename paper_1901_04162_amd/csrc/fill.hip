@@ -93,6 +93,11 @@ struct FillItem {
   const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q, *touch_rev;
   const int32_t *blk_rt;  // per block row: positions of its T+ and T- in the block's list
   const float *elen;      // edge lengths
+  // triangle-block plan (table mode, see fill_tile_tb)
+  const int32_t *tb_t0, *tb_e0, *tb_nbe, *tb_be_off, *tb_be_cut, *tb_pos, *tb_order, *tb_rounds,
+      *tb_tiles;
+  float2 *side;           // cut-edge partial entries, rows of lside complex values
+  long long lside;
   const float *sing;
   const int4 *look;
   const float4 *coef;
@@ -973,6 +978,253 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
+// ---- triangle-block tiles (table mode) -------------------------------------
+// The halo-free tiling: blocks of at most 64 consecutive triangles, and one
+// tile per block pair I <= J evaluates every triangle pair (p in I, q in J)
+// exactly once.  The tile accumulates, in one LDS array without atomics,
+// the entries between the block edges of I (rows) and of J (columns): the
+// edges I and J own (first seen in their triangles) and the non-owner halves
+// of edges cut between blocks.  Lane l takes test triangle l of I; the
+// waves take the source triangles of J in rounds of pairwise non-adjacent
+// triangles with a barrier after each round, so no two waves ever add to
+// one column at once, and within a wave the rows of an edge's plus and
+// minus triangles are added in two passes.  Write-out: the owned x owned
+// rectangle goes to Z (and, transposed, below the diagonal); entries with a
+// non-owner half go to the side buffer, whose rows are the cut edges'
+// non-owner halves and whose columns are the edges (owned parts) followed by
+// the non-owner halves; k_cut_rows and k_cut_cols add them in afterwards.
+constexpr int kTBStride = 2 * kTBEdges + 1;  // odd: rows fall in different banks
+constexpr int kTBAccFloats = kTBEdges * kTBStride;
+constexpr int kTBThreads = 1024;
+
+template <int Q, typename ZT, bool kLDS>
+__device__ __forceinline__ void fill_tile_tb(
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
+    float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tb_pos,
+    const int32_t *__restrict__ tb_order, const int32_t *__restrict__ touch_off,
+    const int32_t *__restrict__ touch_q, const float *__restrict__ sing, ZT *__restrict__ Z,
+    float2 *__restrict__ side) {
+  constexpr int kWaves = kTBThreads / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = uniform(threadIdx.x >> 6);
+  const int tij = S.tb_tiles[local];
+  const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
+  const int nbeI = S.tb_nbe[I], nbeJ = S.tb_nbe[J];
+  for (int i = threadIdx.x; i < nbeI * kTBStride; i += kTBThreads) acc[i] = 0.0f;
+  __syncthreads();
+  const int tI0 = S.tb_t0[I], npI = S.tb_t0[I + 1] - tI0;
+  const int tJ0 = S.tb_t0[J];
+  const bool pv = lane < npI;
+  const int p = tI0 + (pv ? lane : 0);
+  const int prow = pv ? tb_pos[p] : -1;
+  const float *pr = rec + (size_t)p * kRecFloats;
+  const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
+  const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
+  const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
+  const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
+  const int32_t *rs = S.tb_rounds + (size_t)J * (kTBMaxRounds + 1);
+  for (int k = 0; k < kTBMaxRounds; ++k) {
+    const int s0 = uniform(rs[k]), s1 = uniform(rs[k + 1]);
+    if (s0 == s1) break;
+    for (int j = s0 + wave; j < s1; j += kWaves) {
+      const int q = uniform(as_const(tb_order)[tJ0 + j]);
+      const int qcol = uniform(as_const(tb_pos)[q]);
+      cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
+      cint32 *qvi = (cint32 *)(qr + kRecVid);
+      const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
+      const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
+                         pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
+      float Xr[3][3], Xi[3][3];
+      if (!touch) {
+        cdouble *qcd = (cdouble *)(qr + kRecCent);
+        const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
+        const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
+        const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                    lz = (float)(Dz - (double)hz);
+        Moments M;
+        moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly,
+                                           lz, qr, rlo, rhi);
+        const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
+        // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2
+        const float c0r = fmaf(-S.ik2, M.s0r, 0.25f * M.srr);
+        const float c0i = fmaf(-S.ik2, M.s0i, 0.25f * M.sri);
+        float Ar[3], Ai[3], Br[3], Bi[3], palpha[3][3], beta[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Ar[a] = c0r;
+          Ai[a] = c0i;
+          Br[a] = Bi[a] = 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+            beta[a][c] = qr[kRecAlpha + 3 * a + c];
+            Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
+            Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
+            Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
+            Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+          }
+        }
+        const float q0r = 0.25f * M.s0r, q0i = 0.25f * M.s0i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
+                             palpha[a][2] * beta[b][2];
+            Xr[a][b] = fmaf(ab, q0r, Ar[a] + Br[b]);
+            Xi[a][b] = fmaf(ab, q0i, Ai[a] + Bi[b]);
+          }
+      } else {
+        int s = touch_off[p];
+        const int s1t = touch_off[p + 1];
+        while (s < s1t && touch_q[s] != q) ++s;
+        const bool found = s < s1t;  // always: touching pairs are listed both ways
+        const float *x = sing + (size_t)(found ? s : 0) * 18;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
+            Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
+          }
+      }
+      if (pv) {
+        float psig[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) psig[a] = pr[kRecSigma + a];
+        // rows of plus triangles first, then minus: the two triangles of an
+        // edge interior to the block are two lanes of this wave
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int row = (prow >> (8 * a)) & 0xff;
+            if (row == 0xff || (psig[a] < 0.0f) != (pass == 1)) continue;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const int col = (qcol >> (8 * b)) & 0xff;
+              if (col == 0xff) continue;
+              const float sg = psig[a] * qr[kRecSigma + b];
+              float *dst = acc + row * kTBStride + 2 * col;
+              dst[0] += sg * Xr[a][b];
+              dst[1] += sg * Xi[a][b];
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // write-out: Z = j k eta/(4 pi) acc; a wave per row, lanes along it
+  const int e0I = S.tb_e0[I], nownI = S.tb_e0[I + 1] - e0I;
+  const int e0J = S.tb_e0[J], nownJ = S.tb_e0[J + 1] - e0J;
+  const int32_t *cutI = S.tb_be_cut + S.tb_be_off[I], *cutJ = S.tb_be_cut + S.tb_be_off[J];
+  const float pref = S.pref;
+  for (int r = wave; r < nownI; r += kWaves) {
+    ZT *zr = Z + (size_t)(e0I + r) * S.ldz + e0J;
+    for (int c = lane; c < nownJ; c += 64) {
+      const float *a = acc + r * kTBStride + 2 * c;
+      ZT v;
+      v.x = -pref * a[1];
+      v.y = pref * a[0];
+      zr[c] = v;
+    }
+  }
+  if (I != J)
+    for (int c = wave; c < nownJ; c += kWaves) {
+      ZT *zc = Z + (size_t)(e0J + c) * S.ldz + e0I;
+      for (int r = lane; r < nownI; r += 64) {
+        const float *a = acc + r * kTBStride + 2 * c;
+        ZT v;
+        v.x = -pref * a[1];
+        v.y = pref * a[0];
+        zc[r] = v;
+      }
+    }
+  // rows that are non-owner halves: side[cut row][column of the J part]
+  for (int r = nownI + wave; r < nbeI; r += kWaves) {
+    float2 *sr = side + (size_t)cutI[r - nownI] * S.lside;
+    for (int c = lane; c < nbeJ; c += 64) {
+      const float *a = acc + r * kTBStride + 2 * c;
+      const long long col = c < nownJ ? (long long)(e0J + c) : (long long)S.ne + cutJ[c - nownJ];
+      sr[col] = make_float2(-pref * a[1], pref * a[0]);
+    }
+  }
+  // columns that are non-owner halves, as rows of the side buffer (the
+  // diagonal tile has them among its rows already)
+  if (I != J)
+    for (int c = nownJ + wave; c < nbeJ; c += kWaves) {
+      float2 *sr = side + (size_t)cutJ[c - nownJ] * S.lside;
+      for (int r = lane; r < nbeI; r += 64) {
+        const float *a = acc + r * kTBStride + 2 * c;
+        const long long col = r < nownI ? (long long)(e0I + r) : (long long)S.ne + cutI[r - nownI];
+        sr[col] = make_float2(-pref * a[1], pref * a[0]);
+      }
+    }
+  __syncthreads();
+}
+
+template <int Q, bool kLDS, typename ZT>
+__global__ __launch_bounds__(kTBThreads)
+__attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_fill_tb(
+    FillItem S, FillRule W, int ntiles) {
+  extern __shared__ float4 smem4[];
+  float *acc = reinterpret_cast<float *>(smem4);
+  const TabPtrs tab = load_table<kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
+  float rlo = INFINITY, rhi = 0.0f;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
+    fill_tile_tb<Q, ZT, kLDS>(S, W, tab, acc, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order,
+                              S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
+  if (rlo < S.lo_ok || rhi > S.hi_ok) atomicOr(S.status, 1);
+}
+
+// Cut-edge fix-up, one 64 x 64 tile per workgroup: 64 cut edges c (rows) by
+// 64 consecutive edges n (columns).  Each entry Z[c][n] is completed from
+// the owned part the fill wrote and the side buffer, (c^ x own n), and for a
+// cut n also (own c x n^) and (c^ x n^), and written back along the row.
+// The completed tile is then transposed through LDS into the columns c of
+// the rows n that are not cut (Z = Z^T; cut rows are completed by their own
+// tiles), so every column write of one row falls within the tile's span.
+constexpr int kFixTile = 64;
+
+template <typename ZT>
+__global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long ldz, int ne,
+                                                 int ncut, const int32_t *__restrict__ cut_edge,
+                                                 const int32_t *__restrict__ cut_idx,
+                                                 const float2 *__restrict__ side,
+                                                 long long lside) {
+  __shared__ ZT tile[kFixTile][kFixTile + 1];
+  const int n0 = blockIdx.x * kFixTile, ci0 = blockIdx.y * kFixTile;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 4 waves
+  const int n = n0 + tx;
+  const int cn = n < ne ? cut_idx[n] : -1;
+  for (int i = ty; i < kFixTile; i += 4) {
+    const int ci = ci0 + i;
+    if (ci >= ncut || n >= ne) continue;
+    const int c = cut_edge[ci];
+    const float2 a = side[(size_t)ci * lside + n];
+    ZT z = Z[(size_t)c * ldz + n];
+    z.x += a.x;
+    z.y += a.y;
+    if (cn >= 0) {
+      const float2 b = side[(size_t)cn * lside + c];
+      const float2 d = side[(size_t)ci * lside + ne + cn];
+      z.x += b.x + d.x;
+      z.y += b.y + d.y;
+    }
+    Z[(size_t)c * ldz + n] = z;
+    tile[i][tx] = z;
+  }
+  __syncthreads();
+  // columns: row n0 + j (if not cut) receives the 64 values at columns c
+  const int ci = ci0 + tx;
+  const int c = ci < ncut ? cut_edge[ci] : 0;
+  for (int j = ty; j < kFixTile; j += 4) {
+    const int m = n0 + j;
+    if (m >= ne || ci >= ncut || cut_idx[m] >= 0) continue;
+    Z[(size_t)m * ldz + c] = tile[tx][j];
+  }
+}
+
 // Several items in one persistent launch: the workgroups stride through the
 // concatenated tile list, so every workgroup visits the items in order and
 // loads each item's table once.
@@ -1150,6 +1402,17 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.blk_pos = m->d_blk_pos;
   S.blk_rt = m->d_blk_rt;
   S.elen = m->d_elen;
+  S.tb_t0 = m->d_tb_t0;
+  S.tb_e0 = m->d_tb_e0;
+  S.tb_nbe = m->d_tb_nbe;
+  S.tb_be_off = m->d_tb_be_off;
+  S.tb_be_cut = m->d_tb_be_cut;
+  S.tb_pos = m->d_tb_pos;
+  S.tb_order = m->d_tb_order;
+  S.tb_rounds = m->d_tb_rounds;
+  S.tb_tiles = m->d_tb_tiles;
+  S.side = reinterpret_cast<float2 *>(m->d_side);
+  S.lside = (long long)m->ne + m->n_cut;
   S.touch_off = m->d_touch_off;
   S.touch_q = m->d_touch_q;
   S.touch_rev = m->d_touch_rev;
@@ -1340,8 +1603,81 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
   return rc;
 }
 
+template <int Q, bool kLDS, typename ZT>
+static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t lds,
+                       hipStream_t s) {
+  auto kern = k_fill_tb<Q, kLDS, ZT>;
+  static std::once_flag once;
+  static long long grid = 0;
+  static hipError_t ge = hipSuccess;
+  std::call_once(once, [&]() {
+    int dev = 0, ncu = 0, per = 0;
+    ge = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+    if (ge == hipSuccess) ge = hipGetDevice(&dev);
+    if (ge == hipSuccess) ge = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ge == hipSuccess)
+      ge = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kTBThreads, lds);
+    grid = (long long)ncu * per;
+  });
+  if (ge != hipSuccess) return hip_fail(ge, "triangle-block fill set-up");
+  if (grid < 1) {
+    set_error("mf_fill_Z: triangle-block fill kernel does not fit on a compute unit");
+    return MF_EINVAL;
+  }
+  const int ntiles = (int)m->tb_tiles.size();
+  const long long g = std::min<long long>(grid, ntiles);
+  if (getenv("MOMFILL_VERBOSE"))
+    fprintf(stderr, "[momfill] k_fill_tb Q=%d lds_table=%d tiles=%d grid=%lld lds=%zu B cut=%d\n",
+            Q, (int)kLDS, ntiles, g, lds, m->n_cut);
+  hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(kTBThreads), lds, s, S, W, ntiles);
+  MF_HIP(hipGetLastError());
+  if (m->n_cut > 0) {
+    const dim3 fg((unsigned)((m->ne + kFixTile - 1) / kFixTile),
+                  (unsigned)((m->n_cut + kFixTile - 1) / kFixTile));
+    hipLaunchKernelGGL(k_cut_fix<ZT>, fg, dim3(256), 0, s, reinterpret_cast<ZT *>(S.Z), S.ldz,
+                       m->ne, m->n_cut, m->d_cut_edge, m->d_cut_idx,
+                       reinterpret_cast<const float2 *>(m->d_side), S.lside);
+    MF_HIP(hipGetLastError());
+  }
+  return MF_OK;
+}
+
+template <bool kLDS, typename ZT>
+static int launch_tb_q(mf_mesh *m, int nq, const FillItem &S, const FillRule &W, size_t lds,
+                       hipStream_t s) {
+  switch (nq) {
+    case 3: return launch_tb_t<3, kLDS, ZT>(m, S, W, lds, s);
+    case 6: return launch_tb_t<6, kLDS, ZT>(m, S, W, lds, s);
+    default: return launch_tb_t<7, kLDS, ZT>(m, S, W, lds, s);
+  }
+}
+
+// Table-mode EFIE fill on the triangle-block plan (k_fill_tb and the cut-edge
+// fix-ups), one item.
+static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, const mf_tables *tab, void *Z,
+                          int z_dtype, int64_t ldz, hipStream_t s) {
+  FillItem S = make_item(m, r, k, MF_MODE_TABLE, tab, Z, ldz, m->d_sing, 0);
+  FillRule W;
+  for (int i = 0; i < kMaxQ; ++i) W.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+  int dev = 0, maxlds = 0;
+  MF_HIP(hipGetDevice(&dev));
+  MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t base = sizeof(float) * kTBAccFloats + 16;
+  const size_t tbytes = table_lds_bytes(tab);
+  const bool in_lds = base + tbytes <= (size_t)maxlds;
+  const size_t lds = in_lds ? base + tbytes : base;
+  if (z_dtype == MF_C64)
+    return in_lds ? launch_tb_q<true, float2>(m, r.nq, S, W, lds, s)
+                  : launch_tb_q<false, float2>(m, r.nq, S, W, lds, s);
+  return in_lds ? launch_tb_q<true, double2>(m, r.nq, S, W, lds, s)
+                : launch_tb_q<false, double2>(m, r.nq, S, W, lds, s);
+}
+
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s) {
+  if (mode == MF_MODE_TABLE && m->tb_ok)
+    return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s);
   FillLaunch *L = nullptr;
   const float *sing = m->d_sing;
   int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &Z, z_dtype, &ldz, &sing, nullptr, &L);

@@ -20,6 +20,14 @@ enum { MF_OP_EFIE = 0, MF_OP_MFIE = 1 };
 constexpr int kModeMfie = 0x100;
 constexpr int kMaxBlockEdges = 80;  // RWG edges per row/column block of a tile
 constexpr int kMaxBlockTris = 64;   // triangles carrying a block's edges (one per lane)
+// Triangle-block plan (table-mode fill): blocks of at most 64 consecutive
+// triangles and 112 block edges (edges with a triangle in the block), the
+// source triangles of a block in rounds of at most 16 pairwise non-adjacent
+// triangles, at most kTBMaxRounds rounds.
+constexpr int kTBTris = 64;
+constexpr int kTBEdges = 112;
+constexpr int kTBRound = 16;
+constexpr int kTBMaxRounds = 12;
 
 // Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
 //  [0,21)  rho_i = r_i - c      (i-major, xyz)           FP32
@@ -125,6 +133,23 @@ struct mf_mesh {
   std::vector<int32_t> tiles;      // (I << 16) | J for every block pair I <= J
   int nblk = 0, max_blk_tris = 0;
 
+  // Triangle-block plan: block b holds triangles [tb_t0[b], tb_t0[b+1]) and
+  // owns the edges [tb_e0[b], tb_e0[b+1]) (those first seen in its
+  // triangles); its block edges are the owned edges (local index e - e0)
+  // followed by the non-owner halves of cut edges owned by earlier blocks.
+  bool tb_ok = false;
+  int tb_nblk = 0, n_cut = 0;
+  std::vector<int32_t> tb_t0, tb_e0;
+  std::vector<int32_t> tb_nbe;       // block edges per block
+  std::vector<int32_t> tb_be_off;    // nblk+1 CSR of the non-owner halves' cut indices
+  std::vector<int32_t> tb_be_cut;
+  std::vector<int32_t> tb_pos;       // nt: packed local block-edge index of local edges 0..2
+  std::vector<int32_t> tb_order;     // nt: triangles of each block in round order
+  std::vector<int32_t> tb_rounds;    // nblk*(kTBMaxRounds+1) round starts in the block's order
+  std::vector<int32_t> tb_tiles;     // (I << 16) | J, I <= J
+  std::vector<int32_t> cut_idx;      // ne: index of a cut edge, -1 if interior to a block
+  std::vector<int32_t> cut_edge;     // n_cut: edge of each cut index
+
   // device copies
   int32_t *d_tri = nullptr, *d_tedge = nullptr;
   int32_t *d_edges = nullptr;      // ne*6, as edges
@@ -142,6 +167,11 @@ struct mf_mesh {
   unsigned long long *d_scratch = nullptr;  // small reductions and flags
   int *d_status = nullptr;
   double *d_sph = nullptr;         // range scan: bounding spheres of 32-triangle runs
+  int32_t *d_tb_t0 = nullptr, *d_tb_e0 = nullptr, *d_tb_nbe = nullptr, *d_tb_be_off = nullptr,
+          *d_tb_be_cut = nullptr, *d_tb_pos = nullptr, *d_tb_order = nullptr,
+          *d_tb_rounds = nullptr, *d_tb_tiles = nullptr, *d_cut_idx = nullptr,
+          *d_cut_edge = nullptr;
+  float *d_side = nullptr;         // n_cut x (ne + n_cut) complex: cut-edge partial entries
   void *ws = nullptr;              // the caller's device workspace (mf_mesh_set_workspace)
   size_t ws_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

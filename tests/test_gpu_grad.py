@@ -193,3 +193,62 @@ def test_autograd_path(mf):
     # same kernels; FP64 atomics may add in another order
     assert torch.allclose(Vt.grad, dV, rtol=1e-10, atol=1e-12 * float(dV.abs().max()))
     assert abs(float(kt.grad) - float(dk.item())) <= 1e-10 * abs(float(dk.item()))
+
+
+@pytest.fixture(scope="module")
+def ico4_fd(orc, ico4):
+    """Finite-difference reference of the 7,680-unknown case on the FP64
+    oracle (direct exponential): dL/dV at 64 seeded coordinates (local loss,
+    central differences with one Richardson step), dL/dk (full loss filled in
+    triangle-pair order, Richardson), and the derivatives along 8 seeded
+    random unit directions in the 7,686-dimensional space of the coordinates
+    (full loss, central differences, h = 1e-4)."""
+    V, F, k, Q, m, W = ico4
+    E = m.edges()
+    Wn = W.cpu().numpy().astype(np.complex128)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(V.size, 64, replace=False))
+    say("oracle FD: 64 coordinates")
+    g_idx, _ = orc.grad_fd(V, F, E, k, Q, Wn, idx, with_k=False)
+
+    def loss(Vx, kx):
+        Z = orc.fill_rows(Vx, F, E, kx, Q, 0, E.shape[0])
+        return float(np.sum(np.real(np.conj(Wn) * Z)))
+
+    say("oracle FD: dL/dk")
+    hk = 1e-4 * k
+    d = [(loss(V, k + hh) - loss(V, k - hh)) / (2 * hh) for hh in (hk, hk / 2)]
+    gk = (4 * d[1] - d[0]) / 3
+    D = np.random.default_rng(13).standard_normal((8, V.size))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    h = 1e-4
+    dd = np.zeros(8)
+    for i in range(8):
+        say("oracle FD: direction", i)
+        step = D[i].reshape(V.shape)
+        dd[i] = (loss(V + h * step, k) - loss(V - h * step, k)) / (2 * h)
+    return idx, g_idx, gk, D, dd
+
+
+@pytest.mark.parametrize("mode,tol,bar", [("direct", None, 1e-5), ("table", 1e-6, 1e-4)])
+def test_grad_against_fd_full_size(mf, ico4, ico4_fd, mode, tol, bar):
+    """The adjoint of the 7,680-unknown jittered sphere (k = 10, 6-point rule,
+    W complex64 N(0,1)) against the oracle's finite differences: 64 vertex
+    coordinates, 8 random directions and dL/dk, each error relative to the
+    norm of its reference.  Table mode holds its tables fixed and
+    differentiates the interpolant, so its bar carries the table's own
+    derivative error."""
+    V, F, k, Q, m, W = ico4
+    idx, g_idx, gk_ref, D, dd = ico4_fd
+    T = None
+    if mode == "table":
+        lo, hi = mf.r_range(m, V, Q)
+        T = mf.build_tables(k, lo, hi, tol)
+    say("adjoint", mode)
+    dV, dk = mf.fill_Z_backward(m, V, k, Q, mode, T, W)
+    g = dV.cpu().numpy().ravel()
+    e_coord = np.linalg.norm(g[idx] - g_idx) / np.linalg.norm(g_idx)
+    e_dir = np.linalg.norm(D @ g - dd) / np.linalg.norm(dd)
+    e_k = abs(float(dk.item()) - gk_ref) / abs(gk_ref)
+    say(f"  {mode}: 64 coordinates {e_coord:.3e}, 8 directions {e_dir:.3e}, dL/dk {e_k:.3e}")
+    assert e_coord <= bar and e_dir <= bar and e_k <= bar

@@ -405,3 +405,57 @@ def test_sampled_plate(mf, orc, tol):
     V, F = meshes.plate()
     _sampled_check(mf, orc, V, F, 2 * np.pi, 7, tol, 1500, 30, modes=("table",),
                    bound_table=max(1e-5, 10 * tol))
+
+
+def test_triangle_block_fill_scrambled_mesh(mf, orc):
+    """The triangle-block table fill on a mesh whose triangles are in random
+    order: nearly every edge is cut between blocks, so almost every entry is
+    completed from the side buffer by the cut-edge fix-ups.  Full matrix
+    against the oracle's table mode with the same table."""
+    import torch
+
+    V, F = meshes.icosphere(2)
+    F = F[np.random.default_rng(4).permutation(len(F))]
+    k, Q, tol = 2 * np.pi, 3, 1e-6
+    m = mf.Mesh(F, V.shape[0])
+    nb, nt, ncut, nr = m.tb_plan()
+    say("scrambled ico2: blocks", nb, "cut edges", ncut, "of", m.n_edges)
+    assert ncut > m.n_edges // 2
+    E = m.edges()
+    lo, hi = mf.r_range(m, V, Q)
+    T = mf.build_tables(k, lo, hi, tol)
+    G = orc.build_table(orc.GREEN, k, lo, hi, tol)
+    ref = orc.fill(V, F, k, Q, mode=orc.TABLE, gtable=G, edges=E)
+    Z = mf.fill_Z(m, V, k, Q, "table", T, dtype=torch.complex128)
+    mf.sync_status(m)
+    err = _rel(Z.cpu().numpy(), ref)
+    say("  rel err against the oracle's table mode", err)
+    assert err <= 1e-6
+    z = Z.cpu().numpy()
+    # reciprocity to FP32 rounding (parts of two cut rows are added in another order)
+    assert np.abs(z - z.T).max() <= 1e-6 * np.abs(z).max()
+
+
+def test_triangle_block_fill_matches_edge_block_fill(mf):
+    """The benchmark sphere's table fill on the triangle-block plan against the
+    same fill on the edge-block plan (the kernel of batched launches): the two
+    sum the same FP32 terms in another order."""
+    import torch
+
+    V, F = meshes.icosphere(5)
+    k, Q = 17.0, 7
+    m = mf.Mesh(F, V.shape[0])
+    lo, hi = mf.r_range(m, V, Q)
+    T = mf.build_tables(k, lo, hi, 1e-5)
+    E = m.n_edges
+    Z1 = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+    Z2 = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+    say("triangle-block fill")
+    mf.fill_Z(m, V, k, Q, "table", T, out=Z1)
+    say("edge-block fill (one-item batch)")
+    b = mf.Batch([(m, V, k, T, Z2)], Q, "table")
+    b.fill()
+    mf.sync_status(m)
+    d = float(torch.linalg.norm(Z1 - Z2) / torch.linalg.norm(Z2))
+    say("  relative difference", d)
+    assert d <= 3e-7
