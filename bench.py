@@ -502,6 +502,11 @@ def main():
         mf.sync_status(mesh)
         return wall / steps, np.array(fill_ms)
 
+    # tile-shape tuner: times the table-fill kernels on this fill, keeps the fastest
+    lo0, hi0 = mf.r_range(mesh, Vd, Q)
+    _, tune_choice, tune_name, tune_ms = mf.tune_fill(mesh, Vd, k, Q, "table",
+                                                      mf.build_tables(k, lo0, hi0, args.tol), out=Z)
+    log(f"tuner: {tune_name} ({tune_ms} ms)")
     # uniform 1 % sample of the matrix for the parity of the timed fills
     flat = np.sort(np.random.default_rng(2).choice(E * E, size=E * E // 100, replace=False))
     flat_d = torch.tensor(flat, device="cuda")
@@ -531,6 +536,10 @@ def main():
             "triangles": T_, "unknowns": E, "k": k, "quad_order": Q, "tol": args.tol,
             "green_table_samples": T.n_green, "green_table_buckets": T.m_green,
             "exp_table_samples": T.n_exp,
+            "fill_kernel": tune_name,
+            "tuner_ms_tb1024_tb512_eb1024": tune_ms,
+            "triangle_block_plan": dict(zip(("blocks", "tiles", "cut_edges", "rounds"),
+                                            mesh.tb_plan())),
         },
         "green_evals_per_s": evals / s_table,
         "table_fill_only": {

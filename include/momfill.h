@@ -200,6 +200,29 @@ int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_orde
               const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
               hipStream_t stream);
 
+/* ---- tuner ---------------------------------------------------------------
+ * A table-mode fill can run on three kernels: 0, the triangle-block tiling
+ * (mf_mesh_tb_plan) with 1024 threads per workgroup (16 waves, one source
+ * triangle per wave and round); 1, the same tiling with 512 threads (8 waves,
+ * two source triangles per wave and round, twice the registers per lane);
+ * 2, the edge-block tiling (mf_mesh_plan), which repeats the pairs its blocks
+ * share but needs no cut-edge fix-up.  mf_fill_tune runs the fill of its
+ * arguments (those of mf_fill_Z, MF_PART_ flags excluded) once per kernel to
+ * warm up and once timed with HIP events, keeps the fastest for later
+ * mf_fill_Z calls on this mesh and records it under (triangles, edges,
+ * rule, mode, output type, table placement) for the process and, when the
+ * environment variable MOMFILL_TUNE_CACHE names a file, in that file, so that
+ * later processes take the choice without timing.  *choice receives the
+ * kernel; ms (3 floats, may be NULL) the timings in milliseconds, zeros when
+ * the cache answered.  Z holds the fill when the call returns (synchronous).
+ * Direct mode has one kernel (choice 2, no timing).  mf_fill_Z on a mesh that
+ * was not tuned takes the cached choice for its key, else kernel 0. */
+int mf_fill_tune(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order, int mode,
+                 const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
+                 hipStream_t stream, int32_t *choice, float *ms);
+/* Description of a kernel choice (static string). */
+const char *mf_fill_choice_name(int32_t choice);
+
 /* ---- MFIE fill (Section IV-B: the K operator beside the EFIE) -----------
  * Z_dev receives the MFIE matrix of the closed PEC surface, tested with the
  * RWG functions themselves (n the unit normal (x1 - x0) x (x2 - x0) of each
@@ -280,8 +303,9 @@ int mf_batch_fill(mf_batch *batch, hipStream_t stream);
  * threads per workgroup (2, 3 or 4 waves per SIMD, trading each lane's
  * register budget against the latency hiding of the table gathers), keeping
  * the fastest for the batch; the choice is cached per (quad_order, mode,
- * table placement, z_dtype) for the life of the process, so later batches of
- * the same kind skip the timing.  The outputs hold the batch's result when
+ * table placement, z_dtype) for the process and in the MOMFILL_TUNE_CACHE
+ * file when it is set (as for mf_fill_tune), so later batches of the same
+ * kind skip the timing.  The outputs hold the batch's result when
  * mf_batch_create returns.  mf_batch_info reports the choice (*threads) and
  * the three timings in milliseconds (tune_ms3, zeros when the cache
  * answered); either pointer may be NULL. */

@@ -222,6 +222,23 @@ def fill_Z(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table", tables
     return out
 
 
+def tune_fill(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table",
+              tables: Tables = None, dtype=torch.complex64, out: torch.Tensor = None):
+    """Times the kernels a fill of these arguments can run on, keeps the
+    fastest for this mesh (and in the MOMFILL_TUNE_CACHE file when set).
+    Returns (Z, choice, description, [ms per kernel]); Z holds the fill."""
+    Vd = _vertices(V)
+    Z, zt = _z_out(mesh, dtype, out)
+    ch = C.c_int32()
+    ms = (C.c_float * 3)()
+    check(lib().mf_fill_tune(mesh.device_handle, C.c_void_p(Vd.data_ptr()), float(k),
+                             int(quad_order), MODES[mode],
+                             tables.handle if tables is not None else None,
+                             C.c_void_p(Z.data_ptr()), zt, Z.stride(0), _stream(), C.byref(ch),
+                             ms))
+    return Z, ch.value, lib().mf_fill_choice_name(ch.value).decode(), [float(x) for x in ms]
+
+
 def fill_mfie(mesh: Mesh, V, k: float, quad_order: int, mode: str = "table",
               tables: Tables = None, dtype=torch.complex64,
               out: torch.Tensor = None) -> torch.Tensor:

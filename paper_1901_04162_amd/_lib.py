@@ -30,6 +30,7 @@ EXPORTS = [
     "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
     "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
     "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static", "mf_mesh_tb_plan",
+    "mf_fill_tune", "mf_fill_choice_name",
 ]
 
 
@@ -100,6 +101,10 @@ def lib():
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.mf_r_range.argtypes = [vp, vp, C.c_int, dp, dp, vp]
         L.mf_r_range_static.argtypes = [vp, vp, C.c_int, dp, dp, vp]
+        L.mf_fill_tune.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, vp, vp, C.c_int,
+                                   C.c_int64, vp, ip, C.POINTER(C.c_float)]
+        L.mf_fill_choice_name.argtypes = [C.c_int32]
+        L.mf_fill_choice_name.restype = C.c_char_p
         L.mf_build_tables.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, vp,
                                       C.c_size_t, C.POINTER(vp), vp]
         L.mf_tables_destroy.argtypes = [vp]

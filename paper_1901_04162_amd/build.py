@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmomfill.so")
 SOURCES = ["api.cpp", "geometry.hip", "tables.hip", "fill.hip", "backward.hip", "scatter.hip",
-           "mfie.hip", "angular.hip"]
+           "mfie.hip", "angular.hip", "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -995,9 +995,7 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
 // the non-owner halves; k_cut_rows and k_cut_cols add them in afterwards.
 constexpr int kTBStride = 2 * kTBEdges + 1;  // odd: rows fall in different banks
 constexpr int kTBAccFloats = kTBEdges * kTBStride;
-constexpr int kTBThreads = 1024;
-
-template <int Q, typename ZT, bool kLDS>
+template <int Q, typename ZT, bool kLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tb_pos,
@@ -1163,7 +1161,7 @@ __device__ __forceinline__ void fill_tile_tb(
   __syncthreads();
 }
 
-template <int Q, bool kLDS, typename ZT>
+template <int Q, bool kLDS, typename ZT, int kTBThreads>
 __global__ __launch_bounds__(kTBThreads)
 __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_fill_tb(
     FillItem S, FillRule W, int ntiles) {
@@ -1172,7 +1170,7 @@ __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_
   const TabPtrs tab = load_table<kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
   float rlo = INFINITY, rhi = 0.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile_tb<Q, ZT, kLDS>(S, W, tab, acc, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order,
+    fill_tile_tb<Q, ZT, kLDS, kTBThreads>(S, W, tab, acc, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order,
                               S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
   if (rlo < S.lo_ok || rhi > S.hi_ok) atomicOr(S.status, 1);
 }
@@ -1518,8 +1516,6 @@ int fill_launch_run(FillLaunch *L, hipStream_t s) { return dispatch(*L, false, s
 // placement and output type in this process.
 int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads) {
   static const int kCand[3] = {512, 768, 1024};
-  static std::mutex mu;
-  static std::map<std::tuple<int, int, int, int>, int> cache;
   if (ms3)
     for (int i = 0; i < 3; ++i) ms3[i] = 0.0f;
   if (L->n < 2 || L->op != MF_OP_EFIE || L->sparse) {  // single fills keep the defaults
@@ -1529,12 +1525,13 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
                                                    : fill_threads<MF_MODE_TABLE>());
     return MF_OK;
   }
-  const auto key = std::make_tuple(L->nq, L->base, (int)L->lds_tab, L->z_dtype);
+  const std::string key = "batch q=" + std::to_string(L->nq) + " mode=" + std::to_string(L->base) +
+                          " ldstable=" + std::to_string((int)L->lds_tab) +
+                          " z=" + std::to_string(L->z_dtype);
   {
-    std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      L->threads = it->second;
+    int cached = 0;
+    if (tune_cache_get(key, &cached) && (cached == 512 || cached == 768 || cached == 1024)) {
+      L->threads = cached;
       L->grid = 0;
       if (threads) *threads = L->threads;
       return dispatch(*L, true, nullptr);
@@ -1572,10 +1569,7 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
   if (rc) return rc;
   L->threads = best;
   L->grid = 0;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    cache[key] = best;
-  }
+  tune_cache_put(key, best);
   if (threads) *threads = best;
   return dispatch(*L, true, nullptr);
 }
@@ -1603,10 +1597,10 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
   return rc;
 }
 
-template <int Q, bool kLDS, typename ZT>
+template <int Q, bool kLDS, typename ZT, int kTBThreads>
 static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
-  auto kern = k_fill_tb<Q, kLDS, ZT>;
+  auto kern = k_fill_tb<Q, kLDS, ZT, kTBThreads>;
   static std::once_flag once;
   static long long grid = 0;
   static hipError_t ge = hipSuccess;
@@ -1643,20 +1637,27 @@ static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t 
   return MF_OK;
 }
 
-template <bool kLDS, typename ZT>
+template <bool kLDS, typename ZT, int kTBThreads>
 static int launch_tb_q(mf_mesh *m, int nq, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
   switch (nq) {
-    case 3: return launch_tb_t<3, kLDS, ZT>(m, S, W, lds, s);
-    case 6: return launch_tb_t<6, kLDS, ZT>(m, S, W, lds, s);
-    default: return launch_tb_t<7, kLDS, ZT>(m, S, W, lds, s);
+    case 3: return launch_tb_t<3, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    case 6: return launch_tb_t<6, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    default: return launch_tb_t<7, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
   }
+}
+
+template <typename ZT, int kTBThreads>
+static int launch_tb_z(mf_mesh *m, int nq, bool in_lds, const FillItem &S, const FillRule &W,
+                       size_t lds, hipStream_t s) {
+  return in_lds ? launch_tb_q<true, ZT, kTBThreads>(m, nq, S, W, lds, s)
+                : launch_tb_q<false, ZT, kTBThreads>(m, nq, S, W, lds, s);
 }
 
 // Table-mode EFIE fill on the triangle-block plan (k_fill_tb and the cut-edge
 // fix-ups), one item.
 static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, const mf_tables *tab, void *Z,
-                          int z_dtype, int64_t ldz, hipStream_t s) {
+                          int z_dtype, int64_t ldz, hipStream_t s, int threads) {
   FillItem S = make_item(m, r, k, MF_MODE_TABLE, tab, Z, ldz, m->d_sing, 0);
   FillRule W;
   for (int i = 0; i < kMaxQ; ++i) W.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
@@ -1667,17 +1668,30 @@ static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, const mf_tables *
   const size_t tbytes = table_lds_bytes(tab);
   const bool in_lds = base + tbytes <= (size_t)maxlds;
   const size_t lds = in_lds ? base + tbytes : base;
-  if (z_dtype == MF_C64)
-    return in_lds ? launch_tb_q<true, float2>(m, r.nq, S, W, lds, s)
-                  : launch_tb_q<false, float2>(m, r.nq, S, W, lds, s);
-  return in_lds ? launch_tb_q<true, double2>(m, r.nq, S, W, lds, s)
-                : launch_tb_q<false, double2>(m, r.nq, S, W, lds, s);
+  if (threads == 512)
+    return z_dtype == MF_C64 ? launch_tb_z<float2, 512>(m, r.nq, in_lds, S, W, lds, s)
+                             : launch_tb_z<double2, 512>(m, r.nq, in_lds, S, W, lds, s);
+  return z_dtype == MF_C64 ? launch_tb_z<float2, 1024>(m, r.nq, in_lds, S, W, lds, s)
+                           : launch_tb_z<double2, 1024>(m, r.nq, in_lds, S, W, lds, s);
+}
+
+const char *fill_choice_name(int c) {
+  switch (c) {
+    case kFillTB1024: return "triangle blocks of 64, 1024 threads (16 waves, one source triangle per wave and round)";
+    case kFillTB512: return "triangle blocks of 64, 512 threads (8 waves, two source triangles per wave and round)";
+    case kFillEB1024: return "edge blocks of 80 edges / 64 triangles, 1024 threads";
+    default: return "unknown";
+  }
 }
 
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s) {
-  if (mode == MF_MODE_TABLE && m->tb_ok)
-    return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s);
+  if (mode == MF_MODE_TABLE && m->tb_ok) {
+    int c = m->fill_choice;
+    if (c < 0) c = cached_fill_choice(m, r.nq, mode, z_dtype, tab);
+    if (c == kFillTB512) return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s, 512);
+    if (c != kFillEB1024) return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s, 1024);
+  }
   FillLaunch *L = nullptr;
   const float *sing = m->d_sing;
   int rc = fill_launch_create(1, &m, &k, &tab, r, mode, &Z, z_dtype, &ldz, &sing, nullptr, &L);

@@ -138,6 +138,7 @@ struct mf_mesh {
   // triangles); its block edges are the owned edges (local index e - e0)
   // followed by the non-owner halves of cut edges owned by earlier blocks.
   bool tb_ok = false;
+  int fill_choice = -1;            // tuned kernel of table-mode single fills (-1: cache/default)
   int tb_nblk = 0, n_cut = 0;
   std::vector<int32_t> tb_t0, tb_e0;
   std::vector<int32_t> tb_nbe;       // block edges per block
@@ -205,6 +206,16 @@ int launch_singular(mf_mesh *m, const double *V, const Rule &r, double k, int pa
                     hipStream_t s, float *out = nullptr);
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s);
+// Kernels a table-mode single fill can run (the tuner's candidates).
+enum { kFillTB1024 = 0, kFillTB512 = 1, kFillEB1024 = 2, kFillChoices = 3 };
+const char *fill_choice_name(int c);
+// Tuning cache: per process, and in the file named by MOMFILL_TUNE_CACHE
+// when it is set (read once, appended to).  Keys are text.
+bool tune_cache_get(const std::string &key, int *value);
+void tune_cache_put(const std::string &key, int value);
+std::string fill_tune_key(const mf_mesh *m, int nq, int mode, int z_dtype, const mf_tables *tab);
+// The cached choice for this fill, or the default (kFillTB1024).
+int cached_fill_choice(const mf_mesh *m, int nq, int mode, int z_dtype, const mf_tables *tab);
 // MFIE: touching-pair blocks (FP64, one-way, with the identity term on the
 // self pairs) into m->d_sing; then the fill with mode | kModeMfie.
 int launch_singular_mfie(mf_mesh *m, const double *V, const Rule &r, double k, hipStream_t s);
