@@ -27,7 +27,7 @@ METRIC = "Z entries/s + Green evals/s, table vs direct-exp, at rel err ≤1e-5 v
 FLOPS_PER_EVAL = 40
 PEAK_FP32 = 157.3             # TFLOP/s, MI355X FP32 vector peak
 FILL_KERNEL_SRC = os.path.join(ROOT, "paper_1901_04162_amd", "csrc", "fill.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fill_table_ico5_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fill_tb_ico5_traffic.txt")
 
 
 def log(*a):
@@ -35,10 +35,11 @@ def log(*a):
 
 
 def _traffic():
-    """HBM bytes per fill launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+    """HBM bytes per launch of the tile kernel and of the cut-edge fix-up from
+    the committed counter summary, if it was taken on the current kernel
+    source; else (None, None)."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, None
     src = hashlib.sha256(open(FILL_KERNEL_SRC, "rb").read()).hexdigest()[:16]
     vals = {}
     for line in open(TRAFFIC_FILE):
@@ -46,11 +47,11 @@ def _traffic():
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("fill_source_sha256_16") != src:
-        return None
+        return None, None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]), float(vals["fixup_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 def _lscpu():
@@ -495,7 +496,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(steps):
             fn()
-            fill_ms.append(mf.timings(mesh))
+            fill_ms.append(mf.timings(mesh) + mf.fill_timings(mesh))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         mf.set_timing(False)
@@ -550,7 +551,9 @@ def main():
         "phases_ms": {"geometry": float(ph_table[:, 0].mean()),
                       "touching_pairs_fp64": float(ph_table[:, 1].mean()),
                       "regular_fill": float(ph_table[:, 2].mean()),
-                      "range_and_tables": float(s_table * 1e3 - ph_table.sum(1).mean())},
+                      "range_and_tables": float(s_table * 1e3 - ph_table[:, :3].sum(1).mean()),
+                      "regular_fill_tile_kernel": float(ph_table[:, 3].mean()),
+                      "regular_fill_cut_edge_fixup": float(ph_table[:, 4].mean())},
     }
     if not args.no_direct:
         s_direct, ph_direct = timed(step_direct, args.steps, args.warmup)
@@ -564,20 +567,33 @@ def main():
         }
         out["table_over_direct"] = s_direct / s_table
         out["table_over_direct_fill_only"] = float(ph_direct[:, 2].mean() / ph_table[:, 2].mean())
-    fill_s = float(ph_table[:, 2].mean()) * 1e-3
-    achieved = FLOPS_PER_EVAL * evals_alg / fill_s / 1e12
-    traffic = _traffic()
+    # roofline of the dominant kernel: the tile kernel of the regular fill
+    # (k_fill_tb on the triangle-block plan; the cut-edge fix-up after it is
+    # HBM-bound and reported beside it)
+    tile_s = float(ph_table[:, 3].mean()) * 1e-3
+    fix_s = float(ph_table[:, 4].mean()) * 1e-3
+    achieved = FLOPS_PER_EVAL * evals_alg / tile_s / 1e12
+    traffic, fix_traffic = _traffic()
+    tb = fix_s > 0.0
     out["roofline"] = {
         "bound": "alu",
-        "kernel": "k_fill (table mode)",
+        "kernel": "k_fill_tb (table mode, triangle blocks)" if tb else "k_fill (table mode, edge blocks)",
         "achieved": achieved,
         "peak": PEAK_FP32,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32,
-        "traffic": traffic,
+        "traffic": traffic if tb else None,
         "flops_per_launch": FLOPS_PER_EVAL * evals_alg,
-        "launch_ms": fill_s * 1e3,
+        "launch_ms": tile_s * 1e3,
     }
+    if tb:
+        out["cut_edge_fixup"] = {
+            "kernel": "k_cut_fix",
+            "ms": fix_s * 1e3,
+            "cut_edges": mesh.tb_plan()[2],
+            "hbm_bytes": fix_traffic,
+            "hbm_tb_per_s": fix_traffic / fix_s / 1e12 if fix_traffic else None,
+        }
     del Z, flat_d
     torch.cuda.empty_cache()
     if not args.no_mfie:

@@ -386,6 +386,10 @@ int mf_fill_Z_backward(mf_mesh *mesh, const double *vertices_dev, double k, int 
  * timed fill has run on the mesh. */
 void mf_set_timing(int on);
 int mf_mesh_timings(mf_mesh *mesh, float *ms3);
+/* The regular-fill phase of the last timed fill split in two: ms2[0] the
+ * tile kernel, ms2[1] the cut-edge fix-up of the triangle-block plan (0 when
+ * the fill ran on another kernel, then ms2[0] is the whole phase). */
+int mf_mesh_fill_timings(mf_mesh *mesh, float *ms2);
 
 /* Synchronises `stream` and returns a deferred device-side status of the
  * last fill on this mesh (MF_ERANGE) or MF_OK. */

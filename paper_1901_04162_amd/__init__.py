@@ -416,6 +416,14 @@ def timings(mesh: Mesh):
     return tuple(float(x) for x in ms)
 
 
+def fill_timings(mesh: Mesh):
+    """(tile kernel, cut-edge fix-up) milliseconds of the last timed fill's
+    regular phase (fix-up 0 when the fill had none)."""
+    ms = (C.c_float * 2)()
+    check(lib().mf_mesh_fill_timings(mesh.device_handle, ms))
+    return float(ms[0]), float(ms[1])
+
+
 def sync_status(mesh: Mesh):
     check(lib().mf_sync_status(mesh.device_handle, _stream()))
 

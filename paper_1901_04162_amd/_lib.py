@@ -30,7 +30,7 @@ EXPORTS = [
     "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
     "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
     "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static", "mf_mesh_tb_plan",
-    "mf_fill_tune", "mf_fill_choice_name",
+    "mf_fill_tune", "mf_fill_choice_name", "mf_mesh_fill_timings",
 ]
 
 
@@ -120,6 +120,7 @@ def lib():
         L.mf_set_timing.argtypes = [C.c_int]
         L.mf_set_timing.restype = None
         L.mf_mesh_timings.argtypes = [vp, C.POINTER(C.c_float)]
+        L.mf_mesh_fill_timings.argtypes = [vp, C.POINTER(C.c_float)]
         _lib = L
     return _lib
 

@@ -809,7 +809,11 @@ int mf_fill_Z(mf_mesh *m, const double *V, double k, int quad_order, int mode,
   if (timed) MF_HIP(hipEventRecord(m->ev[1], s));
   if ((rc = launch_singular(m, V, r, k, part, s))) return rc;
   if (timed) MF_HIP(hipEventRecord(m->ev[2], s));
-  if ((rc = launch_fill(m, r, k, mode, tab, Z, z_dtype, ldz, s))) return rc;
+  m->timing_now = timed;
+  m->split = false;
+  rc = launch_fill(m, r, k, mode, tab, Z, z_dtype, ldz, s);
+  m->timing_now = false;
+  if (rc) return rc;
   if (timed) MF_HIP(hipEventRecord(m->ev[3], s));
   m->timed = timed;
   return MF_OK;
@@ -1235,6 +1239,19 @@ int mf_mesh_timings(mf_mesh *m, float *ms3) {
   if (!m || !ms3 || !m->timed) return fail(MF_EINVAL, "mf_mesh_timings: no timed fill");
   MF_HIP(hipEventSynchronize(m->ev[3]));
   for (int i = 0; i < 3; ++i) MF_HIP(hipEventElapsedTime(&ms3[i], m->ev[i], m->ev[i + 1]));
+  return MF_OK;
+}
+
+int mf_mesh_fill_timings(mf_mesh *m, float *ms2) {
+  if (!m || !ms2 || !m->timed) return fail(MF_EINVAL, "mf_mesh_fill_timings: no timed fill");
+  MF_HIP(hipEventSynchronize(m->ev[3]));
+  if (!m->split) {
+    MF_HIP(hipEventElapsedTime(&ms2[0], m->ev[2], m->ev[3]));
+    ms2[1] = 0.0f;
+    return MF_OK;
+  }
+  MF_HIP(hipEventElapsedTime(&ms2[0], m->ev[2], m->ev[4]));
+  MF_HIP(hipEventElapsedTime(&ms2[1], m->ev[4], m->ev[3]));
   return MF_OK;
 }
 

@@ -1626,6 +1626,10 @@ static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t 
             Q, (int)kLDS, ntiles, g, lds, m->n_cut);
   hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(kTBThreads), lds, s, S, W, ntiles);
   MF_HIP(hipGetLastError());
+  if (m->timing_now) {
+    MF_HIP(hipEventRecord(m->ev[4], s));
+    m->split = true;
+  }
   if (m->n_cut > 0) {
     const dim3 fg((unsigned)((m->ne + kFixTile - 1) / kFixTile),
                   (unsigned)((m->n_cut + kFixTile - 1) / kFixTile));

@@ -175,8 +175,11 @@ struct mf_mesh {
   float *d_side = nullptr;         // n_cut x (ne + n_cut) complex: cut-edge partial entries
   void *ws = nullptr;              // the caller's device workspace (mf_mesh_set_workspace)
   size_t ws_bytes = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool timed = false;
+  // phase events of a timed fill: ev[0..3] around geometry, touching pairs
+  // and the regular fill; ev[4] inside the regular fill, between the tile
+  // kernel and the cut-edge fix-up (recorded when `split` is set)
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timed = false, timing_now = false, split = false;
 };
 
 namespace mf {
