@@ -222,6 +222,12 @@ int mf_fill_tune(mf_mesh *mesh, const double *vertices_dev, double k, int quad_o
                  hipStream_t stream, int32_t *choice, float *ms);
 /* Description of a kernel choice (static string). */
 const char *mf_fill_choice_name(int32_t choice);
+/* Pins the kernel of this mesh's table-mode mf_fill_Z calls to `choice`
+ * (0, 1 or 2 as above; for callers that tune by their own measurements or
+ * reproduce a given kernel), or with -1 returns to the cached choice or
+ * kernel 0.  A mesh without a triangle-block plan runs kernel 2 whatever is
+ * pinned.  MF_EINVAL for another value. */
+int mf_mesh_set_fill_choice(mf_mesh *mesh, int32_t choice);
 
 /* ---- MFIE fill (Section IV-B: the K operator beside the EFIE) -----------
  * Z_dev receives the MFIE matrix of the closed PEC surface, tested with the

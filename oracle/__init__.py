@@ -13,7 +13,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# MOMFILL_ORACLE_SO names another build of oracle.c (the sanitizer test loads
+# an ASan/UBSan build this way); default: the in-tree liboracle.so.
+_SO_TREE = os.path.join(_HERE, "liboracle.so")
+_SO = os.environ.get("MOMFILL_ORACLE_SO") or _SO_TREE
 
 EXP, GREEN = 0, 1
 TABLE, DIRECT = 0, 1
@@ -27,12 +30,12 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-Wall", "-Wextra",
-        os.path.join(_HERE, "oracle.c"), "-o", _SO, "-lm",
+        os.path.join(_HERE, "oracle.c"), "-o", _SO_TREE, "-lm",
     ]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return _SO
+    return _SO_TREE
 
 
 _lib = None

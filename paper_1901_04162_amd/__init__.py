@@ -75,6 +75,11 @@ class Mesh:
         check(lib().mf_mesh_tb_plan(self._h, C.byref(nb), C.byref(nt), C.byref(nc), C.byref(mr)))
         return nb.value, nt.value, nc.value, mr.value
 
+    def set_fill_choice(self, choice: int):
+        """Pins the kernel of table-mode fills (0, 1, 2: see
+        mf_fill_choice_name; -1: cached choice or kernel 0)."""
+        check(lib().mf_mesh_set_fill_choice(self._h, int(choice)))
+
     def plan(self):
         """(blocks, tiles, largest triangles per block) of the regular fill."""
         nb, mt = C.c_int32(), C.c_int32()

@@ -12,7 +12,9 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime first)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SO_PATH = os.path.join(_HERE, "libmomfill.so")
+# MOMFILL_SO names another build of the same sources (the host-sanitizer test
+# loads one this way); default: the in-tree library.
+SO_PATH = os.environ.get("MOMFILL_SO") or os.path.join(_HERE, "libmomfill.so")
 
 MF_OK, MF_EINVAL, MF_EMESH, MF_ERANGE, MF_ENOMEM, MF_EHIP, MF_ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 MF_MODE_TABLE, MF_MODE_DIRECT = 0, 1
@@ -30,7 +32,7 @@ EXPORTS = [
     "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
     "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
     "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static", "mf_mesh_tb_plan",
-    "mf_fill_tune", "mf_fill_choice_name", "mf_mesh_fill_timings",
+    "mf_fill_tune", "mf_fill_choice_name", "mf_mesh_fill_timings", "mf_mesh_set_fill_choice",
 ]
 
 
@@ -121,6 +123,7 @@ def lib():
         L.mf_set_timing.restype = None
         L.mf_mesh_timings.argtypes = [vp, C.POINTER(C.c_float)]
         L.mf_mesh_fill_timings.argtypes = [vp, C.POINTER(C.c_float)]
+        L.mf_mesh_set_fill_choice.argtypes = [vp, C.c_int32]
         _lib = L
     return _lib
 

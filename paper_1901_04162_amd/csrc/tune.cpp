@@ -112,8 +112,7 @@ int mf_fill_tune(mf_mesh *m, const double *V, double k, int quad_order, int mode
     for (int c = 0; c < kFillChoices; ++c) ms[c] = 0.0f;
   // direct mode (and meshes without a triangle-block plan) have one kernel
   if (mode != MF_MODE_TABLE || !m->tb_ok) {
-    m->fill_choice = kFillEB1024;
-    *choice = kFillEB1024;
+    *choice = kFillEB1024;  // the table-mode choice of the mesh stays as it is
     return MF_OK;
   }
   const std::string key = fill_tune_key(m, r.nq, mode, z_dtype, tab);
@@ -165,5 +164,13 @@ int mf_fill_tune(mf_mesh *m, const double *V, double k, int quad_order, int mode
 }
 
 const char *mf_fill_choice_name(int32_t choice) { return fill_choice_name(choice); }
+
+int mf_mesh_set_fill_choice(mf_mesh *m, int32_t choice) {
+  if (!m) return (set_error("mf_mesh_set_fill_choice: null mesh"), MF_EINVAL);
+  if (choice < -1 || choice >= kFillChoices)
+    return (set_error("mf_mesh_set_fill_choice: choice must be -1, 0, 1 or 2"), MF_EINVAL);
+  m->fill_choice = choice;
+  return MF_OK;
+}
 
 }  // extern "C"

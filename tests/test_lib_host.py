@@ -99,6 +99,20 @@ def test_argument_errors_without_gpu():
     assert b"ldz" in L.mf_last_error() or L.mf_last_error()
 
 
+def test_fill_choice_pinning_without_gpu():
+    import paper_1901_04162_amd as mf
+
+    V, F = meshes.icosphere(2)
+    m = mf.Mesh(F, V.shape[0])
+    for c in (-1, 0, 1, 2):
+        m.set_fill_choice(c)
+    for c in (-2, 3):
+        with pytest.raises(mf.MomfillError) as e:
+            m.set_fill_choice(c)
+        assert e.value.code == mf._lib.MF_EINVAL
+    assert mf.lib().mf_mesh_set_fill_choice(None, 0) == mf._lib.MF_EINVAL
+
+
 @pytest.mark.parametrize("s", [2, 4])
 def test_tile_plan_shape(s):
     import paper_1901_04162_amd as mf
