@@ -176,11 +176,15 @@ def adjoint_timing(mf, steps):
             mf.fill_Z_backward(m, Vd, k, Q, mode, T, W)
         torch.cuda.synchronize()
         out[f"{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        mf.fill_Z(m, Vd, k, Q, "table", T)
-    torch.cuda.synchronize()
-    out["forward_table_ms"] = (time.perf_counter() - t0) / steps * 1e3
+    for mode in ("table", "direct"):
+        mf.fill_Z(m, Vd, k, Q, mode, T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mf.fill_Z(m, Vd, k, Q, mode, T)
+        torch.cuda.synchronize()
+        out[f"forward_{mode}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+        out[f"{mode}_over_forward"] = out[f"{mode}_ms"] / out[f"forward_{mode}_ms"]
     return out
 
 

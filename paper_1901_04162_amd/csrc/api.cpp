@@ -170,8 +170,12 @@ static void build_touching(mf_mesh *m) {
       m->touch_rev[s] = (int32_t)(std::lower_bound(b, e, p) - m->touch_q.begin());
     }
   m->touch_p.resize(m->touch_q.size());
+  m->touch_u.clear();
   for (int p = 0; p < nt; ++p)
-    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) m->touch_p[s] = p;
+    for (int32_t s = m->touch_off[p]; s < m->touch_off[p + 1]; ++s) {
+      m->touch_p[s] = p;
+      if (p <= m->touch_q[s]) m->touch_u.push_back(s);
+    }
 }
 
 // Row/column blocks of the tiled fill: runs of consecutive edges (so every
@@ -458,6 +462,7 @@ static bool carve_mesh(const mf_mesh *m, Arena &A, mf_mesh *d) {
          MF_TAKE(d_edges, m->edges.size()) && MF_TAKE(d_tsign, m->tsign.size()) &&
          MF_TAKE(d_touch_off, m->touch_off.size()) && MF_TAKE(d_touch_q, m->touch_q.size()) &&
          MF_TAKE(d_touch_rev, m->touch_rev.size()) && MF_TAKE(d_touch_p, m->touch_p.size()) &&
+         MF_TAKE(d_touch_u, m->touch_u.size()) &&
          MF_TAKE(d_blk_off, m->blk_off.size()) && MF_TAKE(d_blk_tri, m->blk_tri.size()) &&
          MF_TAKE(d_blk_pos, m->blk_pos.size()) && MF_TAKE(d_tiles, m->tiles.size()) &&
          MF_TAKE(d_blk_e0, m->blk_e0.size()) && MF_TAKE(d_blk_rt, m->blk_rt.size()) &&
@@ -630,7 +635,8 @@ int mf_mesh_set_workspace(mf_mesh *m, void *ws, size_t bytes, hipStream_t s) {
       (rc = upload(m->d_touch_off, m->touch_off, s)) ||
       (rc = upload(m->d_touch_q, m->touch_q, s)) ||
       (rc = upload(m->d_touch_rev, m->touch_rev, s)) ||
-      (rc = upload(m->d_touch_p, m->touch_p, s)) || (rc = upload(m->d_blk_off, m->blk_off, s)) ||
+      (rc = upload(m->d_touch_p, m->touch_p, s)) || (rc = upload(m->d_touch_u, m->touch_u, s)) ||
+      (rc = upload(m->d_blk_off, m->blk_off, s)) ||
       (rc = upload(m->d_blk_tri, m->blk_tri, s)) || (rc = upload(m->d_blk_pos, m->blk_pos, s)) ||
       (rc = upload(m->d_tiles, m->tiles, s)) || (rc = upload(m->d_blk_e0, m->blk_e0, s)) ||
       (rc = upload(m->d_blk_rt, m->blk_rt, s)) || (rc = upload(m->d_tb_t0, m->tb_t0, s)) ||

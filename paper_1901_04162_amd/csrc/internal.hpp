@@ -123,6 +123,7 @@ struct mf_mesh {
   std::vector<int32_t> touch_q;
   std::vector<int32_t> touch_rev;  // index of (q,p) for pair (p,q)
   std::vector<int32_t> touch_p;    // p of each touching pair
+  std::vector<int32_t> touch_u;    // the pairs with p <= q (each unordered pair once)
   std::vector<int32_t> blk_e0;     // nblk+1: first edge of each block
   std::vector<int32_t> blk_off;    // nblk+1: triangles needed by each edge block
   std::vector<int32_t> blk_tri;
@@ -157,6 +158,7 @@ struct mf_mesh {
   int8_t *d_tsign = nullptr;
   int32_t *d_touch_off = nullptr, *d_touch_q = nullptr, *d_touch_rev = nullptr;
   int32_t *d_touch_p = nullptr;    // p of each touching pair
+  int32_t *d_touch_u = nullptr;    // touch_u
   int32_t *d_blk_off = nullptr, *d_blk_tri = nullptr, *d_blk_pos = nullptr;
   int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr, *d_blk_rt = nullptr;
   float *d_elen = nullptr;         // ne edge lengths (FP32, from the FP64 vertices)

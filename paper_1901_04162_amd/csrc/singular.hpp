@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "dual.hpp"
 #include "internal.hpp"
 
 namespace mf {
@@ -19,48 +20,50 @@ struct RuleArg {
 // from the edge formulas of Wilton et al. (IEEE TAP 32(3), 1984) and Graglia
 // (IEEE TAP 41(10), 1993): project r onto the plane, sum one logarithm per
 // edge and, off the plane, one arctangent pair per edge.
-__device__ inline void tri_potentials(const double x[3][3], const double *r, double *S, double *Vv) {
-  const double e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
-  const double e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
-  double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                 e1[0] * e2[1] - e1[1] * e2[0]};
-  const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+// T is double, or Dual<N> for the adjoint's derivatives (dual.hpp).
+template <class T>
+__device__ inline void tri_potentials(const T x[3][3], const T *r, T *S, T *Vv) {
+  const T e1[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+  const T e2[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+  T n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+            e1[0] * e2[1] - e1[1] * e2[0]};
+  const T nn = d_sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   n[0] /= nn;
   n[1] /= nn;
   n[2] /= nn;
-  const double h = n[0] * (r[0] - x[0][0]) + n[1] * (r[1] - x[0][1]) + n[2] * (r[2] - x[0][2]);
-  const double ah = fabs(h);
-  const double pr[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
-  double s = 0.0, vin[3] = {0.0, 0.0, 0.0};
+  const T h = n[0] * (r[0] - x[0][0]) + n[1] * (r[1] - x[0][1]) + n[2] * (r[2] - x[0][2]);
+  const T ah = d_fabs(h);
+  const T pr[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
+  T s = 0.0, vin[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 3; ++i) {
-    const double *a = x[i], *b = x[(i + 1) % 3];
-    double t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-    const double len = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    const T *a = x[i], *b = x[(i + 1) % 3];
+    T t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const T len = d_sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     t[0] /= len;
     t[1] /= len;
     t[2] /= len;
-    const double m[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2],
-                         t[0] * n[1] - t[1] * n[0]};
-    const double ap[3] = {a[0] - pr[0], a[1] - pr[1], a[2] - pr[2]};
-    const double bp[3] = {b[0] - pr[0], b[1] - pr[1], b[2] - pr[2]};
-    const double sa = ap[0] * t[0] + ap[1] * t[1] + ap[2] * t[2];
-    const double sb = bp[0] * t[0] + bp[1] * t[1] + bp[2] * t[2];
-    const double p0 = ap[0] * m[0] + ap[1] * m[1] + ap[2] * m[2];
-    const double q2 = p0 * p0 + h * h;
-    const double Ra = sqrt((r[0] - a[0]) * (r[0] - a[0]) + (r[1] - a[1]) * (r[1] - a[1]) +
-                           (r[2] - a[2]) * (r[2] - a[2]));
-    const double Rb = sqrt((r[0] - b[0]) * (r[0] - b[0]) + (r[1] - b[1]) * (r[1] - b[1]) +
-                           (r[2] - b[2]) * (r[2] - b[2]));
-    double lg = 0.0, at = 0.0;
-    if (q2 > 0.0) {
+    const T m[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2],
+                    t[0] * n[1] - t[1] * n[0]};
+    const T ap[3] = {a[0] - pr[0], a[1] - pr[1], a[2] - pr[2]};
+    const T bp[3] = {b[0] - pr[0], b[1] - pr[1], b[2] - pr[2]};
+    const T sa = ap[0] * t[0] + ap[1] * t[1] + ap[2] * t[2];
+    const T sb = bp[0] * t[0] + bp[1] * t[1] + bp[2] * t[2];
+    const T p0 = ap[0] * m[0] + ap[1] * m[1] + ap[2] * m[2];
+    const T q2 = p0 * p0 + h * h;
+    const T Ra = d_sqrt((r[0] - a[0]) * (r[0] - a[0]) + (r[1] - a[1]) * (r[1] - a[1]) +
+                        (r[2] - a[2]) * (r[2] - a[2]));
+    const T Rb = d_sqrt((r[0] - b[0]) * (r[0] - b[0]) + (r[1] - b[1]) * (r[1] - b[1]) +
+                        (r[2] - b[2]) * (r[2] - b[2]));
+    T lg = 0.0, at = 0.0;
+    if (val(q2) > 0.0) {
       // log((Rb + sb)/(Ra + sa)); R + s = q2/(R - s) when s < 0 avoids cancellation
-      const double fb = sb >= 0.0 ? Rb + sb : q2 / (Rb - sb);
-      const double fa = sa >= 0.0 ? Ra + sa : q2 / (Ra - sa);
-      lg = log(fb / fa);
-      at = atan(p0 * sb / (q2 + ah * Rb)) - atan(p0 * sa / (q2 + ah * Ra));
+      const T fb = val(sb) >= 0.0 ? Rb + sb : q2 / (Rb - sb);
+      const T fa = val(sa) >= 0.0 ? Ra + sa : q2 / (Ra - sa);
+      lg = d_log(fb / fa);
+      at = d_atan(p0 * sb / (q2 + ah * Rb)) - d_atan(p0 * sa / (q2 + ah * Ra));
     }
     s += p0 * lg - ah * at;
-    const double cv = 0.5 * (q2 * lg + sb * Rb - sa * Ra);
+    const T cv = 0.5 * (q2 * lg + sb * Rb - sa * Ra);
     vin[0] += cv * m[0];
     vin[1] += cv * m[1];
     vin[2] += cv * m[2];
@@ -134,17 +137,17 @@ __device__ inline void tri_field(const double x[3][3], const double *r, double *
 }
 
 // (exp(-jkR) - 1)/R, with its Taylor series for kR < 1e-4.
-__device__ inline void ghat(double k, double R, double &re, double &im) {
-  const double x = k * R;
-  if (x < 1e-4) {
+template <class T>
+__device__ inline void ghat(T k, T R, T &re, T &im) {
+  const T x = k * R;
+  if (val(x) < 1e-4) {
     re = -0.5 * k * k * R;
     im = -k + k * k * k * R * R / 6.0;
     return;
   }
-  double sh, ch, s1, c1;
-  sincos(0.5 * x, &sh, &ch);
-  s1 = 2.0 * sh * ch;
-  (void)c1;
+  T sh, ch;
+  d_sincos(0.5 * x, &sh, &ch);
+  const T s1 = 2.0 * sh * ch;
   re = -2.0 * sh * sh / R;
   im = -s1 / R;
 }
@@ -160,32 +163,31 @@ __device__ inline void ghat(double k, double R, double &re, double &im) {
 // oneway_terms hands every term w_i [...] of the sum to sink(a, b, re, im)
 // and returns A_q; the caller applies the 1/A_q.  Only the outer points
 // i_begin <= i < i_end are taken (all of them by default).
-template <class Sink>
-__device__ inline double oneway_terms(const double xp[3][3], const double xq[3][3],
-                                      const RuleArg &R, double k, int part, Sink &&sink,
-                                      int i_begin = 0, int i_end = kMaxQ) {
-  const double e1[3] = {xq[1][0] - xq[0][0], xq[1][1] - xq[0][1], xq[1][2] - xq[0][2]};
-  const double e2[3] = {xq[2][0] - xq[0][0], xq[2][1] - xq[0][1], xq[2][2] - xq[0][2]};
-  const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
-               cz = e1[0] * e2[1] - e1[1] * e2[0];
-  const double Aq = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
-  const double ik2 = 1.0 / (k * k);
+template <class T, class Sink>
+__device__ inline T oneway_terms(const T xp[3][3], const T xq[3][3], const RuleArg &R, T k,
+                                 int part, Sink &&sink, int i_begin = 0, int i_end = kMaxQ) {
+  const T e1[3] = {xq[1][0] - xq[0][0], xq[1][1] - xq[0][1], xq[1][2] - xq[0][2]};
+  const T e2[3] = {xq[2][0] - xq[0][0], xq[2][1] - xq[0][1], xq[2][2] - xq[0][2]};
+  const T cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+          cz = e1[0] * e2[1] - e1[1] * e2[0];
+  const T Aq = 0.5 * d_sqrt(cx * cx + cy * cy + cz * cz);
+  const T ik2 = 1.0 / (k * k);
   for (int i = i_begin; i < R.nq && i < i_end; ++i) {
-    double ri[3];
+    T ri[3];
     for (int c = 0; c < 3; ++c)
       ri[c] = R.b[i][0] * xp[0][c] + R.b[i][1] * xp[1][c] + R.b[i][2] * xp[2][c];
-    double S, Vv[3];
+    T S, Vv[3];
     tri_potentials(xq, ri, &S, Vv);
-    double m1r[3] = {0, 0, 0}, m1i[3] = {0, 0, 0};  // Aq sum_j w_j r_j ghat
-    double g0r = 0.0, g0i = 0.0;                    // Aq sum_j w_j ghat
+    T m1r[3] = {0.0, 0.0, 0.0}, m1i[3] = {0.0, 0.0, 0.0};  // Aq sum_j w_j r_j ghat
+    T g0r = 0.0, g0i = 0.0;                                // Aq sum_j w_j ghat
     for (int j = 0; j < R.nq; ++j) {
-      double rq[3];
+      T rq[3];
       for (int c = 0; c < 3; ++c)
         rq[c] = R.b[j][0] * xq[0][c] + R.b[j][1] * xq[1][c] + R.b[j][2] * xq[2][c];
-      const double d0 = ri[0] - rq[0], d1 = ri[1] - rq[1], d2 = ri[2] - rq[2];
-      double gr, gi;
-      ghat(k, sqrt(d0 * d0 + d1 * d1 + d2 * d2), gr, gi);
-      const double wa = Aq * R.w[j];
+      const T d0 = ri[0] - rq[0], d1 = ri[1] - rq[1], d2 = ri[2] - rq[2];
+      T gr, gi;
+      ghat(k, d_sqrt(d0 * d0 + d1 * d1 + d2 * d2), gr, gi);
+      const T wa = Aq * R.w[j];
       g0r += wa * gr;
       g0i += wa * gi;
       for (int c = 0; c < 3; ++c) {
@@ -193,16 +195,16 @@ __device__ inline double oneway_terms(const double xp[3][3], const double xq[3][
         m1i[c] += wa * rq[c] * gi;
       }
     }
-    const double phr = S + g0r, phi = g0i;
+    const T phr = S + g0r, phi = g0i;
     for (int b = 0; b < 3; ++b) {
-      double psr[3], psi[3];
+      T psr[3], psi[3];
       for (int c = 0; c < 3; ++c) {
         psr[c] = Vv[c] + (ri[c] - xq[b][c]) * S + m1r[c] - xq[b][c] * g0r;
         psi[c] = m1i[c] - xq[b][c] * g0i;
       }
       for (int a = 0; a < 3; ++a) {
-        const double ua[3] = {ri[0] - xp[a][0], ri[1] - xp[a][1], ri[2] - xp[a][2]};
-        double br = 0.0, bi = 0.0;
+        const T ua[3] = {ri[0] - xp[a][0], ri[1] - xp[a][1], ri[2] - xp[a][2]};
+        T br = 0.0, bi = 0.0;
         if (!(part & MF_PART_PHI)) {
           br += 0.25 * (ua[0] * psr[0] + ua[1] * psr[1] + ua[2] * psr[2]);
           bi += 0.25 * (ua[0] * psi[0] + ua[1] * psi[1] + ua[2] * psi[2]);
