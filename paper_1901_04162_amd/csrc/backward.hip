@@ -56,10 +56,12 @@ struct BwdScalars {
   float k, ik2, pref;  // pref = k eta0 / (4 pi)
   float w[kMaxQ];
   float bary[kMaxQ][3];
-  // Green table (cubic), global memory
+  // Green table (cubic): one-sample bucket records (lookup.hpp) and the
+  // interval coefficients, (c0, c1) then (c2, c3), gn intervals
   const int4 *gl;
   const float4 *g01, *g23;
   float ginv, gbias, gmax;
+  int gn;
   long long ldz;
 };
 
@@ -90,6 +92,7 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
                                          const float (&pal)[3][3], const float (&psig)[3],
                                          const double *pcd, const float *__restrict__ qr,
                                          int prow, int qcol, const float2 *Wt, int ldw,
+                                         const float4 *g01, const float4 *g23,
                                          float (&Gv)[3][3], float (&Gl)[3], float (&gq)[9],
                                          float &gk) {
   float beta[3][3], qsig[3];
@@ -141,6 +144,9 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
   for (int i = 0; i < Q; ++i) {
     const float prho[3] = {pr[kRecRho + 3 * i], pr[kRecRho + 3 * i + 1], pr[kRecRho + 3 * i + 2]};
     const float ax = prho[0] + lx, ay = prho[1] + ly, az = prho[2] + lz;
+    // the j sums of this test point: sum w w g (t0) and sum w w g rho'_j (t1);
+    // sum hi (r_i - r_j) (Fp)
+    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
     float Fp[3] = {0.f, 0.f, 0.f};
     // B_ij pieces that do not depend on j
     const float bpr =
@@ -153,20 +159,40 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
       tq_r[c] = 0.25f * fmaf(O_r, prho[c], Qv_r[c]);
       tq_i[c] = 0.25f * fmaf(O_i, prho[c], Qv_i[c]);
     }
+    // table mode: the bucket records of every source point are gathered
+    // first, so that their latencies overlap
+    float Rj[Q], rij[Q];
+    int4 wj[Q];
+    if (MODE == MF_MODE_TABLE) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const float d0 = hx + (ax - qr[kRecRho + 3 * j]), d1 = hy + (ay - qr[kRecRho + 3 * j + 1]),
+                    d2 = hz + (az - qr[kRecRho + 3 * j + 2]);
+        const float R2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        rij[j] = __builtin_amdgcn_rsqf(R2);
+        Rj[j] = R2 * rij[j];
+        wj[j] = look_record(S.gl, look_bucket(Rj[j], S.ginv, S.gbias, S.gmax));
+      }
+    }
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const float rq0 = qr[kRecRho + 3 * j], rq1 = qr[kRecRho + 3 * j + 1],
                   rq2 = qr[kRecRho + 3 * j + 2];
       const float d0 = hx + (ax - rq0), d1 = hy + (ay - rq1), d2 = hz + (az - rq2);
-      const float R2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-      const float ri = __builtin_amdgcn_rsqf(R2);
-      const float R = R2 * ri;
-      float gr, gi, dgr, dgi, er, ei;  // g, dg/dR, exp(-jkR)
+      float ri, R;
+      if (MODE == MF_MODE_TABLE) {
+        ri = rij[j];
+        R = Rj[j];
+      } else {
+        const float R2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        ri = __builtin_amdgcn_rsqf(R2);
+        R = R2 * ri;
+      }
+      float gr, gi, dgr, dgi;  // g, dg/dR
       if (MODE == MF_MODE_TABLE) {
         float u;
-        const int ii =
-            look_interval(look_record(S.gl, look_bucket(R, S.ginv, S.gbias, S.gmax)), R, u);
-        const float4 A = S.g01[ii], B = S.g23[ii];
+        const int ii = look_interval1(wj[j], R, u);
+        const float4 A = g01[ii], B = g23[ii];
         // g = c0 + c1 u + c2 u^2 + c3 u^3, g' = c1 + 2 c2 u + 3 c3 u^2
         const float der = fmaf(3.0f * B.z, u, 2.0f * B.x);
         const float dei = fmaf(3.0f * B.w, u, 2.0f * B.y);
@@ -175,15 +201,11 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
         const float2 g = cubic(A, B, u);
         gr = g.x;
         gi = g.y;
-        er = R * gr;
-        ei = R * gi;
       } else {
         float sn, cs;
         sincosf(S.k * R, &sn, &cs);
-        er = cs;
-        ei = -sn;
-        gr = er * ri;
-        gi = ei * ri;
+        gr = cs * ri;
+        gi = -sn * ri;
         // dg/dR = -(jk + 1/R) g
         dgr = fmaf(S.k, gi, -ri * gr);
         dgi = fmaf(-S.k, gr, -ri * gi);
@@ -194,27 +216,34 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
       const float Br = fmaf(0.25f, fmaf(O_r, rr, qdot_r), bpr);
       const float Bi = fmaf(0.25f, fmaf(O_i, rr, qdot_i), bpi);
       const float ww = S.w[i] * S.w[j];
-      const float wri = ww * ri;
-      const float hi = wri * (dgr * Bi + dgi * Br);  // Im(w w g' B / R)
+      const float hi = (ww * ri) * (dgr * Bi + dgi * Br);  // Im(w w g' B / R)
       const float wgr = ww * gr, wgi = ww * gi;
       const float rq[3] = {rq0, rq1, rq2}, d[3] = {d0, d1, d2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float tpr = 0.25f * fmaf(O_r, rq[c], P_r[c]);
-        const float tpi = 0.25f * fmaf(O_i, rq[c], P_i[c]);
-        Fp[c] += fmaf(hi, d[c], fmaf(wgr, tpi, wgi * tpr));
-        Fq[j][c] += fmaf(-hi, d[c], fmaf(wgr, tq_i[c], wgi * tq_r[c]));
-        spr[c] = fmaf(wgr, prho[c], spr[c]);
-        spi[c] = fmaf(wgi, prho[c], spi[c]);
-        sqr_[c] = fmaf(wgr, rq[c], sqr_[c]);
-        sqi_[c] = fmaf(wgi, rq[c], sqi_[c]);
+        Fp[c] = fmaf(hi, d[c], Fp[c]);
+        Fq[j][c] = fmaf(-hi, d[c], fmaf(wgr, tq_i[c], fmaf(wgi, tq_r[c], Fq[j][c])));
+        t1r[c] = fmaf(wgr, rq[c], t1r[c]);
+        t1i[c] = fmaf(wgi, rq[c], t1i[c]);
       }
-      kg_i += wgr * Bi + wgi * Br;
-      ke_r += ww * (er * Br - ei * Bi);
-      s0r += wgr;
-      s0i += wgi;
-      srr = fmaf(wgr, rr, srr);
-      sri = fmaf(wgi, rr, sri);
+      t0r += wgr;
+      t0i += wgi;
+      // exp(-jkR) = R g
+      kg_i = fmaf(wgr, Bi, fmaf(wgi, Br, kg_i));
+      ke_r = fmaf(R, fmaf(wgr, Br, -wgi * Bi), ke_r);
+    }
+    // the moments, and the j sums of w w g (O rho'_j + P)/4 in Fp
+    s0r += t0r;
+    s0i += t0i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      spr[c] = fmaf(t0r, prho[c], spr[c]);
+      spi[c] = fmaf(t0i, prho[c], spi[c]);
+      sqr_[c] += t1r[c];
+      sqi_[c] += t1i[c];
+      srr = fmaf(prho[c], t1r[c], srr);
+      sri = fmaf(prho[c], t1i[c], sri);
+      Fp[c] += 0.25f * (fmaf(O_i, t1r[c], P_i[c] * t0r) + fmaf(O_r, t1i[c], P_r[c] * t0i));
     }
     // Re[c z] = -pref Im z, chained to the vertices through r_i's weights
 #pragma unroll
@@ -363,7 +392,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
         const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
         float gq[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // q vertex gradient
         if (!touching(pv0, pv1, pv2, qvi) && pv)
-          bwd_pair<Q, MODE>(S, pr, pal, psig, pcd, qr, prow, qcol, Wt, kBwdBM, Gv, Gl, gq, gk);
+          bwd_pair<Q, MODE>(S, pr, pal, psig, pcd, qr, prow, qcol, Wt, kBwdBM, S.g01, S.g23, Gv,
+                            Gl, gq, gk);
         // sum over lanes, one atomic per coordinate of q
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
@@ -390,17 +420,21 @@ __global__ __launch_bounds__(kBwdThreads) void k_bwd_regular(
 // weights Wt[r][c] (block edges of I by those of J, stride kTBEdges) come
 // from W through each block edge's global edge: owned edges e0 + r, then the
 // edges of the non-owner halves.  p's gradient is summed over the waves in
-// LDS before its atomics; q's over the lanes of its wave.
+// LDS (in the weights' space, once the pairs are done) before its atomics;
+// q's over the lanes of its wave.  With kLDS the Green table's coefficients
+// follow the weights in LDS.
 struct BwdTB {
   const int32_t *tiles, *t0, *e0, *nbe, *be_off, *be_cut, *pos, *cut_edge;
 };
 constexpr int kBwdTBWt = kTBEdges * kTBEdges;  // float2
+// Green intervals whose coefficients fit in LDS beside the weights
+constexpr int kBwdLdsCoef = (160 * 1024 - 8 * kBwdTBWt) / 32;
 
 __device__ __forceinline__ int block_edge(const BwdTB &B, int blk, int e0, int nown, int r) {
   return r < nown ? e0 + r : B.cut_edge[B.be_cut[B.be_off[blk] + r - nown]];
 }
 
-template <int Q, int MODE, typename ZT>
+template <int Q, int MODE, bool kLDS, typename ZT>
 __global__ __launch_bounds__(kBwdTBThreads) void k_bwd_tb(BwdScalars S, BwdTB B,
                                                           const float *__restrict__ rec,
                                                           const ZT *__restrict__ W,
@@ -409,7 +443,14 @@ __global__ __launch_bounds__(kBwdTBThreads) void k_bwd_tb(BwdScalars S, BwdTB B,
   constexpr int kWaves = kBwdTBThreads / 64;
   extern __shared__ float4 bsm4[];
   float2 *Wt = reinterpret_cast<float2 *>(bsm4);
-  float *red = reinterpret_cast<float *>(Wt + kBwdTBWt);  // [9][kWaves][64]
+  float *red = reinterpret_cast<float *>(bsm4);  // [9][kWaves][64], over Wt after the pairs
+  const float4 *g01 = S.g01, *g23 = S.g23;
+  if (kLDS) {
+    float4 *c = bsm4 + kBwdTBWt / 2;
+    for (int i = threadIdx.x; i < 2 * S.gn; i += kBwdTBThreads) c[i] = S.g01[i];
+    g01 = c;
+    g23 = c + S.gn;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
   float gk = 0.0f;
@@ -464,7 +505,8 @@ __global__ __launch_bounds__(kBwdTBThreads) void k_bwd_tb(BwdScalars S, BwdTB B,
       const int *qvi = reinterpret_cast<const int *>(qr + kRecVid);
       float gq[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (pv && !touching(pv0, pv1, pv2, qvi))
-        bwd_pair<Q, MODE>(S, pr, pal, psig, pcd, qr, prow, qcol, Wt, kTBEdges, Gv, Gl, gq, gk);
+        bwd_pair<Q, MODE>(S, pr, pal, psig, pcd, qr, prow, qcol, Wt, kTBEdges, g01, g23, Gv,
+                          Gl, gq, gk);
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const float v = wave_sum(gq[c]);
@@ -473,6 +515,7 @@ __global__ __launch_bounds__(kBwdTBThreads) void k_bwd_tb(BwdScalars S, BwdTB B,
     }
     float gpv[9];
     p_gradient(pal, psig, Gv, Gl, gpv);
+    __syncthreads();  // every wave is done with Wt
 #pragma unroll
     for (int c = 0; c < 9; ++c) red[(c * kWaves + wave) * 64 + lane] = pv ? gpv[c] : 0.0f;
     __syncthreads();
@@ -621,19 +664,23 @@ static int grid_for(const void *kern, int threads, size_t lds, int ntiles, long 
   return MF_OK;
 }
 
-template <int Q, int MODE, typename ZT>
-static int launch_bwd_t(mf_mesh *m, BwdScalars S, const ZT *W, double *dV, double *dk,
-                        hipStream_t s) {
+template <int Q, int MODE, bool kLDS, typename ZT>
+static int launch_bwd_tb(mf_mesh *m, BwdScalars S, const ZT *W, double *dV, double *dk,
+                         hipStream_t s) {
   long long grid = 0;
   int rc;
-  if (m->tb_ok) {
-    auto kern = k_bwd_tb<Q, MODE, ZT>;
-    const size_t lds = sizeof(float2) * kBwdTBWt + sizeof(float) * 9 * kBwdTBThreads;
+  {
+    auto kern = k_bwd_tb<Q, MODE, kLDS, ZT>;
+    static_assert(sizeof(float) * 9 * kBwdTBThreads <= sizeof(float2) * kBwdTBWt,
+                  "the wave reduction lives in the weights' space");
+    const size_t lds_max =
+        sizeof(float2) * kBwdTBWt + (kLDS ? sizeof(float4) * 2 * kBwdLdsCoef : 0);
+    const size_t lds = sizeof(float2) * kBwdTBWt + (kLDS ? sizeof(float4) * 2 * S.gn : 0);
     static std::once_flag once;  // per instantiation
     static hipError_t ge = hipSuccess;
     std::call_once(once, [&]() {
       ge = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
     });
     if (ge != hipSuccess) return hip_fail(ge, "adjoint set-up");
     S.ntiles = (int)m->tb_tiles.size();
@@ -643,6 +690,20 @@ static int launch_bwd_t(mf_mesh *m, BwdScalars S, const ZT *W, double *dV, doubl
             m->d_tb_be_off, m->d_tb_be_cut, m->d_tb_pos, m->d_cut_edge};
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBwdTBThreads), lds, s, S, B, m->d_rec, W,
                        dV, dk);
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <int Q, int MODE, typename ZT>
+static int launch_bwd_t(mf_mesh *m, BwdScalars S, const ZT *W, double *dV, double *dk,
+                        hipStream_t s) {
+  long long grid = 0;
+  int rc;
+  if (m->tb_ok) {
+    if (MODE == MF_MODE_TABLE && S.gn <= kBwdLdsCoef)
+      return launch_bwd_tb<Q, MODE, true, ZT>(m, S, W, dV, dk, s);
+    return launch_bwd_tb<Q, MODE, false, ZT>(m, S, W, dV, dk, s);
   } else {
     auto kern = k_bwd_regular<Q, MODE, ZT>;
     S.ntiles = (int)m->tiles.size();
@@ -702,12 +763,13 @@ int launch_backward(mf_mesh *m, const double *V, const Rule &r, double k, int mo
   S.ldz = ldz;
   if (mode == MF_MODE_TABLE) {
     const mf_tables::One &g = tab->g;
-    S.gl = g.look;
+    S.gl = g.look1;
     S.g01 = g.coef;
     S.g23 = g.coef + (g.n - 1);
-    S.ginv = g.binv;
-    S.gbias = g.bbias;
-    S.gmax = g.btop;
+    S.ginv = g.binv1;
+    S.gbias = g.bbias1;
+    S.gmax = g.btop1;
+    S.gn = g.n - 1;
   }
   int rc = z_dtype == MF_C64 ? launch_bwd_z<float2>(m, r, mode, S, W, dV, dk, s)
                              : launch_bwd_z<double2>(m, r, mode, S, W, dV, dk, s);
