@@ -191,8 +191,8 @@ __device__ __forceinline__ void bwd_pair(const BwdScalars &S, const float *__res
       float gr, gi, dgr, dgi;  // g, dg/dR
       if (MODE == MF_MODE_TABLE) {
         float u;
-        const int ii = look_interval1(wj[j], R, u);
-        const float4 A = g01[ii], B = g23[ii];
+        const int off = look_offset1(wj[j], R, u);
+        const float4 A = at_offset(g01, off), B = at_offset(g23, off);
         // g = c0 + c1 u + c2 u^2 + c3 u^3, g' = c1 + 2 c2 u + 3 c3 u^2
         const float der = fmaf(3.0f * B.z, u, 2.0f * B.x);
         const float dei = fmaf(3.0f * B.w, u, 2.0f * B.y);

@@ -291,7 +291,8 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
                                               const FillScalars &S, const FillRule &W,
                                               const float *pr, const float *nrm, const float *nq,
                                               float hx, float hy, float hz, float lx, float ly,
-                                              float lz, cfloat *qr, float &rlo, float &rhi) {
+                                              float lz, cfloat *qr, float &rlo, float &rhi,
+                                              bool range = true) {
   zero(M);
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
@@ -309,17 +310,25 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
       const float dy = ay - qr[kRecRho + 3 * j + 1];
       const float dz = az - qr[kRecRho + 3 * j + 2];
       r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-      rlo = fminf(rlo, r[j]);
-      rhi = fmaxf(rhi, r[j]);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
+    }
+    // the table-range check of these distances (range is wave-uniform)
+    if (range) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        rlo = fminf(rlo, r[j]);
+        rhi = fmaxf(rhi, r[j]);
+      }
     }
     float u[Q];
     float4 A[Q], B[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const int ii = look_interval1(w[j], r[j], u[j]);
-      A[j] = tab.c01[ii];
-      B[j] = kLDS ? tab.c01[ii + kLdsCoefHalf] : tab.c23[ii];
+      const int off = look_offset1(w[j], r[j], u[j]);
+      A[j] = at_offset(tab.c01, off);
+      // in LDS the (c2, c3) half sits a constant distance after (c0, c1): one
+      // address, the distance in the read's offset field
+      B[j] = kLDS ? at_offset(tab.c01, off + 16 * kLdsCoefHalf) : at_offset(tab.c23, off);
     }
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -1040,8 +1049,14 @@ __device__ __forceinline__ void fill_tile_tb(
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
         Moments M;
+        // Every point distance of the pair lies within d -+ (radius p +
+        // radius q); only waves where that interval leaves the table's range
+        // for some lane check each distance (the slack covers rounding).
+        const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
+        const float rr = pr[kRecRad] + qr[kRecRad], sl = 1e-5f * (dd + rr);
+        const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
         moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly,
-                                           lz, qr, rlo, rhi);
+                                           lz, qr, rlo, rhi, __any(near_end) != 0);
         const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
         // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2
         const float c0r = fmaf(-S.ik2, M.s0r, 0.25f * M.srr);

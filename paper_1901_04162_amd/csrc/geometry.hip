@@ -95,7 +95,9 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
   vi[0] = vid[0];
   vi[1] = vid[1];
   vi[2] = vid[2];
-  o[63] = 0.0f;
+  float rf = (float)rb;
+  if ((double)rf < rb) rf = nextafterf(rf, INFINITY);
+  o[kRecRad] = rf;
 }
 
 int launch_geometry(mf_mesh *m, const double *V, const Rule &r, hipStream_t s) {

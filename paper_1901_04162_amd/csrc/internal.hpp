@@ -36,9 +36,10 @@ constexpr int kTBMaxRounds = 12;
 //  [51,54) sigma_a = s_a l_a  (0 for a boundary edge)    FP32
 //  [54,60) centroid c as three doubles                    FP64
 //  [60,63) vertex indices                                 int32
+//  63      radius of the quadrature points about c, rounded up  FP32
 constexpr int kRecFloats = 64;
 constexpr int kRecRho = 0, kRecWRho = 21, kRecAlpha = 42, kRecSigma = 51, kRecCent = 54,
-              kRecVid = 60;
+              kRecVid = 60, kRecRad = 63;
 
 // Carves a caller-owned device workspace into arrays: `bottom` takes space
 // from the low end (arrays that outlive a call), `top` from the high end
@@ -97,7 +98,7 @@ struct mf_tables {
     int mb = 0;
     float binv = 0.0f, bbias = 0.0f, btop = 0.0f;
     // Green table only: the one-sample bucket records the fill kernels read
-    // (look_interval1 in lookup.hpp), width just under the smallest interval
+    // (look_offset1 in lookup.hpp), width just under the smallest interval
     int4 *look1 = nullptr;
     int mb1 = 0;
     float binv1 = 0.0f, bbias1 = 0.0f, btop1 = 0.0f;

@@ -45,16 +45,22 @@ __device__ __forceinline__ int look_interval(const int4 &w, float r, float &u) {
 // The fill kernels read a second set of records whose buckets are just
 // narrower than the smallest sample interval, the width of the paper's hash:
 // such a bucket holds at most one sample, and its record
-//   { i0, x(i0), x(i0 + 1), unused }
+//   { 16 i0, x(i0), x(i0 + 1), unused }
 // gives the interval as i0 + [r >= x(i0 + 1)] (x(i0 + 1) = +inf when i0 is the
 // last interval).  Either x(i0 + 1) lies in the bucket, or beyond it and then
 // no r of the bucket reaches it.  One compare and one select fewer per lookup,
-// for twice the records.
-__device__ __forceinline__ int look_interval1(const int4 &w, float r, float &u) {
+// for twice the records.  The interval comes back as the byte offset of its
+// 16-byte coefficient record, which the gather takes as it is.
+__device__ __forceinline__ int look_offset1(const int4 &w, float r, float &u) {
   const float x1 = __int_as_float(w.z);
   const bool a1 = r >= x1;
   u = r - (a1 ? x1 : __int_as_float(w.y));
-  return w.x + (int)a1;
+  return w.x + (a1 ? 16 : 0);
+}
+
+// The float4 at byte offset off from base.
+__device__ __forceinline__ float4 at_offset(const float4 *base, int off) {
+  return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
 // Cubic of interval i in Horner form, (c0, c1) and (c2, c3) complex.

@@ -282,9 +282,10 @@ __global__ void k_pack_look(const double *r, const int *nb, int n, int mb, int4 
   look[b] = make_int4(i0, __float_as_int((float)r[i0]), __float_as_int(s1), __float_as_int(s2));
 }
 
-// One-sample bucket records (look_interval1 in lookup.hpp): the interval
-// containing the bucket's first point, its first sample and the next sample
-// (+inf after the last interval).  Two samples in one bucket set *bad.
+// One-sample bucket records (look_offset1 in lookup.hpp): the byte offset
+// 16 i0 of the coefficients of the interval i0 containing the bucket's first
+// point, its first sample and the next sample (+inf after the last
+// interval).  Two samples in one bucket set *bad.
 __global__ void k_pack_look1(const double *r, const int *nb, int n, int mb, int4 *look,
                              int *bad) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -305,7 +306,7 @@ __global__ void k_pack_look1(const double *r, const int *nb, int n, int mb, int4
   if (i0 > n - 2) i0 = n - 2;
   if (c < n - 1 && nb[c] == b && c + 1 < n - 1 && nb[c + 1] == b) atomicOr(bad, 1);
   const float x1 = i0 + 1 < n - 1 ? (float)r[i0 + 1] : __int_as_float(0x7f800000);
-  look[b] = make_int4(i0, __float_as_int((float)r[i0]), __float_as_int(x1), 0);
+  look[b] = make_int4(16 * i0, __float_as_int((float)r[i0]), __float_as_int(x1), 0);
 }
 
 // Cubic Lagrange polynomial of interval i (stencil s..s+3) re-expanded in
