@@ -31,9 +31,10 @@
 //   Re[c sum_ab Omega'_ab (X(p,q)[a][b] + X(q,p)[b][a]) / 2],
 // Omega' from W[e(p,a), e(q,b)] + W[e(q,b), e(p,a)] (W alone for p = q),
 // with X the singularity-cancelled blocks of the forward fill.  Its
-// derivatives with respect to the pair's distinct vertex coordinates and k
-// (at most 16) are carried through that FP64 evaluation in forward mode
-// (dual.hpp), a few tangents per thread.
+// derivatives with respect to the coordinates of the pair's distinct vertices
+// but one (at most 12) are carried through that FP64 evaluation in forward
+// mode (dual.hpp), one tangent per thread; the first vertex and k follow from
+// the share's translation invariance and homogeneity.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -571,8 +572,13 @@ __device__ T touching_share(const T xp[3][3], const T xq[3][3], const RuleArg &R
 }
 
 // Thread (pair u, group g) carries tangents g*N .. g*N + N - 1 of the pair's
-// list: x, y, z of its distinct vertices (p's three, then q's others), then k.
-constexpr int kTouchTangents = 16;  // at most 5 distinct vertices and k
+// list: x, y, z of its distinct vertices after the first (p's second and
+// third, then q's others).  The rest follows from two invariances of the
+// share: it does not change when the pair is translated, so the first
+// vertex's gradient is minus the sum of the others'; and it is homogeneous,
+// share(a V, k / a) = a^2 share(V, k), so
+//   k d/dk = sum_v x_v . d/dx_v - 2 share = sum_{v > 0} (x_v - x_0) . d/dx_v - 2 share.
+constexpr int kTouchTangents = 12;  // at most 4 vertices besides the first
 constexpr int kTouchN = 1;
 constexpr int kTouchGroups = (kTouchTangents + kTouchN - 1) / kTouchN;
 
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(256) void k_bwd_touching(
     dv[a] = vp[a];
     if (vq[a] != vp[0] && vq[a] != vp[1] && vq[a] != vp[2]) dv[nd++] = vq[a];
   }
-  const int ntan = 3 * nd + 1, t0 = g * kTouchN;
+  const int ntan = 3 * (nd - 1), t0 = g * kTouchN;
   if (t0 >= ntan) return;
   for (int a = 0; a < 3; ++a) {
     const int ea = tedge[3 * p + a];
@@ -625,28 +631,31 @@ __global__ __launch_bounds__(256) void k_bwd_touching(
       Wi[3 * a + b] = wi;
     }
   }
-  // seed: tangent t = 3 * (distinct vertex) + coordinate, or k at t = 3 nd
-  T xp[3][3], xq[3][3], kd(k);
+  // seed: tangent t moves coordinate t % 3 of distinct vertex 1 + t / 3
+  T xp[3][3], xq[3][3];
   for (int a = 0; a < 3; ++a)
     for (int c = 0; c < 3; ++c) {
       xp[a][c] = T(V[3 * (size_t)vp[a] + c]);
       xq[a][c] = T(V[3 * (size_t)vq[a] + c]);
       for (int j = 0; j < kTouchN; ++j) {
         const int t = t0 + j;
-        const bool on = t < 3 * nd && t % 3 == c;
-        xp[a][c].d[j] = on && dv[t / 3] == vp[a] ? 1.0 : 0.0;
-        xq[a][c].d[j] = on && dv[t / 3] == vq[a] ? 1.0 : 0.0;
+        const bool on = t < ntan && t % 3 == c;
+        xp[a][c].d[j] = on && dv[1 + t / 3] == vp[a] ? 1.0 : 0.0;
+        xq[a][c].d[j] = on && dv[1 + t / 3] == vq[a] ? 1.0 : 0.0;
       }
     }
-  for (int j = 0; j < kTouchN; ++j) kd.d[j] = t0 + j == 3 * nd ? 1.0 : 0.0;
-  const T share = touching_share(xp, xq, R, kd, Wr, Wi, sp, sq);
+  const T share = touching_share(xp, xq, R, T(k), Wr, Wi, sp, sq);
+  double gk = g == 0 ? -2.0 * share.v : 0.0;
   for (int j = 0; j < kTouchN; ++j) {
     const int t = t0 + j;
-    if (t < 3 * nd)
-      atomicAdd(&dV[3 * (size_t)dv[t / 3] + t % 3], share.d[j]);
-    else if (t == 3 * nd)
-      atomicAdd(dk, share.d[j]);
+    if (t >= ntan) break;
+    const int v = dv[1 + t / 3], c = t % 3;
+    const double d = share.d[j];
+    atomicAdd(&dV[3 * (size_t)v + c], d);
+    atomicAdd(&dV[3 * (size_t)dv[0] + c], -d);
+    gk += (V[3 * (size_t)v + c] - V[3 * (size_t)dv[0] + c]) * d;
   }
+  atomicAdd(dk, gk / k);
 }
 
 __global__ void k_zero(double *p, int64_t n) {
