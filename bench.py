@@ -560,6 +560,9 @@ def main():
                       "regular_fill_cut_edge_fixup": float(ph_table[:, 4].mean())},
     }
     if not args.no_direct:
+        # the same tuner on the direct fill (its own cache key), then the timing
+        _, _, tune_name_d, tune_ms_d = mf.tune_fill(mesh, Vd, k, Q, "direct", None, out=Z)
+        log(f"tuner (direct): {tune_name_d} ({tune_ms_d} ms)")
         s_direct, ph_direct = timed(step_direct, args.steps, args.warmup)
         gathered["direct"] = Z.view(-1)[flat_d].cpu().numpy()
         log(f"direct step {s_direct*1e3:.2f} ms; phases {ph_direct.mean(0).round(3).tolist()}")
@@ -568,6 +571,10 @@ def main():
             "z_entries_per_s": E * E / s_direct,
             "green_evals_per_s": evals / s_direct,
             "regular_fill_ms": float(ph_direct[:, 2].mean()),
+            "regular_fill_tile_kernel_ms": float(ph_direct[:, 3].mean()),
+            "regular_fill_cut_edge_fixup_ms": float(ph_direct[:, 4].mean()),
+            "fill_kernel": tune_name_d,
+            "tuner_ms_tb1024_tb512_eb1024": tune_ms_d,
         }
         out["table_over_direct"] = s_direct / s_table
         out["table_over_direct_fill_only"] = float(ph_direct[:, 2].mean() / ph_table[:, 2].mean())

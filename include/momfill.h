@@ -201,28 +201,32 @@ int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_orde
               hipStream_t stream);
 
 /* ---- tuner ---------------------------------------------------------------
- * A table-mode fill can run on three kernels: 0, the triangle-block tiling
+ * A full EFIE fill (table or direct mode, no MF_PART_ flags) can run on three
+ * kernels: 0, the triangle-block tiling
  * (mf_mesh_tb_plan) with 1024 threads per workgroup (16 waves, one source
  * triangle per wave and round); 1, the same tiling with 512 threads (8 waves,
  * two source triangles per wave and round, twice the registers per lane);
  * 2, the edge-block tiling (mf_mesh_plan), which repeats the pairs its blocks
- * share but needs no cut-edge fix-up.  mf_fill_tune runs the fill of its
+ * share but needs no cut-edge fix-up (partial fills always run on it).  In
+ * direct mode the fix-up also adds, in FP64, the reference part of the
+ * entries of cut edges.  mf_fill_tune runs the fill of its
  * arguments (those of mf_fill_Z, MF_PART_ flags excluded) once per kernel to
  * warm up and once timed with HIP events, keeps the fastest for later
- * mf_fill_Z calls on this mesh and records it under (triangles, edges,
+ * mf_fill_Z calls on this mesh in that mode and records it under (triangles, edges,
  * rule, mode, output type, table placement) for the process and, when the
  * environment variable MOMFILL_TUNE_CACHE names a file, in that file, so that
  * later processes take the choice without timing.  *choice receives the
  * kernel; ms (3 floats, may be NULL) the timings in milliseconds, zeros when
  * the cache answered.  Z holds the fill when the call returns (synchronous).
- * Direct mode has one kernel (choice 2, no timing).  mf_fill_Z on a mesh that
- * was not tuned takes the cached choice for its key, else kernel 0. */
+ * A mesh without a triangle-block plan has one kernel (choice 2, no timing).
+ * mf_fill_Z on a mesh that was not tuned takes the cached choice for its key,
+ * else kernel 0. */
 int mf_fill_tune(mf_mesh *mesh, const double *vertices_dev, double k, int quad_order, int mode,
                  const mf_tables *tables, void *Z_dev, int z_dtype, int64_t ldz,
                  hipStream_t stream, int32_t *choice, float *ms);
 /* Description of a kernel choice (static string). */
 const char *mf_fill_choice_name(int32_t choice);
-/* Pins the kernel of this mesh's table-mode mf_fill_Z calls to `choice`
+/* Pins the kernel of this mesh's full mf_fill_Z calls (both modes) to `choice`
  * (0, 1 or 2 as above; for callers that tune by their own measurements or
  * reproduce a given kernel), or with -1 returns to the cached choice or
  * kernel 0.  A mesh without a triangle-block plan runs kernel 2 whatever is

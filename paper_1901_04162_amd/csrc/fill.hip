@@ -98,6 +98,8 @@ struct FillItem {
       *tb_tiles;
   float2 *side;           // cut-edge partial entries, rows of lside complex values
   long long lside;
+  const int32_t *edges;   // ne x 6: v_lo, v_hi, T+, T-, a+, a-
+  const int32_t *cut_idx; // ne: cut index of an edge, -1 inside a block
   const float *sing;
   const int4 *look;
   const float4 *coef;
@@ -459,6 +461,29 @@ __device__ __forceinline__ void moments_direct_split(Moments &M, const FillScala
   }
 }
 
+// The reference of direct mode for a triangle pair with FP64 centroid offset
+// D: d = |D|, 1/d (0 when the centroids coincide) and exp(-jkd).  Evaluated
+// without contraction, so that the fill and the cut-edge fix-up, which
+// recompute it, round it identically (the sign of D does not matter).
+struct PairRef {
+  double d, d2, id, sn, cs;
+};
+__device__ __forceinline__ PairRef pair_ref(double Dx, double Dy, double Dz, double kd) {
+#pragma clang fp contract(off)
+  PairRef P;
+  P.d2 = Dx * Dx + Dy * Dy + Dz * Dz;
+  P.d = sqrt(P.d2);
+  P.id = P.d > 0.0 ? 1.0 / P.d : 0.0;
+  sincos(kd * P.d, &P.sn, &P.cs);
+  return P;
+}
+
+// FP32 rounding of the reference exp(-jkd)/d.
+__device__ __forceinline__ float2 pair_ref_g(const PairRef &P) {
+#pragma clang fp contract(off)
+  return make_float2((float)(P.cs * P.id), (float)(-P.sn * P.id));
+}
+
 // Complex product (xr + j xi)(er + j ei) in place.
 __device__ __forceinline__ void crot(float &xr, float &xi, float er, float ei) {
   const float yr = fmaf(xr, er, -xi * ei);
@@ -469,17 +494,53 @@ __device__ __forceinline__ void crot(float &xr, float &xi, float er, float ei) {
 // Second difference of the per-pair references over the four triangle pairs
 // of entry (row r of block I, column c of block J), in FP64, times
 // -l_m l_n / k^2: the reference part of the entry's div-div term.
-__device__ __forceinline__ void ref_part(const FillItem &S, const float2 *gref, int I, int J,
-                                         int r, int c, int em, int en, float &vr, float &vi) {
-  const int rtI = S.blk_rt[I * kMaxBlockEdges + r], rtJ = S.blk_rt[J * kMaxBlockEdges + c];
-  const int pp = rtI & 0xff, pm = (rtI >> 8) & 0xff, qp = rtJ & 0xff, qm = (rtJ >> 8) & 0xff;
-  const float2 a = gref[qp * kRefStride + pp], b = gref[qm * kRefStride + pp];
-  const float2 c2 = gref[qp * kRefStride + pm], d = gref[qm * kRefStride + pm];
+// The second difference a - b - c + d of the references of an entry's four
+// triangle pairs (+m +n, +m -n, -m +n, -m -n), in FP64, times -l_m l_n / k^2.
+__device__ __forceinline__ void ref_second_difference(const FillItem &S, float2 a, float2 b,
+                                                      float2 c2, float2 d, int em, int en,
+                                                      float &vr, float &vi) {
   const double sr = ((double)a.x - (double)b.x) - ((double)c2.x - (double)d.x);
   const double si = ((double)a.y - (double)b.y) - ((double)c2.y - (double)d.y);
   const double f = -((double)S.elen[em] * (double)S.elen[en]) / (S.kd * S.kd);
   vr = (float)(f * sr);
   vi = (float)(f * si);
+}
+
+__device__ __forceinline__ void ref_part(const FillItem &S, const float2 *gref, int I, int J,
+                                         int r, int c, int em, int en, float &vr, float &vi) {
+  const int rtI = S.blk_rt[I * kMaxBlockEdges + r], rtJ = S.blk_rt[J * kMaxBlockEdges + c];
+  const int pp = rtI & 0xff, pm = (rtI >> 8) & 0xff, qp = rtJ & 0xff, qm = (rtJ >> 8) & 0xff;
+  ref_second_difference(S, gref[qp * kRefStride + pp], gref[qm * kRefStride + pp],
+                        gref[qp * kRefStride + pm], gref[qm * kRefStride + pm], em, en, vr, vi);
+}
+
+// Direct-mode moments of one regular pair: the split-phase moments rotated
+// by exp(-jkd), the FP32 reference g = fl(exp(-jkd)/d) and, in scr/sci, S0
+// less g (the remainder of the reference kept, g added back in FP64 at
+// write-out).
+template <int Q>
+__device__ __forceinline__ void direct_pair(Moments &M, const FillScalars &S, const FillRule &W,
+                                            const float *pr, cfloat *qr, double Dx, double Dy,
+                                            double Dz, float hx, float hy, float hz, float &gr,
+                                            float &gi, float &scr, float &sci) {
+  const PairRef P = pair_ref(Dx, Dy, Dz, S.kd);
+  const bool has_ref = P.d > 0.0;
+  moments_direct_split<Q>(M, S, W, pr, hx, hy, hz, (float)P.d, (float)P.d2, (float)P.id,
+                          has_ref ? 0.0f : 1.0f, qr);
+  const float er = (float)P.cs, ei = (float)-P.sn;  // exp(-jkd)
+  crot(M.s0r, M.s0i, er, ei);
+  crot(M.srr, M.sri, er, ei);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    crot(M.spr[c], M.spi[c], er, ei);
+    crot(M.sqr[c], M.sqi[c], er, ei);
+  }
+  const double gcr = P.cs * P.id, gci = -P.sn * P.id;
+  const float2 g = pair_ref_g(P);
+  gr = g.x;
+  gi = g.y;
+  scr = M.s0r + (float)(gcr - (double)gr);
+  sci = M.s0i + (float)(gci - (double)gi);
 }
 
 // The item's Green table: the interval coefficients are copied into LDS
@@ -558,27 +619,8 @@ __device__ __forceinline__ void fill_tile(
           s0r = scr = M.s0r;
           s0i = sci = M.s0i;
         } else {
-          const double d2 = Dx * Dx + Dy * Dy + Dz * Dz;
-          const double d = sqrt(d2);
-          const bool has_ref = d > 0.0;
-          const double id = has_ref ? 1.0 / d : 0.0;
-          moments_direct_split<Q>(M, S, W, pr, hx, hy, hz, (float)d, (float)d2, (float)id,
-                                  has_ref ? 0.0f : 1.0f, qr);
-          double sn, cs;
-          sincos(S.kd * d, &sn, &cs);
-          const float er = (float)cs, ei = (float)-sn;  // exp(-jkd)
-          crot(M.s0r, M.s0i, er, ei);
-          crot(M.srr, M.sri, er, ei);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            crot(M.spr[c], M.spi[c], er, ei);
-            crot(M.sqr[c], M.sqi[c], er, ei);
-          }
-          // reference exp(-jkd)/d: its FP32 rounding g and the remainder
-          const double gcr = cs * id, gci = -sn * id;
-          const float gr = (float)gcr, gi = (float)gci;
-          scr = M.s0r + (float)(gcr - (double)gr);
-          sci = M.s0i + (float)(gci - (double)gi);
+          float gr, gi;
+          direct_pair<Q>(M, S, W, pr, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
           if (kRef) {
             if (pv) gref[qi * kRefStride + pidx] = make_float2(gr, gi);
             s0r = gr + scr;
@@ -1004,9 +1046,9 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
 // the non-owner halves; k_cut_rows and k_cut_cols add them in afterwards.
 constexpr int kTBStride = 2 * kTBEdges + 1;  // odd: rows fall in different banks
 constexpr int kTBAccFloats = kTBEdges * kTBStride;
-template <int Q, typename ZT, bool kLDS, int kTBThreads>
+template <int Q, int MODE, typename ZT, bool kLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
-    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, int local, float &rlo,
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tb_pos,
     const int32_t *__restrict__ tb_order, const int32_t *__restrict__ touch_off,
     const int32_t *__restrict__ touch_q, const float *__restrict__ sing, ZT *__restrict__ Z,
@@ -1046,21 +1088,34 @@ __device__ __forceinline__ void fill_tile_tb(
         cdouble *qcd = (cdouble *)(qr + kRecCent);
         const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
-        const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
-                    lz = (float)(Dz - (double)hz);
         Moments M;
-        // Every point distance of the pair lies within d -+ (radius p +
-        // radius q); only waves where that interval leaves the table's range
-        // for some lane check each distance (the slack covers rounding).
-        const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
-        const float rr = pr[kRecRad] + qr[kRecRad], sl = 1e-5f * (dd + rr);
-        const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
-        moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx, ly,
-                                           lz, qr, rlo, rhi, __any(near_end) != 0);
+        // s0r/s0i: S0 of the vector terms; scr/sci: S0 of the div-div term
+        // (direct mode: less the reference that the write-out adds in FP64)
+        float s0r, s0i, scr, sci;
+        if (MODE == MF_MODE_TABLE) {
+          const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                      lz = (float)(Dz - (double)hz);
+          // Every point distance of the pair lies within d -+ (radius p +
+          // radius q); only waves where that interval leaves the table's range
+          // for some lane check each distance (the slack covers rounding).
+          const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
+          const float rr = pr[kRecRad] + qr[kRecRad], sl = 1e-5f * (dd + rr);
+          const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
+          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx,
+                                             ly, lz, qr, rlo, rhi, __any(near_end) != 0);
+          s0r = scr = M.s0r;
+          s0i = sci = M.s0i;
+        } else {
+          float gr, gi;
+          direct_pair<Q>(M, S, W, pr, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
+          if (pv) gref[(q - tJ0) * kRefStride + lane] = make_float2(gr, gi);
+          s0r = gr + scr;
+          s0i = gi + sci;
+        }
         const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
         // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2
-        const float c0r = fmaf(-S.ik2, M.s0r, 0.25f * M.srr);
-        const float c0i = fmaf(-S.ik2, M.s0i, 0.25f * M.sri);
+        const float c0r = fmaf(-S.ik2, scr, 0.25f * M.srr);
+        const float c0i = fmaf(-S.ik2, sci, 0.25f * M.sri);
         float Ar[3], Ai[3], Br[3], Bi[3], palpha[3][3], beta[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1077,7 +1132,7 @@ __device__ __forceinline__ void fill_tile_tb(
             Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
           }
         }
-        const float q0r = 0.25f * M.s0r, q0i = 0.25f * M.s0i;
+        const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -1088,6 +1143,8 @@ __device__ __forceinline__ void fill_tile_tb(
             Xi[a][b] = fmaf(ab, q0i, Ai[a] + Bi[b]);
           }
       } else {
+        // touching pairs carry no reference
+        if (MODE != MF_MODE_TABLE && pv) gref[(q - tJ0) * kRefStride + lane] = make_float2(0.f, 0.f);
         int s = touch_off[p];
         const int s1t = touch_off[p + 1];
         while (s < s1t && touch_q[s] != q) ++s;
@@ -1127,9 +1184,28 @@ __device__ __forceinline__ void fill_tile_tb(
     }
     __syncthreads();
   }
-  // write-out: Z = j k eta/(4 pi) acc; a wave per row, lanes along it
   const int e0I = S.tb_e0[I], nownI = S.tb_e0[I + 1] - e0I;
   const int e0J = S.tb_e0[J], nownJ = S.tb_e0[J + 1] - e0J;
+  if (MODE != MF_MODE_TABLE) {
+    // direct mode: the reference part of every owned entry whose edges are
+    // both inside their blocks (the cut-edge fix-up adds it to the others)
+    for (int e = threadIdx.x; e < nownI * nownJ; e += kTBThreads) {
+      const int r = e / nownJ, c = e % nownJ;
+      const int em = e0I + r, en = e0J + c;
+      if (S.cut_idx[em] >= 0 || S.cut_idx[en] >= 0) continue;
+      const int pp = S.edges[6 * em + 2] - tI0, pm = S.edges[6 * em + 3] - tI0;
+      const int qp = S.edges[6 * en + 2] - tJ0, qm = S.edges[6 * en + 3] - tJ0;
+      float vr, vi;
+      ref_second_difference(S, gref[qp * kRefStride + pp], gref[qm * kRefStride + pp],
+                            gref[qp * kRefStride + pm], gref[qm * kRefStride + pm], em, en, vr,
+                            vi);
+      float *a = acc + r * kTBStride + 2 * c;
+      a[0] += vr;
+      a[1] += vi;
+    }
+    __syncthreads();
+  }
+  // write-out: Z = j k eta/(4 pi) acc; a wave per row, lanes along it
   const int32_t *cutI = S.tb_be_cut + S.tb_be_off[I], *cutJ = S.tb_be_cut + S.tb_be_off[J];
   const float pref = S.pref;
   for (int r = wave; r < nownI; r += kWaves) {
@@ -1176,18 +1252,23 @@ __device__ __forceinline__ void fill_tile_tb(
   __syncthreads();
 }
 
-template <int Q, bool kLDS, typename ZT, int kTBThreads>
+template <int Q, int MODE, bool kLDS, typename ZT, int kTBThreads>
 __global__ __launch_bounds__(kTBThreads)
 __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_fill_tb(
     FillItem S, FillRule W, int ntiles) {
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
-  const TabPtrs tab = load_table<kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
+  // after the accumulator: the table's coefficients (table mode) or the
+  // tile's per-pair references (direct mode)
+  const TabPtrs tab =
+      load_table<MODE == MF_MODE_TABLE && kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
+  float2 *gref = reinterpret_cast<float2 *>(smem4 + kTBAccFloats / 4 + 1);
   float rlo = INFINITY, rhi = 0.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile_tb<Q, ZT, kLDS, kTBThreads>(S, W, tab, acc, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order,
-                              S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
-  if (rlo < S.lo_ok || rhi > S.hi_ok) atomicOr(S.status, 1);
+    fill_tile_tb<Q, MODE, ZT, kLDS, kTBThreads>(S, W, tab, acc, gref, t, rlo, rhi, S.rec, S.tb_pos,
+                                                S.tb_order, S.touch_off, S.touch_q, S.sing,
+                                                reinterpret_cast<ZT *>(S.Z), S.side);
+  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
 // Cut-edge fix-up, one 64 x 64 tile per workgroup: 64 cut edges c (rows) by
@@ -1199,12 +1280,29 @@ __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_
 // tiles), so every column write of one row falls within the tile's span.
 constexpr int kFixTile = 64;
 
-template <typename ZT>
+// The reference of triangle pair (p, q) as the fill rounded it: zero for a
+// touching pair.
+__device__ __forceinline__ float2 tri_pair_ref(const FillItem &S, int p, int q) {
+  const float *pr = S.rec + (size_t)p * kRecFloats, *qr = S.rec + (size_t)q * kRecFloats;
+  const int *pv = reinterpret_cast<const int *>(pr + kRecVid);
+  const int *qv = reinterpret_cast<const int *>(qr + kRecVid);
+  bool touch = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) touch = touch || pv[a] == qv[b];
+  if (touch) return make_float2(0.f, 0.f);
+  const double *pc = reinterpret_cast<const double *>(pr + kRecCent);
+  const double *qc = reinterpret_cast<const double *>(qr + kRecCent);
+  return pair_ref_g(pair_ref(pc[0] - qc[0], pc[1] - qc[1], pc[2] - qc[2], S.kd));
+}
+
+template <typename ZT, bool kRef>
 __global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long ldz, int ne,
                                                  int ncut, const int32_t *__restrict__ cut_edge,
                                                  const int32_t *__restrict__ cut_idx,
                                                  const float2 *__restrict__ side,
-                                                 long long lside) {
+                                                 long long lside, FillItem S) {
   __shared__ ZT tile[kFixTile][kFixTile + 1];
   const int n0 = blockIdx.x * kFixTile, ci0 = blockIdx.y * kFixTile;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 4 waves
@@ -1223,6 +1321,16 @@ __global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long l
       const float2 d = side[(size_t)ci * lside + ne + cn];
       z.x += b.x + d.x;
       z.y += b.y + d.y;
+    }
+    if (kRef) {
+      // direct mode: the reference part of the completed entry
+      const int cp = S.edges[6 * c + 2], cm = S.edges[6 * c + 3];
+      const int np = S.edges[6 * n + 2], nm = S.edges[6 * n + 3];
+      float vr, vi;
+      ref_second_difference(S, tri_pair_ref(S, cp, np), tri_pair_ref(S, cp, nm),
+                            tri_pair_ref(S, cm, np), tri_pair_ref(S, cm, nm), c, n, vr, vi);
+      z.x += -S.pref * vi;
+      z.y += S.pref * vr;
     }
     Z[(size_t)c * ldz + n] = z;
     tile[i][tx] = z;
@@ -1426,6 +1534,8 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.tb_tiles = m->d_tb_tiles;
   S.side = reinterpret_cast<float2 *>(m->d_side);
   S.lside = (long long)m->ne + m->n_cut;
+  S.edges = m->d_edges;
+  S.cut_idx = m->d_cut_idx;
   S.touch_off = m->d_touch_off;
   S.touch_q = m->d_touch_q;
   S.touch_rev = m->d_touch_rev;
@@ -1612,10 +1722,10 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
   return rc;
 }
 
-template <int Q, bool kLDS, typename ZT, int kTBThreads>
+template <int Q, int MODE, bool kLDS, typename ZT, int kTBThreads>
 static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
-  auto kern = k_fill_tb<Q, kLDS, ZT, kTBThreads>;
+  auto kern = k_fill_tb<Q, MODE, kLDS, ZT, kTBThreads>;
   static std::once_flag once;
   static long long grid = 0;
   static hipError_t ge = hipSuccess;
@@ -1637,8 +1747,9 @@ static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t 
   const int ntiles = (int)m->tb_tiles.size();
   const long long g = std::min<long long>(grid, ntiles);
   if (getenv("MOMFILL_VERBOSE"))
-    fprintf(stderr, "[momfill] k_fill_tb Q=%d lds_table=%d tiles=%d grid=%lld lds=%zu B cut=%d\n",
-            Q, (int)kLDS, ntiles, g, lds, m->n_cut);
+    fprintf(stderr,
+            "[momfill] k_fill_tb Q=%d mode=%d lds_table=%d tiles=%d grid=%lld lds=%zu B cut=%d\n",
+            Q, MODE, (int)kLDS, ntiles, g, lds, m->n_cut);
   hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(kTBThreads), lds, s, S, W, ntiles);
   MF_HIP(hipGetLastError());
   if (m->timing_now) {
@@ -1648,50 +1759,58 @@ static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t 
   if (m->n_cut > 0) {
     const dim3 fg((unsigned)((m->ne + kFixTile - 1) / kFixTile),
                   (unsigned)((m->n_cut + kFixTile - 1) / kFixTile));
-    hipLaunchKernelGGL(k_cut_fix<ZT>, fg, dim3(256), 0, s, reinterpret_cast<ZT *>(S.Z), S.ldz,
-                       m->ne, m->n_cut, m->d_cut_edge, m->d_cut_idx,
-                       reinterpret_cast<const float2 *>(m->d_side), S.lside);
+    hipLaunchKernelGGL((k_cut_fix<ZT, MODE != MF_MODE_TABLE>), fg, dim3(256), 0, s,
+                       reinterpret_cast<ZT *>(S.Z), S.ldz, m->ne, m->n_cut, m->d_cut_edge,
+                       m->d_cut_idx, reinterpret_cast<const float2 *>(m->d_side), S.lside, S);
     MF_HIP(hipGetLastError());
   }
   return MF_OK;
 }
 
-template <bool kLDS, typename ZT, int kTBThreads>
+template <int MODE, bool kLDS, typename ZT, int kTBThreads>
 static int launch_tb_q(mf_mesh *m, int nq, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
   switch (nq) {
-    case 3: return launch_tb_t<3, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
-    case 6: return launch_tb_t<6, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
-    default: return launch_tb_t<7, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    case 3: return launch_tb_t<3, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    case 6: return launch_tb_t<6, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    default: return launch_tb_t<7, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
   }
 }
 
 template <typename ZT, int kTBThreads>
-static int launch_tb_z(mf_mesh *m, int nq, bool in_lds, const FillItem &S, const FillRule &W,
-                       size_t lds, hipStream_t s) {
-  return in_lds ? launch_tb_q<true, ZT, kTBThreads>(m, nq, S, W, lds, s)
-                : launch_tb_q<false, ZT, kTBThreads>(m, nq, S, W, lds, s);
+static int launch_tb_z(mf_mesh *m, int nq, int mode, bool in_lds, const FillItem &S,
+                       const FillRule &W, size_t lds, hipStream_t s) {
+  if (mode == MF_MODE_DIRECT)
+    return launch_tb_q<MF_MODE_DIRECT, false, ZT, kTBThreads>(m, nq, S, W, lds, s);
+  return in_lds ? launch_tb_q<MF_MODE_TABLE, true, ZT, kTBThreads>(m, nq, S, W, lds, s)
+                : launch_tb_q<MF_MODE_TABLE, false, ZT, kTBThreads>(m, nq, S, W, lds, s);
 }
 
-// Table-mode EFIE fill on the triangle-block plan (k_fill_tb and the cut-edge
-// fix-ups), one item.
-static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, const mf_tables *tab, void *Z,
-                          int z_dtype, int64_t ldz, hipStream_t s, int threads) {
-  FillItem S = make_item(m, r, k, MF_MODE_TABLE, tab, Z, ldz, m->d_sing, 0);
+// EFIE fill on the triangle-block plan (k_fill_tb and the cut-edge fix-up),
+// one item, table or direct mode.
+static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab,
+                          void *Z, int z_dtype, int64_t ldz, hipStream_t s, int threads) {
+  FillItem S = make_item(m, r, k, mode, tab, Z, ldz, m->d_sing, 0);
   FillRule W;
   for (int i = 0; i < kMaxQ; ++i) W.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
   int dev = 0, maxlds = 0;
   MF_HIP(hipGetDevice(&dev));
   MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const size_t base = sizeof(float) * kTBAccFloats + 16;
-  const size_t tbytes = table_lds_bytes(tab);
-  const bool in_lds = base + tbytes <= (size_t)maxlds;
-  const size_t lds = in_lds ? base + tbytes : base;
+  bool in_lds = false;
+  size_t lds = base;
+  if (mode == MF_MODE_TABLE) {
+    const size_t tbytes = table_lds_bytes(tab);
+    in_lds = base + tbytes <= (size_t)maxlds;
+    if (in_lds) lds += tbytes;
+  } else {
+    lds += sizeof(float2) * kRefFloat2;  // the tile's per-pair references
+  }
   if (threads == 512)
-    return z_dtype == MF_C64 ? launch_tb_z<float2, 512>(m, r.nq, in_lds, S, W, lds, s)
-                             : launch_tb_z<double2, 512>(m, r.nq, in_lds, S, W, lds, s);
-  return z_dtype == MF_C64 ? launch_tb_z<float2, 1024>(m, r.nq, in_lds, S, W, lds, s)
-                           : launch_tb_z<double2, 1024>(m, r.nq, in_lds, S, W, lds, s);
+    return z_dtype == MF_C64 ? launch_tb_z<float2, 512>(m, r.nq, mode, in_lds, S, W, lds, s)
+                             : launch_tb_z<double2, 512>(m, r.nq, mode, in_lds, S, W, lds, s);
+  return z_dtype == MF_C64 ? launch_tb_z<float2, 1024>(m, r.nq, mode, in_lds, S, W, lds, s)
+                           : launch_tb_z<double2, 1024>(m, r.nq, mode, in_lds, S, W, lds, s);
 }
 
 const char *fill_choice_name(int c) {
@@ -1705,11 +1824,11 @@ const char *fill_choice_name(int c) {
 
 int launch_fill(mf_mesh *m, const Rule &r, double k, int mode, const mf_tables *tab, void *Z,
                 int z_dtype, int64_t ldz, hipStream_t s) {
-  if (mode == MF_MODE_TABLE && m->tb_ok) {
-    int c = m->fill_choice;
+  if ((mode == MF_MODE_TABLE || mode == MF_MODE_DIRECT) && m->tb_ok) {
+    int c = m->fill_choice[mode];
     if (c < 0) c = cached_fill_choice(m, r.nq, mode, z_dtype, tab);
-    if (c == kFillTB512) return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s, 512);
-    if (c != kFillEB1024) return launch_fill_tb(m, r, k, tab, Z, z_dtype, ldz, s, 1024);
+    if (c == kFillTB512) return launch_fill_tb(m, r, k, mode, tab, Z, z_dtype, ldz, s, 512);
+    if (c != kFillEB1024) return launch_fill_tb(m, r, k, mode, tab, Z, z_dtype, ldz, s, 1024);
   }
   FillLaunch *L = nullptr;
   const float *sing = m->d_sing;

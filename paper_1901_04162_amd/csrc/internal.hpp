@@ -140,7 +140,7 @@ struct mf_mesh {
   // triangles); its block edges are the owned edges (local index e - e0)
   // followed by the non-owner halves of cut edges owned by earlier blocks.
   bool tb_ok = false;
-  int fill_choice = -1;            // tuned kernel of table-mode single fills (-1: cache/default)
+  int fill_choice[2] = {-1, -1};   // tuned kernel of single fills per mode (-1: cache/default)
   int tb_nblk = 0, n_cut = 0;
   std::vector<int32_t> tb_t0, tb_e0;
   std::vector<int32_t> tb_nbe;       // block edges per block

@@ -1,8 +1,8 @@
 // Tuning of the fill kernels: the cache of choices and the single-fill tuner.
 //
-// A table-mode fill can run on three kernels (fill_choice_name): the
-// triangle-block tiling with 16 or 8 waves per workgroup, or the edge-block
-// tiling.  mf_fill_tune times them on the caller's own fill and keeps the
+// An EFIE fill (table or direct mode) can run on three kernels
+// (fill_choice_name): the triangle-block tiling with 16 or 8 waves per
+// workgroup, or the edge-block tiling.  mf_fill_tune times them on the caller's own fill and keeps the
 // fastest, per (triangles, edges, rule, mode, output type, table placement);
 // batched launches keep their workgroup size the same way.  Choices are kept
 // for the process and, when MOMFILL_TUNE_CACHE names a file, in that file
@@ -110,15 +110,15 @@ int mf_fill_tune(mf_mesh *m, const double *V, double k, int quad_order, int mode
             MF_EINVAL);
   if (ms)
     for (int c = 0; c < kFillChoices; ++c) ms[c] = 0.0f;
-  // direct mode (and meshes without a triangle-block plan) have one kernel
-  if (mode != MF_MODE_TABLE || !m->tb_ok) {
-    *choice = kFillEB1024;  // the table-mode choice of the mesh stays as it is
+  // meshes without a triangle-block plan have one kernel
+  if (!m->tb_ok) {
+    *choice = kFillEB1024;
     return MF_OK;
   }
   const std::string key = fill_tune_key(m, r.nq, mode, z_dtype, tab);
   int c = -1;
   if (tune_cache_get(key, &c) && c >= 0 && c < kFillChoices) {
-    m->fill_choice = c;
+    m->fill_choice[mode] = c;
     *choice = c;
     return MF_OK;
   }
@@ -134,7 +134,7 @@ int mf_fill_tune(mf_mesh *m, const double *V, double k, int quad_order, int mode
   int best = kFillTB1024;
   float best_ms = INFINITY;
   for (int cand = 0; cand < kFillChoices && !rc; ++cand) {
-    m->fill_choice = cand;
+    m->fill_choice[mode] = cand;
     rc = launch_fill(m, r, k, mode, tab, Z, z_dtype, ldz, s);  // warm-up
     if (rc) break;
     he = hipEventRecord(e0, s);
@@ -153,10 +153,10 @@ int mf_fill_tune(mf_mesh *m, const double *V, double k, int quad_order, int mode
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) {
-    m->fill_choice = -1;
+    m->fill_choice[mode] = -1;
     return rc;
   }
-  m->fill_choice = best;
+  m->fill_choice[mode] = best;
   *choice = best;
   tune_cache_put(key, best);
   // leave the output as the chosen kernel computes it
@@ -169,7 +169,7 @@ int mf_mesh_set_fill_choice(mf_mesh *m, int32_t choice) {
   if (!m) return (set_error("mf_mesh_set_fill_choice: null mesh"), MF_EINVAL);
   if (choice < -1 || choice >= kFillChoices)
     return (set_error("mf_mesh_set_fill_choice: choice must be -1, 0, 1 or 2"), MF_EINVAL);
-  m->fill_choice = choice;
+  m->fill_choice[0] = m->fill_choice[1] = choice;
   return MF_OK;
 }
 

@@ -407,11 +407,13 @@ def test_sampled_plate(mf, orc, tol):
                    bound_table=max(1e-5, 10 * tol))
 
 
-def test_triangle_block_fill_scrambled_mesh(mf, orc):
-    """The triangle-block table fill on a mesh whose triangles are in random
-    order: nearly every edge is cut between blocks, so almost every entry is
-    completed from the side buffer by the cut-edge fix-ups.  Full matrix
-    against the oracle's table mode with the same table."""
+@pytest.mark.parametrize("mode", ["table", "direct"])
+def test_triangle_block_fill_scrambled_mesh(mf, orc, mode):
+    """The triangle-block fill on a mesh whose triangles are in random order:
+    nearly every edge is cut between blocks, so almost every entry is
+    completed from the side buffer by the cut-edge fix-up (in direct mode the
+    fix-up also adds those entries' FP64 reference part).  Full matrix against
+    the oracle (table mode: with the same table)."""
     import torch
 
     V, F = meshes.icosphere(2)
@@ -419,18 +421,23 @@ def test_triangle_block_fill_scrambled_mesh(mf, orc):
     k, Q, tol = 2 * np.pi, 3, 1e-6
     m = mf.Mesh(F, V.shape[0])
     nb, nt, ncut, nr = m.tb_plan()
-    say("scrambled ico2: blocks", nb, "cut edges", ncut, "of", m.n_edges)
+    say("scrambled ico2:", mode, "blocks", nb, "cut edges", ncut, "of", m.n_edges)
     assert ncut > m.n_edges // 2
     E = m.edges()
-    lo, hi = mf.r_range(m, V, Q)
-    T = mf.build_tables(k, lo, hi, tol)
-    G = orc.build_table(orc.GREEN, k, lo, hi, tol)
-    ref = orc.fill(V, F, k, Q, mode=orc.TABLE, gtable=G, edges=E)
-    Z = mf.fill_Z(m, V, k, Q, "table", T, dtype=torch.complex128)
+    T = None
+    if mode == "table":
+        lo, hi = mf.r_range(m, V, Q)
+        T = mf.build_tables(k, lo, hi, tol)
+        G = orc.build_table(orc.GREEN, k, lo, hi, tol)
+        ref = orc.fill(V, F, k, Q, mode=orc.TABLE, gtable=G, edges=E)
+    else:
+        ref = orc.fill(V, F, k, Q, edges=E)
+    m.set_fill_choice(0)
+    Z = mf.fill_Z(m, V, k, Q, mode, T, dtype=torch.complex128)
     mf.sync_status(m)
     err = _rel(Z.cpu().numpy(), ref)
-    say("  rel err against the oracle's table mode", err)
-    assert err <= 1e-6
+    say("  rel err against the oracle", err)
+    assert err <= (1e-6 if mode == "table" else 3e-7)
     z = Z.cpu().numpy()
     # reciprocity to FP32 rounding (parts of two cut rows are added in another order)
     assert np.abs(z - z.T).max() <= 1e-6 * np.abs(z).max()
@@ -459,3 +466,37 @@ def test_triangle_block_fill_matches_edge_block_fill(mf):
     d = float(torch.linalg.norm(Z1 - Z2) / torch.linalg.norm(Z2))
     say("  relative difference", d)
     assert d <= 3e-7
+
+
+def test_direct_triangle_blocks_match_edge_blocks(mf, orc):
+    """Direct mode on the benchmark sphere: the triangle-block kernel (each
+    unordered pair once, cut-edge references added by the fix-up) against the
+    edge-block kernel, and both against the FP64 oracle on 20,000 uniformly
+    sampled entries."""
+    import torch
+
+    V, F = meshes.icosphere(5)
+    k, Q = 17.0, 7
+    m = mf.Mesh(F, V.shape[0])
+    E = m.n_edges
+    Zs = []
+    for choice in (0, 2):
+        say("direct, kernel", mf.lib().mf_fill_choice_name(choice).decode())
+        m.set_fill_choice(choice)
+        Z = torch.empty((E, E), dtype=torch.complex64, device="cuda")
+        mf.fill_Z(m, V, k, Q, "direct", None, out=Z)
+        torch.cuda.synchronize()
+        Zs.append(Z)
+    m.set_fill_choice(-1)
+    d = float(torch.linalg.norm(Zs[0] - Zs[1]) / torch.linalg.norm(Zs[1]))
+    say("  relative difference", d)
+    assert d <= 2e-7
+    rng = np.random.default_rng(8)
+    flat = rng.choice(E * E, 20000, replace=False)
+    rows, cols = flat // E, flat % E
+    ref = orc.fill_entries(V, F, m.edges(), k, Q, rows, cols)
+    for Z in Zs:
+        z = Z.cpu().numpy()[rows, cols]
+        err = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
+        say("  sampled rel err", err)
+        assert err <= 1e-6
