@@ -1046,9 +1046,16 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
 // the non-owner halves; k_cut_rows and k_cut_cols add them in afterwards.
 constexpr int kTBStride = 2 * kTBEdges + 1;  // odd: rows fall in different banks
 constexpr int kTBAccFloats = kTBEdges * kTBStride;
-template <int Q, int MODE, typename ZT, bool kLDS, int kTBThreads>
+// Test-point offsets of a tile's test triangles staged in LDS (21 floats per
+// triangle, odd stride), read there by the test-point loop instead of from
+// the triangle records.
+constexpr int kRhoFloats = 3 * kMaxQ;
+// and, per triangle pair, alpha (9), sigma (3) and the radius: 13 floats
+constexpr int kAuxFloats = 13;
+template <int Q, int MODE, typename ZT, bool kLDS, bool kRhoLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
-    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref, int local, float &rlo,
+    const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref,
+    float *rho_lds, float *aux_lds, int local, float &rlo,
     float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tb_pos,
     const int32_t *__restrict__ tb_order, const int32_t *__restrict__ touch_off,
     const int32_t *__restrict__ touch_q, const float *__restrict__ sing, ZT *__restrict__ Z,
@@ -1059,14 +1066,29 @@ __device__ __forceinline__ void fill_tile_tb(
   const int tij = S.tb_tiles[local];
   const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
   const int nbeI = S.tb_nbe[I], nbeJ = S.tb_nbe[J];
-  for (int i = threadIdx.x; i < nbeI * kTBStride; i += kTBThreads) acc[i] = 0.0f;
-  __syncthreads();
   const int tI0 = S.tb_t0[I], npI = S.tb_t0[I + 1] - tI0;
   const int tJ0 = S.tb_t0[J];
+  for (int i = threadIdx.x; i < nbeI * kTBStride; i += kTBThreads) acc[i] = 0.0f;
+  if (kRhoLDS) {
+    for (int x = threadIdx.x; x < npI * kRhoFloats; x += kTBThreads) {
+      const int l = x / kRhoFloats, e = x - l * kRhoFloats;
+      rho_lds[x] = rec[(size_t)(tI0 + l) * kRecFloats + kRecRho + e];
+    }
+    for (int x = threadIdx.x; x < npI * kAuxFloats; x += kTBThreads) {
+      const int l = x / kAuxFloats, e = x - l * kAuxFloats;
+      aux_lds[x] = rec[(size_t)(tI0 + l) * kRecFloats + (e < 12 ? kRecAlpha + e : kRecRad)];
+    }
+  }
+  __syncthreads();
   const bool pv = lane < npI;
   const int p = tI0 + (pv ? lane : 0);
   const int prow = pv ? tb_pos[p] : -1;
   const float *pr = rec + (size_t)p * kRecFloats;
+  // the test points' offsets (kRecRho = 0 in both layouts)
+  const float *prho = kRhoLDS ? rho_lds + (pv ? lane : 0) * kRhoFloats : pr;
+  // alpha at [0, 9), sigma at [9, 12) in both layouts (kRecSigma = kRecAlpha + 9)
+  const float *paux = kRhoLDS ? aux_lds + (pv ? lane : 0) * kAuxFloats : pr + kRecAlpha;
+  const float prad = kRhoLDS ? paux[12] : pr[kRecRad];
   const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
   const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
   const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
@@ -1099,15 +1121,15 @@ __device__ __forceinline__ void fill_tile_tb(
           // radius q); only waves where that interval leaves the table's range
           // for some lane check each distance (the slack covers rounding).
           const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
-          const float rr = pr[kRecRad] + qr[kRecRad], sl = 1e-5f * (dd + rr);
+          const float rr = prad + qr[kRecRad], sl = 1e-5f * (dd + rr);
           const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
-          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx,
-                                             ly, lz, qr, rlo, rhi, __any(near_end) != 0);
+          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, prho, nullptr, nullptr, hx, hy, hz,
+                                             lx, ly, lz, qr, rlo, rhi, __any(near_end) != 0);
           s0r = scr = M.s0r;
           s0i = sci = M.s0i;
         } else {
           float gr, gi;
-          direct_pair<Q>(M, S, W, pr, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
+          direct_pair<Q>(M, S, W, prho, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
           if (pv) gref[(q - tJ0) * kRefStride + lane] = make_float2(gr, gi);
           s0r = gr + scr;
           s0i = gi + sci;
@@ -1124,7 +1146,7 @@ __device__ __forceinline__ void fill_tile_tb(
           Br[a] = Bi[a] = 0.f;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+            palpha[a][c] = paux[3 * a + c];
             beta[a][c] = qr[kRecAlpha + 3 * a + c];
             Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
             Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
@@ -1161,7 +1183,7 @@ __device__ __forceinline__ void fill_tile_tb(
       if (pv) {
         float psig[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) psig[a] = pr[kRecSigma + a];
+        for (int a = 0; a < 3; ++a) psig[a] = paux[9 + a];
         // rows of plus triangles first, then minus: the two triangles of an
         // edge interior to the block are two lanes of this wave
 #pragma unroll
@@ -1252,22 +1274,33 @@ __device__ __forceinline__ void fill_tile_tb(
   __syncthreads();
 }
 
-template <int Q, int MODE, bool kLDS, typename ZT, int kTBThreads>
+template <int Q, int MODE, bool kLDS, bool kRhoLDS, typename ZT, int kTBThreads>
 __global__ __launch_bounds__(kTBThreads)
 __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_fill_tb(
     FillItem S, FillRule W, int ntiles) {
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
-  // after the accumulator: the table's coefficients (table mode) or the
-  // tile's per-pair references (direct mode)
+  // after the accumulator: the table's coefficients (table mode; the test
+  // points' offsets in the gap between their two halves) or the tile's
+  // per-pair references and then the offsets (direct mode)
   const TabPtrs tab =
       load_table<MODE == MF_MODE_TABLE && kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
   float2 *gref = reinterpret_cast<float2 *>(smem4 + kTBAccFloats / 4 + 1);
+  // table mode with the coefficients in LDS: the offsets in the gap after
+  // (c0, c1), the per-pair fields in the gap after (c2, c3)
+  float *rho_lds =
+      MODE != MF_MODE_TABLE ? reinterpret_cast<float *>(gref + kRefFloat2)
+      : kLDS               ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 + (S.tn - 1))
+                           : reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1);
+  float *aux_lds = MODE == MF_MODE_TABLE && kLDS
+                       ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 + kLdsCoefHalf +
+                                                   (S.tn - 1))
+                       : rho_lds + kRhoFloats * kTBTris;
   float rlo = INFINITY, rhi = 0.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
-    fill_tile_tb<Q, MODE, ZT, kLDS, kTBThreads>(S, W, tab, acc, gref, t, rlo, rhi, S.rec, S.tb_pos,
-                                                S.tb_order, S.touch_off, S.touch_q, S.sing,
-                                                reinterpret_cast<ZT *>(S.Z), S.side);
+    fill_tile_tb<Q, MODE, ZT, kLDS, kRhoLDS, kTBThreads>(
+        S, W, tab, acc, gref, rho_lds, aux_lds, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order, S.touch_off,
+        S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
@@ -1722,10 +1755,10 @@ int launch_fill_near(mf_mesh *m, const Rule &r, double k, int mode, const mf_tab
   return rc;
 }
 
-template <int Q, int MODE, bool kLDS, typename ZT, int kTBThreads>
+template <int Q, int MODE, bool kLDS, bool kRhoLDS, typename ZT, int kTBThreads>
 static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
-  auto kern = k_fill_tb<Q, MODE, kLDS, ZT, kTBThreads>;
+  auto kern = k_fill_tb<Q, MODE, kLDS, kRhoLDS, ZT, kTBThreads>;
   static std::once_flag once;
   static long long grid = 0;
   static hipError_t ge = hipSuccess;
@@ -1767,23 +1800,24 @@ static int launch_tb_t(mf_mesh *m, const FillItem &S, const FillRule &W, size_t 
   return MF_OK;
 }
 
-template <int MODE, bool kLDS, typename ZT, int kTBThreads>
+template <int MODE, bool kLDS, bool kRhoLDS, typename ZT, int kTBThreads>
 static int launch_tb_q(mf_mesh *m, int nq, const FillItem &S, const FillRule &W, size_t lds,
                        hipStream_t s) {
   switch (nq) {
-    case 3: return launch_tb_t<3, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
-    case 6: return launch_tb_t<6, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
-    default: return launch_tb_t<7, MODE, kLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    case 3: return launch_tb_t<3, MODE, kLDS, kRhoLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    case 6: return launch_tb_t<6, MODE, kLDS, kRhoLDS, ZT, kTBThreads>(m, S, W, lds, s);
+    default: return launch_tb_t<7, MODE, kLDS, kRhoLDS, ZT, kTBThreads>(m, S, W, lds, s);
   }
 }
 
 template <typename ZT, int kTBThreads>
-static int launch_tb_z(mf_mesh *m, int nq, int mode, bool in_lds, const FillItem &S,
+static int launch_tb_z(mf_mesh *m, int nq, int mode, bool in_lds, bool rho_lds, const FillItem &S,
                        const FillRule &W, size_t lds, hipStream_t s) {
   if (mode == MF_MODE_DIRECT)
-    return launch_tb_q<MF_MODE_DIRECT, false, ZT, kTBThreads>(m, nq, S, W, lds, s);
-  return in_lds ? launch_tb_q<MF_MODE_TABLE, true, ZT, kTBThreads>(m, nq, S, W, lds, s)
-                : launch_tb_q<MF_MODE_TABLE, false, ZT, kTBThreads>(m, nq, S, W, lds, s);
+    return launch_tb_q<MF_MODE_DIRECT, false, true, ZT, kTBThreads>(m, nq, S, W, lds, s);
+  if (!in_lds) return launch_tb_q<MF_MODE_TABLE, false, true, ZT, kTBThreads>(m, nq, S, W, lds, s);
+  return rho_lds ? launch_tb_q<MF_MODE_TABLE, true, true, ZT, kTBThreads>(m, nq, S, W, lds, s)
+                 : launch_tb_q<MF_MODE_TABLE, true, false, ZT, kTBThreads>(m, nq, S, W, lds, s);
 }
 
 // EFIE fill on the triangle-block plan (k_fill_tb and the cut-edge fix-up),
@@ -1797,20 +1831,32 @@ static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, int mode, const m
   MF_HIP(hipGetDevice(&dev));
   MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   const size_t base = sizeof(float) * kTBAccFloats + 16;
-  bool in_lds = false;
+  const size_t rho_bytes = sizeof(float) * kRhoFloats * kTBTris;
+  const size_t aux_bytes = sizeof(float) * kAuxFloats * kTBTris;
+  bool in_lds = false, rho_lds = true;
   size_t lds = base;
   if (mode == MF_MODE_TABLE) {
     const size_t tbytes = table_lds_bytes(tab);
     in_lds = base + tbytes <= (size_t)maxlds;
-    if (in_lds) lds += tbytes;
+    if (in_lds) {
+      // the offsets go in the gap between the two coefficient halves
+      lds += tbytes;
+      rho_lds = (size_t)(tab->g.n - 1) * sizeof(float4) + std::max(rho_bytes, aux_bytes) <=
+                sizeof(float4) * (size_t)kLdsCoefHalf;
+    } else {
+      lds += rho_bytes + aux_bytes;
+    }
   } else {
-    lds += sizeof(float2) * kRefFloat2;  // the tile's per-pair references
+    // the tile's per-pair references, then the staged fields
+    lds += sizeof(float2) * kRefFloat2 + rho_bytes + aux_bytes;
   }
   if (threads == 512)
-    return z_dtype == MF_C64 ? launch_tb_z<float2, 512>(m, r.nq, mode, in_lds, S, W, lds, s)
-                             : launch_tb_z<double2, 512>(m, r.nq, mode, in_lds, S, W, lds, s);
-  return z_dtype == MF_C64 ? launch_tb_z<float2, 1024>(m, r.nq, mode, in_lds, S, W, lds, s)
-                           : launch_tb_z<double2, 1024>(m, r.nq, mode, in_lds, S, W, lds, s);
+    return z_dtype == MF_C64
+               ? launch_tb_z<float2, 512>(m, r.nq, mode, in_lds, rho_lds, S, W, lds, s)
+               : launch_tb_z<double2, 512>(m, r.nq, mode, in_lds, rho_lds, S, W, lds, s);
+  return z_dtype == MF_C64
+             ? launch_tb_z<float2, 1024>(m, r.nq, mode, in_lds, rho_lds, S, W, lds, s)
+             : launch_tb_z<double2, 1024>(m, r.nq, mode, in_lds, rho_lds, S, W, lds, s);
 }
 
 const char *fill_choice_name(int c) {
