@@ -112,10 +112,22 @@ struct FillItem {
 };
 typedef FillItem FillScalars;
 
-// Quadrature weights, common to every item of a launch.
+// Quadrature weights, common to every item of a launch, and the rule in a
+// triangle's own frame: point j is rho_j = s_j e1 + t_j e2 with e1 = v0 - c,
+// e2 = v1 - c and (s_j, t_j) = (l0 - l2, l1 - l2) from its barycentric
+// coordinates (sum l = 1, sum (v - c) = 0), the same for every triangle.
 struct FillRule {
   float w[kMaxQ];
+  float s2[kMaxQ], t2[kMaxQ];  // 2 s_j, 2 t_j
+  float ws[kMaxQ], wt[kMaxQ];  // w_j s_j, w_j t_j
 };
+
+// Which of s_j, t_j vanish in the symmetric rules (the orbit order of the
+// rule's definition): 0 both (the centroid), 1 t = 0, 2 s = 0, 3 s = t.
+// Orbit points (x, y, y), (y, x, y), (y, y, x) give kinds 1, 2, 3.
+__host__ __device__ constexpr int bary_kind(int Q, int j) {
+  return Q == 7 ? (j == 0 ? 0 : 1 + (j - 1) % 3) : 1 + j % 3;
+}
 
 struct TabPtrs {
   const int4 *look;     // one-sample bucket records {i0, x(i0), x(i0 + 1), -}
@@ -360,6 +372,161 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
       add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
     }
   }
+}
+
+// EFIE table mode in the rule's own frame.  With rho_i = -(s_i alpha_0 +
+// t_i alpha_1) on the test triangle and rho'_j = -(s_j beta_0 + t_j beta_1)
+// on the source triangle (alpha_a = c_p - v_a, beta_b = c_q - v_b), and the
+// rule's three weight vectors u^0 = w, u^s = w s, u^t = w t, the four
+// moments of a pair come from nine bilinear forms of g,
+//   N_xy = sum_ij u^x_i u^y_j g_ij,        x, y in {0, s, t},
+// through the dot products D_ab = alpha_a.beta_b:
+//   S0 = N_00,   alpha_a.Srho' = -(D_a0 N_0s + D_a1 N_0t),
+//   beta_b.Srho = -(D_0b N_s0 + D_1b N_t0),
+//   Srr = D_00 N_ss + D_01 N_st + D_10 N_ts + D_11 N_tt.
+// The inner sums over the source points skip the terms where s_j or t_j is
+// zero (bary_kind).  The distances use the same frame: with a_i = D + rho_i,
+// A = |a_i|^2 and B_b = a_i.beta_b,
+//   R^2 = A + 2 s_j B_0 + 2 t_j B_1 + |rho'_j|^2,
+// two operations per point pair instead of six.
+struct Bary {
+  float r[9], i[9];  // N_00, N_0s, N_0t, N_s0, N_ss, N_st, N_t0, N_ts, N_tt
+};
+
+template <int Q, bool kLDS>
+__device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const FillScalars &S,
+                                             const FillRule &W, const float *pr, float hx,
+                                             float hy, float hz, float lx, float ly, float lz,
+                                             cfloat *qr, float &rlo, float &rhi,
+                                             bool range = true) {
+#pragma unroll
+  for (int x = 0; x < 9; ++x) N.r[x] = N.i[x] = 0.0f;
+  float nq[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const float qx = qr[kRecRho + 3 * j], qy = qr[kRecRho + 3 * j + 1],
+                qz = qr[kRecRho + 3 * j + 2];
+    nq[j] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+  }
+  const float b0x = qr[kRecAlpha], b0y = qr[kRecAlpha + 1], b0z = qr[kRecAlpha + 2];
+  const float b1x = qr[kRecAlpha + 3], b1y = qr[kRecAlpha + 4], b1z = qr[kRecAlpha + 5];
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    const float ax = hx + (pr[kRecRho + 3 * i] + lx), ay = hy + (pr[kRecRho + 3 * i + 1] + ly),
+                az = hz + (pr[kRecRho + 3 * i + 2] + lz);
+    const float A = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float B0 = fmaf(ax, b0x, fmaf(ay, b0y, az * b0z));
+    const float B1 = fmaf(ax, b1x, fmaf(ay, b1y, az * b1z));
+    const float B01 = B0 + B1;
+    float r[Q];
+    int4 w[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int kind = bary_kind(Q, j);
+      // the centroid's rho'_j is zero up to the rounding of its FP64 mean
+      const float r2 = kind == 0   ? A
+                       : kind == 1 ? fmaf(W.s2[j], B0, A + nq[j])
+                       : kind == 2 ? fmaf(W.t2[j], B1, A + nq[j])
+                                   : fmaf(W.s2[j], B01, A + nq[j]);
+      r[j] = __builtin_amdgcn_sqrtf(r2);
+      w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
+    }
+    if (range) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        rlo = fminf(rlo, r[j]);
+        rhi = fmaxf(rhi, r[j]);
+      }
+    }
+    float u[Q];
+    float4 Ac[Q], Bc[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int off = look_offset1(w[j], r[j], u[j]);
+      Ac[j] = at_offset(tab.c01, off);
+      Bc[j] = kLDS ? at_offset(tab.c01, off + 16 * kLdsCoefHalf) : at_offset(tab.c23, off);
+    }
+    float t0r = 0.f, t0i = 0.f, tsr = 0.f, tsi = 0.f, ttr = 0.f, tti = 0.f;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int kind = bary_kind(Q, j);
+      const float2 g = cubic(Ac[j], Bc[j], u[j]);
+      t0r = fmaf(W.w[j], g.x, t0r);
+      t0i = fmaf(W.w[j], g.y, t0i);
+      if (kind == 1 || kind == 3) {
+        tsr = fmaf(W.ws[j], g.x, tsr);
+        tsi = fmaf(W.ws[j], g.y, tsi);
+      }
+      if (kind == 2 || kind == 3) {
+        ttr = fmaf(W.wt[j], g.x, ttr);
+        tti = fmaf(W.wt[j], g.y, tti);
+      }
+    }
+    const float u3[3] = {W.w[i], W.ws[i], W.wt[i]};
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      N.r[3 * x] = fmaf(u3[x], t0r, N.r[3 * x]);
+      N.i[3 * x] = fmaf(u3[x], t0i, N.i[3 * x]);
+      N.r[3 * x + 1] = fmaf(u3[x], tsr, N.r[3 * x + 1]);
+      N.i[3 * x + 1] = fmaf(u3[x], tsi, N.i[3 * x + 1]);
+      N.r[3 * x + 2] = fmaf(u3[x], ttr, N.r[3 * x + 2]);
+      N.i[3 * x + 2] = fmaf(u3[x], tti, N.i[3 * x + 2]);
+    }
+  }
+}
+
+// The nine local entries of a regular pair from its bilinear forms:
+//   X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + D_ab S0)/4 - S0/k^2;
+// PART drops the vector part (MF_PART_PHI) or the scalar part (MF_PART_A).
+template <int PART>
+__device__ __forceinline__ void entries_bary(const Bary &N, const float (&al)[3][3],
+                                             const float (&be)[3][3], float ik2,
+                                             float (&Xr)[3][3], float (&Xi)[3][3]) {
+  constexpr bool vec = !(PART & MF_PART_PHI), sca = !(PART & MF_PART_A);
+  float D[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      D[a][b] = fmaf(al[a][0], be[b][0], fmaf(al[a][1], be[b][1], al[a][2] * be[b][2]));
+  float c0r = 0.f, c0i = 0.f;
+  if (vec) {
+    c0r = 0.25f * fmaf(D[0][0], N.r[4], fmaf(D[0][1], N.r[5], fmaf(D[1][0], N.r[7],
+                                                                      D[1][1] * N.r[8])));
+    c0i = 0.25f * fmaf(D[0][0], N.i[4], fmaf(D[0][1], N.i[5], fmaf(D[1][0], N.i[7],
+                                                                      D[1][1] * N.i[8])));
+  }
+  if (sca) {
+    c0r = fmaf(-ik2, N.r[0], c0r);
+    c0i = fmaf(-ik2, N.i[0], c0i);
+  }
+  const float q0r = 0.25f * N.r[0], q0i = 0.25f * N.i[0];
+  float Ar[3], Ai[3], Br[3], Bi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Ar[a] = c0r;
+    Ai[a] = c0i;
+    Br[a] = Bi[a] = 0.0f;
+    if (vec) {
+      // alpha_a.Srho' / 4 and beta_a.Srho / 4
+      Ar[a] -= 0.25f * fmaf(D[a][0], N.r[1], D[a][1] * N.r[2]);
+      Ai[a] -= 0.25f * fmaf(D[a][0], N.i[1], D[a][1] * N.i[2]);
+      Br[a] = -0.25f * fmaf(D[0][a], N.r[3], D[1][a] * N.r[6]);
+      Bi[a] = -0.25f * fmaf(D[0][a], N.i[3], D[1][a] * N.i[6]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      float vr = Ar[a] + Br[b], vi = Ai[a] + Bi[b];
+      if (vec) {
+        vr = fmaf(D[a][b], q0r, vr);
+        vi = fmaf(D[a][b], q0i, vi);
+      }
+      Xr[a][b] = vr;
+      Xi[a][b] = vi;
+    }
 }
 
 // Direct mode: exp(-jkR)/R from rsqrt and sincos; the test-point loop stays
@@ -609,77 +776,86 @@ __device__ __forceinline__ void fill_tile(
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                     lz = (float)(Dz - (double)hz);
-        Moments M;
-        // s0r/s0i: S0 for the vector terms; scr/sci: S0 for the div-div term,
-        // less the reference the write-out adds back in FP64 (direct mode)
-        float s0r, s0i, scr, sci;
         if (MODE == MF_MODE_TABLE) {
-          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, pr, nullptr, nullptr, hx, hy, hz, lx,
-                                             ly, lz, qr, rlo, rhi);
-          s0r = scr = M.s0r;
-          s0i = sci = M.s0i;
-        } else {
-          float gr, gi;
-          direct_pair<Q>(M, S, W, pr, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
-          if (kRef) {
-            if (pv) gref[qi * kRefStride + pidx] = make_float2(gr, gi);
-            s0r = gr + scr;
-            s0i = gi + sci;
-          } else {
-            s0r = scr = gr + scr;
-            s0i = sci = gi + sci;
-          }
-        }
-        const float srr = M.srr, sri = M.sri;
-        const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
+          Bary N;
+          moments_bary<Q, kLDS>(N, tab, S, W, pr, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          float al[3][3], be[3][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
-        // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2,
-        // with the parts that depend on a or b alone formed once
-        float c0r = 0.f, c0i = 0.f;
-        if (!(PART & MF_PART_PHI)) {
-          c0r = 0.25f * srr;
-          c0i = 0.25f * sri;
-        }
-        if (!(PART & MF_PART_A)) {
-          c0r = fmaf(-S.ik2, scr, c0r);
-          c0i = fmaf(-S.ik2, sci, c0i);
-        }
-        float Ar[3], Ai[3], Br[3], Bi[3], beta[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          Ar[a] = c0r;
-          Ai[a] = c0i;
-          Br[a] = Bi[a] = 0.f;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) beta[a][c] = qr[kRecAlpha + 3 * a + c];
-          if (!(PART & MF_PART_PHI)) {
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
-              Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
-              Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
-              Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+              al[a][c] = pr[kRecAlpha + 3 * a + c];
+              be[a][c] = qr[kRecAlpha + 3 * a + c];
+            }
+          entries_bary<PART>(N, al, be, S.ik2, Xr, Xi);
+        } else {
+          Moments M;
+          // s0r/s0i: S0 for the vector terms; scr/sci: S0 for the div-div term,
+          // less the reference the write-out adds back in FP64 (direct mode)
+          float s0r, s0i, scr, sci;
+          {
+            float gr, gi;
+            direct_pair<Q>(M, S, W, pr, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
+            if (kRef) {
+              if (pv) gref[qi * kRefStride + pidx] = make_float2(gr, gi);
+              s0r = gr + scr;
+              s0i = gi + sci;
+            } else {
+              s0r = scr = gr + scr;
+              s0i = sci = gi + sci;
             }
           }
-        }
-        const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
+          const float srr = M.srr, sri = M.sri;
+          const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+          for (int a = 0; a < 3; ++a)
 #pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            float vr = Ar[a] + Br[b], vi = Ai[a] + Bi[b];
+            for (int c = 0; c < 3; ++c) palpha[a][c] = pr[kRecAlpha + 3 * a + c];
+          // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2,
+          // with the parts that depend on a or b alone formed once
+          float c0r = 0.f, c0i = 0.f;
+          if (!(PART & MF_PART_PHI)) {
+            c0r = 0.25f * srr;
+            c0i = 0.25f * sri;
+          }
+          if (!(PART & MF_PART_A)) {
+            c0r = fmaf(-S.ik2, scr, c0r);
+            c0i = fmaf(-S.ik2, sci, c0i);
+          }
+          float Ar[3], Ai[3], Br[3], Bi[3], beta[3][3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            Ar[a] = c0r;
+            Ai[a] = c0i;
+            Br[a] = Bi[a] = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) beta[a][c] = qr[kRecAlpha + 3 * a + c];
             if (!(PART & MF_PART_PHI)) {
-              const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
-                               palpha[a][2] * beta[b][2];
-              vr = fmaf(ab, q0r, vr);
-              vi = fmaf(ab, q0i, vi);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
+                Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
+                Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
+                Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+              }
             }
-            Xr[a][b] = vr;
-            Xi[a][b] = vi;
           }
+          const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              float vr = Ar[a] + Br[b], vi = Ai[a] + Bi[b];
+              if (!(PART & MF_PART_PHI)) {
+                const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
+                                 palpha[a][2] * beta[b][2];
+                vr = fmaf(ab, q0r, vr);
+                vi = fmaf(ab, q0i, vi);
+              }
+              Xr[a][b] = vr;
+              Xi[a][b] = vi;
+            }
+        }
       } else {
         int s = touch_off[p];
         const int s1 = touch_off[p + 1];
@@ -1110,10 +1286,14 @@ __device__ __forceinline__ void fill_tile_tb(
         cdouble *qcd = (cdouble *)(qr + kRecCent);
         const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
-        Moments M;
-        // s0r/s0i: S0 of the vector terms; scr/sci: S0 of the div-div term
-        // (direct mode: less the reference that the write-out adds in FP64)
-        float s0r, s0i, scr, sci;
+        float palpha[3][3], beta[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            palpha[a][c] = paux[3 * a + c];
+            beta[a][c] = qr[kRecAlpha + 3 * a + c];
+          }
         if (MODE == MF_MODE_TABLE) {
           const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
                       lz = (float)(Dz - (double)hz);
@@ -1123,47 +1303,47 @@ __device__ __forceinline__ void fill_tile_tb(
           const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
           const float rr = prad + qr[kRecRad], sl = 1e-5f * (dd + rr);
           const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
-          moments_table<Q, MF_OP_EFIE, kLDS>(M, tab, S, W, prho, nullptr, nullptr, hx, hy, hz,
-                                             lx, ly, lz, qr, rlo, rhi, __any(near_end) != 0);
-          s0r = scr = M.s0r;
-          s0i = sci = M.s0i;
+          Bary N;
+          moments_bary<Q, kLDS>(N, tab, S, W, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi,
+                                __any(near_end) != 0);
+          entries_bary<0>(N, palpha, beta, S.ik2, Xr, Xi);
         } else {
-          float gr, gi;
+          Moments M;
+          // s0r/s0i: S0 of the vector terms; scr/sci: S0 of the div-div term
+          // less the reference that the write-out adds in FP64
+          float gr, gi, scr, sci;
           direct_pair<Q>(M, S, W, prho, qr, Dx, Dy, Dz, hx, hy, hz, gr, gi, scr, sci);
           if (pv) gref[(q - tJ0) * kRefStride + lane] = make_float2(gr, gi);
-          s0r = gr + scr;
-          s0i = gi + sci;
-        }
-        const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
-        // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2
-        const float c0r = fmaf(-S.ik2, scr, 0.25f * M.srr);
-        const float c0i = fmaf(-S.ik2, sci, 0.25f * M.sri);
-        float Ar[3], Ai[3], Br[3], Bi[3], palpha[3][3], beta[3][3];
+          const float s0r = gr + scr, s0i = gi + sci;
+          const float *spr = M.spr, *spi = M.spi, *sqr = M.sqr, *sqi = M.sqi;
+          // X_ab = (Srr + alpha_a.Srho' + beta_b.Srho + (alpha_a.beta_b) S0)/4 - S0/k^2
+          const float c0r = fmaf(-S.ik2, scr, 0.25f * M.srr);
+          const float c0i = fmaf(-S.ik2, sci, 0.25f * M.sri);
+          float Ar[3], Ai[3], Br[3], Bi[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          Ar[a] = c0r;
-          Ai[a] = c0i;
-          Br[a] = Bi[a] = 0.f;
+          for (int a = 0; a < 3; ++a) {
+            Ar[a] = c0r;
+            Ai[a] = c0i;
+            Br[a] = Bi[a] = 0.f;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            palpha[a][c] = paux[3 * a + c];
-            beta[a][c] = qr[kRecAlpha + 3 * a + c];
-            Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
-            Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
-            Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
-            Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+            for (int c = 0; c < 3; ++c) {
+              Ar[a] = fmaf(0.25f * palpha[a][c], sqr[c], Ar[a]);
+              Ai[a] = fmaf(0.25f * palpha[a][c], sqi[c], Ai[a]);
+              Br[a] = fmaf(0.25f * beta[a][c], spr[c], Br[a]);
+              Bi[a] = fmaf(0.25f * beta[a][c], spi[c], Bi[a]);
+            }
           }
+          const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
+                               palpha[a][2] * beta[b][2];
+              Xr[a][b] = fmaf(ab, q0r, Ar[a] + Br[b]);
+              Xi[a][b] = fmaf(ab, q0i, Ai[a] + Bi[b]);
+            }
         }
-        const float q0r = 0.25f * s0r, q0i = 0.25f * s0i;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const float ab = palpha[a][0] * beta[b][0] + palpha[a][1] * beta[b][1] +
-                             palpha[a][2] * beta[b][2];
-            Xr[a][b] = fmaf(ab, q0r, Ar[a] + Br[b]);
-            Xi[a][b] = fmaf(ab, q0i, Ai[a] + Bi[b]);
-          }
       } else {
         // touching pairs carry no reference
         if (MODE != MF_MODE_TABLE && pv) gref[(q - tJ0) * kRefStride + lane] = make_float2(0.f, 0.f);
@@ -1593,6 +1773,31 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
 // Builds the launch of n items (all with the same rule, mode and Z type).
 // With more than one item the item list is copied to the device here
 // (synchronously); running the launch afterwards only enqueues the kernel.
+// The rule's weights and frame coefficients (FillRule).  The kernels take the
+// zero pattern of s_j, t_j from bary_kind; it is checked here against the
+// rule's barycentric coordinates.
+static bool fill_rule(const Rule &r, FillRule *W) {
+  *W = FillRule{};
+  for (int j = 0; j < r.nq; ++j) {
+    const double s = r.bary[j][0] - r.bary[j][2], t = r.bary[j][1] - r.bary[j][2];
+    const int kind = bary_kind(r.nq, j);
+    const bool ok = kind == 0   ? (s == 0.0 && t == 0.0)
+                    : kind == 1 ? (s != 0.0 && t == 0.0)
+                    : kind == 2 ? (s == 0.0 && t != 0.0)
+                                : (s != 0.0 && s == t);
+    if (!ok) {
+      set_error("fill: quadrature rule does not have the orbit layout of the kernels");
+      return false;
+    }
+    W->w[j] = (float)r.w[j];
+    W->s2[j] = (float)(2.0 * s);
+    W->t2[j] = (float)(2.0 * t);
+    W->ws[j] = (float)(r.w[j] * s);
+    W->wt[j] = (float)(r.w[j] * t);
+  }
+  return true;
+}
+
 size_t fill_items_bytes(int n) { return sizeof(FillItem) * (size_t)n; }
 
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
@@ -1609,7 +1814,10 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   L->part = mode & (MF_PART_A | MF_PART_PHI);
   L->op = (mode & kModeMfie) ? MF_OP_MFIE : MF_OP_EFIE;
   L->z_dtype = z_dtype;
-  for (int i = 0; i < kMaxQ; ++i) L->rule.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+  if (!fill_rule(r, &L->rule)) {
+    delete L;
+    return MF_EINVAL;
+  }
   L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 3 : 2) + 16;
   // direct EFIE: the per-pair references of the div-div term
   if (L->op == MF_OP_EFIE && L->base == MF_MODE_DIRECT && !(L->part & MF_PART_A))
@@ -1826,7 +2034,7 @@ static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, int mode, const m
                           void *Z, int z_dtype, int64_t ldz, hipStream_t s, int threads) {
   FillItem S = make_item(m, r, k, mode, tab, Z, ldz, m->d_sing, 0);
   FillRule W;
-  for (int i = 0; i < kMaxQ; ++i) W.w[i] = i < r.nq ? (float)r.w[i] : 0.0f;
+  if (!fill_rule(r, &W)) return MF_EINVAL;
   int dev = 0, maxlds = 0;
   MF_HIP(hipGetDevice(&dev));
   MF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
