@@ -242,13 +242,14 @@ def sweep_timing(mf, steps, group=8, tol=1e-5):
     for md in mesh_data:
         mf.sync_status(md[0])
     entries = sum(md[0].n_edges ** 2 for md in mesh_data) * len(ks)
-    threads, tune_ms = batches[0].tuning()
+    shape, threads, tune_ms = batches[0].tuning()
     return {
         "workload": "3 jittered icospheres (1280/5120/20480 triangles) x 32 k in [4, 20] rad/m, "
                     "6-point rule, table tol 1e-5, complex64; 4 launches of 24 items in one graph",
         "items": len(mesh_data) * len(ks),
+        "tuned_tile_shape": f"{shape} blocks",
         "tuned_threads": threads,
-        "tuning_ms_512_768_1024": tune_ms,
+        "tuning_ms_eb512_eb768_eb1024_tb1024_tb512": tune_ms,
         "ms_per_sweep": dt * 1e3,
         "z_entries_per_s": entries / dt,
         "table_build_ms_per_sweep": t_tables * 1e3,

@@ -309,17 +309,31 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *vert
  * allocates nothing and copies nothing, so a HIP graph can capture it. */
 int mf_batch_fill(mf_batch *batch, hipStream_t stream);
 /* Tile-shape tuner.  mf_batch_create, before returning, fills the batch once
- * on the null stream and times the persistent launch with 512, 768 and 1024
- * threads per workgroup (2, 3 or 4 waves per SIMD, trading each lane's
- * register budget against the latency hiding of the table gathers), keeping
- * the fastest for the batch; the choice is cached per (quad_order, mode,
- * table placement, z_dtype) for the process and in the MOMFILL_TUNE_CACHE
- * file when it is set (as for mf_fill_tune), so later batches of the same
- * kind skip the timing.  The outputs hold the batch's result when
- * mf_batch_create returns.  mf_batch_info reports the choice (*threads) and
- * the three timings in milliseconds (tune_ms3, zeros when the cache
- * answered); either pointer may be NULL. */
-int mf_batch_info(const mf_batch *batch, int32_t *threads, float *tune_ms3);
+ * on the null stream and times the persistent launch with each candidate
+ * tile shape: edge-block tiles (runs of at most 80 edges, the tiles of
+ * neighbouring blocks sharing triangles) with 512, 768 and 1024 threads per
+ * workgroup (2, 3 or 4 waves per SIMD: each lane's register budget against
+ * the latency hiding of the table gathers), and, when every item's mesh has
+ * a triangle-block plan (mf_mesh_tb_plan), triangle-block tiles (each
+ * unordered triangle pair evaluated once, cut edges completed by a fix-up
+ * per item) with 1024 and 512 threads (one or two source triangles per wave
+ * and round).  It keeps the fastest; the choice is cached per (quad_order,
+ * mode, table placement, z_dtype, plan availability) for the process and
+ * in the MOMFILL_TUNE_CACHE file when it is set (as for mf_fill_tune), so
+ * later batches of the same kind skip the timing.  The outputs hold the
+ * batch's result when mf_batch_create returns.  mf_batch_info reports the
+ * choice (*threads, *tile_shape: 0 edge blocks, 1 triangle blocks) and the
+ * five timings in milliseconds in the order above (tune_ms5; zeros for the
+ * candidates not run and when the cache answered); any pointer may be
+ * NULL.  With triangle-block plans the workspace holds a cut-edge side
+ * buffer per item, 8 n_cut (E + n_cut) bytes. */
+int mf_batch_info(const mf_batch *batch, int32_t *threads, int32_t *tile_shape,
+                  float *tune_ms5);
+/* Pins the batch's launch to candidate `choice` of the tuner's list (0-2:
+ * edge blocks at 512, 768, 1024 threads; 3, 4: triangle blocks at 1024, 512
+ * threads) for its later mf_batch_fill calls, for tests and measurements.
+ * MF_EINVAL for an index out of range or triangle blocks without plans. */
+int mf_batch_set_choice(mf_batch *batch, int32_t choice);
 void mf_batch_destroy(mf_batch *batch);
 
 /* ---- near-field fill (Section II-A) --------------------------------------

@@ -396,13 +396,23 @@ class Batch:
     def fill(self):
         check(lib().mf_batch_fill(self._h, _stream()))
 
+    # the tuner's candidates, in the order of its timings
+    CANDIDATES = (("edge", 512), ("edge", 768), ("edge", 1024), ("triangle", 1024),
+                  ("triangle", 512))
+
     def tuning(self):
-        """(threads per workgroup picked by the tuner, its three timings in ms
-        for 512/768/1024 threads; zeros when an earlier batch's choice was reused)."""
+        """(tile shape picked by the tuner, "edge" or "triangle" blocks,
+        threads per workgroup, its timings in ms for CANDIDATES; zeros for
+        candidates not run and when an earlier batch's choice was reused)."""
         t = C.c_int32()
-        ms = (C.c_float * 3)()
-        check(lib().mf_batch_info(self._h, C.byref(t), ms))
-        return t.value, [float(v) for v in ms]
+        sh = C.c_int32()
+        ms = (C.c_float * len(self.CANDIDATES))()
+        check(lib().mf_batch_info(self._h, C.byref(t), C.byref(sh), ms))
+        return ("edge", "triangle")[sh.value], t.value, [float(v) for v in ms]
+
+    def set_choice(self, shape: str, threads: int):
+        """Pins the launch to one of CANDIDATES for later fill() calls."""
+        check(lib().mf_batch_set_choice(self._h, self.CANDIDATES.index((shape, int(threads)))))
 
     def __del__(self, _L=_L):
         if getattr(self, "_h", None) and _L._lib is not None:

@@ -29,7 +29,7 @@ EXPORTS = [
     "mf_batch_destroy", "mf_near_create", "mf_near_info", "mf_near_pattern", "mf_fill_near",
     "mf_near_destroy", "mf_rhs_planewave", "mf_far_field", "mf_fill_mfie",
     "mf_rhs_planewave_mfie", "mf_fill_angular", "mf_angular_rmax", "mf_build_exp_table",
-    "mf_batch_info", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
+    "mf_batch_info", "mf_batch_set_choice", "mf_mesh_workspace_bytes", "mf_mesh_set_workspace",
     "mf_tables_workspace_bytes", "mf_exp_table_workspace_bytes", "mf_batch_workspace_bytes",
     "mf_near_workspace_bytes", "mf_near_set_workspace", "mf_r_range_static", "mf_mesh_tb_plan",
     "mf_fill_tune", "mf_fill_choice_name", "mf_mesh_fill_timings", "mf_mesh_set_fill_choice",
@@ -87,7 +87,9 @@ def lib():
         L.mf_rhs_planewave.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int, vp]
         L.mf_rhs_planewave_mfie.argtypes = [vp, vp, C.c_double, C.c_int, dp, dp, vp, C.c_int,
                                             vp]
-        L.mf_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.mf_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_float)]
+        L.mf_batch_set_choice.argtypes = [vp, C.c_int32]
         L.mf_fill_angular.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp,
                                       C.c_int, C.c_int64, vp]
         L.mf_angular_rmax.argtypes = [vp, vp, C.c_int, dp, vp]

@@ -522,10 +522,12 @@ struct mf_batch {
   std::vector<mf_mesh *> mesh;
   std::vector<const double *> V;
   std::vector<double> k;
-  std::vector<float *> sing;  // per-item touching-pair blocks (owned)
+  std::vector<float *> sing;  // per-item touching-pair blocks (in the workspace)
+  std::vector<float *> side;  // per-item cut-edge side buffers (in the workspace)
   mf::FillLaunch *launch = nullptr;
   int threads = 0;             // workgroup size picked by the tuner
-  float tune_ms[3] = {0.0f, 0.0f, 0.0f};
+  int shape = 0;               // tile shape picked by the tuner (0 edge, 1 triangle blocks)
+  float tune_ms[mf::kBatchChoices] = {};
 };
 
 using namespace mf;
@@ -906,12 +908,23 @@ int mf_fill_angular(mf_mesh *m, const double *V, double k, int quad_order, int n
 
 // The batch's device arrays: per item its touching-pair blocks, then the
 // item list of the launch (d == nullptr: count only).
+// The batch's workspace: per item its touching-pair blocks and, when every
+// mesh has a triangle-block plan, a cut-edge side buffer (each item fills
+// its own, so items that share a mesh can run in one launch), then the item
+// list.
 static bool carve_batch(int n, mf_mesh *const *meshes, Arena &A, std::vector<float *> *sing,
-                        void **items) {
+                        std::vector<float *> *side, void **items) {
+  bool tb = n > 1;
+  for (int i = 0; i < n; ++i) tb = tb && meshes[i]->tb_ok;
   for (int i = 0; i < n; ++i) {
     float *p = nullptr;
     if (!A.bottom(&p, 18 * std::max<size_t>(meshes[i]->touch_q.size(), 1))) return false;
     if (sing) (*sing)[i] = p;
+    float *q = nullptr;
+    if (tb && !A.bottom(&q, 2 * (size_t)meshes[i]->n_cut *
+                                ((size_t)meshes[i]->ne + meshes[i]->n_cut)))
+      return false;
+    if (side) (*side)[i] = q;
   }
   char *it = nullptr;
   if (!A.bottom(&it, fill_items_bytes(n))) return false;
@@ -924,7 +937,7 @@ int mf_batch_workspace_bytes(int32_t n, mf_mesh *const *meshes, size_t *bytes) {
   for (int i = 0; i < n; ++i)
     if (!meshes[i]) return fail(MF_EINVAL, "mf_batch_workspace_bytes: NULL mesh");
   Arena A = Arena::counter();
-  carve_batch(n, meshes, A, nullptr, nullptr);
+  carve_batch(n, meshes, A, nullptr, nullptr, nullptr);
   *bytes = A.lo;
   return MF_OK;
 }
@@ -969,21 +982,23 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, c
   int rc = MF_OK;
   for (int i = 0; i < n && !rc; ++i) rc = ensure_device(meshes[i]);
   b->sing.assign(n, nullptr);
+  b->side.assign(n, nullptr);
   void *items = nullptr;
   Arena A(ws, ws_bytes);
-  if (!rc && !carve_batch(n, meshes, A, &b->sing, &items))
+  if (!rc && !carve_batch(n, meshes, A, &b->sing, &b->side, &items))
     rc = fail(MF_EINVAL, "mf_batch_create: workspace too small (mf_batch_workspace_bytes)");
   if (!rc) {
     std::vector<const float *> sing(b->sing.begin(), b->sing.end());
+    const bool sides = n > 1 && b->side[0] != nullptr;
     rc = fill_launch_create(n, meshes, k, tab, r, mode, Z, z_dtype, ldz, sing.data(), items,
-                            &b->launch);
+                            &b->launch, sides ? b->side.data() : nullptr);
   }
   // tile-shape tuning on the real inputs: geometry and touching blocks first,
   // then the launch variants (writing the outputs); all on the null stream
   if (!rc) {
     *out = b;
     rc = mf_batch_fill(b, nullptr);
-    if (!rc) rc = fill_launch_autotune(b->launch, nullptr, b->tune_ms, &b->threads);
+    if (!rc) rc = fill_launch_autotune(b->launch, nullptr, b->tune_ms, &b->threads, &b->shape);
     if (!rc) {
       hipError_t e = hipStreamSynchronize(nullptr);
       if (e != hipSuccess) rc = hip_fail(e, "mf_batch_create: tuning");
@@ -998,11 +1013,21 @@ int mf_batch_create(int32_t n, mf_mesh *const *meshes, const double *const *V, c
   return MF_OK;
 }
 
-int mf_batch_info(const mf_batch *b, int32_t *threads, float *tune_ms3) {
+int mf_batch_info(const mf_batch *b, int32_t *threads, int32_t *tile_shape, float *tune_ms5) {
   if (!b) return fail(MF_EINVAL, "mf_batch_info: batch is NULL");
   if (threads) *threads = b->threads;
-  if (tune_ms3)
-    for (int i = 0; i < 3; ++i) tune_ms3[i] = b->tune_ms[i];
+  if (tile_shape) *tile_shape = b->shape;
+  if (tune_ms5)
+    for (int i = 0; i < kBatchChoices; ++i) tune_ms5[i] = b->tune_ms[i];
+  return MF_OK;
+}
+
+int mf_batch_set_choice(mf_batch *b, int32_t choice) {
+  if (!b) return fail(MF_EINVAL, "mf_batch_set_choice: batch is NULL");
+  const int rc = fill_launch_set_choice(b->launch, choice);
+  if (rc) return rc;
+  b->shape = choice >= 3 ? 1 : 0;
+  b->threads = choice == 0 ? 512 : choice == 1 ? 768 : choice == 4 ? 512 : 1024;
   return MF_OK;
 }
 

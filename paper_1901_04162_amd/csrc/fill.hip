@@ -81,6 +81,7 @@ constexpr int fill_threads_op() {
 // tile_end - 1 belong to this item).
 struct FillItem {
   int tile_begin, tile_end;
+  int tb_begin, tb_end;  // the item's range in the batch's triangle-block tile list
   int ne;
   double kd;  // wavenumber (FP64: the per-pair reference phase of direct mode)
   float k, ik2;
@@ -100,6 +101,8 @@ struct FillItem {
   long long lside;
   const int32_t *edges;   // ne x 6: v_lo, v_hi, T+, T-, a+, a-
   const int32_t *cut_idx; // ne: cut index of an edge, -1 inside a block
+  const int32_t *cut_edge;  // n_cut: edge of each cut index
+  int n_cut;
   const float *sing;
   const int4 *look;
   const float4 *coef;
@@ -1484,6 +1487,44 @@ __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_
   if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
+// Several items on the triangle-block plan in one persistent launch: the
+// workgroups stride through the items' concatenated triangle-block tile
+// lists (as k_fill_batch does over edge-block tiles), loading each item's
+// table once; every item has its own side buffer, and its cut-edge fix-up
+// follows the launch.
+template <int Q, int MODE, bool kLDS, bool kRhoLDS, typename ZT, int kTBThreads>
+__global__ __launch_bounds__(kTBThreads)
+__attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_fill_tb_batch(
+    const FillItem *__restrict__ items, int n_items, FillRule W) {
+  extern __shared__ float4 smem4[];
+  float *acc = reinterpret_cast<float *>(smem4);
+  float2 *gref = reinterpret_cast<float2 *>(smem4 + kTBAccFloats / 4 + 1);
+  const int G = gridDim.x;
+  for (int it = 0; it < n_items; ++it) {
+    const FillItem &S = items[it];
+    int t = S.tb_begin + (((int)blockIdx.x - S.tb_begin) % G + G) % G;
+    if (t >= S.tb_end) continue;
+    const TabPtrs tab =
+        load_table<MODE == MF_MODE_TABLE && kLDS, kTBThreads>(S, smem4 + kTBAccFloats / 4 + 1);
+    float *rho_lds =
+        MODE != MF_MODE_TABLE ? reinterpret_cast<float *>(gref + kRefFloat2)
+        : kLDS ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 + (S.tn - 1))
+               : reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1);
+    float *aux_lds = MODE == MF_MODE_TABLE && kLDS
+                         ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 +
+                                                     kLdsCoefHalf + (S.tn - 1))
+                         : rho_lds + kRhoFloats * kTBTris;
+    float rlo = INFINITY, rhi = 0.0f;
+    for (; t < S.tb_end; t += G)
+      fill_tile_tb<Q, MODE, ZT, kLDS, kRhoLDS, kTBThreads>(
+          S, W, tab, acc, gref, rho_lds, aux_lds, t - S.tb_begin, rlo, rhi, S.rec, S.tb_pos,
+          S.tb_order, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
+    if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+    // the next item's table overwrites this one's in LDS
+    __syncthreads();
+  }
+}
+
 // Cut-edge fix-up, one 64 x 64 tile per workgroup: 64 cut edges c (rows) by
 // 64 consecutive edges n (columns).  Each entry Z[c][n] is completed from
 // the owned part the fill wrote and the side buffer, (c^ x own n), and for a
@@ -1598,6 +1639,12 @@ struct FillLaunch {
   int threads = 0;  // workgroup size of a batched launch (0: the mode's default)
   bool lds_tab = false, sparse = false;
   long long grid = 0;
+  // Batched launch on the triangle-block plan (every item's mesh has one and
+  // a side buffer of its own): shape 1 selects it.
+  bool tb_ok = false, tb_in_lds = false, tb_rho_lds = true;
+  int shape = 0, tb_total = 0;
+  size_t tb_lds = 0;
+  std::vector<FillItem> host_items;  // for the per-item cut-edge fix-ups
 };
 
 template <typename K>
@@ -1705,7 +1752,72 @@ static int launch_z(FillLaunch &L, bool plan_only, hipStream_t s) {
   }
 }
 
+// Batched launch on the triangle-block plan, then each item's cut-edge
+// fix-up (as launch_tb_t does for one item).
+template <int Q, int MODE, bool kLDS, bool kRhoLDS, typename ZT, int kThr>
+static int launch_tb_batch(FillLaunch &L, bool plan_only, hipStream_t s) {
+  auto kern = k_fill_tb_batch<Q, MODE, kLDS, kRhoLDS, ZT, kThr>;
+  if (L.grid == 0) {
+    int dev = 0, ncu = 0, per = 0;
+    MF_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)L.tb_lds));
+    MF_HIP(hipGetDevice(&dev));
+    MF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThr, L.tb_lds));
+    if (per < 1) {
+      set_error("batched triangle-block fill kernel does not fit on a compute unit");
+      return MF_EINVAL;
+    }
+    L.grid = std::min<long long>((long long)ncu * per, std::max(L.tb_total, 1));
+    if (getenv("MOMFILL_VERBOSE"))
+      fprintf(stderr, "[momfill] k_fill_tb_batch Q=%d mode=%d lds_table=%d items=%d grid=%lld x %d lds=%zu B\n",
+              Q, MODE, (int)kLDS, L.n, L.grid, kThr, L.tb_lds);
+  }
+  if (plan_only || L.tb_total == 0) return MF_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3(kThr), L.tb_lds, s, L.d_items, L.n,
+                     L.rule);
+  MF_HIP(hipGetLastError());
+  for (const FillItem &S : L.host_items) {
+    if (S.n_cut <= 0) continue;
+    const dim3 fg((unsigned)((S.ne + kFixTile - 1) / kFixTile),
+                  (unsigned)((S.n_cut + kFixTile - 1) / kFixTile));
+    hipLaunchKernelGGL((k_cut_fix<ZT, MODE != MF_MODE_TABLE>), fg, dim3(256), 0, s,
+                       reinterpret_cast<ZT *>(S.Z), S.ldz, S.ne, S.n_cut, S.cut_edge, S.cut_idx,
+                       reinterpret_cast<const float2 *>(S.side), S.lside, S);
+    MF_HIP(hipGetLastError());
+  }
+  return MF_OK;
+}
+
+template <int Q, int MODE, bool kLDS, bool kRhoLDS, typename ZT>
+static int launch_tb_batch_t(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.threads == 512) return launch_tb_batch<Q, MODE, kLDS, kRhoLDS, ZT, 512>(L, plan_only, s);
+  return launch_tb_batch<Q, MODE, kLDS, kRhoLDS, ZT, 1024>(L, plan_only, s);
+}
+
+template <int Q, typename ZT>
+static int launch_tb_batch_q(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.base == MF_MODE_DIRECT)
+    return launch_tb_batch_t<Q, MF_MODE_DIRECT, false, true, ZT>(L, plan_only, s);
+  if (!L.tb_in_lds) return launch_tb_batch_t<Q, MF_MODE_TABLE, false, true, ZT>(L, plan_only, s);
+  return L.tb_rho_lds ? launch_tb_batch_t<Q, MF_MODE_TABLE, true, true, ZT>(L, plan_only, s)
+                      : launch_tb_batch_t<Q, MF_MODE_TABLE, true, false, ZT>(L, plan_only, s);
+}
+
+template <typename ZT>
+static int launch_tb_batch_z(FillLaunch &L, bool plan_only, hipStream_t s) {
+  switch (L.nq) {
+    case 3: return launch_tb_batch_q<3, ZT>(L, plan_only, s);
+    case 6: return launch_tb_batch_q<6, ZT>(L, plan_only, s);
+    default: return launch_tb_batch_q<7, ZT>(L, plan_only, s);
+  }
+}
+
 static int dispatch(FillLaunch &L, bool plan_only, hipStream_t s) {
+  if (L.shape == 1) {
+    if (L.z_dtype == MF_C64) return launch_tb_batch_z<float2>(L, plan_only, s);
+    return launch_tb_batch_z<double2>(L, plan_only, s);
+  }
   if (L.z_dtype == MF_C64) return launch_z<float2>(L, plan_only, s);
   return launch_z<double2>(L, plan_only, s);
 }
@@ -1718,10 +1830,12 @@ static size_t table_lds_bytes(const mf_tables *tab) {
 
 static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
                           const mf_tables *tab, void *Z, int64_t ldz, const float *sing,
-                          int tile_begin) {
+                          int tile_begin, int tb_begin = 0, float *side = nullptr) {
   FillItem S{};
   S.tile_begin = tile_begin;
   S.tile_end = tile_begin + (int)m->tiles.size();
+  S.tb_begin = tb_begin;
+  S.tb_end = tb_begin + (m->tb_ok ? (int)m->tb_tiles.size() : 0);
   S.ne = m->ne;
   S.kd = k;
   S.k = (float)k;
@@ -1745,10 +1859,12 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.tb_order = m->d_tb_order;
   S.tb_rounds = m->d_tb_rounds;
   S.tb_tiles = m->d_tb_tiles;
-  S.side = reinterpret_cast<float2 *>(m->d_side);
+  S.side = reinterpret_cast<float2 *>(side ? side : m->d_side);
   S.lside = (long long)m->ne + m->n_cut;
   S.edges = m->d_edges;
   S.cut_idx = m->d_cut_idx;
+  S.cut_edge = m->d_cut_edge;
+  S.n_cut = m->tb_ok ? m->n_cut : 0;
   S.touch_off = m->d_touch_off;
   S.touch_q = m->d_touch_q;
   S.touch_rev = m->d_touch_rev;
@@ -1770,9 +1886,6 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   return S;
 }
 
-// Builds the launch of n items (all with the same rule, mode and Z type).
-// With more than one item the item list is copied to the device here
-// (synchronously); running the launch afterwards only enqueues the kernel.
 // The rule's weights and frame coefficients (FillRule).  The kernels take the
 // zero pattern of s_j, t_j from bary_kind; it is checked here against the
 // rule's barycentric coordinates.
@@ -1798,11 +1911,15 @@ static bool fill_rule(const Rule &r, FillRule *W) {
   return true;
 }
 
+// Builds the launch of n items (all with the same rule, mode and Z type).
+// With more than one item the item list is copied to the device here
+// (synchronously); running the launch afterwards only enqueues the kernel.
 size_t fill_items_bytes(int n) { return sizeof(FillItem) * (size_t)n; }
 
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
                        const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
-                       const float *const *sing, void *items_dev, FillLaunch **out) {
+                       const float *const *sing, void *items_dev, FillLaunch **out,
+                       float *const *side) {
   FillLaunch *L = new (std::nothrow) FillLaunch;
   if (!L) {
     set_error("out of host memory");
@@ -1822,32 +1939,65 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
   // direct EFIE: the per-pair references of the div-div term
   if (L->op == MF_OP_EFIE && L->base == MF_MODE_DIRECT && !(L->part & MF_PART_A))
     L->lds += sizeof(float2) * kRefFloat2;
+  // triangle-block tiles for a batch: EFIE, no partial mode, every mesh with a
+  // triangle-block plan and every item with a side buffer of its own
+  bool tb = n > 1 && L->op == MF_OP_EFIE && L->part == 0 && side != nullptr;
+  for (int i = 0; i < n && tb; ++i) tb = m[i]->tb_ok && side[i] != nullptr;
   std::vector<FillItem> items(n);
   size_t tmax = 0;
-  int tiles = 0;
+  int tiles = 0, tb_tiles = 0, tn_max = 0;
   for (int i = 0; i < n; ++i) {
     items[i] = make_item(m[i], r, k[i], L->base, tab ? tab[i] : nullptr, Z[i], ldz[i], sing[i],
-                         tiles);
+                         tiles, tb_tiles, tb ? side[i] : nullptr);
     if (L->op == MF_OP_MFIE) items[i].pref = (float)(1.0 / (4.0 * M_PI));
     tiles = items[i].tile_end;
-    if (L->base == MF_MODE_TABLE) tmax = std::max(tmax, table_lds_bytes(tab[i]));
+    tb_tiles = items[i].tb_end;
+    if (L->base == MF_MODE_TABLE) {
+      tmax = std::max(tmax, table_lds_bytes(tab[i]));
+      tn_max = std::max(tn_max, tab[i]->g.n);
+    }
   }
   L->total_tiles = tiles;
   L->first = items[0];
   int rc = MF_OK;
-  if (L->base == MF_MODE_TABLE) {
-    int dev = 0, maxlds = 0;
+  int dev = 0, maxlds = 0;
+  {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess)
       e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) rc = hip_fail(e, "device attributes");
+  }
+  if (!rc && L->base == MF_MODE_TABLE) {
     // the MFIE reads its table through the vector L1: with the table in LDS
     // its fill measured slower (bank conflicts against its longer moments)
-    if (!rc && L->op != MF_OP_MFIE && L->lds + tmax <= (size_t)maxlds) {
+    if (L->op != MF_OP_MFIE && L->lds + tmax <= (size_t)maxlds) {
       L->lds_tab = true;
       L->lds += tmax;
     }
   }
+  if (!rc && tb) {
+    // LDS of the triangle-block tile as for a single fill (launch_fill_tb)
+    const size_t base = sizeof(float) * kTBAccFloats + 16;
+    const size_t rho_bytes = sizeof(float) * kRhoFloats * kTBTris;
+    const size_t aux_bytes = sizeof(float) * kAuxFloats * kTBTris;
+    size_t lds = base;
+    if (L->base == MF_MODE_TABLE) {
+      L->tb_in_lds = base + tmax <= (size_t)maxlds;
+      if (L->tb_in_lds) {
+        lds += tmax;
+        L->tb_rho_lds = (size_t)(tn_max - 1) * sizeof(float4) + std::max(rho_bytes, aux_bytes) <=
+                        sizeof(float4) * (size_t)kLdsCoefHalf;
+      } else {
+        lds += rho_bytes + aux_bytes;
+      }
+    } else {
+      lds += sizeof(float2) * kRefFloat2 + rho_bytes + aux_bytes;
+    }
+    L->tb_ok = lds <= (size_t)maxlds;
+    L->tb_lds = lds;
+    L->tb_total = tb_tiles;
+  }
+  L->host_items = items;
   if (!rc && n > 1 && L->op == MF_OP_MFIE) {
     set_error("the MFIE fill takes one item");
     rc = MF_EINVAL;
@@ -1874,16 +2024,22 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
 
 int fill_launch_run(FillLaunch *L, hipStream_t s) { return dispatch(*L, false, s); }
 
-// Tile-shape tuner of batched launches: the workgroup size sets the waves per
-// SIMD (2, 3 or 4) and with them the register budget of a lane (256, 168 or
-// 128 VGPRs) against the latency hiding of the LDS gathers.  Each candidate
-// runs the whole launch once to warm up and once timed with HIP events; the
-// fastest is kept for every later launch with the same rule, mode, table
-// placement and output type in this process.
-int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads) {
-  static const int kCand[3] = {512, 768, 1024};
-  if (ms3)
-    for (int i = 0; i < 3; ++i) ms3[i] = 0.0f;
+// Tile-shape tuner of batched launches.  Candidates: edge-block tiles with
+// 512, 768 or 1024 threads per workgroup (2, 3 or 4 waves per SIMD, trading
+// each lane's register budget against the latency hiding of the table
+// gathers) and, when every item has a triangle-block plan and a side buffer,
+// triangle-block tiles with 1024 or 512 threads (one or two source
+// triangles per wave and round).  Each candidate runs the whole launch once
+// to warm up and once timed with HIP events; the fastest is kept for every
+// later launch with the same rule, mode, table placement, output type and
+// plan availability in this process (and in the MOMFILL_TUNE_CACHE file).
+static const int kBatchCand[kBatchChoices][2] = {
+    {0, 512}, {0, 768}, {0, 1024}, {1, 1024}, {1, 512}};
+
+int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms, int *threads, int *shape) {
+  if (ms)
+    for (int i = 0; i < kBatchChoices; ++i) ms[i] = 0.0f;
+  if (shape) *shape = 0;
   if (L->n < 2 || L->op != MF_OP_EFIE || L->sparse) {  // single fills keep the defaults
     if (threads)
       *threads = L->threads ? L->threads
@@ -1891,15 +2047,21 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
                                                    : fill_threads<MF_MODE_TABLE>());
     return MF_OK;
   }
+  const int nc = L->tb_ok ? kBatchChoices : 3;
   const std::string key = "batch q=" + std::to_string(L->nq) + " mode=" + std::to_string(L->base) +
                           " ldstable=" + std::to_string((int)L->lds_tab) +
-                          " z=" + std::to_string(L->z_dtype);
+                          " z=" + std::to_string(L->z_dtype) + " tb=" + std::to_string((int)L->tb_ok);
+  auto apply = [&](int c) {
+    L->shape = kBatchCand[c][0];
+    L->threads = kBatchCand[c][1];
+    L->grid = 0;
+    if (threads) *threads = L->threads;
+    if (shape) *shape = L->shape;
+  };
   {
-    int cached = 0;
-    if (tune_cache_get(key, &cached) && (cached == 512 || cached == 768 || cached == 1024)) {
-      L->threads = cached;
-      L->grid = 0;
-      if (threads) *threads = L->threads;
+    int cached = -1;
+    if (tune_cache_get(key, &cached) && cached >= 0 && cached < nc) {
+      apply(cached);
       return dispatch(*L, true, nullptr);
     }
   }
@@ -1910,33 +2072,42 @@ int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads)
     (void)hipEventDestroy(e0);
     return hip_fail(he, "tuner events");
   }
-  int rc = MF_OK, best = 768;
+  int rc = MF_OK, best = 1;
   float best_ms = INFINITY;
-  for (int c = 0; c < 3 && !rc; ++c) {
-    L->threads = kCand[c];
-    L->grid = 0;
+  for (int c = 0; c < nc && !rc; ++c) {
+    apply(c);
     rc = dispatch(*L, false, s);  // warm-up (and grid plan)
     if (rc) break;
     he = hipEventRecord(e0, s);
     if (he == hipSuccess) rc = dispatch(*L, false, s);
     if (!rc && he == hipSuccess) he = hipEventRecord(e1, s);
     if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    float t = 0.0f;
+    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
     if (he != hipSuccess) rc = hip_fail(he, "tuner timing");
-    if (ms3) ms3[c] = ms;
-    if (!rc && ms < best_ms) {
-      best_ms = ms;
-      best = kCand[c];
+    if (ms) ms[c] = t;
+    if (!rc && t < best_ms) {
+      best_ms = t;
+      best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  L->threads = best;
-  L->grid = 0;
+  apply(best);
   tune_cache_put(key, best);
-  if (threads) *threads = best;
+  return dispatch(*L, true, nullptr);
+}
+
+int fill_launch_set_choice(FillLaunch *L, int c) {
+  if (L->n < 2 || L->op != MF_OP_EFIE || L->sparse || c < 0 || c >= kBatchChoices ||
+      (kBatchCand[c][0] == 1 && !L->tb_ok)) {
+    set_error("mf_batch_set_choice: no such candidate for this batch");
+    return MF_EINVAL;
+  }
+  L->shape = kBatchCand[c][0];
+  L->threads = kBatchCand[c][1];
+  L->grid = 0;
   return dispatch(*L, true, nullptr);
 }
 

@@ -240,14 +240,23 @@ struct FillLaunch;
 // items_dev: device memory of fill_items_bytes(n) for the item list of a
 // batched launch (n > 1), owned by the caller; may be null for one item.
 size_t fill_items_bytes(int n);
+// side: per-item side buffers (2 n_cut (ne + n_cut) floats each) that let a
+// batch of EFIE items run on the triangle-block plan; may be null.
 int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_tables *const *tab,
                        const Rule &r, int mode, void *const *Z, int z_dtype, const int64_t *ldz,
-                       const float *const *sing, void *items_dev, FillLaunch **out);
+                       const float *const *sing, void *items_dev, FillLaunch **out,
+                       float *const *side = nullptr);
 int fill_launch_run(FillLaunch *L, hipStream_t s);
-// Times the workgroup-size variants of a batched launch (running it), keeps
-// the fastest; ms3 (may be NULL) receives the three timings (512, 768, 1024
-// threads), *threads the choice.
-int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms3, int *threads);
+// Candidates of the batch tuner: edge-block tiles at 512, 768, 1024 threads,
+// then triangle-block tiles at 1024 and 512 threads.
+constexpr int kBatchChoices = 5;
+// Times the tile-shape variants of a batched launch (running it), keeps the
+// fastest; ms (may be NULL) receives the kBatchChoices timings (zeros for
+// candidates not run), *threads and *shape (0 edge blocks, 1 triangle
+// blocks) the choice.
+int fill_launch_autotune(FillLaunch *L, hipStream_t s, float *ms, int *threads, int *shape);
+// Pins candidate c (index into the tuner's list) for later runs.
+int fill_launch_set_choice(FillLaunch *L, int c);
 void fill_launch_destroy(FillLaunch *L);
 int build_tables_device(mf_tables *t, double tol, hipStream_t s, bool green = true);
 // Upper bound of the device workspace a table build needs (both tables, or

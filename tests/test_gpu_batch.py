@@ -61,13 +61,20 @@ def _items(mf, mode, Q, tol=1e-6):
 
 
 @pytest.mark.parametrize("mode", ["table", "direct"])
-def test_batch_matches_single_fills(mf, mode):
+@pytest.mark.parametrize("cand", range(5))
+def test_batch_matches_single_fills(mf, mode, cand):
+    """Every tile shape of the batch tuner (edge blocks at three workgroup
+    sizes, triangle blocks at two) against single fills, both modes."""
     import torch
 
     Q = 6
-    say("batch vs single", mode)
+    shape, threads = mf.Batch.CANDIDATES[cand]
+    say("batch vs single", mode, shape, threads)
     specs = _items(mf, mode, Q)
     b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, mode)
+    b.set_choice(shape, threads)
+    for s in specs:
+        s["Z"].fill_(float("nan"))
     b.fill()
     torch.cuda.synchronize()
     for s in specs:
@@ -87,6 +94,7 @@ def test_batch_matches_oracle(mf, orc):
     say("batch vs oracle")
     specs = _items(mf, "table", Q, tol=1e-6)
     b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
+    b.set_choice("triangle", 1024)
     b.fill()
     torch.cuda.synchronize()
     for i, s in enumerate(specs):
@@ -99,15 +107,18 @@ def test_batch_matches_oracle(mf, orc):
         assert err <= 1e-5
 
 
-def test_batch_graph_replay(mf):
+@pytest.mark.parametrize("shape", ["edge", "triangle"])
+def test_batch_graph_replay(mf, shape):
     """Captured once, replayed three times with eager work in between; every
-    replay must reproduce the eager batch."""
+    replay must reproduce the eager batch (both tile shapes: the
+    triangle-block launch adds a fix-up kernel per item)."""
     import torch
 
     Q = 6
-    say("batch graph replay")
+    say("batch graph replay", shape)
     specs = _items(mf, "table", Q)
     b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
+    b.set_choice(shape, 1024)
     b.fill()
     torch.cuda.synchronize()
     eager = [s["Z"].clone() for s in specs]
@@ -186,8 +197,9 @@ def test_sweep_meshes_sampled(mf, orc):
 
 
 def test_batch_tuner(mf):
-    """The tile-shape tuner runs at creation: it picks one of the three
-    workgroup sizes, leaves the batch's result in the outputs, and a second
+    """The tile-shape tuner runs at creation: it times the five candidates
+    (edge-block tiles at three workgroup sizes, triangle-block tiles at two),
+    picks the fastest, leaves the batch's result in the outputs, and a second
     batch of the same kind reuses the choice without timing again."""
     import torch
 
@@ -196,13 +208,13 @@ def test_batch_tuner(mf):
     specs = _items(mf, "table", Q)
     b = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs], Q, "table")
     torch.cuda.synchronize()
-    threads, ms = b.tuning()
-    say("  threads", threads, "ms", ms)
-    assert threads in (512, 768, 1024)
-    assert all(t > 0 for t in ms) and min(ms) == ms[(512, 768, 1024).index(threads)]
+    shape, threads, ms = b.tuning()
+    say("  shape", shape, "threads", threads, "ms", ms)
+    assert (shape, threads) in mf.Batch.CANDIDATES
+    assert all(t > 0 for t in ms) and min(ms) == ms[mf.Batch.CANDIDATES.index((shape, threads))]
     for s in specs:
         ref = mf.fill_Z(s["mesh"], s["Vd"], s["k"], Q, "table", s["T"]).cpu().numpy()
         assert _rel(s["Z"].cpu().numpy(), ref) <= 1e-6  # result present after creation
     b2 = mf.Batch([(s["mesh"], s["Vd"], s["k"], s["T"], s["Z"]) for s in specs[:2]], Q, "table")
-    t2, ms2 = b2.tuning()
-    assert t2 == threads and ms2 == [0.0, 0.0, 0.0]
+    sh2, t2, ms2 = b2.tuning()
+    assert (sh2, t2) == (shape, threads) and ms2 == [0.0] * 5
