@@ -178,6 +178,85 @@ static void build_touching(mf_mesh *m) {
     }
 }
 
+// Rounds of a block's source triangles for an accumulation without atomics:
+// at most cap triangles per round and no two of a round adjacent (sharing an
+// edge), so no two waves add to one column at once.  adj[3 i + a] is the
+// local index of triangle i's neighbour across its edge a inside the block, or
+// -1.  First fit over a few orders: the two classes of a breadth-first
+// two-colouring of the adjacency (a triangulated patch is mostly bipartite,
+// then the rounds come out full), index order, and seeded shuffles; the order
+// with the fewest rounds wins.  order receives the local indices in round
+// order, starts the maxr + 1 round starts; false when more than maxr rounds
+// would be needed.
+static bool block_rounds(const std::vector<int> &adj, int n, int cap, int maxr, int32_t *order,
+                         int32_t *starts, uint64_t &seed) {
+  std::vector<int> par(n, -1), round_of(n, -1), best_round(n, -1), cnt(maxr, 0);
+  std::vector<int32_t> ord, queue;
+  for (int s0 = 0; s0 < n; ++s0) {  // two-colouring, breadth first
+    if (par[s0] >= 0) continue;
+    par[s0] = 0;
+    queue.assign(1, s0);
+    for (size_t h = 0; h < queue.size(); ++h)
+      for (int a = 0; a < 3; ++a) {
+        const int o = adj[3 * (size_t)queue[h] + a];
+        if (o >= 0 && par[o] < 0) {
+          par[o] = 1 - par[queue[h]];
+          queue.push_back(o);
+        }
+      }
+  }
+  auto first_fit = [&](const std::vector<int32_t> &o) -> int {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    int nr = 0;
+    for (int t : o) round_of[t] = -1;
+    for (int t : o) {
+      int r = 0;
+      for (; r < maxr; ++r) {
+        if (cnt[r] >= cap) continue;
+        bool clash = false;
+        for (int a = 0; a < 3 && !clash; ++a) {
+          const int nb = adj[3 * (size_t)t + a];
+          clash = nb >= 0 && round_of[nb] == r;
+        }
+        if (!clash) break;
+      }
+      if (r == maxr) return maxr + 1;
+      round_of[t] = r;
+      ++cnt[r];
+      nr = std::max(nr, r + 1);
+    }
+    return nr;
+  };
+  const int ideal = (n + cap - 1) / cap;
+  int best = maxr + 1;
+  for (int trial = 0; trial < 36 && best > ideal; ++trial) {
+    ord.resize(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    if (trial < 2)
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int x, int y) { return (par[x] ^ trial) < (par[y] ^ trial); });
+    else if (trial > 2)
+      for (int i = n - 1; i > 0; --i) {  // seeded shuffle
+        seed = seed * 6364136223846793005ull + 1442695040888963407ull;
+        std::swap(ord[i], ord[(int)((seed >> 33) % (uint64_t)(i + 1))]);
+      }
+    const int nr = first_fit(ord);
+    if (nr < best) {
+      best = nr;
+      best_round = round_of;
+    }
+  }
+  if (best > maxr) return false;
+  int pos = 0;
+  for (int r = 0; r <= maxr; ++r) {
+    starts[r] = pos;
+    if (r < best)
+      for (int t = 0; t < n; ++t)
+        if (best_round[t] == r) order[pos++] = t;
+  }
+  return true;
+}
+
 // Row/column blocks of the tiled fill: runs of consecutive edges (so every
 // tile is a contiguous rectangle of Z) carrying at most kMaxBlockTris
 // triangles and kMaxBlockEdges edges.  Boundaries come from a dynamic program
@@ -250,6 +329,34 @@ static void build_blocks(mf_mesh *m) {
     }
     m->blk_off[b + 1] = (int32_t)m->blk_tri.size();
     m->max_blk_tris = std::max(m->max_blk_tris, (int)tl.size());
+  }
+  // rounds of each edge block's triangles (block_rounds), for the MFIE tile,
+  // which accumulates both directions of a pair without atomics: blk_ord holds
+  // positions in the block's triangle list, in round order
+  m->blk_ord.assign(m->blk_tri.size(), 0);
+  m->blk_rounds.assign((size_t)m->nblk * (kEBMaxRounds + 1), 0);
+  {
+    std::vector<int> adj, pos_of(m->nt, -1);
+    uint64_t seed = 0x2545f4914f6cdd1dull;
+    for (int b = 0; b < m->nblk; ++b) {
+      const int p0 = m->blk_off[b], n = m->blk_off[b + 1] - p0;
+      for (int i = 0; i < n; ++i) pos_of[m->blk_tri[p0 + i]] = i;
+      adj.assign(3 * (size_t)n, -1);
+      for (int i = 0; i < n; ++i) {
+        const int t = m->blk_tri[p0 + i];
+        for (int a = 0; a < 3; ++a) {
+          const int e = m->tedge[3 * (size_t)t + a];
+          if (e < 0) continue;
+          const int o = E[6 * (size_t)e + 2] == t ? E[6 * (size_t)e + 3] : E[6 * (size_t)e + 2];
+          adj[3 * (size_t)i + a] = pos_of[o];
+        }
+      }
+      // at most 3 neighbours each: first fit never needs more than
+      // n / kEBRound + 4 rounds, within kEBMaxRounds for n <= kMaxBlockTris
+      block_rounds(adj, n, kEBRound, kEBMaxRounds, &m->blk_ord[p0],
+                   &m->blk_rounds[(size_t)b * (kEBMaxRounds + 1)], seed);
+      for (int i = 0; i < n; ++i) pos_of[m->blk_tri[p0 + i]] = -1;
+    }
   }
   // Z is symmetric (Galerkin reciprocity): only block pairs I <= J are filled.
   // Tiles pack I and J into 16 bits each (unsigned); with at most 65535
@@ -355,87 +462,27 @@ static void build_tb_plan(mf_mesh *m) {
     }
     m->tb_pos[t] = (int32_t)pk;
   }
-  // rounds: first fit into rounds of at most kTBRound triangles with no two
-  // neighbours in one round, over a few orders of the block's triangles: the
-  // two classes of a breadth-first two-colouring of its triangle adjacency
-  // (a triangulated patch is mostly bipartite, then the rounds come out full),
-  // index order, and seeded shuffles; the order with the fewest rounds wins.
+  // rounds of each block's triangles (block_rounds)
   m->tb_order.assign(nt, 0);
   m->tb_rounds.assign((size_t)nb * (kTBMaxRounds + 1), 0);
-  std::vector<int> round_of(nt, -1), par(nt, -1), best_round(nt, -1);
-  std::vector<int32_t> order, queue;
+  std::vector<int> adj;
+  std::vector<int32_t> order;
   uint64_t seed = 0x9e3779b97f4a7c15ull;
   for (int b = 0; b < nb; ++b) {
     const int t0 = m->tb_t0[b], t1 = m->tb_t0[b + 1], n = t1 - t0;
-    auto nbr = [&](int t, int a) -> int {
-      const int e = m->tedge[3 * (size_t)t + a];
-      if (e < 0) return -1;
-      const int o = E[6 * (size_t)e + 2] == t ? E[6 * (size_t)e + 3] : E[6 * (size_t)e + 2];
-      return o >= t0 && o < t1 ? o : -1;
-    };
-    for (int s0 = t0; s0 < t1; ++s0) {  // two-colouring, breadth first
-      if (par[s0] >= 0) continue;
-      par[s0] = 0;
-      queue.assign(1, s0);
-      for (size_t h = 0; h < queue.size(); ++h)
-        for (int a = 0; a < 3; ++a) {
-          const int o = nbr(queue[h], a);
-          if (o >= 0 && par[o] < 0) {
-            par[o] = 1 - par[queue[h]];
-            queue.push_back(o);
-          }
-        }
-    }
-    auto first_fit = [&](const std::vector<int32_t> &ord) -> int {
-      int cnt[kTBMaxRounds] = {};
-      int nr = 0;
-      for (int t : ord) round_of[t] = -1;
-      for (int t : ord) {
-        int r = 0;
-        for (; r < kTBMaxRounds; ++r) {
-          if (cnt[r] >= kTBRound) continue;
-          bool clash = false;
-          for (int a = 0; a < 3 && !clash; ++a) {
-            const int o = nbr(t, a);
-            clash = o >= 0 && round_of[o] == r;
-          }
-          if (!clash) break;
-        }
-        if (r == kTBMaxRounds) return kTBMaxRounds + 1;
-        round_of[t] = r;
-        ++cnt[r];
-        nr = std::max(nr, r + 1);
+    adj.assign(3 * (size_t)n, -1);
+    for (int t = t0; t < t1; ++t)
+      for (int a = 0; a < 3; ++a) {
+        const int e = m->tedge[3 * (size_t)t + a];
+        if (e < 0) continue;
+        const int o = E[6 * (size_t)e + 2] == t ? E[6 * (size_t)e + 3] : E[6 * (size_t)e + 2];
+        if (o >= t0 && o < t1) adj[3 * (size_t)(t - t0) + a] = o - t0;
       }
-      return nr;
-    };
-    const int ideal = (n + kTBRound - 1) / kTBRound;
-    int best = kTBMaxRounds + 1;
-    for (int trial = 0; trial < 36 && best > ideal; ++trial) {
-      order.resize(n);
-      for (int i = 0; i < n; ++i) order[i] = t0 + i;
-      if (trial < 2)
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int x, int y) { return (par[x] ^ trial) < (par[y] ^ trial); });
-      else if (trial > 2)
-        for (int i = n - 1; i > 0; --i) {  // seeded shuffle
-          seed = seed * 6364136223846793005ull + 1442695040888963407ull;
-          std::swap(order[i], order[(int)((seed >> 33) % (uint64_t)(i + 1))]);
-        }
-      const int nr = first_fit(order);
-      if (nr < best) {
-        best = nr;
-        for (int t = t0; t < t1; ++t) best_round[t] = round_of[t];
-      }
-    }
-    if (best > kTBMaxRounds) return;
-    int32_t *rs = &m->tb_rounds[(size_t)b * (kTBMaxRounds + 1)];
-    int pos = 0;
-    for (int r = 0; r <= kTBMaxRounds; ++r) {
-      rs[r] = pos;
-      if (r < best)
-        for (int t = t0; t < t1; ++t)
-          if (best_round[t] == r) m->tb_order[t0 + pos++] = t;
-    }
+    order.assign(n, 0);
+    if (!block_rounds(adj, n, kTBRound, kTBMaxRounds, order.data(),
+                      &m->tb_rounds[(size_t)b * (kTBMaxRounds + 1)], seed))
+      return;
+    for (int i = 0; i < n; ++i) m->tb_order[t0 + i] = t0 + order[i];
   }
   m->tb_tiles.clear();
   for (int I = 0; I < nb; ++I)
@@ -466,6 +513,7 @@ static bool carve_mesh(const mf_mesh *m, Arena &A, mf_mesh *d) {
          MF_TAKE(d_blk_off, m->blk_off.size()) && MF_TAKE(d_blk_tri, m->blk_tri.size()) &&
          MF_TAKE(d_blk_pos, m->blk_pos.size()) && MF_TAKE(d_tiles, m->tiles.size()) &&
          MF_TAKE(d_blk_e0, m->blk_e0.size()) && MF_TAKE(d_blk_rt, m->blk_rt.size()) &&
+         MF_TAKE(d_blk_ord, m->blk_ord.size()) && MF_TAKE(d_blk_rounds, m->blk_rounds.size()) &&
          MF_TAKE(d_elen, (size_t)m->ne) && MF_TAKE(d_sing1, 18 * npair) &&
          MF_TAKE(d_sing, 18 * npair) && MF_TAKE(d_scratch, 16) && MF_TAKE(d_status, 4) &&
          MF_TAKE(d_qp64, 3 * kMaxQ * nt) && MF_TAKE(d_brad, 4 * nt) &&
@@ -641,7 +689,8 @@ int mf_mesh_set_workspace(mf_mesh *m, void *ws, size_t bytes, hipStream_t s) {
       (rc = upload(m->d_blk_off, m->blk_off, s)) ||
       (rc = upload(m->d_blk_tri, m->blk_tri, s)) || (rc = upload(m->d_blk_pos, m->blk_pos, s)) ||
       (rc = upload(m->d_tiles, m->tiles, s)) || (rc = upload(m->d_blk_e0, m->blk_e0, s)) ||
-      (rc = upload(m->d_blk_rt, m->blk_rt, s)) || (rc = upload(m->d_tb_t0, m->tb_t0, s)) ||
+      (rc = upload(m->d_blk_rt, m->blk_rt, s)) || (rc = upload(m->d_blk_ord, m->blk_ord, s)) ||
+      (rc = upload(m->d_blk_rounds, m->blk_rounds, s)) || (rc = upload(m->d_tb_t0, m->tb_t0, s)) ||
       (rc = upload(m->d_tb_e0, m->tb_e0, s)) || (rc = upload(m->d_tb_nbe, m->tb_nbe, s)) ||
       (rc = upload(m->d_tb_be_off, m->tb_be_off, s)) ||
       (rc = upload(m->d_tb_be_cut, m->tb_be_cut, s)) || (rc = upload(m->d_tb_pos, m->tb_pos, s)) ||

@@ -93,6 +93,7 @@ struct FillItem {
   const float *rec;
   const int32_t *tiles, *blk_e0, *blk_off, *blk_tri, *blk_pos, *touch_off, *touch_q, *touch_rev;
   const int32_t *blk_rt;  // per block row: positions of its T+ and T- in the block's list
+  const int32_t *blk_ord, *blk_rounds;  // round order of each block's triangles (MFIE)
   const float *elen;      // edge lengths
   // triangle-block plan (table mode, see fill_tile_tb)
   const int32_t *tb_t0, *tb_e0, *tb_nbe, *tb_be_off, *tb_be_cut, *tb_pos, *tb_order, *tb_rounds,
@@ -983,7 +984,7 @@ __device__ __forceinline__ void fill_tile_mfie(
   const int tij = tiles[local];
   const int I = (int)((unsigned)tij >> 16), J = tij & 0xffff;
   const bool rev = I != J;  // also the block (J, I)
-  for (int i = threadIdx.x; i < 2 * kAccFloats; i += kFillThreads) acc[i] = 0.0f;
+  for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc[i] = 0.0f;
   if (rev)
     for (int i = threadIdx.x; i < kAccFloats; i += kFillThreads) acc2[i] = 0.0f;
   __syncthreads();
@@ -1021,137 +1022,145 @@ __device__ __forceinline__ void fill_tile_mfie(
     const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
     const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
 
-    for (int qi = wave; qi < nq; qi += kWaves) {
-      const int q = uniform(as_const(blk_tri)[q0 + qi]);
-      const int qcol = uniform(as_const(blk_pos)[q0 + qi]);
-      cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
-      cint32 *qvi = (cint32 *)(qr + kRecVid);
-      const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
-      const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
-                         pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
-      float Xr[3][3], Xi[3][3];
-      float Rr[3][3], Ri[3][3];  // reverse block [b][a] (q tested against p)
-      if (!touch) {
-        cdouble *qcd = (cdouble *)(qr + kRecCent);
-        const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
-        const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
-        const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
-                    lz = (float)(Dz - (double)hz);
-        // unit normal of q (from its record, wave-uniform)
-        float qn[3];
-        {
-          float e1[3], e2[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            e1[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 3 + c];
-            e2[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 6 + c];
-          }
-          cross3(e1, e2, qn);
-          const float inv = __builtin_amdgcn_rsqf(dot3(qn, qn));
-#pragma unroll
-          for (int c = 0; c < 3; ++c) qn[c] *= inv;
-        }
-        MomentsM M;
-        if (MODE == MF_MODE_TABLE)
-          moments_table<Q, MF_OP_MFIE, kLDS>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
-        else
-          moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          float tau[3], Yr[3], Yi[3];
-          cross3(palpha[a], nrm, tau);
-          cross3(tau, M.dr, Yr);
-          cross3(tau, M.di, Yi);
-          const float yr = dot3(tau, M.xr) + M.m0r;
-          const float yi = dot3(tau, M.xi) + M.m0i;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            Yr[c] += M.sr[c];
-            Yi[c] += M.si[c];
-          }
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
-                                   qr[kRecAlpha + 3 * b + 2]};
-            Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
-            Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
-          }
-        }
-        if (rev) {
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            float tau[3], Yr[3], Yi[3];
-            const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
-                                   qr[kRecAlpha + 3 * b + 2]};
-            cross3(beta, qn, tau);
-            cross3(M.dr, tau, Yr);  // tau x Md' = Md x tau (Md' = -Md)
-            cross3(M.di, tau, Yi);
-            const float yr = dot3(tau, M.qxr) + M.q0r;
-            const float yi = dot3(tau, M.qxi) + M.q0i;
+    // the source triangles in rounds of pairwise non-adjacent triangles, one
+    // per wave, with a barrier after each round: no two waves add to one
+    // column of the forward block or one row of the reverse block at once
+    const int32_t *rs = S.blk_rounds + (size_t)J * (kEBMaxRounds + 1);
+    for (int rd = 0; rd < kEBMaxRounds; ++rd) {
+      const int r0 = uniform(rs[rd]), r1 = uniform(rs[rd + 1]);
+      if (r0 == r1) break;
+      for (int j = r0 + wave; j < r1; j += kWaves) {
+        const int qi = uniform(as_const(S.blk_ord)[q0 + j]);
+        const int q = uniform(as_const(blk_tri)[q0 + qi]);
+        const int qcol = uniform(as_const(blk_pos)[q0 + qi]);
+        cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
+        cint32 *qvi = (cint32 *)(qr + kRecVid);
+        const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
+        const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
+                           pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
+        float Xr[3][3], Xi[3][3];
+        float Rr[3][3], Ri[3][3];  // reverse block [b][a] (q tested against p)
+        if (!touch) {
+          cdouble *qcd = (cdouble *)(qr + kRecCent);
+          const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
+          const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
+          const float lx = (float)(Dx - (double)hx), ly = (float)(Dy - (double)hy),
+                      lz = (float)(Dz - (double)hz);
+          // unit normal of q (from its record, wave-uniform)
+          float qn[3];
+          {
+            float e1[3], e2[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              Yr[c] += M.qsr[c];
-              Yi[c] += M.qsi[c];
+              e1[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 3 + c];
+              e2[c] = qr[kRecAlpha + c] - qr[kRecAlpha + 6 + c];
             }
+            cross3(e1, e2, qn);
+            const float inv = __builtin_amdgcn_rsqf(dot3(qn, qn));
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              Rr[b][a] = 0.25f * (dot3(palpha[a], Yr) + yr);
-              Ri[b][a] = 0.25f * (dot3(palpha[a], Yi) + yi);
-            }
+            for (int c = 0; c < 3; ++c) qn[c] *= inv;
           }
-        }
-      } else {
-        int s = touch_off[p];
-        const int s1 = touch_off[p + 1];
-        while (s < s1 && touch_q[s] != q) ++s;
-        const bool found = s < s1;  // always: touching pairs are listed both ways
-        const float *x = sing + (size_t)(found ? s : 0) * 18;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
-            Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
-          }
-        if (rev) {  // the pair (q, p), block [b][a]
-          const float *y = sing + (size_t)(found ? touch_rev[s] : 0) * 18;
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              Rr[b][a] = found ? y[2 * (3 * b + a)] : 0.0f;
-              Ri[b][a] = found ? y[2 * (3 * b + a) + 1] : 0.0f;
-            }
-        }
-      }
-      if (pv) {
-        // The forward block as in the EFIE tile: halves by the sign of the
-        // source triangle, rows in two passes by the sign of the test
-        // triangle, plain adds.  The reverse block (rows of the source
-        // triangle's edges) would need halves of its own and keeps atomics.
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass)
+          MomentsM M;
+          if (MODE == MF_MODE_TABLE)
+            moments_table<Q, MF_OP_MFIE, kLDS>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          else
+            moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            const int row = (prow >> (8 * a)) & 0xff;
-            if (row == 0xff || (psig[a] < 0.0f) != (pass == 1)) continue;
+            float tau[3], Yr[3], Yi[3];
+            cross3(palpha[a], nrm, tau);
+            cross3(tau, M.dr, Yr);
+            cross3(tau, M.di, Yi);
+            const float yr = dot3(tau, M.xr) + M.m0r;
+            const float yi = dot3(tau, M.xi) + M.m0i;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              Yr[c] += M.sr[c];
+              Yi[c] += M.si[c];
+            }
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-              const int col = (qcol >> (8 * b)) & 0xff;
-              if (col == 0xff) continue;
-              const float qs = qr[kRecSigma + b];
-              const float sg = psig[a] * qs;
-              float *dst = acc + (qs < 0.0f ? kAccFloats : 0) + row * kAccStride + 2 * col;
-              dst[0] += sg * Xr[a][b];
-              dst[1] += sg * Xi[a][b];
-              if (rev) {
-                float *dst2 = acc2 + col * kAccStride + 2 * row;
-                atomicAdd(dst2, sg * Rr[b][a]);
-                atomicAdd(dst2 + 1, sg * Ri[b][a]);
+              const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
+                                     qr[kRecAlpha + 3 * b + 2]};
+              Xr[a][b] = 0.25f * (dot3(beta, Yr) + yr);
+              Xi[a][b] = 0.25f * (dot3(beta, Yi) + yi);
+            }
+          }
+          if (rev) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              float tau[3], Yr[3], Yi[3];
+              const float beta[3] = {qr[kRecAlpha + 3 * b], qr[kRecAlpha + 3 * b + 1],
+                                     qr[kRecAlpha + 3 * b + 2]};
+              cross3(beta, qn, tau);
+              cross3(M.dr, tau, Yr);  // tau x Md' = Md x tau (Md' = -Md)
+              cross3(M.di, tau, Yi);
+              const float yr = dot3(tau, M.qxr) + M.q0r;
+              const float yi = dot3(tau, M.qxi) + M.q0i;
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                Yr[c] += M.qsr[c];
+                Yi[c] += M.qsi[c];
+              }
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                Rr[b][a] = 0.25f * (dot3(palpha[a], Yr) + yr);
+                Ri[b][a] = 0.25f * (dot3(palpha[a], Yi) + yi);
               }
             }
           }
+        } else {
+          int s = touch_off[p];
+          const int s1 = touch_off[p + 1];
+          while (s < s1 && touch_q[s] != q) ++s;
+          const bool found = s < s1;  // always: touching pairs are listed both ways
+          const float *x = sing + (size_t)(found ? s : 0) * 18;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              Xr[a][b] = found ? x[2 * (3 * a + b)] : 0.0f;
+              Xi[a][b] = found ? x[2 * (3 * a + b) + 1] : 0.0f;
+            }
+          if (rev) {  // the pair (q, p), block [b][a]
+            const float *y = sing + (size_t)(found ? touch_rev[s] : 0) * 18;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                Rr[b][a] = found ? y[2 * (3 * b + a)] : 0.0f;
+                Ri[b][a] = found ? y[2 * (3 * b + a) + 1] : 0.0f;
+              }
+          }
+        }
+        if (pv) {
+          // Plain adds: the rounds keep the waves apart, and within the wave
+          // the rows of an edge's plus and minus triangles (two lanes) are
+          // added in two passes, in both blocks.
+#pragma unroll
+          for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const int row = (prow >> (8 * a)) & 0xff;
+              if (row == 0xff || (psig[a] < 0.0f) != (pass == 1)) continue;
+#pragma unroll
+              for (int b = 0; b < 3; ++b) {
+                const int col = (qcol >> (8 * b)) & 0xff;
+                if (col == 0xff) continue;
+                const float sg = psig[a] * qr[kRecSigma + b];
+                float *dst = acc + row * kAccStride + 2 * col;
+                dst[0] += sg * Xr[a][b];
+                dst[1] += sg * Xi[a][b];
+                if (rev) {
+                  float *dst2 = acc2 + col * kAccStride + 2 * row;
+                  dst2[0] += sg * Rr[b][a];
+                  dst2[1] += sg * Ri[b][a];
+                }
+              }
+            }
+        }
       }
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -1162,8 +1171,8 @@ __device__ __forceinline__ void fill_tile_mfie(
     const int r = e / nj, c = e % nj;
     ZT v;
     const int o = r * kAccStride + 2 * c;
-    v.x = S.pref * (acc[o] + acc[kAccFloats + o]);
-    v.y = S.pref * (acc[o + 1] + acc[kAccFloats + o + 1]);
+    v.x = S.pref * acc[o];
+    v.y = S.pref * acc[o + 1];
     Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
   }
   if (rev) {
@@ -1184,12 +1193,11 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
                                    fill_threads_op<MODE, OP>() / 256))) void k_fill(
     FillItem S, FillRule W) {
   constexpr int kFillThreads = fill_threads_op<MODE, OP>();
-  // the EFIE's two halves; the MFIE's two halves of its forward block and its
-  // reverse block
-  constexpr int kAccs = OP == MF_OP_MFIE ? 3 : 2;
+  // the EFIE's two halves; the MFIE's forward and reverse blocks
+  constexpr int kAccs = 2;
   extern __shared__ float4 smem4[];
   float *acc = reinterpret_cast<float *>(smem4);
-  float *acc2 = OP == MF_OP_MFIE ? acc + 2 * kAccFloats : nullptr;
+  float *acc2 = OP == MF_OP_MFIE ? acc + kAccFloats : nullptr;
   const TabPtrs tab = load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(
       S, smem4 + kAccs * kAccFloats / 4 + 1);
   float2 *gref = reinterpret_cast<float2 *>(acc + 2 * kAccFloats + 4);  // direct mode
@@ -1845,6 +1853,8 @@ static FillItem make_item(const mf_mesh *m, const Rule &r, double k, int base,
   S.rec = m->d_rec;
   S.tiles = m->d_tiles;
   S.blk_e0 = m->d_blk_e0;
+  S.blk_ord = m->d_blk_ord;
+  S.blk_rounds = m->d_blk_rounds;
   S.blk_off = m->d_blk_off;
   S.blk_tri = m->d_blk_tri;
   S.blk_pos = m->d_blk_pos;
@@ -1935,7 +1945,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
     delete L;
     return MF_EINVAL;
   }
-  L->lds = sizeof(float) * kAccFloats * (L->op == MF_OP_MFIE ? 3 : 2) + 16;
+  L->lds = sizeof(float) * kAccFloats * 2 + 16;
   // direct EFIE: the per-pair references of the div-div term
   if (L->op == MF_OP_EFIE && L->base == MF_MODE_DIRECT && !(L->part & MF_PART_A))
     L->lds += sizeof(float2) * kRefFloat2;
@@ -1968,9 +1978,7 @@ int fill_launch_create(int n, mf_mesh *const *m, const double *k, const mf_table
     if (e != hipSuccess) rc = hip_fail(e, "device attributes");
   }
   if (!rc && L->base == MF_MODE_TABLE) {
-    // the MFIE reads its table through the vector L1: with the table in LDS
-    // its fill measured slower (bank conflicts against its longer moments)
-    if (L->op != MF_OP_MFIE && L->lds + tmax <= (size_t)maxlds) {
+    if (L->lds + tmax <= (size_t)maxlds) {
       L->lds_tab = true;
       L->lds += tmax;
     }

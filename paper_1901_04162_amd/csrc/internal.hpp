@@ -28,6 +28,10 @@ constexpr int kTBTris = 64;
 constexpr int kTBEdges = 112;
 constexpr int kTBRound = 16;
 constexpr int kTBMaxRounds = 12;
+// The MFIE tile (edge blocks, 8 waves) walks each block's source triangles
+// in rounds of at most kEBRound pairwise non-adjacent triangles.
+constexpr int kEBRound = 8;
+constexpr int kEBMaxRounds = 16;
 
 // Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
 //  [0,21)  rho_i = r_i - c      (i-major, xyz)           FP32
@@ -132,6 +136,9 @@ struct mf_mesh {
   // nblk*kMaxBlockEdges: for row r of block b, the positions in the block's
   // triangle list of the row edge's T+ (bits 0-7) and T- (bits 8-15)
   std::vector<int32_t> blk_rt;
+  // per block, positions in its triangle list in round order (block_rounds),
+  // and nblk*(kEBMaxRounds+1) round starts
+  std::vector<int32_t> blk_ord, blk_rounds;
   std::vector<int32_t> tiles;      // (I << 16) | J for every block pair I <= J
   int nblk = 0, max_blk_tris = 0;
 
@@ -162,6 +169,7 @@ struct mf_mesh {
   int32_t *d_touch_u = nullptr;    // touch_u
   int32_t *d_blk_off = nullptr, *d_blk_tri = nullptr, *d_blk_pos = nullptr;
   int32_t *d_tiles = nullptr, *d_blk_e0 = nullptr, *d_blk_rt = nullptr;
+  int32_t *d_blk_ord = nullptr, *d_blk_rounds = nullptr;
   float *d_elen = nullptr;         // ne edge lengths (FP32, from the FP64 vertices)
   float *d_rec = nullptr;          // nt * kRecFloats
   double *d_qp64 = nullptr;        // nt * kMaxQ * 3 quadrature points (FP64)
