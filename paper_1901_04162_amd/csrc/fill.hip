@@ -296,47 +296,67 @@ __device__ __forceinline__ void green_to_k(float k, float ri, float &gr, float &
 template <int OP>
 using MomentsOf = typename std::conditional<OP == MF_OP_MFIE, MomentsM, Moments>::type;
 
-// Table mode.  The test-point loop stays rolled and reads rho_i from the
-// record; the lookups of one test point go in three steps over all source
-// points at once (distances and bucket-record reads, then coefficient reads,
-// then the cubic and the sums), so that the dependent reads overlap.  The interval search is the bucket lookup of
-// Eq. (6) in the record form of lookup.hpp (one gather gives the interval
-// and its first sample), and the cubic of Eq. (5) is evaluated in Horner
-// form about that sample.  The MFIE takes K = (1/R + jk) g/R from the same
-// value and adds the third inner sum T2.
-template <int Q, int OP, bool kLDS>
-__device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &tab,
-                                              const FillScalars &S, const FillRule &W,
-                                              const float *pr, const float *nrm, const float *nq,
-                                              float hx, float hy, float hz, float lx, float ly,
-                                              float lz, cfloat *qr, float &rlo, float &rhi,
-                                              bool range = true) {
+// MFIE table mode.  The test-point loop stays rolled and reads rho_i from
+// the record; the lookups of one test point go in three steps over all
+// source points at once (distances and bucket-record reads, then
+// coefficient reads, then the cubic and the sums), so that the dependent
+// reads overlap.  The interval search is the bucket lookup of Eq. (6) in the
+// record form of lookup.hpp (one gather gives the interval and its first
+// sample), and the cubic of Eq. (5) is evaluated in Horner form about that
+// sample; K = (1/R + jk) g/R follows from the same value.  As in the EFIE's
+// table mode (moments_bary) the distances and the inner sum T1 use the
+// rule's own frame: R^2 = |a|^2 + 2 s_j a.beta_0 + 2 t_j a.beta_1 +
+// |rho'_j|^2, and T1 = sum_j w_j K rho'_j = -(beta_0 T_s + beta_1 T_t) with
+// T_s = sum w_j s_j K, T_t = sum w_j t_j K (the zero terms skipped); the
+// weights w_j |rho'_j|^2 of the third inner sum T2 are formed once per pair.
+template <int Q, bool kLDS>
+__device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &tab,
+                                                   const FillScalars &S, const FillRule &W,
+                                                   const float *pr, const float *nrm,
+                                                   const float *nq, float hx, float hy, float hz,
+                                                   float lx, float ly, float lz, cfloat *qr,
+                                                   float &rlo, float &rhi) {
   zero(M);
+  float n2[Q], wr2[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const float qx = qr[kRecRho + 3 * j], qy = qr[kRecRho + 3 * j + 1],
+                qz = qr[kRecRho + 3 * j + 2];
+    n2[j] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+    wr2[j] = W.w[j] * n2[j];
+  }
+  float b0[3], b1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    b0[c] = qr[kRecAlpha + c];
+    b1[c] = qr[kRecAlpha + 3 + c];
+  }
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
     float pri[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) pri[c] = pr[kRecRho + 3 * i + c];
     const float ax = hx + (pri[0] + lx), ay = hy + (pri[1] + ly), az = hz + (pri[2] + lz);
-    float t0r = 0.f, t0i = 0.f, t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};
-    float t2r = 0.f, t2i = 0.f;
+    const float A2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+    const float B0 = fmaf(ax, b0[0], fmaf(ay, b0[1], az * b0[2]));
+    const float B1 = fmaf(ax, b1[0], fmaf(ay, b1[1], az * b1[2]));
+    const float B01 = B0 + B1;
     float r[Q];
     int4 w[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const float dx = ax - qr[kRecRho + 3 * j + 0];
-      const float dy = ay - qr[kRecRho + 3 * j + 1];
-      const float dz = az - qr[kRecRho + 3 * j + 2];
-      r[j] = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      const int kind = bary_kind(Q, j);
+      const float r2 = kind == 0   ? A2
+                       : kind == 1 ? fmaf(W.s2[j], B0, A2 + n2[j])
+                       : kind == 2 ? fmaf(W.t2[j], B1, A2 + n2[j])
+                                   : fmaf(W.s2[j], B01, A2 + n2[j]);
+      r[j] = __builtin_amdgcn_sqrtf(r2);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
-    // the table-range check of these distances (range is wave-uniform)
-    if (range) {
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        rlo = fminf(rlo, r[j]);
-        rhi = fmaxf(rhi, r[j]);
-      }
+    for (int j = 0; j < Q; ++j) {
+      rlo = fminf(rlo, r[j]);
+      rhi = fmaxf(rhi, r[j]);
     }
     float u[Q];
     float4 A[Q], B[Q];
@@ -348,33 +368,37 @@ __device__ __forceinline__ void moments_table(MomentsOf<OP> &M, const TabPtrs &t
       // address, the distance in the read's offset field
       B[j] = kLDS ? at_offset(tab.c01, off + 16 * kLdsCoefHalf) : at_offset(tab.c23, off);
     }
+    float t0r = 0.f, t0i = 0.f, tsr = 0.f, tsi = 0.f, ttr = 0.f, tti = 0.f;
+    float t2r = 0.f, t2i = 0.f;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
+      const int kind = bary_kind(Q, j);
       const float2 g = cubic(A[j], B[j], u[j]);
       float gr = g.x, gi = g.y;
-      if constexpr (OP == MF_OP_MFIE) green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
+      green_to_k(S.k, __builtin_amdgcn_rcpf(r[j]), gr, gi);
       t0r = fmaf(W.w[j], gr, t0r);
       t0i = fmaf(W.w[j], gi, t0i);
+      if (kind == 1 || kind == 3) {
+        tsr = fmaf(W.ws[j], gr, tsr);
+        tsi = fmaf(W.ws[j], gi, tsi);
+      }
+      if (kind == 2 || kind == 3) {
+        ttr = fmaf(W.wt[j], gr, ttr);
+        tti = fmaf(W.wt[j], gi, tti);
+      }
+      if (kind != 0) {  // the centroid's |rho'_j|^2 is zero up to rounding
+        t2r = fmaf(wr2[j], gr, t2r);
+        t2i = fmaf(wr2[j], gi, t2i);
+      }
+    }
+    float t1r[3], t1i[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float wq = qr[kRecWRho + 3 * j + c];
-        t1r[c] = fmaf(wq, gr, t1r[c]);
-        t1i[c] = fmaf(wq, gi, t1i[c]);
-      }
-      if constexpr (OP == MF_OP_MFIE) {
-        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
-                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
-                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
-        t2r = fmaf(wr2, gr, t2r);
-        t2i = fmaf(wr2, gi, t2i);
-      }
+    for (int c = 0; c < 3; ++c) {
+      t1r[c] = -fmaf(b0[c], tsr, b1[c] * ttr);
+      t1i[c] = -fmaf(b0[c], tsi, b1[c] * tti);
     }
-    if constexpr (OP == MF_OP_MFIE) {
-      const float a[3] = {ax, ay, az};
-      add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
-    } else {
-      add_point(M, W.w[i], pri, t0r, t0i, t1r, t1i);
-    }
+    const float a[3] = {ax, ay, az};
+    add_point(M, W.w[i], pri, a, nrm, nq, t0r, t0i, t1r, t1i, t2r, t2i);
   }
 }
 
@@ -541,6 +565,15 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
                                                const float *nrm, const float *nq, float hx, float hy, float hz, float lx, float ly,
                                                float lz, cfloat *qr) {
   zero(M);
+  // the third inner sum's weights w_j |rho'_j|^2, once per pair (MFIE)
+  float wr2[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    wr2[j] = OP == MF_OP_MFIE
+                 ? fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
+                        fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
+                             qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]))
+                 : 0.0f;
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
     float pri[3];
@@ -569,11 +602,8 @@ __device__ __forceinline__ void moments_direct(MomentsOf<OP> &M, const FillScala
         t1i[c] = fmaf(wq, gi, t1i[c]);
       }
       if constexpr (OP == MF_OP_MFIE) {
-        const float wr2 = fmaf(qr[kRecWRho + 3 * j], qr[kRecRho + 3 * j],
-                               fmaf(qr[kRecWRho + 3 * j + 1], qr[kRecRho + 3 * j + 1],
-                                    qr[kRecWRho + 3 * j + 2] * qr[kRecRho + 3 * j + 2]));
-        t2r = fmaf(wr2, gr, t2r);
-        t2i = fmaf(wr2, gi, t2i);
+        t2r = fmaf(wr2[j], gr, t2r);
+        t2i = fmaf(wr2[j], gi, t2i);
       }
     }
     if constexpr (OP == MF_OP_MFIE) {
@@ -1062,7 +1092,8 @@ __device__ __forceinline__ void fill_tile_mfie(
           }
           MomentsM M;
           if (MODE == MF_MODE_TABLE)
-            moments_table<Q, MF_OP_MFIE, kLDS>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+            moments_table_mfie<Q, kLDS>(M, tab, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr,
+                                        rlo, rhi);
           else
             moments_direct<Q, MF_OP_MFIE>(M, S, W, pr, nrm, qn, hx, hy, hz, lx, ly, lz, qr);
 #pragma unroll
