@@ -102,7 +102,7 @@ int mf_mesh_plan(const mf_mesh *mesh, int32_t *n_blocks, int64_t *n_tiles,
  * MF_MODE_TABLE and no MF_PART_ flag): blocks of at most 64 consecutive
  * triangles and 112 edges with a triangle in the block, one tile per block
  * pair I <= J (each unordered triangle pair evaluated once), the source
- * triangles of a block in rounds of at most 16 of which no two share an
+ * triangles of a block in rounds of at most 32 of which no two share an
  * edge.  n_cut edges have their two triangles in different blocks: their
  * entries are completed from a side buffer in the mesh workspace.  All four
  * outputs are 0 when the mesh has no such plan (then the edge-block plan
@@ -203,9 +203,9 @@ int mf_fill_Z(mf_mesh *mesh, const double *vertices_dev, double k, int quad_orde
 /* ---- tuner ---------------------------------------------------------------
  * A full EFIE fill (table or direct mode, no MF_PART_ flags) can run on three
  * kernels: 0, the triangle-block tiling
- * (mf_mesh_tb_plan) with 1024 threads per workgroup (16 waves, one source
- * triangle per wave and round); 1, the same tiling with 512 threads (8 waves,
- * two source triangles per wave and round, twice the registers per lane);
+ * (mf_mesh_tb_plan) with 1024 threads per workgroup (16 waves, two source
+ * triangles per wave and round); 1, the same tiling with 512 threads (8 waves,
+ * four source triangles per wave and round, twice the registers per lane);
  * 2, the edge-block tiling (mf_mesh_plan), which repeats the pairs its blocks
  * share but needs no cut-edge fix-up (partial fills always run on it).  In
  * direct mode the fix-up also adds, in FP64, the reference part of the
@@ -316,8 +316,8 @@ int mf_batch_fill(mf_batch *batch, hipStream_t stream);
  * the latency hiding of the table gathers), and, when every item's mesh has
  * a triangle-block plan (mf_mesh_tb_plan), triangle-block tiles (each
  * unordered triangle pair evaluated once, cut edges completed by a fix-up
- * per item) with 1024 and 512 threads (one or two source triangles per wave
- * and round).  It keeps the fastest; the choice is cached per (quad_order,
+ * per item) with 1024 and 512 threads (two or four source triangles per
+ * wave and round).  It keeps the fastest; the choice is cached per (quad_order,
  * mode, table placement, z_dtype, plan availability) for the process and
  * in the MOMFILL_TUNE_CACHE file when it is set (as for mf_fill_tune), so
  * later batches of the same kind skip the timing.  The outputs hold the

@@ -2279,8 +2279,8 @@ static int launch_fill_tb(mf_mesh *m, const Rule &r, double k, int mode, const m
 
 const char *fill_choice_name(int c) {
   switch (c) {
-    case kFillTB1024: return "triangle blocks of 64, 1024 threads (16 waves, one source triangle per wave and round)";
-    case kFillTB512: return "triangle blocks of 64, 512 threads (8 waves, two source triangles per wave and round)";
+    case kFillTB1024: return "triangle blocks of 64, 1024 threads (16 waves, two source triangles per wave and round)";
+    case kFillTB512: return "triangle blocks of 64, 512 threads (8 waves, four source triangles per wave and round)";
     case kFillEB1024: return "edge blocks of 80 edges / 64 triangles, 1024 threads";
     default: return "unknown";
   }

@@ -22,11 +22,11 @@ constexpr int kMaxBlockEdges = 80;  // RWG edges per row/column block of a tile
 constexpr int kMaxBlockTris = 64;   // triangles carrying a block's edges (one per lane)
 // Triangle-block plan (table-mode fill): blocks of at most 64 consecutive
 // triangles and 112 block edges (edges with a triangle in the block), the
-// source triangles of a block in rounds of at most 16 pairwise non-adjacent
+// source triangles of a block in rounds of at most 32 pairwise non-adjacent
 // triangles, at most kTBMaxRounds rounds.
 constexpr int kTBTris = 64;
 constexpr int kTBEdges = 112;
-constexpr int kTBRound = 16;
+constexpr int kTBRound = 32;
 constexpr int kTBMaxRounds = 12;
 // The MFIE tile (edge blocks, 8 waves) walks each block's source triangles
 // in rounds of at most kEBRound pairwise non-adjacent triangles.
