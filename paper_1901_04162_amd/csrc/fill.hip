@@ -1268,8 +1268,12 @@ constexpr int kTBAccFloats = kTBEdges * kTBStride;
 // triangle, odd stride), read there by the test-point loop instead of from
 // the triangle records.
 constexpr int kRhoFloats = 3 * kMaxQ;
-// and, per triangle pair, alpha (9), sigma (3) and the radius: 13 floats
-constexpr int kAuxFloats = 13;
+// and the fields every triangle pair reads: alpha [0, 9), sigma [9, 12), the
+// radius 12, the vertex ids [13, 16) and the FP64 centroid [16, 22) (22
+// floats, so each centroid is 8-byte aligned); held in LDS rather than in
+// registers across the pair loop
+constexpr int kAuxFloats = 22;
+constexpr int kAuxVid = 13, kAuxCent = 16;
 template <int Q, int MODE, typename ZT, bool kLDS, bool kRhoLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref,
@@ -1294,7 +1298,11 @@ __device__ __forceinline__ void fill_tile_tb(
     }
     for (int x = threadIdx.x; x < npI * kAuxFloats; x += kTBThreads) {
       const int l = x / kAuxFloats, e = x - l * kAuxFloats;
-      aux_lds[x] = rec[(size_t)(tI0 + l) * kRecFloats + (e < 12 ? kRecAlpha + e : kRecRad)];
+      const int f = e < 12         ? kRecAlpha + e
+                    : e == 12      ? kRecRad
+                    : e < kAuxCent ? kRecVid + (e - kAuxVid)
+                                   : kRecCent + (e - kAuxCent);
+      aux_lds[x] = rec[(size_t)(tI0 + l) * kRecFloats + f];
     }
   }
   __syncthreads();
@@ -1307,10 +1315,9 @@ __device__ __forceinline__ void fill_tile_tb(
   // alpha at [0, 9), sigma at [9, 12) in both layouts (kRecSigma = kRecAlpha + 9)
   const float *paux = kRhoLDS ? aux_lds + (pv ? lane : 0) * kAuxFloats : pr + kRecAlpha;
   const float prad = kRhoLDS ? paux[12] : pr[kRecRad];
-  const double *pcd = reinterpret_cast<const double *>(pr + kRecCent);
-  const double pcx = pcd[0], pcy = pcd[1], pcz = pcd[2];
-  const int *pvi = reinterpret_cast<const int *>(pr + kRecVid);
-  const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
+  // the centroid and vertex ids: read per pair from LDS when staged there
+  const double *pcd = reinterpret_cast<const double *>(kRhoLDS ? paux + kAuxCent : pr + kRecCent);
+  const int *pvi = reinterpret_cast<const int *>(kRhoLDS ? paux + kAuxVid : pr + kRecVid);
   const int32_t *rs = S.tb_rounds + (size_t)J * (kTBMaxRounds + 1);
   for (int k = 0; k < kTBMaxRounds; ++k) {
     const int s0 = uniform(rs[k]), s1 = uniform(rs[k + 1]);
@@ -1321,12 +1328,13 @@ __device__ __forceinline__ void fill_tile_tb(
       cfloat *qr = as_const(rec) + (size_t)q * kRecFloats;
       cint32 *qvi = (cint32 *)(qr + kRecVid);
       const int qv0 = qvi[0], qv1 = qvi[1], qv2 = qvi[2];
+      const int pv0 = pvi[0], pv1 = pvi[1], pv2 = pvi[2];
       const bool touch = pv0 == qv0 || pv0 == qv1 || pv0 == qv2 || pv1 == qv0 || pv1 == qv1 ||
                          pv1 == qv2 || pv2 == qv0 || pv2 == qv1 || pv2 == qv2;
       float Xr[3][3], Xi[3][3];
       if (!touch) {
         cdouble *qcd = (cdouble *)(qr + kRecCent);
-        const double Dx = pcx - qcd[0], Dy = pcy - qcd[1], Dz = pcz - qcd[2];
+        const double Dx = pcd[0] - qcd[0], Dy = pcd[1] - qcd[1], Dz = pcd[2] - qcd[2];
         const float hx = (float)Dx, hy = (float)Dy, hz = (float)Dz;
         float palpha[3][3], beta[3][3];
 #pragma unroll
