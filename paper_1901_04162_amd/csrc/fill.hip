@@ -724,11 +724,25 @@ __device__ __forceinline__ void direct_pair(Moments &M, const FillScalars &S, co
                                             const float *pr, cfloat *qr, double Dx, double Dy,
                                             double Dz, float hx, float hy, float hz, float &gr,
                                             float &gi, float &scr, float &sci) {
-  const PairRef P = pair_ref(Dx, Dy, Dz, S.kd);
-  const bool has_ref = P.d > 0.0;
-  moments_direct_split<Q>(M, S, W, pr, hx, hy, hz, (float)P.d, (float)P.d2, (float)P.id,
-                          has_ref ? 0.0f : 1.0f, qr);
-  const float er = (float)P.cs, ei = (float)-P.sn;  // exp(-jkd)
+  // everything the pair needs from its FP64 reference, in FP32, before the
+  // long point-pair loop: the doubles do not stay live across it
+  float er, ei, dgr, dgi, fd, fd2, fid, one;
+  {
+    const PairRef P = pair_ref(Dx, Dy, Dz, S.kd);
+    er = (float)P.cs;  // exp(-jkd)
+    ei = (float)-P.sn;
+    const double gcr = P.cs * P.id, gci = -P.sn * P.id;
+    const float2 g = pair_ref_g(P);
+    gr = g.x;
+    gi = g.y;
+    dgr = (float)(gcr - (double)gr);
+    dgi = (float)(gci - (double)gi);
+    fd = (float)P.d;
+    fd2 = (float)P.d2;
+    fid = (float)P.id;
+    one = P.d > 0.0 ? 0.0f : 1.0f;
+  }
+  moments_direct_split<Q>(M, S, W, pr, hx, hy, hz, fd, fd2, fid, one, qr);
   crot(M.s0r, M.s0i, er, ei);
   crot(M.srr, M.sri, er, ei);
 #pragma unroll
@@ -736,12 +750,8 @@ __device__ __forceinline__ void direct_pair(Moments &M, const FillScalars &S, co
     crot(M.spr[c], M.spi[c], er, ei);
     crot(M.sqr[c], M.sqi[c], er, ei);
   }
-  const double gcr = P.cs * P.id, gci = -P.sn * P.id;
-  const float2 g = pair_ref_g(P);
-  gr = g.x;
-  gi = g.y;
-  scr = M.s0r + (float)(gcr - (double)gr);
-  sci = M.s0i + (float)(gci - (double)gi);
+  scr = M.s0r + dgr;
+  sci = M.s0i + dgi;
 }
 
 // The item's Green table: the interval coefficients are copied into LDS
