@@ -60,7 +60,7 @@ struct AngArgs {
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// exp(-jkR): the linear table of Eq. (4), one 80-byte bucket record per
+// exp(-jkR): the linear table of Eq. (4), one 64-byte bucket record per
 // lookup (the bucket of a coarsened Eq. (6) hash holds both candidate
 // intervals and the sample between them), or sincos.  A table distance
 // beyond r_max (by more than rounding) raises the status flag.
@@ -77,12 +77,13 @@ __device__ __forceinline__ void exp_jkr(const AngArgs &A, double R, double &re, 
   bad |= !(R <= A.ermax * (1.0 + 1e-12));
   int b = (int)(R * A.einv);
   b = b < 0 ? 0 : (b > A.em - 1 ? A.em - 1 : b);
-  const double2 *o = reinterpret_cast<const double2 *>(A.elook + 10 * (size_t)b);
-  const double2 h = o[0], lv = o[1], ls = o[2], rv = o[3], rs = o[4];
+  const double2 *o = reinterpret_cast<const double2 *>(A.elook + 8 * (size_t)b);
+  const double2 h = o[0], lv = o[1], rv = o[2];
+  const float4 sl = *reinterpret_cast<const float4 *>(o + 3);
   const bool right = R >= h.x;
   const double u = R - h.y;
-  re = fma(right ? rs.x : ls.x, u, right ? rv.x : lv.x);
-  im = fma(right ? rs.y : ls.y, u, right ? rv.y : lv.y);
+  re = fma((double)(right ? sl.z : sl.x), u, right ? rv.x : lv.x);
+  im = fma((double)(right ? sl.w : sl.y), u, right ? rv.y : lv.y);
 }
 
 // Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on P_n,

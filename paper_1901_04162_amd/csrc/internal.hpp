@@ -107,11 +107,12 @@ struct mf_tables {
     int mb1 = 0;
     float binv1 = 0.0f, bbias1 = 0.0f, btop1 = 0.0f;
     float4 *coef = nullptr;
-    // FP64 lookup of the Exp table: m64 bucket records of 10 doubles, bucket
+    // FP64 lookup of the Exp table: m64 bucket records of 64 bytes, bucket
     // b = (int)(r * inv64) of width just under the smallest sample interval,
     // so at most one sample (split) lies inside a bucket: {split, x_b, the
-    // interval left of split as E + slope (r - x_b) (4 doubles), the
-    // interval right of it likewise (4 doubles)}
+    // value at x_b of the interval left of split and of the one right of it
+    // (2 + 2 doubles), then the two intervals' slopes as 4 floats}; a lookup
+    // evaluates E + slope (r - x_b)
     double *look64 = nullptr;
     int m64 = 0;
     double inv64 = 0.0;

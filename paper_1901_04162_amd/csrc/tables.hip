@@ -361,8 +361,9 @@ __global__ void k_pack_exp(const double *r, const double *f, int n, float4 *coef
 // of Eq. (6) for a table that starts at r = 0): bucket b = (int)(r * inv)
 // with width just under the smallest sample interval holds at most one
 // sample; its record carries that sample (split, +inf if none), the bucket
-// start x_b and both candidate intervals as value-at-x_b and slope, so one
-// 80-byte read answers a lookup.  Sample buckets use the lookup's own formula.
+// start x_b and both candidate intervals as value-at-x_b (FP64) and slope
+// (FP32: the slope only multiplies r - x_b, less than one bucket), so one
+// 64-byte read answers a lookup.  Sample buckets use the lookup's own formula.
 __global__ void k_node_bucket64(const double *r, int n, double inv, int *nb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) nb[i] = (int)(r[i] * inv);
@@ -401,11 +402,21 @@ __global__ void k_pack_look64(const double *r, const double *f, const int *nb, i
   iL = iL < 0 ? 0 : (iL > n - 2 ? n - 2 : iL);
   iR = iR < 0 ? 0 : (iR > n - 2 ? n - 2 : iR);
   const double xb = (double)b / inv;
-  double *o = look + 10 * (size_t)b;
+  double *o = look + 8 * (size_t)b;
+  double L[4], Rr[4];
+  linear_at(r, f, iL, xb, L);
+  linear_at(r, f, iR, xb, Rr);
   o[0] = split;
   o[1] = xb;
-  linear_at(r, f, iL, xb, o + 2);
-  linear_at(r, f, iR, xb, o + 6);
+  o[2] = L[0];
+  o[3] = L[1];
+  o[4] = Rr[0];
+  o[5] = Rr[1];
+  float *sl = reinterpret_cast<float *>(o + 6);
+  sl[0] = (float)L[2];
+  sl[1] = (float)L[3];
+  sl[2] = (float)Rr[2];
+  sl[3] = (float)Rr[3];
 }
 
 // ---- host driver ---------------------------------------------------------
@@ -587,7 +598,7 @@ static int pack(mf_tables *T, int kind, mf_tables::One &o, hipStream_t s) {
     const double w = 0.999 * o.delta;
     o.inv64 = 1.0 / w;
     o.m64 = (int)(T->rmax * o.inv64) + 1;
-    if (!A.bottom(&o.look64, 10 * (size_t)o.m64)) return out_of_space();
+    if (!A.bottom(&o.look64, 8 * (size_t)o.m64)) return out_of_space();
     hipLaunchKernelGGL(k_node_bucket64, dim3(blocks(o.n, 256)), dim3(256), 0, s, o.r, o.n,
                        o.inv64, nb);
     hipLaunchKernelGGL(k_pack_look64, dim3(blocks(o.m64, 256)), dim3(256), 0, s, o.r, o.f, nb,
@@ -628,7 +639,7 @@ static void count_table(Arena &A, int kind, double k, double rmin, double rmax, 
   A.bottom(&coef, (kind == kGreen ? 2 : 1) * n);
   if (kind == kGreen)
     A.bottom(&look, (size_t)std::floor((rmax - rmin) / (kBucketWidth1 * dmin)) + 3);
-  if (kind == kExp && rmin == 0.0) A.bottom(&r, 10 * ((size_t)(rmax / (0.999 * dmin)) + 3));
+  if (kind == kExp && rmin == 0.0) A.bottom(&r, 8 * ((size_t)(rmax / (0.999 * dmin)) + 3));
   // temporaries: placement cells and counters, or the packing's bucket list
   const size_t place = Arena::up(sizeof(double) * 2 * (size_t)P.ncell) + 2 * 256;
   const size_t packing = Arena::up(sizeof(int) * (n + 1)) + 256;
