@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -542,6 +543,9 @@ def main():
             "triangles": T_, "unknowns": E, "k": k, "quad_order": Q, "tol": args.tol,
             "green_table_samples": T.n_green, "green_table_buckets": T.m_green,
             "exp_table_samples": T.n_exp,
+            # sampling density over [r_min, r_max] (Eq. (2) quotes 1e3-1e4 per wavelength)
+            "green_samples_per_wavelength": T.n_green * (2 * math.pi / k) / (T.r_max - T.r_min),
+            "exp_samples_per_wavelength": T.n_exp * (2 * math.pi / k) / (T.r_max - T.r_min),
             "fill_kernel": tune_name,
             "tuner_ms_tb1024_tb512_eb1024": tune_ms,
             "triangle_block_plan": dict(zip(("blocks", "tiles", "cut_edges", "rounds"),
