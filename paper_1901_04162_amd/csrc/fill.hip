@@ -429,13 +429,8 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
                                              bool range = true) {
 #pragma unroll
   for (int x = 0; x < 9; ++x) N.r[x] = N.i[x] = 0.0f;
-  float nq[Q];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const float qx = qr[kRecRho + 3 * j], qy = qr[kRecRho + 3 * j + 1],
-                qz = qr[kRecRho + 3 * j + 2];
-    nq[j] = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-  }
+  // |rho'_j|^2 from the source record (scalar loads, formed by k_geometry)
+  cfloat *nq = qr + kRecRho2;
   const float b0x = qr[kRecAlpha], b0y = qr[kRecAlpha + 1], b0z = qr[kRecAlpha + 2];
   const float b1x = qr[kRecAlpha + 3], b1y = qr[kRecAlpha + 4], b1z = qr[kRecAlpha + 5];
 #pragma unroll 1

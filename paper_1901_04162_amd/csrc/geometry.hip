@@ -62,14 +62,18 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
   float *o = rec + (size_t)t * kRecFloats;
   double rb = 0.0;
   for (int i = 0; i < kMaxQ; ++i) {
+    float rr[3] = {0.0f, 0.0f, 0.0f};  // the FP32 offsets as stored
     double P[3] = {0.0, 0.0, 0.0};
     if (i < R.nq) quad_point(R, i, x[0], x[1], x[2], P);
     for (int d = 0; d < 3; ++d) {
       const double rho = i < R.nq ? P[d] - c[d] : 0.0;
       o[kRecRho + 3 * i + d] = (float)rho;
       o[kRecWRho + 3 * i + d] = (float)(i < R.nq ? R.w[i] * rho : 0.0);
+      rr[d] = (float)rho;
       if (qp64 && i < R.nq) qp64[((size_t)t * kMaxQ + i) * 3 + d] = P[d];
     }
+    // |rho_i|^2 from the stored FP32 offsets, with the fill's own FP32 formula
+    o[kRecRho2 + i] = fmaf(rr[0], rr[0], fmaf(rr[1], rr[1], rr[2] * rr[2]));
     if (i < R.nq) {
       const double dd[3] = {P[0] - c[0], P[1] - c[1], P[2] - c[2]};
       rb = fmax(rb, sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
@@ -97,6 +101,7 @@ __global__ void k_geometry(const double *__restrict__ V, const int32_t *__restri
   vi[2] = vid[2];
   float rf = (float)rb;
   if ((double)rf < rb) rf = nextafterf(rf, INFINITY);
+  o[kRecRho2 + kMaxQ] = 0.0f;
   o[kRecRad] = rf;
 }
 

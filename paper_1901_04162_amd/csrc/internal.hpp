@@ -33,7 +33,7 @@ constexpr int kTBMaxRounds = 12;
 constexpr int kEBRound = 8;
 constexpr int kEBMaxRounds = 16;
 
-// Per-triangle record read by the regular-pair kernel (64 floats, 256 B):
+// Per-triangle record read by the regular-pair kernel (72 floats, 288 B):
 //  [0,21)  rho_i = r_i - c      (i-major, xyz)           FP32
 //  [21,42) w_i rho_i                                       FP32
 //  [42,51) alpha_a = c - v_a   (a-major, xyz)             FP32
@@ -41,9 +41,11 @@ constexpr int kEBMaxRounds = 16;
 //  [54,60) centroid c as three doubles                    FP64
 //  [60,63) vertex indices                                 int32
 //  63      radius of the quadrature points about c, rounded up  FP32
-constexpr int kRecFloats = 64;
+//  [64,71) |rho_i|^2, the squared offsets (a source triangle's, read by the
+//          table-mode moments through scalar loads)                 FP32
+constexpr int kRecFloats = 72;
 constexpr int kRecRho = 0, kRecWRho = 21, kRecAlpha = 42, kRecSigma = 51, kRecCent = 54,
-              kRecVid = 60, kRecRad = 63;
+              kRecVid = 60, kRecRad = 63, kRecRho2 = 64;
 
 // Carves a caller-owned device workspace into arrays: `bottom` takes space
 // from the low end (arrays that outlive a call), `top` from the high end

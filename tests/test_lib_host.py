@@ -157,8 +157,8 @@ def test_workspaces_without_gpu():
     m = mf.Mesh(F, V.shape[0])
     n = C.c_size_t()
     assert L.mf_mesh_workspace_bytes(m.handle, C.byref(n)) == mf._lib.MF_OK
-    # at least the 256-byte records and the FP64 quadrature points of every triangle
-    assert n.value >= F.shape[0] * (256 + 3 * 7 * 8)
+    # at least the 288-byte records and the FP64 quadrature points of every triangle
+    assert n.value >= F.shape[0] * (288 + 3 * 7 * 8)
     fake = C.c_void_p(1 << 30)
     assert L.mf_mesh_set_workspace(m.handle, fake, n.value - 1, None) == mf._lib.MF_EINVAL
     assert b"too small" in L.mf_last_error()
