@@ -425,8 +425,7 @@ template <int Q, bool kLDS>
 __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const FillScalars &S,
                                              const FillRule &W, const float *pr, float hx,
                                              float hy, float hz, float lx, float ly, float lz,
-                                             cfloat *qr, float &rlo, float &rhi,
-                                             bool range = true) {
+                                             cfloat *qr, bool &oor, bool range = true) {
 #pragma unroll
   for (int x = 0; x < 9; ++x) N.r[x] = N.i[x] = 0.0f;
   // |rho'_j|^2 from the source record (scalar loads, formed by k_geometry)
@@ -455,11 +454,9 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
     if (range) {
+      // a distance outside the table's range sets the lane's flag
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        rlo = fminf(rlo, r[j]);
-        rhi = fmaxf(rhi, r[j]);
-      }
+      for (int j = 0; j < Q; ++j) oor = oor || r[j] < S.lo_ok || r[j] > S.hi_ok;
     }
     float u[Q];
     float4 Ac[Q], Bc[Q];
@@ -772,7 +769,7 @@ template <int Q, int MODE, int PART, typename ZT, int kFillThreads, bool kSparse
           bool kLDS = false>
 __device__ __forceinline__ void fill_tile(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref, int local,
-    float &rlo, float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
+    bool &oor, const float *__restrict__ rec, const int32_t *__restrict__ tiles,
     const int32_t *__restrict__ blk_e0, const int32_t *__restrict__ blk_off,
     const int32_t *__restrict__ blk_tri, const int32_t *__restrict__ blk_pos,
     const int32_t *__restrict__ touch_off, const int32_t *__restrict__ touch_q,
@@ -817,7 +814,7 @@ __device__ __forceinline__ void fill_tile(
                     lz = (float)(Dz - (double)hz);
         if (MODE == MF_MODE_TABLE) {
           Bary N;
-          moments_bary<Q, kLDS>(N, tab, S, W, pr, hx, hy, hz, lx, ly, lz, qr, rlo, rhi);
+          moments_bary<Q, kLDS>(N, tab, S, W, pr, hx, hy, hz, lx, ly, lz, qr, oor);
           float al[3][3], be[3][3];
 #pragma unroll
           for (int a = 0; a < 3; ++a)
@@ -1237,7 +1234,8 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
   const TabPtrs tab = load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(
       S, smem4 + kAccs * kAccFloats / 4 + 1);
   float2 *gref = reinterpret_cast<float2 *>(acc + 2 * kAccFloats + 4);  // direct mode
-  float rlo = INFINITY, rhi = 0.0f;
+  float rlo = INFINITY, rhi = 0.0f;  // the MFIE's distance extremes
+  bool oor = false;                   // the EFIE's out-of-range flag
   const int ntiles = S.tile_end - S.tile_begin;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     if constexpr (OP == MF_OP_MFIE)
@@ -1246,10 +1244,10 @@ __attribute__((amdgpu_waves_per_eu(fill_threads_op<MODE, OP>() / 256,
           S.blk_pos, S.touch_off, S.touch_q, S.touch_rev, S.sing, reinterpret_cast<ZT *>(S.Z));
     else
       fill_tile<Q, MODE, PART, ZT, kFillThreads, kSparse, MODE == MF_MODE_TABLE && kLDS>(
-          S, W, tab, acc, gref, t, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
+          S, W, tab, acc, gref, t, oor, S.rec, S.tiles, S.blk_e0, S.blk_off, S.blk_tri, S.blk_pos,
           S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
   }
-  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+  if (MODE == MF_MODE_TABLE && (oor || rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
 }
 
 // ---- triangle-block tiles (table mode) -------------------------------------
@@ -1282,8 +1280,8 @@ constexpr int kAuxVid = 13, kAuxCent = 16;
 template <int Q, int MODE, typename ZT, bool kLDS, bool kRhoLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref,
-    float *rho_lds, float *aux_lds, int local, float &rlo,
-    float &rhi, const float *__restrict__ rec, const int32_t *__restrict__ tb_pos,
+    float *rho_lds, float *aux_lds, int local, bool &oor, const float *__restrict__ rec,
+    const int32_t *__restrict__ tb_pos,
     const int32_t *__restrict__ tb_order, const int32_t *__restrict__ touch_off,
     const int32_t *__restrict__ touch_q, const float *__restrict__ sing, ZT *__restrict__ Z,
     float2 *__restrict__ side) {
@@ -1319,7 +1317,6 @@ __device__ __forceinline__ void fill_tile_tb(
   const float *prho = kRhoLDS ? rho_lds + (pv ? lane : 0) * kRhoFloats : pr;
   // alpha at [0, 9), sigma at [9, 12) in both layouts (kRecSigma = kRecAlpha + 9)
   const float *paux = kRhoLDS ? aux_lds + (pv ? lane : 0) * kAuxFloats : pr + kRecAlpha;
-  const float prad = kRhoLDS ? paux[12] : pr[kRecRad];
   // the centroid and vertex ids: read per pair from LDS when staged there
   const double *pcd = reinterpret_cast<const double *>(kRhoLDS ? paux + kAuxCent : pr + kRecCent);
   const int *pvi = reinterpret_cast<const int *>(kRhoLDS ? paux + kAuxVid : pr + kRecVid);
@@ -1356,10 +1353,12 @@ __device__ __forceinline__ void fill_tile_tb(
           // radius q); only waves where that interval leaves the table's range
           // for some lane check each distance (the slack covers rounding).
           const float dd = __builtin_amdgcn_sqrtf(fmaf(hx, hx, fmaf(hy, hy, hz * hz)));
-          const float rr = prad + qr[kRecRad], sl = 1e-5f * (dd + rr);
+          // the test triangle's radius read where used (LDS when staged)
+          const float rr = (kRhoLDS ? paux[12] : pr[kRecRad]) + qr[kRecRad];
+          const float sl = 1e-5f * (dd + rr);
           const bool near_end = pv && (dd - rr - sl < S.lo_ok || dd + rr + sl > S.hi_ok);
           Bary N;
-          moments_bary<Q, kLDS>(N, tab, S, W, prho, hx, hy, hz, lx, ly, lz, qr, rlo, rhi,
+          moments_bary<Q, kLDS>(N, tab, S, W, prho, hx, hy, hz, lx, ly, lz, qr, oor,
                                 __any(near_end) != 0);
           entries_bary<0>(N, palpha, beta, S.ik2, Xr, Xi);
         } else {
@@ -1531,12 +1530,12 @@ __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_
                        ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 + kLdsCoefHalf +
                                                    (S.tn - 1))
                        : rho_lds + kRhoFloats * kTBTris;
-  float rlo = INFINITY, rhi = 0.0f;
+  bool oor = false;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x)
     fill_tile_tb<Q, MODE, ZT, kLDS, kRhoLDS, kTBThreads>(
-        S, W, tab, acc, gref, rho_lds, aux_lds, t, rlo, rhi, S.rec, S.tb_pos, S.tb_order, S.touch_off,
+        S, W, tab, acc, gref, rho_lds, aux_lds, t, oor, S.rec, S.tb_pos, S.tb_order, S.touch_off,
         S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
-  if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+  if (MODE == MF_MODE_TABLE && oor) atomicOr(S.status, 1);
 }
 
 // Several items on the triangle-block plan in one persistent launch: the
@@ -1566,12 +1565,12 @@ __attribute__((amdgpu_waves_per_eu(kTBThreads / 256, kTBThreads / 256))) void k_
                          ? reinterpret_cast<float *>(smem4 + kTBAccFloats / 4 + 1 +
                                                      kLdsCoefHalf + (S.tn - 1))
                          : rho_lds + kRhoFloats * kTBTris;
-    float rlo = INFINITY, rhi = 0.0f;
+    bool oor = false;
     for (; t < S.tb_end; t += G)
       fill_tile_tb<Q, MODE, ZT, kLDS, kRhoLDS, kTBThreads>(
-          S, W, tab, acc, gref, rho_lds, aux_lds, t - S.tb_begin, rlo, rhi, S.rec, S.tb_pos,
+          S, W, tab, acc, gref, rho_lds, aux_lds, t - S.tb_begin, oor, S.rec, S.tb_pos,
           S.tb_order, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z), S.side);
-    if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+    if (MODE == MF_MODE_TABLE && oor) atomicOr(S.status, 1);
     // the next item's table overwrites this one's in LDS
     __syncthreads();
   }
@@ -1670,12 +1669,12 @@ __attribute__((amdgpu_waves_per_eu(kFillThreads / 256, kFillThreads / 256))) voi
     if (t >= S.tile_end) continue;
     const TabPtrs tab =
         load_table<MODE == MF_MODE_TABLE && kLDS, kFillThreads>(S, smem4 + 2 * kAccFloats / 4 + 1);
-    float rlo = INFINITY, rhi = 0.0f;
+    bool oor = false;
     for (; t < S.tile_end; t += G)
       fill_tile<Q, MODE, 0, ZT, kFillThreads, false, MODE == MF_MODE_TABLE && kLDS>(
-          S, W, tab, acc, gref, t - S.tile_begin, rlo, rhi, S.rec, S.tiles, S.blk_e0, S.blk_off,
+          S, W, tab, acc, gref, t - S.tile_begin, oor, S.rec, S.tiles, S.blk_e0, S.blk_off,
           S.blk_tri, S.blk_pos, S.touch_off, S.touch_q, S.sing, reinterpret_cast<ZT *>(S.Z));
-    if (MODE == MF_MODE_TABLE && (rlo < S.lo_ok || rhi > S.hi_ok)) atomicOr(S.status, 1);
+    if (MODE == MF_MODE_TABLE && oor) atomicOr(S.status, 1);
   }
 }
 
