@@ -454,9 +454,15 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
     if (range) {
-      // a distance outside the table's range sets the lane's flag
+      // a distance outside the table's range sets the lane's flag; the
+      // smallest and largest of the Q distances decide it without branches
+      float rmin = r[0], rmax = r[0];
 #pragma unroll
-      for (int j = 0; j < Q; ++j) oor = oor || r[j] < S.lo_ok || r[j] > S.hi_ok;
+      for (int j = 1; j < Q; ++j) {
+        rmin = fminf(rmin, r[j]);
+        rmax = fmaxf(rmax, r[j]);
+      }
+      oor = oor | (rmin < S.lo_ok) | (rmax > S.hi_ok);
     }
     float u[Q];
     float4 Ac[Q], Bc[Q];

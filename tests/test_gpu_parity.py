@@ -274,13 +274,18 @@ def test_tetrahedron_only_touching_pairs(mf, orc):
         mf.r_range(m, V, 7)  # no vertex-disjoint pair
 
 
-def test_out_of_range_tables_reported(mf, ico2):
+@pytest.mark.parametrize("side", ["upper", "lower"])
+def test_out_of_range_tables_reported(mf, ico2, side):
+    """Tables that miss the top or the bottom of the distance range: the fill
+    reports it."""
     import torch
 
     c = ico2
     m = mf.Mesh(c["F"], c["V"].shape[0])
-    T = mf.build_tables(c["k"], c["rmin"], 0.5 * (c["rmin"] + c["rmax"]), 1e-6)
-    say("ERANGE")
+    mid = 0.5 * (c["rmin"] + c["rmax"])
+    lo, hi = (c["rmin"], mid) if side == "upper" else (mid, c["rmax"])
+    T = mf.build_tables(c["k"], lo, hi, 1e-6)
+    say("ERANGE", side)
     mf.fill_Z(m, c["V"], c["k"], c["Q"], "table", T, dtype=torch.complex64)
     with pytest.raises(mf.MomfillError) as e:
         mf.sync_status(m)
