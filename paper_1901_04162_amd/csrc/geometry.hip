@@ -229,27 +229,45 @@ __global__ void k_range_far(const float *__restrict__ rec, int nt, int from,
 
 // Witnesses: each triangle against a few index neighbours (close in space for
 // meshes numbered with locality), a few pseudo-random partners and the two
-// ends of the approximate diameter (far[0], far[1]).
-__global__ void k_range_seed(const double *__restrict__ qp64, const float *__restrict__ rec, int nt,
-                             int nq, unsigned long long *__restrict__ out,
-                             const unsigned long long *__restrict__ far) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// ends of the approximate diameter (far[0], far[1]).  One thread per
+// (triangle, witness): blockIdx.y is the witness, so the grid holds
+// kRangeWitnesses times as many threads as triangles and fills the chip; the
+// extremes are reduced over the workgroup before its two atomics.
+constexpr int kRangeWitnesses = 26;
+constexpr int kSeedThreads = 256;
+
+__global__ __launch_bounds__(kSeedThreads) void k_range_seed(
+    const double *__restrict__ qp64, const float *__restrict__ rec, int nt, int nq,
+    unsigned long long *__restrict__ out, const unsigned long long *__restrict__ far) {
+  const int p = blockIdx.x * kSeedThreads + threadIdx.x;
+  const int j = blockIdx.y;
   double lo = INFINITY, hi = 0.0;
   if (p < nt) {
     const int *pv = reinterpret_cast<const int *>(rec + (size_t)p * kRecFloats + kRecVid);
-    const int f0 = (int)(unsigned)(far[0] & 0xffffffffull);
-    const int f1 = (int)(unsigned)(far[1] & 0xffffffffull);
-    for (int j = 0; j < 26; ++j) {
-      const int q = j < 16   ? (p + 2 + j) % nt
-                    : j < 24 ? (int)(((long long)p * 7919 + (long long)j * 104729) % nt)
-                    : j == 24 ? f0
-                              : f1;
-      const int *qv = reinterpret_cast<const int *>(rec + (size_t)q * kRecFloats + kRecVid);
-      if (q == p || share_vertex(pv, qv)) continue;
-      pair_extremes(qp64, nq, p, q, lo, hi);
-    }
+    const int q = j < 16   ? (p + 2 + j) % nt
+                  : j < 24 ? (int)(((long long)p * 7919 + (long long)j * 104729) % nt)
+                  : (int)(unsigned)(far[j - 24] & 0xffffffffull);
+    const int *qv = reinterpret_cast<const int *>(rec + (size_t)q * kRecFloats + kRecVid);
+    if (q != p && !share_vertex(pv, qv)) pair_extremes(qp64, nq, p, q, lo, hi);
   }
-  flush_extremes(lo, hi, out);
+  unsigned long long l = lo < INFINITY ? (unsigned long long)__double_as_longlong(lo) : ~0ull;
+  unsigned long long h = (unsigned long long)__double_as_longlong(hi);
+  l = wave_min_u64(l);
+  h = wave_max_u64(h);
+  __shared__ unsigned long long red[2][kSeedThreads / 64];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = l;
+    red[1][threadIdx.x >> 6] = h;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kSeedThreads / 64; ++w) {
+      l = red[0][w] < l ? red[0][w] : l;
+      h = red[1][w] > h ? red[1][w] : h;
+    }
+    if (l != ~0ull) atomicMin(&out[0], l);
+    atomicMax(&out[1], h);
+  }
 }
 
 // Bounding sphere of every run of kRun triangles (centre, radius covering all
@@ -397,8 +415,8 @@ static int range_scan(mf_mesh *m, const Rule &r, unsigned long long *words, doub
   hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, 0, words, words + 2);
   hipLaunchKernelGGL(k_range_far, tgrid, dim3(256), 0, s, m->d_rec, m->nt, -1, words + 2,
                      words + 3);
-  hipLaunchKernelGGL(k_range_seed, tgrid, dim3(256), 0, s, m->d_qp64, m->d_rec, m->nt, r.nq,
-                     words, words + 2);
+  hipLaunchKernelGGL(k_range_seed, dim3((m->nt + kSeedThreads - 1) / kSeedThreads, kRangeWitnesses),
+                     dim3(kSeedThreads), 0, s, m->d_qp64, m->d_rec, m->nt, r.nq, words, words + 2);
   MF_HIP(hipGetLastError());
   const int nb = (m->nt + kRangeBlock - 1) / kRangeBlock;
   const int nr = range_runs(m->nt);
