@@ -321,8 +321,18 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
   // Skip the block pair when no point pair in it can lower the running
   // minimum or raise the running maximum: 64 threads test the 8 x 8 pairs of
   // its 32-triangle runs' bounding spheres.
+  // The running extremes are read once per workgroup (a relaxed agent-scope
+  // load, not a read-modify-write on the two contended words) and shared
+  // through LDS; an older value only keeps more pairs, never fewer.
   __shared__ int keep;
-  if (threadIdx.x == 0) keep = 0;
+  __shared__ double ext[2];
+  if (threadIdx.x == 0) {
+    keep = 0;
+    ext[0] = __longlong_as_double(
+        (long long)__hip_atomic_load(&out[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    ext[1] = __longlong_as_double(
+        (long long)__hip_atomic_load(&out[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
   __syncthreads();
   constexpr int kRuns = kRangeBlock / kRangeScreen;
   if (threadIdx.x < kRuns * kRuns) {
@@ -333,9 +343,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
       const double *a = sph_round + 4 * ra, *b = sph_round + 4 * rb;
       const double dc = sqrt(sq_dist(a, b)), rr = a[3] + b[3];
       const double dmin = fmax(0.0, dc - rr), dmax = dc + rr;
-      const double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
-      const double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
-      if (!(dmin * dmin * (1.0 - 1e-9) > lo && dmax * dmax * (1.0 + 1e-9) < hi))
+      if (!(dmin * dmin * (1.0 - 1e-9) > ext[0] && dmax * dmax * (1.0 + 1e-9) < ext[1]))
         atomicOr(&keep, 1);
     }
   }
@@ -349,8 +357,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
   const int p = p0 + threadIdx.x;
   const int nqc = min(kRangeChunk, nt - q0);
   for (int i = threadIdx.x; i < nqc; i += kRangeBlock) load_range_tri(brad, rec, q0 + i, sq[i]);
-  double lo = __longlong_as_double((long long)atomicAdd(&out[0], 0ull));
-  double hi = __longlong_as_double((long long)atomicAdd(&out[1], 0ull));
+  double lo = ext[0], hi = ext[1];
   RangeTri P{};
   if (p < nt) load_range_tri(brad, rec, p, P);
   // The pair bounds are screened in FP32 and made conservative: the centre
