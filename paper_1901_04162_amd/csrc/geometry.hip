@@ -181,17 +181,29 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
   return v;
 }
 
-// lo, hi: running extremes of the squared distance
+// lo, hi: running extremes of the squared distance.  Both triangles' points
+// are loaded once into registers (nq is uniform; slots past it are neither
+// loaded nor used).
 __device__ inline void pair_extremes(const double *qp64, int nq, int p, int q, double &lo,
                                      double &hi) {
-  for (int a = 0; a < nq; ++a) {
-    const double *pa = qp64 + ((size_t)p * kMaxQ + a) * 3;
-    for (int b = 0; b < nq; ++b) {
-      const double R2 = sq_dist(pa, qp64 + ((size_t)q * kMaxQ + b) * 3);
-      lo = fmin(lo, R2);
-      hi = fmax(hi, R2);
+  double P[kMaxQ][3], Qp[kMaxQ][3];
+  const double *pp = qp64 + (size_t)p * kMaxQ * 3, *qq = qp64 + (size_t)q * kMaxQ * 3;
+#pragma unroll
+  for (int a = 0; a < kMaxQ; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      P[a][c] = a < nq ? pp[3 * a + c] : 0.0;
+      Qp[a][c] = a < nq ? qq[3 * a + c] : 0.0;
     }
-  }
+#pragma unroll
+  for (int a = 0; a < kMaxQ; ++a)
+#pragma unroll
+    for (int b = 0; b < kMaxQ; ++b)
+      if (a < nq && b < nq) {
+        const double R2 = sq_dist(P[a], Qp[b]);
+        lo = fmin(lo, R2);
+        hi = fmax(hi, R2);
+      }
 }
 
 // out[0], out[1]: bits of the extreme squared distances found so far
