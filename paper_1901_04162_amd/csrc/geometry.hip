@@ -206,18 +206,6 @@ __device__ inline void pair_extremes(const double *qp64, int nq, int p, int q, d
       }
 }
 
-// out[0], out[1]: bits of the extreme squared distances found so far
-__device__ inline void flush_extremes(double lo, double hi, unsigned long long *out) {
-  unsigned long long l = lo < INFINITY ? (unsigned long long)__double_as_longlong(lo) : ~0ull;
-  unsigned long long h = (unsigned long long)__double_as_longlong(hi);
-  l = wave_min_u64(l);
-  h = wave_max_u64(h);
-  if ((threadIdx.x & 63) == 0) {
-    if (l != ~0ull) atomicMin(&out[0], l);
-    atomicMax(&out[1], h);
-  }
-}
-
 // Farthest centroid from the centroid of triangle `from` (or, when from < 0,
 // of the triangle whose index sits in the low half of *from_slot): *out keeps
 // the maximum of (float bits of the squared distance) << 32 | index.  Two
@@ -337,13 +325,15 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
   // load, not a read-modify-write on the two contended words) and shared
   // through LDS; an older value only keeps more pairs, never fewer.
   __shared__ int keep;
+  __shared__ unsigned long long extb[2];
   __shared__ double ext[2];
   if (threadIdx.x == 0) {
     keep = 0;
-    ext[0] = __longlong_as_double(
-        (long long)__hip_atomic_load(&out[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    ext[1] = __longlong_as_double(
-        (long long)__hip_atomic_load(&out[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    extb[0] = __hip_atomic_load(&out[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    extb[1] = __hip_atomic_load(&out[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // no minimum yet (~0): +inf, so that every pair is screened in
+    ext[0] = extb[0] == ~0ull ? INFINITY : __longlong_as_double((long long)extb[0]);
+    ext[1] = __longlong_as_double((long long)extb[1]);
   }
   __syncthreads();
   constexpr int kRuns = kRangeBlock / kRangeScreen;
@@ -419,7 +409,27 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
       pair_extremes(qp64, nq, p0 + (list[e] >> 16), q0 + (list[e] & 0xffff), lo, hi);
     __syncthreads();
   }
-  flush_extremes(lo, hi, out);
+  // Reduce over the workgroup; touch the two contended words only when the
+  // workgroup improves on the extremes it read at its start (bit patterns of
+  // non-negative doubles order as unsigned integers; ~0 is "none yet").
+  unsigned long long l = lo < INFINITY ? (unsigned long long)__double_as_longlong(lo) : ~0ull;
+  unsigned long long h = (unsigned long long)__double_as_longlong(hi);
+  l = wave_min_u64(l);
+  h = wave_max_u64(h);
+  __shared__ unsigned long long red[2][kRangeBlock / 64];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = l;
+    red[1][threadIdx.x >> 6] = h;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRangeBlock / 64; ++w) {
+      l = red[0][w] < l ? red[0][w] : l;
+      h = red[1][w] > h ? red[1][w] : h;
+    }
+    if (l < extb[0]) atomicMin(&out[0], l);
+    if (h > extb[1]) atomicMax(&out[1], h);
+  }
 }
 
 int range_runs(int nt) { return (nt + kRangeScreen - 1) / kRangeScreen; }
