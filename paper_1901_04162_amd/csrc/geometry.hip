@@ -391,13 +391,20 @@ __global__ __launch_bounds__(kRangeBlock) void k_range(const double *__restrict_
         const float D[3] = {(float)(Q.c[0] - P.c[0]), (float)(Q.c[1] - P.c[1]),
                             (float)(Q.c[2] - P.c[2])};
         const float d2 = fmaf(D[0], D[0], fmaf(D[1], D[1], D[2] * D[2]));
+        const float qrb = (float)Q.rb;
+        const float d = sqrtf(d2), rr = prb + qrb;
+        // Bounds from the two radii alone: with sp, sqq <= sqrt(1 + 1e-5) below,
+        // (d + rr)^2 * 1.00002 lies above hi_b and 0.99998 d2 - 2.0001 d rr
+        // below lo_b, with margins far above their FP32 rounding; a pair
+        // outside both cannot move an extreme and skips the normal terms.
+        if ((d + rr) * (d + rr) * 1.00002f < hi_f && fmaf(d2, 0.99998f, -2.0001f * d * rr) > lo_f)
+          continue;
         const float id2 = 1.0f / fmaxf(d2, 1e-30f);
         const float dp = D[0] * pn[0] + D[1] * pn[1] + D[2] * pn[2];
         const float dq = D[0] * (float)Q.n[0] + D[1] * (float)Q.n[1] + D[2] * (float)Q.n[2];
         const float sp = sqrtf(fmaxf(0.0f, 1.0f - dp * dp * id2) + 1e-5f);
         const float sqq = sqrtf(fmaxf(0.0f, 1.0f - dq * dq * id2) + 1e-5f);
-        const float qrb = (float)Q.rb;
-        const float d = sqrtf(d2), dh = 2.0f * d * (prb * sp + qrb * sqq), rr = prb + qrb;
+        const float dh = 2.0f * d * (prb * sp + qrb * sqq);
         const float lo_b = (d2 - dh) - 1e-5f * (d2 + dh);
         const float hi_b = (d2 + dh + rr * rr) * 1.00001f;
         if (lo_b <= lo_f || hi_b >= hi_f) list[atomicAdd(&nlist, 1)] = (threadIdx.x << 16) | j;
