@@ -1653,7 +1653,16 @@ __global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long l
   for (int j = ty; j < kFixTile; j += 4) {
     const int m = n0 + j;
     if (m >= ne || ci >= ncut || cut_idx[m] >= 0) continue;
-    Z[(size_t)m * ldz + c] = tile[tx][j];
+    // an isolated entry per line: streamed past the caches (non-temporal)
+    const ZT v = tile[tx][j];
+    ZT *dst = Z + (size_t)m * ldz + c;
+    if constexpr (sizeof(ZT) == 8) {
+      __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v),
+                                  reinterpret_cast<unsigned long long *>(dst));
+    } else {
+      __builtin_nontemporal_store(v.x, &dst->x);
+      __builtin_nontemporal_store(v.y, &dst->y);
+    }
   }
 }
 
