@@ -1283,6 +1283,19 @@ constexpr int kRhoFloats = 3 * kMaxQ;
 // registers across the pair loop
 constexpr int kAuxFloats = 22;
 constexpr int kAuxVid = 13, kAuxCent = 16;
+// Output written once and never read back by the fill: non-temporal stores
+// stream it past the caches, which keep the reused triangle and bucket
+// records instead.
+template <typename T>
+__device__ __forceinline__ void store_stream(T *dst, T v) {
+  if constexpr (sizeof(T) == 8) {
+    __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double *>(dst));
+  } else {
+    __builtin_nontemporal_store(v.x, &dst->x);
+    __builtin_nontemporal_store(v.y, &dst->y);
+  }
+}
+
 template <int Q, int MODE, typename ZT, bool kLDS, bool kRhoLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref,
@@ -1477,7 +1490,7 @@ __device__ __forceinline__ void fill_tile_tb(
       ZT v;
       v.x = -pref * a[1];
       v.y = pref * a[0];
-      zr[c] = v;
+      store_stream(zr + c, v);
     }
   }
   if (I != J)
@@ -1488,7 +1501,7 @@ __device__ __forceinline__ void fill_tile_tb(
         ZT v;
         v.x = -pref * a[1];
         v.y = pref * a[0];
-        zc[r] = v;
+        store_stream(zc + r, v);
       }
     }
   // rows that are non-owner halves: side[cut row][column of the J part]
@@ -1497,7 +1510,7 @@ __device__ __forceinline__ void fill_tile_tb(
     for (int c = lane; c < nbeJ; c += 64) {
       const float *a = acc + r * kTBStride + 2 * c;
       const long long col = c < nownJ ? (long long)(e0J + c) : (long long)S.ne + cutJ[c - nownJ];
-      sr[col] = make_float2(-pref * a[1], pref * a[0]);
+      store_stream(sr + col, make_float2(-pref * a[1], pref * a[0]));
     }
   }
   // columns that are non-owner halves, as rows of the side buffer (the
@@ -1508,7 +1521,7 @@ __device__ __forceinline__ void fill_tile_tb(
       for (int r = lane; r < nbeI; r += 64) {
         const float *a = acc + r * kTBStride + 2 * c;
         const long long col = r < nownI ? (long long)(e0I + r) : (long long)S.ne + cutI[r - nownI];
-        sr[col] = make_float2(-pref * a[1], pref * a[0]);
+        store_stream(sr + col, make_float2(-pref * a[1], pref * a[0]));
       }
     }
   __syncthreads();
@@ -1653,16 +1666,8 @@ __global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long l
   for (int j = ty; j < kFixTile; j += 4) {
     const int m = n0 + j;
     if (m >= ne || ci >= ncut || cut_idx[m] >= 0) continue;
-    // an isolated entry per line: streamed past the caches (non-temporal)
-    const ZT v = tile[tx][j];
-    ZT *dst = Z + (size_t)m * ldz + c;
-    if constexpr (sizeof(ZT) == 8) {
-      __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v),
-                                  reinterpret_cast<unsigned long long *>(dst));
-    } else {
-      __builtin_nontemporal_store(v.x, &dst->x);
-      __builtin_nontemporal_store(v.y, &dst->y);
-    }
+    // an isolated entry per line: streamed past the caches
+    store_stream(Z + (size_t)m * ldz + c, tile[tx][j]);
   }
 }
 
