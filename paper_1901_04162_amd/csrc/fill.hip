@@ -402,6 +402,19 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
   }
 }
 
+// Output written once and never read back by the fill: non-temporal stores
+// stream it past the caches, which keep the reused triangle and bucket
+// records instead.
+template <typename T>
+__device__ __forceinline__ void store_stream(T *dst, T v) {
+  if constexpr (sizeof(T) == 8) {
+    __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double *>(dst));
+  } else {
+    __builtin_nontemporal_store(v.x, &dst->x);
+    __builtin_nontemporal_store(v.y, &dst->y);
+  }
+}
+
 // EFIE table mode in the rule's own frame.  With rho_i = -(s_i alpha_0 +
 // t_i alpha_1) on the test triangle and rho'_j = -(s_j beta_0 + t_j beta_1)
 // on the source triangle (alpha_a = c_p - v_a, beta_b = c_q - v_b), and the
@@ -962,8 +975,8 @@ __device__ __forceinline__ void fill_tile(
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
-      Z[en.y] = v;
-      if (en.z >= 0) Z[en.z] = v;
+      store_stream(Z + en.y, v);
+      if (en.z >= 0) store_stream(Z + en.z, v);
     }
   } else {
     if (kRef) {
@@ -986,7 +999,7 @@ __device__ __forceinline__ void fill_tile(
       ZT v;
       v.x = -S.pref * ai;
       v.y = S.pref * ar;
-      Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+      store_stream(Z + (size_t)(i0 + r) * S.ldz + (j0 + c), v);
     }
     if (I != J) {
       for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
@@ -996,7 +1009,7 @@ __device__ __forceinline__ void fill_tile(
         ZT v;
         v.x = -S.pref * ai;
         v.y = S.pref * ar;
-        Z[(size_t)(j0 + c) * S.ldz + (i0 + r)] = v;
+        store_stream(Z + (size_t)(j0 + c) * S.ldz + (i0 + r), v);
       }
     }
   }
@@ -1212,7 +1225,7 @@ __device__ __forceinline__ void fill_tile_mfie(
     const int o = r * kAccStride + 2 * c;
     v.x = S.pref * acc[o];
     v.y = S.pref * acc[o + 1];
-    Z[(size_t)(i0 + r) * S.ldz + (j0 + c)] = v;
+    store_stream(Z + (size_t)(i0 + r) * S.ldz + (j0 + c), v);
   }
   if (rev) {
     for (int e = threadIdx.x; e < ni * nj; e += kFillThreads) {
@@ -1220,7 +1233,7 @@ __device__ __forceinline__ void fill_tile_mfie(
       ZT v;
       v.x = S.pref * acc2[r * kAccStride + 2 * c];
       v.y = S.pref * acc2[r * kAccStride + 2 * c + 1];
-      Z[(size_t)(j0 + r) * S.ldz + (i0 + c)] = v;
+      store_stream(Z + (size_t)(j0 + r) * S.ldz + (i0 + c), v);
     }
   }
   __syncthreads();
@@ -1283,19 +1296,6 @@ constexpr int kRhoFloats = 3 * kMaxQ;
 // registers across the pair loop
 constexpr int kAuxFloats = 22;
 constexpr int kAuxVid = 13, kAuxCent = 16;
-// Output written once and never read back by the fill: non-temporal stores
-// stream it past the caches, which keep the reused triangle and bucket
-// records instead.
-template <typename T>
-__device__ __forceinline__ void store_stream(T *dst, T v) {
-  if constexpr (sizeof(T) == 8) {
-    __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double *>(dst));
-  } else {
-    __builtin_nontemporal_store(v.x, &dst->x);
-    __builtin_nontemporal_store(v.y, &dst->y);
-  }
-}
-
 template <int Q, int MODE, typename ZT, bool kLDS, bool kRhoLDS, int kTBThreads>
 __device__ __forceinline__ void fill_tile_tb(
     const FillItem &S, const FillRule &W, const TabPtrs &tab, float *acc, float2 *gref,
@@ -1656,7 +1656,7 @@ __global__ __launch_bounds__(256) void k_cut_fix(ZT *__restrict__ Z, long long l
       z.x += -S.pref * vi;
       z.y += S.pref * vr;
     }
-    Z[(size_t)c * ldz + n] = z;
+    store_stream(Z + (size_t)c * ldz + n, z);
     tile[i][tx] = z;
   }
   __syncthreads();
