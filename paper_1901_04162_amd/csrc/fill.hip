@@ -455,6 +455,9 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
     const float B01 = B0 + B1;
     float r[Q];
     int4 w[Q];
+    // the distances and their gathers at raised wave priority, so that a wave
+    // about to start its memory latency issues ahead of waves doing arithmetic
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int kind = bary_kind(Q, j);
@@ -466,6 +469,7 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
       r[j] = __builtin_amdgcn_sqrtf(r2);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
+    __builtin_amdgcn_s_setprio(0);
     if (range) {
       // a distance outside the table's range sets the lane's flag; the
       // smallest and largest of the Q distances decide it without branches
