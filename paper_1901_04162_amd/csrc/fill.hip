@@ -343,6 +343,7 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
     const float B01 = B0 + B1;
     float r[Q];
     int4 w[Q];
+    __builtin_amdgcn_s_setprio(1);  // gathers issued ahead of arithmetic
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int kind = bary_kind(Q, j);
@@ -353,6 +354,7 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
       r[j] = __builtin_amdgcn_sqrtf(r2);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       rlo = fminf(rlo, r[j]);
