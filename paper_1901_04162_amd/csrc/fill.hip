@@ -343,7 +343,7 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
     const float B01 = B0 + B1;
     float r[Q];
     int4 w[Q];
-    __builtin_amdgcn_s_setprio(1);  // gathers issued ahead of arithmetic
+    __builtin_amdgcn_s_setprio(1);  // gathers and coefficient reads ahead of arithmetic
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int kind = bary_kind(Q, j);
@@ -354,7 +354,6 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
       r[j] = __builtin_amdgcn_sqrtf(r2);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
-    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       rlo = fminf(rlo, r[j]);
@@ -370,6 +369,7 @@ __device__ __forceinline__ void moments_table_mfie(MomentsM &M, const TabPtrs &t
       // address, the distance in the read's offset field
       B[j] = kLDS ? at_offset(tab.c01, off + 16 * kLdsCoefHalf) : at_offset(tab.c23, off);
     }
+    __builtin_amdgcn_s_setprio(0);
     float t0r = 0.f, t0i = 0.f, tsr = 0.f, tsi = 0.f, ttr = 0.f, tti = 0.f;
     float t2r = 0.f, t2i = 0.f;
 #pragma unroll
@@ -457,8 +457,9 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
     const float B01 = B0 + B1;
     float r[Q];
     int4 w[Q];
-    // the distances and their gathers at raised wave priority, so that a wave
-    // about to start its memory latency issues ahead of waves doing arithmetic
+    // the distances, their gathers and the coefficient reads at raised wave
+    // priority, so that a wave about to start its memory latency issues ahead
+    // of waves doing arithmetic
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -471,7 +472,6 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
       r[j] = __builtin_amdgcn_sqrtf(r2);
       w[j] = look_record(tab.look, look_bucket(r[j], S.tinv, S.tbias, S.tmax));
     }
-    __builtin_amdgcn_s_setprio(0);
     if (range) {
       // a distance outside the table's range sets the lane's flag; the
       // smallest and largest of the Q distances decide it without branches
@@ -491,6 +491,7 @@ __device__ __forceinline__ void moments_bary(Bary &N, const TabPtrs &tab, const 
       Ac[j] = at_offset(tab.c01, off);
       Bc[j] = kLDS ? at_offset(tab.c01, off + 16 * kLdsCoefHalf) : at_offset(tab.c23, off);
     }
+    __builtin_amdgcn_s_setprio(0);
     float t0r = 0.f, t0i = 0.f, tsr = 0.f, tsi = 0.f, ttr = 0.f, tti = 0.f;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
